@@ -1,0 +1,362 @@
+"""CPU reference ("oracle") for the differentiable Gaussian-splatting hot path.
+
+TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package; the GPU library never does.  It shares no
+code with the GPU path: the renderer is plain C in ``oracle.c`` (double precision, brute
+force over all Gaussians per pixel, no tiles), the loss gradient and Adam are written
+below in numpy float64, and the binning reference is plain numpy on the GPU's own
+float32 screen-space outputs.
+
+Pins (see ``tests/test_oracle_*.py``): closed-form images of one and two Gaussians, the
+stop-rule stack, spherical-harmonic orthonormality by quadrature, the EWA Jacobian and
+covariance against central differences, compositing invariants, and finite-difference
+gradients on tiny scenes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+_SRC = _HERE / "oracle.c"
+_LIB = _HERE / "liboracle.so"
+
+# ------------------------------------------------------------------ build / load
+_lib = None
+
+
+def build(force: bool = True) -> Path:
+    """Compile ``oracle.c`` with gcc (OpenMP, no floating-point contraction)."""
+    if force or not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+        tmp = _LIB.with_suffix(".so.tmp")
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off", "-Wall",
+               "-o", str(tmp), str(_SRC), "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+            build()
+        L = ctypes.CDLL(str(_LIB))
+        dp = ctypes.POINTER(ctypes.c_double)
+        fp = ctypes.POINTER(ctypes.c_float)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        i64 = ctypes.c_int64
+        L.orc_sh_basis.argtypes = [dp, dp]
+        L.orc_sh_basis.restype = None
+        L.orc_preprocess.argtypes = [i64, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, fp, ip]
+        L.orc_preprocess.restype = ctypes.c_int
+        L.orc_render.argtypes = [i64, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, i64, ip, dp, dp, ip, ip,
+                                 dp, dp, dp, ip]
+        L.orc_render.restype = ctypes.c_int
+        L.orc_preprocess_backward.argtypes = [i64, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_preprocess_backward.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a, ct=ctypes.c_double):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ------------------------------------------------------------------ inputs
+def cam_vec(cam) -> np.ndarray:
+    """18 doubles: R (row-major), t, fx, fy, cx, cy, width, height."""
+    v = np.zeros(18, dtype=np.float64)
+    v[:9] = np.asarray(cam.R, dtype=np.float64).reshape(9)
+    v[9:12] = np.asarray(cam.t, dtype=np.float64)
+    v[12:16] = [cam.fx, cam.fy, cam.cx, cam.cy]
+    v[16:18] = [cam.width, cam.height]
+    return v
+
+
+def _scene_args(scene, params=None):
+    """Raw parameters as float64 arrays.  ``params`` may override them (a tuple of
+    means, log_scales, quats, opacity_logit, sh already in float64), which the
+    finite-difference tests use."""
+    if params is None:
+        params = tuple(_f64(a) for a in scene.param_arrays())
+    return params
+
+
+# ------------------------------------------------------------------ renderer
+PP_FIELDS = ("u", "v", "A", "B", "C", "opacity", "r", "g", "b", "rx", "ry", "cov_a", "cov_b", "cov_c", "depth")
+F_VISIBLE, F_CLAMPX, F_CLAMPY, F_SHCLAMP_R, F_SHCLAMP_G, F_SHCLAMP_B, F_NEAR = 1, 2, 4, 8, 16, 32, 64
+
+
+def sh_basis(dirs) -> np.ndarray:
+    """Real SH basis (degree <= 3, 16 values) at unit directions ``dirs`` [M, 3]."""
+    dirs = _f64(np.atleast_2d(dirs))
+    out = np.zeros((dirs.shape[0], 16))
+    L = lib()
+    for i in range(dirs.shape[0]):
+        row = np.ascontiguousarray(dirs[i])
+        o = np.zeros(16)
+        L.orc_sh_basis(_p(row), _p(o))
+        out[i] = o
+    return out
+
+
+def preprocess(scene, cam, params=None) -> dict:
+    """Per-Gaussian screen-space quantities for one camera (double precision), the
+    float32 depth key and decision flags."""
+    n = scene.n
+    args = _scene_args(scene, params)
+    out = np.zeros((n, 16))
+    z32 = np.zeros(n, dtype=np.float32)
+    flags = np.zeros(n, dtype=np.int32)
+    rc = lib().orc_preprocess(n, scene.sh_degree, *[_p(a) for a in args], _p(cam_vec(cam)), _p(out),
+                              _p(z32, ctypes.c_float), _p(flags, ctypes.c_int32))
+    assert rc == 0, rc
+    res = {k: out[:, i] for i, k in enumerate(PP_FIELDS)}
+    res["z32"] = z32
+    res["flags"] = flags
+    res["visible"] = (flags & F_VISIBLE) != 0
+    return res
+
+
+def all_pixels(width, height) -> np.ndarray:
+    ys, xs = np.mgrid[0:height, 0:width]
+    return np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.int32)
+
+
+def render(scene, cam, bg=(0.0, 0.0, 0.0), pixels=None, dL_dC=None, params=None) -> dict:
+    """Brute-force render of ``pixels`` ([M, 2] int (px, py); default: the whole image).
+
+    Returns ``rgb`` [M, 3], ``T`` [M], ``ncontrib`` [M], ``flag`` [M] and, for a full
+    image, ``image`` [3, H, W].  With ``dL_dC`` ([M, 3], or [3, H, W] for a full image)
+    it also returns the screen-space gradient ``grad2d`` [N, 9] (u, v, A, B, C, opacity,
+    r, g, b), the absolute-term sums ``s2d`` [N, 9] and ``gflag`` [N]."""
+    n = scene.n
+    full = pixels is None
+    if full:
+        pixels = all_pixels(cam.width, cam.height)
+    pixels = np.ascontiguousarray(pixels, dtype=np.int32)
+    m = pixels.shape[0]
+    args = _scene_args(scene, params)
+    rgb = np.zeros((m, 3))
+    T = np.zeros(m)
+    nc = np.zeros(m, dtype=np.int32)
+    flag = np.zeros(m, dtype=np.int32)
+    grad2d = s2d = gflag = None
+    dl = None
+    if dL_dC is not None:
+        dl = _f64(dL_dC)
+        if full and dl.ndim == 3:
+            dl = np.ascontiguousarray(dl.reshape(3, -1).T)
+        assert dl.shape == (m, 3)
+        grad2d = np.zeros((n, 9))
+        s2d = np.zeros((n, 9))
+    gflag = np.zeros(n, dtype=np.int32)
+    bgv = _f64(bg)
+    rc = lib().orc_render(n, scene.sh_degree, *[_p(a) for a in args], _p(cam_vec(cam)), _p(bgv), m,
+                          _p(pixels, ctypes.c_int32), _p(rgb), _p(T), _p(nc, ctypes.c_int32),
+                          _p(flag, ctypes.c_int32), _p(dl), _p(grad2d), _p(s2d), _p(gflag, ctypes.c_int32))
+    assert rc == 0, rc
+    res = {"rgb": rgb, "T": T, "ncontrib": nc, "flag": flag, "gflag": gflag}
+    if full:
+        res["image"] = rgb.T.reshape(3, cam.height, cam.width)
+        res["T_image"] = T.reshape(cam.height, cam.width)
+    if grad2d is not None:
+        res["grad2d"] = grad2d
+        res["s2d"] = s2d
+    return res
+
+
+def n_raw(sh_degree: int) -> int:
+    return 11 + 3 * (sh_degree + 1) ** 2
+
+
+def split_raw(g: np.ndarray, sh_degree: int) -> dict:
+    """[N, P] raw-parameter rows -> arrays in the scene's SoA layout."""
+    K = (sh_degree + 1) ** 2
+    n = g.shape[0]
+    return {
+        "means": np.ascontiguousarray(g[:, 0:3].T),
+        "log_scales": np.ascontiguousarray(g[:, 3:6].T),
+        "quats": np.ascontiguousarray(g[:, 6:10].T),
+        "opacity_logit": np.ascontiguousarray(g[:, 10]),
+        "sh": np.ascontiguousarray(g[:, 11:].reshape(n, K, 3).transpose(1, 2, 0)),
+    }
+
+
+def preprocess_backward(scene, cam, grad2d, s2d=None, params=None) -> dict:
+    """Raw-parameter gradients (SoA dict) from a screen-space gradient [N, 9]; with
+    ``s2d`` also the absolute-term bound ``s`` of each entry (same layout, key
+    ``"s"``)."""
+    n = scene.n
+    P = n_raw(scene.sh_degree)
+    args = _scene_args(scene, params)
+    g = np.zeros((n, P))
+    sr = np.zeros((n, P)) if s2d is not None else None
+    rc = lib().orc_preprocess_backward(n, scene.sh_degree, *[_p(a) for a in args], _p(cam_vec(cam)),
+                                       _p(_f64(grad2d)), _p(None if s2d is None else _f64(s2d)), _p(g), _p(sr))
+    assert rc == 0, rc
+    res = split_raw(g, scene.sh_degree)
+    if sr is not None:
+        res["s"] = split_raw(sr, scene.sh_degree)
+    return res
+
+
+def gradients(scene, cams, dL_dC_views, bg=(0.0, 0.0, 0.0), pixels=None, params=None) -> dict:
+    """Raw-parameter gradients summed over views (``dL_dC_views[v]`` as for
+    ``render``).  Returns the SoA gradient dict with ``s`` bounds and ``gflag``."""
+    total = None
+    stot = None
+    gflag = np.zeros(scene.n, dtype=np.int32)
+    for v, cam in enumerate(cams):
+        pix = None if pixels is None else pixels[v]
+        r = render(scene, cam, bg, pix, dL_dC_views[v], params)
+        g = preprocess_backward(scene, cam, r["grad2d"], r["s2d"], params)
+        s = g.pop("s")
+        if total is None:
+            total, stot = g, s
+        else:
+            for k in total:
+                total[k] = total[k] + g[k]
+                stot[k] = stot[k] + s[k]
+        gflag |= r["gflag"]
+    total["s"] = stot
+    total["gflag"] = gflag
+    return total
+
+
+# ------------------------------------------------------------------ loss
+def l1_loss_grad(image, target, pixel_mask=None):
+    """L1 photometric loss L = sum|C - C*| / (3HW) over the whole image and its gradient
+    sign(C - C*)/(3HW) (sign(0) = 0).  With ``pixel_mask`` ([H, W] bool) the gradient is
+    zero outside the mask but keeps the full-image normalisation, and the loss sums only
+    masked pixels."""
+    image = _f64(image)
+    target = _f64(target)
+    c, h, w = image.shape[-3:]
+    norm = 1.0 / (3.0 * h * w)
+    diff = image - target
+    grad = np.sign(diff) * norm
+    absd = np.abs(diff)
+    if pixel_mask is not None:
+        grad = grad * pixel_mask
+        absd = absd * pixel_mask
+    return absd.sum() * norm, grad
+
+
+# ------------------------------------------------------------------ Adam
+def adam_step(params, grads, m, v, step, lrs, beta1=0.9, beta2=0.999, eps=1e-15, rows=None):
+    """Adam (Kingma & Ba) on the rows ``rows`` (index array or slice over the last
+    axis) of every parameter group; other rows are returned unchanged.  ``params``,
+    ``grads``, ``m``, ``v`` are dicts of arrays whose last axis is the Gaussian index;
+    ``lrs`` maps group -> learning rate; ``step`` is the 1-based step count.  Returns
+    new (params, m, v) in float64."""
+    if rows is None:
+        rows = slice(None)
+    bc1 = 1.0 - beta1 ** step
+    bc2 = 1.0 - beta2 ** step
+    P, M, V = {}, {}, {}
+    for k in params:
+        p = _f64(params[k]).copy()
+        mm = _f64(m[k]).copy()
+        vv = _f64(v[k]).copy()
+        g = _f64(grads[k])[..., rows]
+        mm[..., rows] = beta1 * mm[..., rows] + (1.0 - beta1) * g
+        vv[..., rows] = beta2 * vv[..., rows] + (1.0 - beta2) * g * g
+        mhat = mm[..., rows] / bc1
+        vhat = vv[..., rows] / bc2
+        p[..., rows] = p[..., rows] - lrs[k] * mhat / (np.sqrt(vhat) + eps)
+        P[k], M[k], V[k] = p, mm, vv
+    return P, M, V
+
+
+# ------------------------------------------------------------------ binning reference
+TILE = 16
+
+
+def tile_grid(width, height):
+    return (width + TILE - 1) // TILE, (height + TILE - 1) // TILE
+
+
+def tile_rects(u, v, rx, ry, width, height):
+    """Tile rectangle [x0, x1) x [y0, y1) of each Gaussian from its float32 screen
+    centre and half extents: every pixel whose centre lies in [u - rx, u + rx] x
+    [v - ry, v + ry] is covered.  Evaluated in float32 in this exact order:
+    x0 = clamp(floor((u - rx - 0.5) * 0.0625), 0, TX), x1 = clamp(floor((u + rx - 0.5) *
+    0.0625) + 1, 0, TX), and the same for y."""
+    f = np.float32
+    TX, TY = tile_grid(width, height)
+    u, v, rx, ry = (np.asarray(a, dtype=np.float32) for a in (u, v, rx, ry))
+    with np.errstate(invalid="ignore", over="ignore"):
+        x0 = np.floor(((u - rx) - f(0.5)) * f(0.0625))
+        x1 = np.floor(((u + rx) - f(0.5)) * f(0.0625)) + f(1.0)
+        y0 = np.floor(((v - ry) - f(0.5)) * f(0.0625))
+        y1 = np.floor(((v + ry) - f(0.5)) * f(0.0625)) + f(1.0)
+    cl = lambda a, hi: np.minimum(np.maximum(a, f(0.0)), f(hi)).astype(np.int64)
+    return cl(x0, TX), cl(x1, TX), cl(y0, TY), cl(y1, TY)
+
+
+def bin_reference(u, v, rx, ry, z32, visible, width, height, active=None, use_mask=False):
+    """Per-tile depth-ordered Gaussian lists for one view, from float32 inputs.
+
+    Every visible Gaussian is emitted into each tile of its rectangle (only tiles of the
+    render mask when ``use_mask``; the mask is the union of the rectangles of the
+    visible Gaussians in ``active`` = (begin, end)), in Gaussian-index order; pairs are
+    stably ordered by (tile, depth key bits), so equal depths stay in index order.
+    Returns dict(values, tiles, ranges [T, 2], mask [T] bool, n_pairs, rects)."""
+    TX, TY = tile_grid(width, height)
+    T = TX * TY
+    n = len(u)
+    x0, x1, y0, y1 = tile_rects(u, v, rx, ry, width, height)
+    vis = np.asarray(visible, dtype=bool)
+    mask = np.ones(T, dtype=bool)
+    if use_mask:
+        mask = np.zeros(T, dtype=bool)
+        a0, a1 = (0, n) if active is None else active
+        for i in range(a0, a1):
+            if vis[i] and x1[i] > x0[i] and y1[i] > y0[i]:
+                yy, xx = np.mgrid[y0[i]:y1[i], x0[i]:x1[i]]
+                mask[(yy * TX + xx).ravel()] = True
+    gids, tiles = [], []
+    for i in range(n):
+        if not vis[i] or x1[i] <= x0[i] or y1[i] <= y0[i]:
+            continue
+        yy, xx = np.mgrid[y0[i]:y1[i], x0[i]:x1[i]]
+        t = (yy * TX + xx).ravel()
+        t = t[mask[t]]
+        gids.append(np.full(t.shape, i, dtype=np.int64))
+        tiles.append(t)
+    gids = np.concatenate(gids) if gids else np.zeros(0, dtype=np.int64)
+    tiles = np.concatenate(tiles) if tiles else np.zeros(0, dtype=np.int64)
+    zbits = np.asarray(z32, dtype=np.float32).view(np.uint32).astype(np.int64)[gids]
+    order = np.lexsort((gids, zbits, tiles))
+    gids, tiles = gids[order], tiles[order]
+    ranges = np.zeros((T, 2), dtype=np.int64)
+    if len(tiles):
+        starts = np.searchsorted(tiles, np.arange(T), side="left")
+        ends = np.searchsorted(tiles, np.arange(T), side="right")
+        nonempty = ends > starts
+        ranges[nonempty, 0] = starts[nonempty]
+        ranges[nonempty, 1] = ends[nonempty]
+    return {"values": gids, "tiles": tiles, "ranges": ranges, "mask": mask, "n_pairs": len(gids),
+            "rects": (x0, x1, y0, y1)}
+
+
+def tile_list_reference(u, v, rx, ry, z32, visible, width, height, tile):
+    """The depth-ordered Gaussian list of one tile (for spot checks at full size)."""
+    TX, _ = tile_grid(width, height)
+    x0, x1, y0, y1 = tile_rects(u, v, rx, ry, width, height)
+    tx, ty = tile % TX, tile // TX
+    sel = np.nonzero(np.asarray(visible, bool) & (x0 <= tx) & (tx < x1) & (y0 <= ty) & (ty < y1))[0]
+    zbits = np.asarray(z32, dtype=np.float32).view(np.uint32)[sel].astype(np.int64)
+    return sel[np.lexsort((sel, zbits))]
