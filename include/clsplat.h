@@ -1,0 +1,272 @@
+/*
+ * clsplat — C-ABI of the MI355X (gfx950) hot path of CL-Splats' local optimisation.
+ *
+ * The paper (CL-Splats, Sec. 3 problem statement) updates an existing 3D Gaussian
+ * reconstruction G^{t-1} from new posed images I^t, optimising only the changed
+ * Gaussians O^t (Sec. 3.2 "Mask Majority Voting") with a local kernel (Sec. 3.3 "Local
+ * Optimization Kernel"; Supp. "Local Optimization Kernel", items 1-3) and a masked Adam
+ * step (Supp. "3DGS Optimization in Changed Regions").  The calls below are one
+ * optimisation step of that loop:
+ *
+ *   clsp_project_preprocess  per-Gaussian projection, colour, extent, tile rectangle
+ *                            (Table tab:timings "Forward::Preprocess")
+ *   clsp_bin_and_sort        tile render mask from O^t (item 1), per-tile depth order
+ *                            restricted to masked tiles
+ *   clsp_render_forward      front-to-back compositing of masked tiles (item 2;
+ *                            "Forward::Render")
+ *   clsp_l1_loss_grad        dL/dimage of the L1 photometric loss on masked tiles
+ *   clsp_render_backward     reverse compositing of masked tiles with gradients only for
+ *                            O^t (item 2; "Backward::Render"), then the preprocess
+ *                            backward for O^t only (item 3; "Backward::Preprocess")
+ *   clsp_masked_adam_step    Adam on the rows of O^t only; other rows and their moments
+ *                            are not touched
+ *   clsp_zero_grads          clear the gradient rows of O^t
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every data pointer is a DEVICE pointer owned by the caller, except `cams`, `bg`
+ *   and `hp`, which are HOST pointers read before the call returns.  The library never
+ *   allocates device memory; scratch space is a caller-provided workspace whose size
+ *   the *_workspace_bytes() queries return.
+ * - Every call enqueues work on `stream` (a hipStream_t; NULL is the default stream)
+ *   and returns without synchronising.  Inputs must stay valid until that work is done.
+ * - Arguments are validated on the host before anything is enqueued.  On error nothing
+ *   is enqueued and a negative status is returned; clsp_last_error() gives a message
+ *   (per host thread).  CLSP_ERR_HIP reports a failed launch.
+ * - Floating point is IEEE float32 throughout.
+ * - Gaussian parameters are raw (pre-activation) and component-major (SoA):
+ *   component c of Gaussian i is at [c * n_rows + row(i)], row(i) = gather ? gather[i] : i.
+ *   means[3], log_scales[3], quats[4] (w, x, y, z; normalised inside), opacity_logit[1],
+ *   sh[K][3] with K = (D+1)^2 real spherical-harmonic coefficients per colour channel.
+ * - The change set O^t is the contiguous index range [active.begin, active.end): the
+ *   paper stores the unchanged Gaussians first and the changed ones last (Supp.
+ *   "History Recovery"), so O^t is a suffix.  A full-scene step uses {0, n}.
+ * - Views: one call handles n_views cameras of equal width and height.  Per-view
+ *   outputs are stacked: Gaussian i of view v is entry v*n + i; tile t of view v is the
+ *   global tile v*T + t with T = TX*TY, TX = ceil(W/16), TY = ceil(H/16), t = ty*TX + tx.
+ * - Images are planar: image[v][c][y][x], T_final[v][y][x], n_contrib[v][y][x].
+ *
+ * The forward model (the paper builds on standard 3D Gaussian Splatting, Supp.
+ * "Implementation Details"): pixel (x, y) samples (x + 0.5, y + 0.5); a Gaussian is
+ * projected with p = R mu + t, u = fx X/Z + cx, v = fy Y/Z + cy, screen covariance
+ * J R Sigma R^T J^T + 0.3 I (J with X/Z, Y/Z clamped to 1.3 (W/2)/fx, 1.3 (H/2)/fy);
+ * colour = max(0, sum_k f_k Y_k(dir) + 0.5) with real SH (no Condon-Shortley phase,
+ * k = l^2 + l + m) of the direction from the camera centre; per pixel, Gaussians are
+ * composited front to back in order of the float32 depth key
+ * z32 = fmaf(R[6], x, fmaf(R[7], y, fmaf(R[8], z, t[2]))) (ties: lower index first), with
+ * alpha = min(0.99, o exp(-d^T conic d / 2)), alpha < 1/255 skipped, and compositing
+ * stopped before the Gaussian that would take the transmittance below 1e-4.
+ * Gaussians are culled when z32 <= 0.2, the quaternion is zero, or the opacity is
+ * below 1/255.  The tile rectangle covers every pixel centre within (u +- rx, v +- ry)
+ * where rx, ry bound the ellipse alpha >= 1/255 with a relative margin of 2^-12 for
+ * float32 rounding (rx = sqrt(2 ln(255 o) a) (1 + 2^-12), a, c the diagonal of the
+ * screen covariance):
+ * x0 = clamp(floor((u - rx - 0.5) * 0.0625), 0, TX), x1 = clamp(floor((u + rx - 0.5) *
+ * 0.0625) + 1, 0, TX), evaluated in float32 in that order; y likewise.
+ */
+#ifndef CLSPLAT_H
+#define CLSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t clsp_status;
+#define CLSP_OK 0
+#define CLSP_ERR_INVALID_ARG (-1)
+#define CLSP_ERR_HIP (-3)
+#define CLSP_ERR_UNSUPPORTED (-4)
+
+#define CLSP_TILE 16
+#define CLSP_MAX_VIEWS 64
+#define CLSP_MAX_SIDE 16384
+
+/* hipStream_t; NULL selects the default stream. */
+typedef void *clsp_stream;
+
+/* Pinhole camera, world to camera: p = R x + t (row-major R), OpenCV axes. */
+typedef struct clsp_camera {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+} clsp_camera;
+
+/* Raw Gaussian parameters (device, SoA, see above).  n Gaussians; the arrays hold
+ * n_rows rows; gather (nullable, int32[n]) selects row gather[i] for Gaussian i, which
+ * lets one resident pool serve several stored scene states. */
+typedef struct clsp_gaussians {
+  const float *means;
+  const float *log_scales;
+  const float *quats;
+  const float *opacity_logit;
+  const float *sh;
+  const int32_t *gather;
+  int64_t n;
+  int64_t n_rows;
+  int32_t sh_degree;
+  int32_t reserved;
+} clsp_gaussians;
+
+/* Writable views of the same arrays (Adam updates them in place; gradients use the
+ * same layout with n_rows = n and no gather). */
+typedef struct clsp_params {
+  float *means;
+  float *log_scales;
+  float *quats;
+  float *opacity_logit;
+  float *sh;
+  int64_t n;
+  int32_t sh_degree;
+  int32_t reserved;
+} clsp_params;
+
+typedef struct clsp_range {
+  int64_t begin;
+  int64_t end;
+} clsp_range;
+
+/* Output of clsp_project_preprocess (device), [n_views * n] entries each.
+ *   splat  float[12] per entry: u, v, A, B | C, opacity, r, g | b, rx, ry, 0
+ *          (A, B, C: the inverse screen covariance [[A, B], [B, C]])
+ *   depth  float z32 depth key
+ *   rect   uint32[2] per entry: x0 | x1 << 16, y0 | y1 << 16 (tiles [x0,x1) x [y0,y1));
+ *          empty for culled Gaussians
+ *   flags  uint32: bit 0 visible, 1 x-ratio clamped, 2 y-ratio clamped,
+ *          3..5 colour channel r, g, b clamped at 0 */
+typedef struct clsp_projected {
+  float *splat;
+  float *depth;
+  uint32_t *rect;
+  uint32_t *flags;
+} clsp_projected;
+
+#define CLSP_FLAG_VISIBLE 1u
+#define CLSP_FLAG_CLAMP_X 2u
+#define CLSP_FLAG_CLAMP_Y 4u
+#define CLSP_FLAG_SHCLAMP_R 8u
+
+/* Per-tile depth-ordered lists (device).
+ *   values    uint32[capacity]: entry index v*n + i of each (tile, Gaussian) pair,
+ *             sorted by global tile, then depth key, then Gaussian index
+ *   keys      uint32[capacity]: the global tile of each sorted pair
+ *   ranges    uint32[n_views*T][2]: [start, end) of each tile's pairs; [0, 0) when a
+ *             tile has none or is outside the render mask
+ *   tile_mask uint32[n_views][ceil(T/32)]: bit (t % 32) of word t/32 of view v is set
+ *             when tile t of view v is rendered
+ *   tile_list uint32[n_views*T]: the rendered global tiles, ascending
+ *   counters  uint32[8]: [0] pairs needed P, [1] overflow (1 when P > capacity; then no
+ *             list or range is valid, no tile is rendered, and the caller must grow
+ *             `capacity` and call again), [2] number of rendered tiles, [3] pairs written
+ *             (P, or 0 on overflow), [4] entries with at least one pair, [5] sticky
+ *             overflow: set to 1 on overflow and never cleared by the library, so a
+ *             caller can check once after many steps; [6], [7] reserved.  Slots 0-4 are
+ *             rewritten by every call. */
+typedef struct clsp_bins {
+  uint32_t *values;
+  uint32_t *keys;
+  uint32_t *ranges;
+  uint32_t *tile_mask;
+  uint32_t *tile_list;
+  uint32_t *counters;
+  int64_t capacity;
+} clsp_bins;
+
+/* Adam hyper-parameters (host).  lr per group: 0 means, 1 log_scales, 2 quats,
+ * 3 opacity_logit, 4 sh degree-0 rows (k = 0), 5 higher sh rows (k >= 1).  step is the
+ * 1-based step count used in the bias corrections. */
+typedef struct clsp_adam_hparams {
+  float lr[6];
+  float beta1, beta2, eps;
+  int32_t step;
+} clsp_adam_hparams;
+
+/* Library version string and the last error message of the calling host thread. */
+const char *clsp_version(void);
+const char *clsp_last_error(void);
+
+/* ---------------------------------------------------------------------------------
+ * Forward preprocess (Table tab:timings "Forward::Preprocess"; Sec. 3.3 step 1 reuses
+ * this projection for the render mask and the depth order).
+ * g: raw parameters; cams[n_views] (host); out: [n_views*n] entries as documented for
+ * clsp_projected.  All n Gaussians are projected in every mode: unchanged Gaussians
+ * still occlude and colour the masked tiles.
+ * Errors: null pointers, n < 0, sh_degree not in 0..3, n_views not in 1..64, sizes
+ * not in 1..16384 or differing between views, n_views*n >= 2^32. */
+clsp_status clsp_project_preprocess(const clsp_gaussians *g, const clsp_camera *cams, int32_t n_views,
+                                    const clsp_projected *out, clsp_stream stream);
+
+/* ---------------------------------------------------------------------------------
+ * Render mask and per-tile depth order (Supp. "Local Optimization Kernel", item 1: a
+ * boolean ceil(w/16) x ceil(h/16) mask that is true where at least one changed
+ * Gaussian projects, reusing the projection for the per-tile depth ordering).
+ * With use_mask != 0 the mask is the union of the tile rectangles of the visible
+ * Gaussians in `active` and pairs are emitted only into masked tiles; with use_mask == 0
+ * every tile is rendered.  Capacity overflow is reported on the device (counters[1]);
+ * nothing is read back here.  ws: device workspace of at least
+ * clsp_bin_and_sort_workspace_bytes(n, n_views, width, height, capacity) bytes.
+ * Errors: as above, plus capacity not in 0..2^32-1, active outside [0, n],
+ * workspace too small. */
+size_t clsp_bin_and_sort_workspace_bytes(int64_t n, int32_t n_views, int32_t width, int32_t height,
+                                         int64_t capacity);
+clsp_status clsp_bin_and_sort(const clsp_projected *proj, int64_t n, const clsp_camera *cams, int32_t n_views,
+                              clsp_range active, int32_t use_mask, const clsp_bins *bins, void *ws, size_t ws_bytes,
+                              clsp_stream stream);
+
+/* ---------------------------------------------------------------------------------
+ * Forward rendering of the rendered tiles (Sec. 3.3 step 2; Supp. item 2: threads of
+ * unmasked tiles do no work).  bg: host float[3] background colour.  Writes image,
+ * T_final and n_contrib (1 + position, within the tile's list, of the last Gaussian
+ * blended at the pixel; 0 if none) for the pixels of rendered tiles only; other pixels
+ * are left as they were. */
+clsp_status clsp_render_forward(const clsp_projected *proj, const clsp_bins *bins, const clsp_camera *cams,
+                                int32_t n_views, const float *bg, float *image, float *T_final, uint32_t *n_contrib,
+                                clsp_stream stream);
+
+/* ---------------------------------------------------------------------------------
+ * L1 photometric loss gradient on the rendered tiles: dL_dimage = sign(image - target)
+ * / (3 H W) (sign(0) = 0, full-image normalisation in every mode), zero elsewhere is NOT
+ * written (pixels outside rendered tiles are left as they were).  loss_sum (device
+ * float[1], accumulated +=) receives sum |image - target| / (3 H W) over rendered
+ * pixels; it may be NULL. */
+clsp_status clsp_l1_loss_grad(const float *image, const float *target, const clsp_bins *bins,
+                              const clsp_camera *cams, int32_t n_views, float *dL_dimage, float *loss_sum,
+                              clsp_stream stream);
+
+/* ---------------------------------------------------------------------------------
+ * Backward (Table tab:timings "Backward::Render" and "Backward::Preprocess"; Supp.
+ * items 2-3).  Reverse compositing over the rendered tiles accumulates screen-space
+ * gradients for the Gaussians in `active` only, then the chain rule to raw parameters
+ * runs for `active` only.  Gradients are ADDED to `grads` (layout of clsp_params,
+ * n_rows = n, rows outside `active` never written).  g must be the parameters the
+ * projection was made from; T_final and n_contrib come from clsp_render_forward.
+ * ws: device workspace of clsp_render_backward_workspace_bytes(active.end -
+ * active.begin, n_views) bytes. */
+size_t clsp_render_backward_workspace_bytes(int64_t n_active, int32_t n_views);
+clsp_status clsp_render_backward(const clsp_gaussians *g, const clsp_projected *proj, const clsp_bins *bins,
+                                 const clsp_camera *cams, int32_t n_views, const float *bg, clsp_range active,
+                                 const float *T_final, const uint32_t *n_contrib, const float *dL_dimage,
+                                 const clsp_params *grads, void *ws, size_t ws_bytes, clsp_stream stream);
+
+/* ---------------------------------------------------------------------------------
+ * Masked Adam (Supp. "3DGS Optimization in Changed Regions": gradients and optimiser
+ * updates only for O^t, so the first and second moments cannot move frozen
+ * Gaussians).  For every row in `active` (and, when row_mask is not NULL, with
+ * row_mask[row] != 0): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * theta -= lr * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).  Other rows of
+ * params, m and v are not read or written. */
+clsp_status clsp_masked_adam_step(const clsp_params *params, const clsp_params *grads, const clsp_params *exp_avg,
+                                  const clsp_params *exp_avg_sq, clsp_range active, const uint8_t *row_mask,
+                                  const clsp_adam_hparams *hp, clsp_stream stream);
+
+/* Set the gradient rows in `active` to zero. */
+clsp_status clsp_zero_grads(const clsp_params *grads, clsp_range active, clsp_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLSPLAT_H */

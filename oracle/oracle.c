@@ -304,10 +304,12 @@ static void project_one(const scene_t *sc, int64_t i, const cam_t *cam, gstate_t
     }
   }
 
-  /* extent: alpha >= 1/255 needs d^T conic d <= 2 ln(255 o) */
+  /* extent: alpha >= 1/255 needs d^T conic d <= 2 ln(255 o); the box of that ellipse
+   * has half widths sqrt(2 ln(255 o) a) and sqrt(2 ln(255 o) c).  A relative margin of
+   * 2^-12 keeps a float32 evaluation of the same box conservative. */
   const double kappa = 2.0 * log(255.0 * g->o);
-  g->rx = sqrt(kappa * g->cov2[0]);
-  g->ry = sqrt(kappa * g->cov2[2]);
+  g->rx = sqrt(kappa * g->cov2[0]) * (1.0 + 1.0 / 4096.0);
+  g->ry = sqrt(kappa * g->cov2[2]) * (1.0 + 1.0 / 4096.0);
   g->visible = 1;
   g->flags |= ORC_F_VISIBLE;
 }

@@ -1,0 +1,290 @@
+"""Python face of the clsplat C-ABI: the same calls, taking torch tensors.
+
+Every function here only checks shapes, packs ctypes structs from tensor pointers and
+calls the library on the current torch stream (or the stream given).  All computation
+happens in the HIP kernels; there is no other implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _ffi
+from ._ffi import check
+
+TILE = _ffi.TILE
+
+
+def lib():
+    return _ffi.load()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _f32(t, device=None):
+    t = torch.as_tensor(t, dtype=torch.float32, device=device)
+    return t.contiguous()
+
+
+def tile_grid(width, height):
+    return (width + TILE - 1) // TILE, (height + TILE - 1) // TILE
+
+
+# ------------------------------------------------------------------ cameras
+def camera_array(cams):
+    """ctypes array of clsp_camera from objects with R, t, fx, fy, cx, cy, width,
+    height (e.g. ``scenes.Camera``)."""
+    arr = (_ffi.Camera * len(cams))()
+    for i, c in enumerate(cams):
+        R = np.asarray(c.R, dtype=np.float32).reshape(9)
+        t = np.asarray(c.t, dtype=np.float32).reshape(3)
+        arr[i].R = (ctypes.c_float * 9)(*R.tolist())
+        arr[i].t = (ctypes.c_float * 3)(*t.tolist())
+        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+        arr[i].width, arr[i].height = int(c.width), int(c.height)
+    return arr
+
+
+# ------------------------------------------------------------------ parameter sets
+@dataclass
+class GaussianTensors:
+    """Raw parameters on the device, component-major: means [3, N], log_scales [3, N],
+    quats [4, N], opacity_logit [N], sh [K, 3, N]."""
+    means: torch.Tensor
+    log_scales: torch.Tensor
+    quats: torch.Tensor
+    opacity_logit: torch.Tensor
+    sh: torch.Tensor
+    sh_degree: int
+
+    NAMES = ("means", "log_scales", "quats", "opacity_logit", "sh")
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[-1])
+
+    @classmethod
+    def from_scene(cls, scene, device):
+        return cls(*[_f32(a, device) for a in scene.param_arrays()], scene.sh_degree)
+
+    @classmethod
+    def zeros(cls, n, sh_degree, device):
+        K = (sh_degree + 1) ** 2
+        z = lambda *s: torch.zeros(*s, dtype=torch.float32, device=device)
+        return cls(z(3, n), z(3, n), z(4, n), z(n), z(K, 3, n), sh_degree)
+
+    def zeros_like(self):
+        return GaussianTensors(*[torch.zeros_like(getattr(self, k)) for k in self.NAMES], self.sh_degree)
+
+    def clone(self):
+        return GaussianTensors(*[getattr(self, k).clone() for k in self.NAMES], self.sh_degree)
+
+    def tensors(self):
+        return [getattr(self, k) for k in self.NAMES]
+
+    def check(self):
+        n = self.n
+        K = (self.sh_degree + 1) ** 2
+        shapes = {"means": (3, n), "log_scales": (3, n), "quats": (4, n), "opacity_logit": (n,), "sh": (K, 3, n)}
+        for k, s in shapes.items():
+            t = getattr(self, k)
+            if tuple(t.shape[-len(s):]) != s or t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"{k}: expected contiguous float32 CUDA tensor of shape {s}, got "
+                                 f"{tuple(t.shape)} {t.dtype} contiguous={t.is_contiguous()} cuda={t.is_cuda}")
+
+    def as_gaussians(self, gather=None, n=None):
+        self.check()
+        g = _ffi.Gaussians()
+        g.means, g.log_scales, g.quats = _ptr(self.means), _ptr(self.log_scales), _ptr(self.quats)
+        g.opacity_logit, g.sh = _ptr(self.opacity_logit), _ptr(self.sh)
+        g.n_rows = self.n
+        if gather is not None:
+            if gather.dtype != torch.int32 or not gather.is_contiguous():
+                raise ValueError("gather must be a contiguous int32 tensor")
+            g.gather = _ptr(gather)
+            g.n = int(gather.numel())
+        else:
+            g.gather = None
+            g.n = self.n if n is None else int(n)
+        g.sh_degree = self.sh_degree
+        return g
+
+    def as_params(self):
+        self.check()
+        p = _ffi.Params()
+        p.means, p.log_scales, p.quats = _ptr(self.means), _ptr(self.log_scales), _ptr(self.quats)
+        p.opacity_logit, p.sh = _ptr(self.opacity_logit), _ptr(self.sh)
+        p.n = self.n
+        p.sh_degree = self.sh_degree
+        return p
+
+
+# ------------------------------------------------------------------ buffers
+@dataclass
+class ProjectedBuffers:
+    splat: torch.Tensor   # [V*N, 12] float32
+    depth: torch.Tensor   # [V*N] float32
+    rect: torch.Tensor    # [V*N, 2] int32 (uint32 bit patterns)
+    flags: torch.Tensor   # [V*N] int32
+    n: int
+    views: int
+
+    @classmethod
+    def alloc(cls, n, views, device):
+        e = max(1, n * views)
+        return cls(torch.empty(e, 12, dtype=torch.float32, device=device),
+                   torch.empty(e, dtype=torch.float32, device=device),
+                   torch.empty(e, 2, dtype=torch.int32, device=device),
+                   torch.empty(e, dtype=torch.int32, device=device), n, views)
+
+    def struct(self):
+        p = _ffi.Projected()
+        p.splat, p.depth, p.rect, p.flags = _ptr(self.splat), _ptr(self.depth), _ptr(self.rect), _ptr(self.flags)
+        return p
+
+
+@dataclass
+class BinBuffers:
+    values: torch.Tensor     # [capacity] int32 (entry index)
+    keys: torch.Tensor       # [capacity] int32 (global tile)
+    ranges: torch.Tensor     # [V*T, 2] int32
+    tile_mask: torch.Tensor  # [V, ceil(T/32)] int32
+    tile_list: torch.Tensor  # [V*T] int32
+    counters: torch.Tensor   # [8] int32
+    ws: torch.Tensor         # workspace bytes
+    capacity: int
+    n: int
+    views: int
+    width: int
+    height: int
+
+    @classmethod
+    def alloc(cls, n, views, width, height, capacity, device):
+        TX, TY = tile_grid(width, height)
+        T = TX * TY
+        cap = max(1, int(capacity))
+        wsb = lib().clsp_bin_and_sort_workspace_bytes(n, views, width, height, cap)
+        i32 = lambda *s: torch.zeros(*s, dtype=torch.int32, device=device)
+        return cls(i32(cap), i32(cap), i32(views * T, 2), i32(views, (T + 31) // 32), i32(views * T), i32(8),
+                   torch.empty(max(1, wsb), dtype=torch.uint8, device=device), cap, n, views, width, height)
+
+    def struct(self):
+        b = _ffi.Bins()
+        b.values, b.keys, b.ranges = _ptr(self.values), _ptr(self.keys), _ptr(self.ranges)
+        b.tile_mask, b.tile_list, b.counters = _ptr(self.tile_mask), _ptr(self.tile_list), _ptr(self.counters)
+        b.capacity = self.capacity
+        return b
+
+    def read_counters(self):
+        c = self.counters.cpu().numpy().view(np.uint32)
+        return {"pairs": int(c[_ffi.C_PAIRS]), "overflow": bool(c[_ffi.C_OVERFLOW]), "tiles": int(c[_ffi.C_TILES]),
+                "written": int(c[_ffi.C_WRITTEN]), "entries": int(c[_ffi.C_ENTRIES])}
+
+
+# ------------------------------------------------------------------ calls
+def project_preprocess(g: GaussianTensors, cams, out: ProjectedBuffers | None = None, gather=None, stream=None):
+    n = g.n if gather is None else int(gather.numel())
+    if out is None:
+        out = ProjectedBuffers.alloc(n, len(cams), g.means.device)
+    if out.n != n or out.views != len(cams):
+        raise ValueError("projected buffers sized for another scene")
+    gs = g.as_gaussians(gather)
+    ca = camera_array(cams)
+    check(lib().clsp_project_preprocess(ctypes.byref(gs), ca, len(cams), ctypes.byref(out.struct()), _stream(stream)))
+    return out
+
+
+def bin_and_sort(proj: ProjectedBuffers, cams, active=None, use_mask=False, bins: BinBuffers | None = None,
+                 capacity=None, stream=None):
+    n = proj.n
+    a0, a1 = (0, n) if active is None else (int(active[0]), int(active[1]))
+    if bins is None:
+        cap = capacity if capacity is not None else max(1024, 64 * n * len(cams))
+        bins = BinBuffers.alloc(n, len(cams), cams[0].width, cams[0].height, cap, proj.splat.device)
+    ca = camera_array(cams)
+    check(lib().clsp_bin_and_sort(ctypes.byref(proj.struct()), n, ca, len(cams), _ffi.Range(a0, a1),
+                                  1 if use_mask else 0, ctypes.byref(bins.struct()), _ptr(bins.ws), bins.ws.numel(),
+                                  _stream(stream)))
+    return bins
+
+
+def render_forward(proj, bins, cams, bg=(0.0, 0.0, 0.0), image=None, T_final=None, n_contrib=None, stream=None):
+    V, H, W = len(cams), cams[0].height, cams[0].width
+    dev = proj.splat.device
+    if image is None:
+        image = torch.zeros(V, 3, H, W, dtype=torch.float32, device=dev)
+    if T_final is None:
+        T_final = torch.zeros(V, H, W, dtype=torch.float32, device=dev)
+    if n_contrib is None:
+        n_contrib = torch.zeros(V, H, W, dtype=torch.int32, device=dev)
+    for t, shape in ((image, (V, 3, H, W)), (T_final, (V, H, W)), (n_contrib, (V, H, W))):
+        if tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"output of shape {tuple(t.shape)}, expected contiguous {shape}")
+    bgc = (ctypes.c_float * 3)(*[float(x) for x in bg])
+    check(lib().clsp_render_forward(ctypes.byref(proj.struct()), ctypes.byref(bins.struct()), camera_array(cams), V, bgc,
+                                    _ptr(image), _ptr(T_final), _ptr(n_contrib), _stream(stream)))
+    return image, T_final, n_contrib
+
+
+def l1_loss_grad(image, target, bins, cams, dL=None, loss_sum=None, stream=None):
+    if dL is None:
+        dL = torch.zeros_like(image)
+    if tuple(target.shape) != tuple(image.shape) or target.dtype != torch.float32 or not target.is_contiguous():
+        raise ValueError("target must be a contiguous float32 tensor shaped like image")
+    check(lib().clsp_l1_loss_grad(_ptr(image), _ptr(target), ctypes.byref(bins.struct()), camera_array(cams), len(cams),
+                                  _ptr(dL), _ptr(loss_sum), _stream(stream)))
+    return dL
+
+
+def render_backward_workspace(n_active, views, device):
+    b = lib().clsp_render_backward_workspace_bytes(int(n_active), int(views))
+    return torch.empty(max(1, b), dtype=torch.uint8, device=device)
+
+
+def render_backward(g: GaussianTensors, proj, bins, cams, bg, active, T_final, n_contrib, dL, grads: GaussianTensors,
+                    ws=None, stream=None):
+    a0, a1 = (0, g.n) if active is None else (int(active[0]), int(active[1]))
+    if ws is None:
+        ws = render_backward_workspace(a1 - a0, len(cams), g.means.device)
+    bgc = (ctypes.c_float * 3)(*[float(x) for x in bg])
+    check(lib().clsp_render_backward(ctypes.byref(g.as_gaussians()), ctypes.byref(proj.struct()),
+                                     ctypes.byref(bins.struct()), camera_array(cams), len(cams), bgc,
+                                     _ffi.Range(a0, a1), _ptr(T_final), _ptr(n_contrib), _ptr(dL),
+                                     ctypes.byref(grads.as_params()), _ptr(ws), ws.numel(), _stream(stream)))
+    return grads
+
+
+def zero_grads(grads: GaussianTensors, active=None, stream=None):
+    a0, a1 = (0, grads.n) if active is None else (int(active[0]), int(active[1]))
+    check(lib().clsp_zero_grads(ctypes.byref(grads.as_params()), _ffi.Range(a0, a1), _stream(stream)))
+
+
+# Published 3D Gaussian Splatting default learning rates (position scaled by the scene
+# extent, 1.0 here), in the C-ABI group order.
+DEFAULT_LR = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3, 2.5e-3 / 20.0)
+
+
+def masked_adam_step(params: GaussianTensors, grads, exp_avg, exp_avg_sq, active, step, lr=DEFAULT_LR, beta1=0.9,
+                     beta2=0.999, eps=1e-15, row_mask=None, stream=None):
+    a0, a1 = (0, params.n) if active is None else (int(active[0]), int(active[1]))
+    hp = _ffi.AdamHParams()
+    hp.lr = (ctypes.c_float * 6)(*[float(x) for x in lr])
+    hp.beta1, hp.beta2, hp.eps, hp.step = float(beta1), float(beta2), float(eps), int(step)
+    if row_mask is not None and (row_mask.dtype != torch.uint8 or row_mask.numel() != params.n):
+        raise ValueError("row_mask must be uint8 [N]")
+    check(lib().clsp_masked_adam_step(ctypes.byref(params.as_params()), ctypes.byref(grads.as_params()),
+                                      ctypes.byref(exp_avg.as_params()), ctypes.byref(exp_avg_sq.as_params()),
+                                      _ffi.Range(a0, a1), _ptr(row_mask), ctypes.byref(hp), _stream(stream)))

@@ -1,0 +1,626 @@
+// Tile render mask and per-tile depth order (Supp. "Local Optimization Kernel", item 1).
+//
+// Pipeline for V views of n Gaussians (entry e = v*n + i):
+//   1. mask    : tiles covered by the rectangles of the changed Gaussians (LDS bitmap per
+//                block, OR-ed into the global bitmap), or all tiles in full mode;
+//   2. count   : pairs each entry emits = masked tiles of its rectangle;
+//   3. compact : entries with at least one pair, keyed by their float32 depth bits;
+//   4. sort    : stable LSD radix sort of those keys (equal depths keep entry order);
+//   5. emit    : in depth order, each entry writes (global tile, entry) for its masked
+//                tiles at its prefix-sum offset;
+//   6. sort    : stable LSD radix sort of the pairs by global tile only — the depth
+//                order within a tile comes from step 4, so only ceil(log2(V*T)) key bits
+//                are sorted instead of tile + 32 depth bits;
+//   7. ranges  : [start, end) per tile, and the compact list of tiles to render.
+// Every kernel reads its element count from device memory, so nothing is read back.
+#include "internal.hpp"
+
+namespace clsp {
+namespace {
+
+constexpr int NT = 256;                     // threads per block
+constexpr int RS_ITEMS = 8;                 // keys per thread per chunk
+constexpr int RS_CHUNK = NT * RS_ITEMS;     // 2048 keys staged in LDS per chunk
+constexpr int RS_WAVE_SPAN = 64 * RS_ITEMS; // consecutive keys one wave ranks per chunk
+constexpr int MAX_SORT_BLOCKS = 2048;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_CHUNK = NT * SCAN_ITEMS;
+constexpr int MAX_SCAN_BLOCKS = 1024;
+
+// Counter slots (see clsp_bins).
+constexpr int C_PAIRS = 0, C_OVERFLOW = 1, C_TILES = 2, C_WRITTEN = 3, C_ENTRIES = 4, C_STICKY = 5;
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan across a 256-thread block; s4 is 4 words of LDS.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s4, uint32_t& total) {
+  const uint32_t inc = wave_incl_scan(x);
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 63) s4[w] = inc;
+  __syncthreads();
+  uint32_t off = 0;
+  for (int k = 0; k < w; ++k) off += s4[k];
+  total = s4[0] + s4[1] + s4[2] + s4[3];
+  __syncthreads();
+  return off + inc - x;
+}
+
+__device__ __forceinline__ uint32_t load_count(const uint32_t* p, uint32_t fallback) { return p ? *p : fallback; }
+
+// Contiguous element span of block b out of G for n elements (multiples of `quant`).
+__device__ __forceinline__ void block_span(uint32_t n, int G, int b, uint32_t quant, uint32_t& beg, uint32_t& end) {
+  uint64_t per = ((uint64_t)n + G - 1) / G;
+  per = (per + quant - 1) / quant * quant;
+  uint64_t bg = (uint64_t)b * per;
+  if (bg > n) bg = n;
+  uint64_t en = bg + per;
+  if (en > n) en = n;
+  beg = (uint32_t)bg;
+  end = (uint32_t)en;
+}
+
+// ------------------------------------------------------------------ fills
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t value, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < count; i += (int64_t)gridDim.x * NT) p[i] = value;
+}
+
+// Full mode: every valid tile bit of every view.
+__global__ void mask_all_kernel(uint32_t* mask, int views, int T, int wpv) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= (int64_t)views * wpv) return;
+  const int w = (int)(i % wpv);
+  const int lo = w * 32;
+  uint32_t bits = 0;
+  if (lo + 32 <= T) bits = 0xffffffffu;
+  else if (lo < T) bits = (1u << (T - lo)) - 1u;
+  mask[i] = bits;
+}
+
+// ------------------------------------------------------------------ 1. render mask
+__global__ void __launch_bounds__(NT) mask_kernel(const uint2* __restrict__ rect, const uint32_t* __restrict__ flags,
+                                                  int64_t n, int64_t a0, int64_t a1, int TX, int wpv,
+                                                  uint32_t* __restrict__ mask) {
+  extern __shared__ uint32_t smask[];
+  const int v = blockIdx.y;
+  for (int w = threadIdx.x; w < wpv; w += NT) smask[w] = 0;
+  __syncthreads();
+  const int64_t i = a0 + (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i < a1) {
+    const int64_t e = (int64_t)v * n + i;
+    if (flags[e] & CLSP_FLAG_VISIBLE) {
+      const uint2 r = rect[e];
+      const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
+      for (uint32_t ty = y0; ty < y1; ++ty)
+        for (uint32_t tx = x0; tx < x1; ++tx) {
+          const uint32_t t = ty * TX + tx;
+          atomicOr(&smask[t >> 5], 1u << (t & 31));
+        }
+    }
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < wpv; w += NT)
+    if (smask[w]) atomicOr(&mask[(int64_t)v * wpv + w], smask[w]);
+}
+
+// Number of set bits of `m` in [lo, hi).
+__device__ __forceinline__ uint32_t count_bits(const uint32_t* m, uint32_t lo, uint32_t hi) {
+  uint32_t c = 0;
+  while (lo < hi) {
+    const uint32_t w = lo >> 5, b = lo & 31;
+    const uint32_t take = min(32u - b, hi - lo);
+    const uint32_t sel = (take == 32 ? 0xffffffffu : ((1u << take) - 1u)) << b;
+    c += __popc(m[w] & sel);
+    lo += take;
+  }
+  return c;
+}
+
+// ------------------------------------------------------------------ 2. counts
+__global__ void __launch_bounds__(NT) count_kernel(const uint2* __restrict__ rect, const uint32_t* __restrict__ flags,
+                                                   const uint32_t* __restrict__ mask, int64_t n, int TX, int wpv,
+                                                   int use_mask, uint32_t* __restrict__ cnt, uint32_t* __restrict__ has) {
+  extern __shared__ uint32_t smask[];
+  const int v = blockIdx.y;
+  if (use_mask) {
+    for (int w = threadIdx.x; w < wpv; w += NT) smask[w] = mask[(int64_t)v * wpv + w];
+    __syncthreads();
+  }
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const int64_t e = (int64_t)v * n + i;
+  uint32_t c = 0;
+  if (flags[e] & CLSP_FLAG_VISIBLE) {
+    const uint2 r = rect[e];
+    const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
+    if (x1 > x0 && y1 > y0) {
+      if (!use_mask) {
+        c = (x1 - x0) * (y1 - y0);
+      } else {
+        for (uint32_t ty = y0; ty < y1; ++ty) c += count_bits(smask, ty * TX + x0, ty * TX + x1);
+      }
+    }
+  }
+  cnt[e] = c;
+  has[e] = c > 0 ? 1u : 0u;
+}
+
+// ------------------------------------------------------------------ generic exclusive scan
+__global__ void __launch_bounds__(NT) scan_reduce_kernel(const uint32_t* __restrict__ in, const uint32_t* n_ptr,
+                                                         uint32_t n_host, uint32_t* __restrict__ blk, int G) {
+  __shared__ uint32_t s4[4];
+  const uint32_t n = load_count(n_ptr, n_host);
+  uint32_t beg, end;
+  block_span(n, G, blockIdx.x, SCAN_CHUNK, beg, end);
+  uint32_t acc = 0;
+  for (uint32_t e = beg + threadIdx.x; e < end; e += NT) acc += in[e];
+  uint32_t tot;
+  block_excl_scan(acc, s4, tot);
+  if (threadIdx.x == 0) blk[blockIdx.x] = tot;
+}
+
+// One block: exclusive scan of the G block sums in place; total -> *total_out.
+__global__ void __launch_bounds__(NT) scan_blocks_kernel(uint32_t* __restrict__ blk, int G, uint32_t* total_out) {
+  __shared__ uint32_t s4[4];
+  constexpr int PER = MAX_SCAN_BLOCKS / NT;
+  uint32_t v[PER];
+  uint32_t sum = 0;
+  for (int k = 0; k < PER; ++k) {
+    const int idx = threadIdx.x * PER + k;
+    v[k] = idx < G ? blk[idx] : 0u;
+    sum += v[k];
+  }
+  uint32_t tot;
+  uint32_t off = block_excl_scan(sum, s4, tot);
+  for (int k = 0; k < PER; ++k) {
+    const int idx = threadIdx.x * PER + k;
+    if (idx < G) blk[idx] = off;
+    off += v[k];
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = tot;
+}
+
+__global__ void __launch_bounds__(NT) scan_apply_kernel(const uint32_t* __restrict__ in, const uint32_t* n_ptr,
+                                                        uint32_t n_host, const uint32_t* __restrict__ blk, int G,
+                                                        uint32_t* __restrict__ out) {
+  __shared__ uint32_t s4[4];
+  const uint32_t n = load_count(n_ptr, n_host);
+  uint32_t beg, end;
+  block_span(n, G, blockIdx.x, SCAN_CHUNK, beg, end);
+  uint32_t base = blk[blockIdx.x];
+  for (uint32_t c = beg; c < end; c += SCAN_CHUNK) {
+    uint32_t v[SCAN_ITEMS];
+    uint32_t sum = 0;
+    const uint32_t t0 = c + threadIdx.x * SCAN_ITEMS;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      v[k] = (t0 + k < end) ? in[t0 + k] : 0u;
+      sum += v[k];
+    }
+    uint32_t tot;
+    uint32_t off = base + block_excl_scan(sum, s4, tot);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      if (t0 + k < end) out[t0 + k] = off;
+      off += v[k];
+    }
+    base += tot;
+  }
+}
+
+// ------------------------------------------------------------------ 3. compaction
+__global__ void __launch_bounds__(NT) compact_kernel(const uint32_t* __restrict__ has,
+                                                     const uint32_t* __restrict__ pos,
+                                                     const float* __restrict__ depth, int64_t count,
+                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= count || !has[e]) return;
+  const uint32_t p = pos[e];
+  keys[p] = __float_as_uint(depth[e]);  // depth > 0.2: the bit pattern orders like the value
+  vals[p] = (uint32_t)e;
+}
+
+// ------------------------------------------------------------------ radix sort
+// Digit histogram of each block's span: hist[d * G + b].
+__global__ void __launch_bounds__(NT) rs_upsweep_kernel(const uint32_t* __restrict__ keys, const uint32_t* n_ptr,
+                                                        int shift, int bits, uint32_t* __restrict__ hist, int G) {
+  __shared__ uint32_t h[4][256];
+  const uint32_t n = *n_ptr;
+  const int radix = 1 << bits;
+  const uint32_t msk = (uint32_t)radix - 1u;
+  for (int d = threadIdx.x; d < 4 * 256; d += NT) (&h[0][0])[d] = 0;
+  __syncthreads();
+  uint32_t beg, end;
+  block_span(n, G, blockIdx.x, RS_CHUNK, beg, end);
+  const int w = threadIdx.x >> 6;
+  for (uint32_t e = beg + threadIdx.x; e < end; e += NT) atomicAdd(&h[w][(keys[e] >> shift) & msk], 1u);
+  __syncthreads();
+  for (int d = threadIdx.x; d < radix; d += NT) hist[(int64_t)d * G + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+}
+
+// Block d: exclusive scan over blocks of digit d's counts; digit total -> tot[d].
+__global__ void __launch_bounds__(NT) rs_scan_kernel(uint32_t* __restrict__ hist, int G, uint32_t* __restrict__ tot) {
+  __shared__ uint32_t s4[4];
+  constexpr int PER = MAX_SORT_BLOCKS / NT;
+  uint32_t* row = hist + (int64_t)blockIdx.x * G;
+  uint32_t v[PER];
+  uint32_t sum = 0;
+  for (int k = 0; k < PER; ++k) {
+    const int idx = threadIdx.x * PER + k;
+    v[k] = idx < G ? row[idx] : 0u;
+    sum += v[k];
+  }
+  uint32_t total;
+  uint32_t off = block_excl_scan(sum, s4, total);
+  for (int k = 0; k < PER; ++k) {
+    const int idx = threadIdx.x * PER + k;
+    if (idx < G) row[idx] = off;
+    off += v[k];
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = total;
+}
+
+// Stable scatter of each block's span.  Each wave ranks 512 consecutive keys with
+// ballot-based digit matching; the block then stages the chunk in LDS ordered by digit
+// and writes every digit's run contiguously.
+__global__ void __launch_bounds__(NT) rs_downsweep_kernel(const uint32_t* __restrict__ kin,
+                                                          const uint32_t* __restrict__ vin,
+                                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                          const uint32_t* n_ptr, int shift, int bits,
+                                                          const uint32_t* __restrict__ hist,
+                                                          const uint32_t* __restrict__ tot, int G) {
+  __shared__ uint32_t s_key[RS_CHUNK];
+  __shared__ uint32_t s_val[RS_CHUNK];
+  __shared__ uint32_t s_wcnt[4][256];
+  __shared__ uint32_t s_base[256];
+  __shared__ uint32_t s_choff[256];
+  __shared__ uint32_t s_tot[256];
+  __shared__ uint32_t s4[4];
+
+  const uint32_t n = *n_ptr;
+  uint32_t beg, end;
+  block_span(n, G, blockIdx.x, RS_CHUNK, beg, end);
+  if (beg >= end) return;
+  const int radix = 1 << bits;
+  const uint32_t msk = (uint32_t)radix - 1u;
+  const int tid = threadIdx.x, w = tid >> 6;
+  const uint32_t lane = lane_id();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+  // global base of each digit for this block
+  {
+    const uint32_t t = tid < radix ? tot[tid] : 0u;
+    uint32_t all;
+    const uint32_t ex = block_excl_scan(t, s4, all);
+    if (tid < radix) s_base[tid] = ex + hist[(int64_t)tid * G + blockIdx.x];
+  }
+
+  for (uint32_t c = beg; c < end; c += RS_CHUNK) {
+    const uint32_t clen = min((uint32_t)RS_CHUNK, end - c);
+    for (int d = tid; d < 4 * 256; d += NT) (&s_wcnt[0][0])[d] = 0;
+    __syncthreads();
+
+    uint32_t key[RS_ITEMS], val[RS_ITEMS], rnk[RS_ITEMS];
+    const uint32_t wbase = c + w * RS_WAVE_SPAN;
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+      const uint32_t e = wbase + it * 64 + lane;
+      const bool valid = e < end;
+      key[it] = valid ? kin[e] : 0u;
+      val[it] = valid ? vin[e] : 0u;
+      const uint32_t d = (key[it] >> shift) & msk;
+      uint64_t peers = __ballot(valid);
+      for (int b = 0; b < bits; ++b) {
+        const uint64_t bal = __ballot((d >> b) & 1u);
+        peers &= ((d >> b) & 1u) ? bal : ~bal;
+      }
+      const uint32_t base = valid ? s_wcnt[w][d] : 0u;
+      rnk[it] = base + (uint32_t)__popcll(peers & lt_mask);
+      // the highest lane of each digit group advances the wave's running count
+      if (valid && (peers >> lane) == 1ull) s_wcnt[w][d] = base + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // per digit: offsets of the four waves and the chunk total
+    {
+      uint32_t t = 0;
+      if (tid < radix) {
+        const uint32_t c0 = s_wcnt[0][tid], c1 = s_wcnt[1][tid], c2 = s_wcnt[2][tid], c3 = s_wcnt[3][tid];
+        s_wcnt[0][tid] = 0;
+        s_wcnt[1][tid] = c0;
+        s_wcnt[2][tid] = c0 + c1;
+        s_wcnt[3][tid] = c0 + c1 + c2;
+        t = c0 + c1 + c2 + c3;
+        s_tot[tid] = t;
+      }
+      uint32_t all;
+      const uint32_t ex = block_excl_scan(t, s4, all);
+      if (tid < radix) s_choff[tid] = ex;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+      const uint32_t e = wbase + it * 64 + lane;
+      if (e < end) {
+        const uint32_t d = (key[it] >> shift) & msk;
+        const uint32_t p = s_choff[d] + s_wcnt[w][d] + rnk[it];
+        s_key[p] = key[it];
+        s_val[p] = val[it];
+      }
+    }
+    __syncthreads();
+    for (uint32_t p = tid; p < clen; p += NT) {
+      const uint32_t k = s_key[p];
+      const uint32_t d = (k >> shift) & msk;
+      const uint32_t o = s_base[d] + (p - s_choff[d]);
+      kout[o] = k;
+      vout[o] = s_val[p];
+    }
+    __syncthreads();
+    if (tid < radix) s_base[tid] += s_tot[tid];
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ 5. emission
+__global__ void __launch_bounds__(NT) gather_counts_kernel(const uint32_t* __restrict__ order,
+                                                           const uint32_t* __restrict__ cnt, const uint32_t* n_ptr,
+                                                           uint32_t* __restrict__ out) {
+  const uint32_t m = *n_ptr;
+  for (uint32_t j = blockIdx.x * NT + threadIdx.x; j < m; j += gridDim.x * NT) out[j] = cnt[order[j]];
+}
+
+__global__ void check_capacity_kernel(uint32_t* counters, uint64_t capacity) {
+  const uint32_t p = counters[C_PAIRS];
+  const bool over = (uint64_t)p > capacity;
+  counters[C_OVERFLOW] = over ? 1u : 0u;
+  counters[C_WRITTEN] = over ? 0u : p;
+  if (over) counters[C_STICKY] = 1u;
+}
+
+__global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ order, const uint32_t* __restrict__ offs,
+                                                  const uint2* __restrict__ rect, const uint32_t* __restrict__ mask,
+                                                  const uint32_t* __restrict__ counters, int64_t n, int TX, int T,
+                                                  int wpv, int use_mask, uint32_t* __restrict__ pk,
+                                                  uint32_t* __restrict__ pv) {
+  if (counters[C_OVERFLOW]) return;
+  const uint32_t m = counters[C_ENTRIES];
+  for (uint32_t j = blockIdx.x * NT + threadIdx.x; j < m; j += gridDim.x * NT) {
+    const uint32_t e = order[j];
+    const uint32_t v = (uint32_t)(e / n);
+    const uint2 r = rect[e];
+    const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
+    uint32_t o = offs[j];
+    const uint32_t* vm = mask + (int64_t)v * wpv;
+    const uint32_t gbase = v * (uint32_t)T;
+    for (uint32_t ty = y0; ty < y1; ++ty)
+      for (uint32_t tx = x0; tx < x1; ++tx) {
+        const uint32_t t = ty * TX + tx;
+        if (use_mask && !((vm[t >> 5] >> (t & 31)) & 1u)) continue;
+        pk[o] = gbase + t;
+        pv[o] = e;
+        ++o;
+      }
+  }
+}
+
+// ------------------------------------------------------------------ 7. ranges, tile list
+__global__ void __launch_bounds__(NT) ranges_kernel(const uint32_t* __restrict__ keys,
+                                                    const uint32_t* __restrict__ counters, uint2* __restrict__ ranges) {
+  const uint32_t P = counters[C_WRITTEN];
+  for (uint32_t p = blockIdx.x * NT + threadIdx.x; p < P; p += gridDim.x * NT) {
+    const uint32_t k = keys[p];
+    if (p == 0 || keys[p - 1] != k) ranges[k].x = p;
+    if (p + 1 == P || keys[p + 1] != k) ranges[k].y = p + 1;
+  }
+}
+
+__global__ void __launch_bounds__(NT) tile_flags_kernel(const uint32_t* __restrict__ mask, int views, int T, int wpv,
+                                                        const uint32_t* __restrict__ counters,
+                                                        uint32_t* __restrict__ tflag) {
+  const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (g >= (int64_t)views * T) return;
+  const int v = (int)(g / T), t = (int)(g % T);
+  // no tile is rendered when the pair lists overflowed
+  tflag[g] = (!counters[C_OVERFLOW] && ((mask[(int64_t)v * wpv + (t >> 5)] >> (t & 31)) & 1u)) ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(NT) tile_list_kernel(const uint32_t* __restrict__ tflag,
+                                                       const uint32_t* __restrict__ tpos, int64_t count,
+                                                       uint32_t* __restrict__ list) {
+  const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (g < count && tflag[g]) list[tpos[g]] = (uint32_t)g;
+}
+
+// ------------------------------------------------------------------ host helpers
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int sort_blocks(int64_t nmax) {
+  int64_t g = (nmax + RS_CHUNK - 1) / RS_CHUNK;
+  if (g < 1) g = 1;
+  if (g > MAX_SORT_BLOCKS) g = MAX_SORT_BLOCKS;
+  return (int)g;
+}
+
+int scan_blocks(int64_t nmax) {
+  int64_t g = (nmax + SCAN_CHUNK - 1) / SCAN_CHUNK;
+  if (g < 1) g = 1;
+  if (g > MAX_SCAN_BLOCKS) g = MAX_SCAN_BLOCKS;
+  return (int)g;
+}
+
+int grid_for(int64_t count, int cap = 8192) {
+  int64_t g = (count + NT - 1) / NT;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+// Exclusive scan of in[0, n) (n from n_ptr if given) into out; total -> *total_out.
+hipError_t scan(const uint32_t* in, uint32_t* out, const uint32_t* n_ptr, uint32_t n_host, int64_t nmax,
+                uint32_t* blk, uint32_t* total_out, hipStream_t s) {
+  const int G = scan_blocks(nmax);
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(G), dim3(NT), 0, s, in, n_ptr, n_host, blk, G);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(NT), 0, s, blk, G, total_out);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3(G), dim3(NT), 0, s, in, n_ptr, n_host, blk, G, out);
+  return hipGetLastError();
+}
+
+// Stable LSD radix sort of (keys, vals) on bits [0, total_bits); n from n_ptr.  Passes
+// alternate between (k0, v0) and (k1, v1); returns 0 when the result is in (k0, v0).
+int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_ptr, int64_t nmax,
+               int total_bits, uint32_t* hist, uint32_t* tot, hipStream_t s) {
+  if (total_bits <= 0) return 0;
+  const int passes = (total_bits + 7) / 8;
+  const int per = (total_bits + passes - 1) / passes;
+  const int G = sort_blocks(nmax);
+  int shift = 0, cur = 0;
+  for (int p = 0; p < passes; ++p) {
+    const int bits = min(per, total_bits - shift);
+    uint32_t* ki = cur ? k1 : k0;
+    uint32_t* vi = cur ? v1 : v0;
+    uint32_t* ko = cur ? k0 : k1;
+    uint32_t* vo = cur ? v0 : v1;
+    hipLaunchKernelGGL(rs_upsweep_kernel, dim3(G), dim3(NT), 0, s, ki, n_ptr, shift, bits, hist, G);
+    hipLaunchKernelGGL(rs_scan_kernel, dim3(1 << bits), dim3(NT), 0, s, hist, G, tot);
+    hipLaunchKernelGGL(rs_downsweep_kernel, dim3(G), dim3(NT), 0, s, ki, vi, ko, vo, n_ptr, shift, bits, hist, tot,
+                       G);
+    shift += bits;
+    cur ^= 1;
+  }
+  return cur;
+}
+
+int passes_for(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(count, 4096)), dim3(NT), 0, s, p, value, count);
+  return hipGetLastError();
+}
+
+BinPlan make_bin_plan(int64_t n, int views, int W, int H, int64_t capacity) {
+  BinPlan p{};
+  p.n = n;
+  p.views = views;
+  p.TX = (W + TILE - 1) / TILE;
+  p.TY = (H + TILE - 1) / TILE;
+  p.T = p.TX * p.TY;
+  p.capacity = capacity;
+  const int64_t gt = (int64_t)views * p.T;
+  int bits = 0;
+  while (((int64_t)1 << bits) < gt) ++bits;
+  p.tile_bits = bits;
+  p.entries = (int64_t)views * n;
+  const int64_t E = p.entries > 0 ? p.entries : 1;
+  p.scan_blocks = MAX_SCAN_BLOCKS;
+  p.sort_blocks_gauss = sort_blocks(E);
+  p.sort_blocks_pairs = sort_blocks(capacity);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  p.off_cnt = take(E * 4);
+  p.off_flag = take(E * 4);
+  p.off_keyA = take(E * 4);
+  p.off_valA = take(E * 4);
+  p.off_keyB = take(E * 4);
+  p.off_valB = take(E * 4);
+  p.off_scanBlk = take((MAX_SCAN_BLOCKS + 1) * 4);
+  p.off_hist = take((size_t)256 * MAX_SORT_BLOCKS * 4);
+  p.off_digit = take(256 * 4);
+  const bool need_pair_buf = passes_for(bits) > 0;
+  p.off_pairK = take(need_pair_buf ? (size_t)(capacity > 0 ? capacity : 1) * 4 : 4);
+  p.off_pairV = take(need_pair_buf ? (size_t)(capacity > 0 ? capacity : 1) * 4 : 4);
+  p.off_tflag = take((gt + 1) * 4 * 2);
+  p.total = off;
+  return p;
+}
+
+hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int64_t a0, int64_t a1, int use_mask,
+                               const clsp_bins& bins, char* ws, hipStream_t s) {
+  const int V = p.views;
+  const int64_t n = p.n, E = p.entries, gt = (int64_t)V * p.T;
+  const int wpv = (p.T + 31) / 32;
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(ws + p.off_cnt);
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(ws + p.off_flag);
+  uint32_t* keyA = reinterpret_cast<uint32_t*>(ws + p.off_keyA);
+  uint32_t* valA = reinterpret_cast<uint32_t*>(ws + p.off_valA);
+  uint32_t* keyB = reinterpret_cast<uint32_t*>(ws + p.off_keyB);
+  uint32_t* valB = reinterpret_cast<uint32_t*>(ws + p.off_valB);
+  uint32_t* blk = reinterpret_cast<uint32_t*>(ws + p.off_scanBlk);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(ws + p.off_hist);
+  uint32_t* dtot = reinterpret_cast<uint32_t*>(ws + p.off_digit);
+  uint32_t* pairK = reinterpret_cast<uint32_t*>(ws + p.off_pairK);
+  uint32_t* pairV = reinterpret_cast<uint32_t*>(ws + p.off_pairV);
+  uint32_t* tflag = reinterpret_cast<uint32_t*>(ws + p.off_tflag);
+  uint32_t* tpos = tflag + (gt + 1);
+  const uint2* rect = reinterpret_cast<const uint2*>(proj.rect);
+  uint32_t* counters = bins.counters;
+  hipError_t err;
+
+  // clear outputs (counters[C_STICKY] is left alone: it remembers any overflow)
+  if ((err = launch_fill_u32(counters, 0u, C_STICKY, s)) != hipSuccess) return err;
+  if ((err = launch_fill_u32(bins.ranges, 0u, gt * 2, s)) != hipSuccess) return err;
+  // 1. mask
+  if (use_mask) {
+    if ((err = launch_fill_u32(bins.tile_mask, 0u, (int64_t)V * wpv, s)) != hipSuccess) return err;
+    if (a1 > a0) {
+      hipLaunchKernelGGL(mask_kernel, dim3(ceil_div(a1 - a0, NT), V), dim3(NT), wpv * 4, s, rect, proj.flags, n, a0,
+                         a1, p.TX, wpv, bins.tile_mask);
+    }
+  } else {
+    hipLaunchKernelGGL(mask_all_kernel, dim3(grid_for((int64_t)V * wpv, 1 << 20)), dim3(NT), 0, s, bins.tile_mask, V,
+                       p.T, wpv);
+  }
+  if (E > 0) {
+    // 2. counts
+    hipLaunchKernelGGL(count_kernel, dim3(ceil_div(n, NT), V), dim3(NT), use_mask ? wpv * 4 : 0, s, rect, proj.flags,
+                       bins.tile_mask, n, p.TX, wpv, use_mask, cnt, tmp);
+    // 3. compaction of entries with pairs, keyed by depth
+    uint32_t* pos = keyB;  // scratch until the sort needs it
+    if ((err = scan(tmp, pos, nullptr, (uint32_t)E, E, blk, counters + C_ENTRIES, s)) != hipSuccess) return err;
+    hipLaunchKernelGGL(compact_kernel, dim3(ceil_div(E, NT)), dim3(NT), 0, s, tmp, pos, proj.depth, E, keyA, valA);
+    // 4. depth order (32 key bits, 4 passes -> result back in A)
+    const int where = radix_sort(keyA, valA, keyB, valB, counters + C_ENTRIES, E, 32, hist, dtot, s);
+    uint32_t* order = where ? valB : valA;
+    uint32_t* spare = where ? valA : valB;
+    // 5. offsets of each entry's pairs in depth order, capacity check, emission
+    hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(E)), dim3(NT), 0, s, order, cnt, counters + C_ENTRIES, tmp);
+    if ((err = scan(tmp, spare, counters + C_ENTRIES, 0u, E, blk, counters + C_PAIRS, s)) != hipSuccess) return err;
+    hipLaunchKernelGGL(check_capacity_kernel, dim3(1), dim3(1), 0, s, counters, (uint64_t)p.capacity);
+    const int tpasses = passes_for(p.tile_bits);
+    uint32_t* ek = (tpasses % 2 == 0) ? bins.keys : pairK;
+    uint32_t* ev = (tpasses % 2 == 0) ? bins.values : pairV;
+    hipLaunchKernelGGL(emit_kernel, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, spare, rect, bins.tile_mask,
+                       counters, n, p.TX, p.T, wpv, use_mask, ek, ev);
+    // 6. stable sort by global tile
+    if (tpasses > 0) {
+      uint32_t *k0 = ek, *v0 = ev, *k1 = (ek == bins.keys) ? pairK : bins.keys, *v1 = (ev == bins.values) ? pairV : bins.values;
+      radix_sort(k0, v0, k1, v1, counters + C_WRITTEN, p.capacity, p.tile_bits, hist, dtot, s);
+    }
+    // 7. ranges
+    hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(p.capacity, 1 << 14)), dim3(NT), 0, s, bins.keys, counters,
+                       reinterpret_cast<uint2*>(bins.ranges));
+  }
+  // tile list (masked tiles; all tiles in full mode)
+  hipLaunchKernelGGL(tile_flags_kernel, dim3(ceil_div(gt, NT)), dim3(NT), 0, s, bins.tile_mask, V, p.T, wpv, counters,
+                     tflag);
+  if ((err = scan(tflag, tpos, nullptr, (uint32_t)gt, gt, blk, counters + C_TILES, s)) != hipSuccess) return err;
+  hipLaunchKernelGGL(tile_list_kernel, dim3(ceil_div(gt, NT)), dim3(NT), 0, s, tflag, tpos, gt, bins.tile_list);
+  return hipGetLastError();
+}
+
+}  // namespace clsp

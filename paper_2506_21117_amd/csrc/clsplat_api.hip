@@ -1,0 +1,281 @@
+// extern "C" entry points of libclsplat: argument validation on the host, derived
+// camera constants, workspace carve-up, and launches on the caller's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+clsp_status fail(clsp_status code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+clsp_status hip_status(hipError_t e, const char* where) {
+  if (e == hipSuccess) return CLSP_OK;
+  return fail(CLSP_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+constexpr int64_t MAX_ENTRIES = 0xffffffffLL;
+constexpr int MAX_TILES_PER_VIEW = 65536;
+
+clsp_status check_cams(const clsp_camera* cams, int32_t n_views) {
+  if (!cams) return fail(CLSP_ERR_INVALID_ARG, "cams is NULL");
+  if (n_views < 1 || n_views > CLSP_MAX_VIEWS) return fail(CLSP_ERR_INVALID_ARG, "n_views=%d not in 1..%d", n_views, CLSP_MAX_VIEWS);
+  const int W = cams[0].width, H = cams[0].height;
+  if (W < 1 || H < 1 || W > CLSP_MAX_SIDE || H > CLSP_MAX_SIDE)
+    return fail(CLSP_ERR_INVALID_ARG, "image size %dx%d not in 1..%d", W, H, CLSP_MAX_SIDE);
+  const int TX = (W + CLSP_TILE - 1) / CLSP_TILE, TY = (H + CLSP_TILE - 1) / CLSP_TILE;
+  if (TX * TY > MAX_TILES_PER_VIEW) return fail(CLSP_ERR_INVALID_ARG, "more than %d tiles per view", MAX_TILES_PER_VIEW);
+  for (int v = 0; v < n_views; ++v) {
+    const clsp_camera& c = cams[v];
+    if (c.width != W || c.height != H) return fail(CLSP_ERR_INVALID_ARG, "view %d size differs from view 0", v);
+    if (!(c.fx > 0.f) || !(c.fy > 0.f) || !isfinite(c.fx) || !isfinite(c.fy) || !isfinite(c.cx) || !isfinite(c.cy))
+      return fail(CLSP_ERR_INVALID_ARG, "view %d has invalid intrinsics", v);
+    for (int k = 0; k < 9; ++k)
+      if (!isfinite(c.R[k])) return fail(CLSP_ERR_INVALID_ARG, "view %d rotation not finite", v);
+    for (int k = 0; k < 3; ++k)
+      if (!isfinite(c.t[k])) return fail(CLSP_ERR_INVALID_ARG, "view %d translation not finite", v);
+  }
+  return CLSP_OK;
+}
+
+clsp::DevCam dev_cam(const clsp_camera& c) {
+  clsp::DevCam d;
+  for (int k = 0; k < 9; ++k) d.R[k] = c.R[k];
+  for (int k = 0; k < 3; ++k) d.t[k] = c.t[k];
+  d.fx = c.fx;
+  d.fy = c.fy;
+  d.cx = c.cx;
+  d.cy = c.cy;
+  d.W = c.width;
+  d.H = c.height;
+  d.TX = (c.width + CLSP_TILE - 1) / CLSP_TILE;
+  d.TY = (c.height + CLSP_TILE - 1) / CLSP_TILE;
+  d.limx = 1.3f * (0.5f * (float)c.width) / c.fx;
+  d.limy = 1.3f * (0.5f * (float)c.height) / c.fy;
+  for (int k = 0; k < 3; ++k) d.campos[k] = -(c.R[k] * c.t[0] + c.R[3 + k] * c.t[1] + c.R[6 + k] * c.t[2]);
+  return d;
+}
+
+clsp_status check_gaussians(const clsp_gaussians* g) {
+  if (!g) return fail(CLSP_ERR_INVALID_ARG, "gaussians is NULL");
+  if (g->n < 0) return fail(CLSP_ERR_INVALID_ARG, "n=%lld < 0", (long long)g->n);
+  if (g->sh_degree < 0 || g->sh_degree > 3) return fail(CLSP_ERR_INVALID_ARG, "sh_degree=%d not in 0..3", g->sh_degree);
+  if (g->n > 0) {
+    if (!g->means || !g->log_scales || !g->quats || !g->opacity_logit || !g->sh)
+      return fail(CLSP_ERR_INVALID_ARG, "a Gaussian parameter pointer is NULL");
+    if (!g->gather && g->n_rows < g->n) return fail(CLSP_ERR_INVALID_ARG, "n_rows < n without gather");
+    if (g->gather && g->n_rows < 1) return fail(CLSP_ERR_INVALID_ARG, "n_rows < 1 with gather");
+  }
+  return CLSP_OK;
+}
+
+clsp::RawParams raw_params(const clsp_gaussians* g) {
+  clsp::RawParams r;
+  r.means = g->means;
+  r.log_scales = g->log_scales;
+  r.quats = g->quats;
+  r.opac = g->opacity_logit;
+  r.sh = g->sh;
+  r.gather = g->gather;
+  r.n = g->n;
+  r.n_rows = g->n_rows;
+  r.sh_degree = g->sh_degree;
+  return r;
+}
+
+clsp_status check_params(const clsp_params* p, const char* what) {
+  if (!p) return fail(CLSP_ERR_INVALID_ARG, "%s is NULL", what);
+  if (p->n < 0) return fail(CLSP_ERR_INVALID_ARG, "%s: n < 0", what);
+  if (p->sh_degree < 0 || p->sh_degree > 3) return fail(CLSP_ERR_INVALID_ARG, "%s: sh_degree not in 0..3", what);
+  if (p->n > 0 && (!p->means || !p->log_scales || !p->quats || !p->opacity_logit || !p->sh))
+    return fail(CLSP_ERR_INVALID_ARG, "%s: a pointer is NULL", what);
+  return CLSP_OK;
+}
+
+clsp::MutParams mut_params(const clsp_params* p) {
+  clsp::MutParams m;
+  m.means = p->means;
+  m.log_scales = p->log_scales;
+  m.quats = p->quats;
+  m.opac = p->opacity_logit;
+  m.sh = p->sh;
+  m.n = p->n;
+  m.sh_degree = p->sh_degree;
+  return m;
+}
+
+clsp_status check_range(clsp_range r, int64_t n) {
+  if (r.begin < 0 || r.end < r.begin || r.end > n)
+    return fail(CLSP_ERR_INVALID_ARG, "active range [%lld, %lld) not inside [0, %lld]", (long long)r.begin,
+                (long long)r.end, (long long)n);
+  return CLSP_OK;
+}
+
+clsp_status check_projected(const clsp_projected* p) {
+  if (!p || !p->splat || !p->depth || !p->rect || !p->flags) return fail(CLSP_ERR_INVALID_ARG, "projected buffers missing");
+  return CLSP_OK;
+}
+
+clsp_status check_bins(const clsp_bins* b) {
+  if (!b || !b->values || !b->keys || !b->ranges || !b->tile_mask || !b->tile_list || !b->counters)
+    return fail(CLSP_ERR_INVALID_ARG, "bins buffers missing");
+  if (b->capacity < 0 || b->capacity > MAX_ENTRIES) return fail(CLSP_ERR_INVALID_ARG, "capacity not in 0..2^32-1");
+  return CLSP_OK;
+}
+
+#define CHECK(x)                        \
+  do {                                  \
+    clsp_status _s = (x);               \
+    if (_s != CLSP_OK) return _s;       \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* clsp_version(void) { return "clsplat 0.1 gfx950"; }
+
+const char* clsp_last_error(void) { return g_err; }
+
+clsp_status clsp_project_preprocess(const clsp_gaussians* g, const clsp_camera* cams, int32_t n_views,
+                                    const clsp_projected* out, clsp_stream stream) {
+  CHECK(check_gaussians(g));
+  CHECK(check_cams(cams, n_views));
+  CHECK(check_projected(out));
+  if ((int64_t)n_views * g->n > MAX_ENTRIES) return fail(CLSP_ERR_INVALID_ARG, "n_views * n >= 2^32");
+  const clsp::RawParams rp = raw_params(g);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int v = 0; v < n_views; ++v)
+    CHECK(hip_status(clsp::launch_preprocess(rp, dev_cam(cams[v]), v, out->splat, out->depth, out->rect, out->flags, s),
+                     "project_preprocess"));
+  return CLSP_OK;
+}
+
+size_t clsp_bin_and_sort_workspace_bytes(int64_t n, int32_t n_views, int32_t width, int32_t height, int64_t capacity) {
+  if (n < 0 || n_views < 1 || width < 1 || height < 1 || capacity < 0) return 0;
+  return clsp::make_bin_plan(n, n_views, width, height, capacity).total;
+}
+
+clsp_status clsp_bin_and_sort(const clsp_projected* proj, int64_t n, const clsp_camera* cams, int32_t n_views,
+                              clsp_range active, int32_t use_mask, const clsp_bins* bins, void* ws, size_t ws_bytes,
+                              clsp_stream stream) {
+  CHECK(check_projected(proj));
+  CHECK(check_cams(cams, n_views));
+  CHECK(check_bins(bins));
+  if (n < 0) return fail(CLSP_ERR_INVALID_ARG, "n < 0");
+  if ((int64_t)n_views * n > MAX_ENTRIES) return fail(CLSP_ERR_INVALID_ARG, "n_views * n >= 2^32");
+  CHECK(check_range(active, n));
+  const clsp::BinPlan plan = clsp::make_bin_plan(n, n_views, cams[0].width, cams[0].height, bins->capacity);
+  if (!ws || ws_bytes < plan.total)
+    return fail(CLSP_ERR_INVALID_ARG, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, plan.total);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return hip_status(clsp::launch_bin_and_sort(plan, *proj, active.begin, active.end, use_mask ? 1 : 0, *bins,
+                                              static_cast<char*>(ws), s),
+                    "bin_and_sort");
+}
+
+clsp_status clsp_render_forward(const clsp_projected* proj, const clsp_bins* bins, const clsp_camera* cams,
+                                int32_t n_views, const float* bg, float* image, float* T_final, uint32_t* n_contrib,
+                                clsp_stream stream) {
+  CHECK(check_projected(proj));
+  CHECK(check_bins(bins));
+  CHECK(check_cams(cams, n_views));
+  if (!bg || !image || !T_final || !n_contrib) return fail(CLSP_ERR_INVALID_ARG, "render_forward output or bg is NULL");
+  const int W = cams[0].width, H = cams[0].height;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return hip_status(clsp::launch_render_forward(*proj, *bins, n_views, W, H, (W + CLSP_TILE - 1) / CLSP_TILE,
+                                                (H + CLSP_TILE - 1) / CLSP_TILE, bg, image, T_final, n_contrib, s),
+                    "render_forward");
+}
+
+clsp_status clsp_l1_loss_grad(const float* image, const float* target, const clsp_bins* bins, const clsp_camera* cams,
+                              int32_t n_views, float* dL_dimage, float* loss_sum, clsp_stream stream) {
+  CHECK(check_bins(bins));
+  CHECK(check_cams(cams, n_views));
+  if (!image || !target || !dL_dimage) return fail(CLSP_ERR_INVALID_ARG, "l1_loss_grad pointer is NULL");
+  const int W = cams[0].width, H = cams[0].height;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return hip_status(clsp::launch_l1_loss_grad(image, target, *bins, n_views, W, H, (W + CLSP_TILE - 1) / CLSP_TILE,
+                                              (H + CLSP_TILE - 1) / CLSP_TILE, dL_dimage, loss_sum, s),
+                    "l1_loss_grad");
+}
+
+size_t clsp_render_backward_workspace_bytes(int64_t n_active, int32_t n_views) {
+  if (n_active < 0 || n_views < 1) return 0;
+  return (size_t)n_active * n_views * clsp::G2D_STRIDE * sizeof(float);
+}
+
+clsp_status clsp_render_backward(const clsp_gaussians* g, const clsp_projected* proj, const clsp_bins* bins,
+                                 const clsp_camera* cams, int32_t n_views, const float* bg, clsp_range active,
+                                 const float* T_final, const uint32_t* n_contrib, const float* dL_dimage,
+                                 const clsp_params* grads, void* ws, size_t ws_bytes, clsp_stream stream) {
+  CHECK(check_gaussians(g));
+  if (g->gather) return fail(CLSP_ERR_INVALID_ARG, "render_backward needs un-gathered parameters");
+  CHECK(check_projected(proj));
+  CHECK(check_bins(bins));
+  CHECK(check_cams(cams, n_views));
+  CHECK(check_params(grads, "grads"));
+  CHECK(check_range(active, g->n));
+  if (grads->n != g->n || grads->sh_degree != g->sh_degree)
+    return fail(CLSP_ERR_INVALID_ARG, "grads layout differs from the parameters");
+  if (!bg || !T_final || !n_contrib || !dL_dimage) return fail(CLSP_ERR_INVALID_ARG, "render_backward input is NULL");
+  const int64_t na = active.end - active.begin;
+  const size_t need = clsp_render_backward_workspace_bytes(na, n_views);
+  if (na > 0 && (!ws || ws_bytes < need))
+    return fail(CLSP_ERR_INVALID_ARG, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+  if (na == 0) return CLSP_OK;
+  const int W = cams[0].width, H = cams[0].height;
+  const int TX = (W + CLSP_TILE - 1) / CLSP_TILE, TY = (H + CLSP_TILE - 1) / CLSP_TILE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  float* g2d = static_cast<float*>(ws);
+  CHECK(hip_status(clsp::launch_render_backward(*proj, *bins, n_views, g->n, W, H, TX, TY, bg, active.begin,
+                                                active.end, T_final, n_contrib, dL_dimage, g2d, s),
+                   "render_backward"));
+  const clsp::RawParams rp = raw_params(g);
+  const clsp::MutParams gm = mut_params(grads);
+  for (int v = 0; v < n_views; ++v)
+    CHECK(hip_status(clsp::launch_preprocess_backward(rp, dev_cam(cams[v]), v, active.begin, active.end, proj->flags,
+                                                      g2d, gm, s),
+                     "preprocess_backward"));
+  return CLSP_OK;
+}
+
+clsp_status clsp_masked_adam_step(const clsp_params* params, const clsp_params* grads, const clsp_params* exp_avg,
+                                  const clsp_params* exp_avg_sq, clsp_range active, const uint8_t* row_mask,
+                                  const clsp_adam_hparams* hp, clsp_stream stream) {
+  CHECK(check_params(params, "params"));
+  CHECK(check_params(grads, "grads"));
+  CHECK(check_params(exp_avg, "exp_avg"));
+  CHECK(check_params(exp_avg_sq, "exp_avg_sq"));
+  if (!hp) return fail(CLSP_ERR_INVALID_ARG, "hparams is NULL");
+  const int64_t n = params->n;
+  if (grads->n != n || exp_avg->n != n || exp_avg_sq->n != n || grads->sh_degree != params->sh_degree ||
+      exp_avg->sh_degree != params->sh_degree || exp_avg_sq->sh_degree != params->sh_degree)
+    return fail(CLSP_ERR_INVALID_ARG, "params, grads and moments differ in layout");
+  CHECK(check_range(active, n));
+  if (hp->step < 1) return fail(CLSP_ERR_INVALID_ARG, "step must be >= 1");
+  if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f && hp->beta2 >= 0.f && hp->beta2 < 1.f && hp->eps >= 0.f))
+    return fail(CLSP_ERR_INVALID_ARG, "invalid Adam betas or eps");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return hip_status(clsp::launch_adam(mut_params(params), mut_params(grads), mut_params(exp_avg), mut_params(exp_avg_sq),
+                                      active.begin, active.end, row_mask, *hp, s),
+                    "masked_adam_step");
+}
+
+clsp_status clsp_zero_grads(const clsp_params* grads, clsp_range active, clsp_stream stream) {
+  CHECK(check_params(grads, "grads"));
+  CHECK(check_range(active, grads->n));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return hip_status(clsp::launch_zero_rows(mut_params(grads), active.begin, active.end, s), "zero_grads");
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Internal declarations of the gfx950 kernels behind the clsplat C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "clsplat.h"
+
+namespace clsp {
+
+constexpr int TILE = CLSP_TILE;
+constexpr int TILE_PIX = TILE * TILE;  // 256 pixels = one workgroup of four wave64s
+constexpr int SPLAT_STRIDE = 12;       // floats per projected record
+constexpr int G2D_STRIDE = 12;         // floats per screen-space gradient row (9 used)
+
+// Compositing constants of the forward model.
+constexpr float ALPHA_MIN = 1.0f / 255.0f;
+constexpr float ALPHA_MAX = 0.99f;
+constexpr float T_STOP = 1e-4f;
+constexpr float NEAR_Z = 0.2f;
+constexpr float LOWPASS = 0.3f;
+constexpr float EXTENT_MARGIN = 1.0f + 1.0f / 4096.0f;
+
+// Camera as the kernels take it (by value): the C-ABI camera plus derived constants.
+struct DevCam {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float limx, limy;      // 1.3 x half-image tangent
+  float campos[3];       // camera centre in world space
+  int W, H, TX, TY;
+};
+
+struct RawParams {
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opac;
+  const float* sh;
+  const int32_t* gather;
+  int64_t n;
+  int64_t n_rows;
+  int sh_degree;
+};
+
+struct MutParams {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opac;
+  float* sh;
+  int64_t n;
+  int sh_degree;
+};
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------- launchers
+// preprocess.hip
+hipError_t launch_preprocess(const RawParams& g, const DevCam& cam, int view, float* splat, float* depth,
+                             uint32_t* rect, uint32_t* flags, hipStream_t s);
+hipError_t launch_preprocess_backward(const RawParams& g, const DevCam& cam, int view, int64_t a0, int64_t a1,
+                                      const uint32_t* flags, const float* grad2d, const MutParams& grads,
+                                      hipStream_t s);
+
+// binning.hip
+struct BinPlan {
+  int64_t n;          // Gaussians per view
+  int views;
+  int TX, TY, T;      // tiles per view
+  int64_t capacity;
+  int tile_bits;      // bits of the global tile index
+  int64_t entries;    // views * n
+  // workspace carve-up (byte offsets)
+  size_t off_cnt, off_flag, off_keyA, off_valA, off_keyB, off_valB, off_scanBlk, off_hist, off_digit,
+      off_pairK, off_pairV, off_tflag, total;
+  int scan_blocks;
+  int sort_blocks_gauss, sort_blocks_pairs;
+};
+BinPlan make_bin_plan(int64_t n, int views, int W, int H, int64_t capacity);
+hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int64_t a0, int64_t a1, int use_mask,
+                               const clsp_bins& bins, char* ws, hipStream_t s);
+
+// render.hip
+hipError_t launch_render_forward(const clsp_projected& proj, const clsp_bins& bins, int views, int W, int H,
+                                 int TX, int TY, const float bg[3], float* image, float* T_final,
+                                 uint32_t* n_contrib, hipStream_t s);
+hipError_t launch_l1_loss_grad(const float* image, const float* target, const clsp_bins& bins, int views, int W,
+                               int H, int TX, int TY, float* dL, float* loss_sum, hipStream_t s);
+hipError_t launch_render_backward(const clsp_projected& proj, const clsp_bins& bins, int views, int64_t n, int W,
+                                  int H, int TX, int TY, const float bg[3], int64_t a0, int64_t a1,
+                                  const float* T_final, const uint32_t* n_contrib, const float* dL,
+                                  float* grad2d, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
+
+// adam.hip
+hipError_t launch_adam(const MutParams& p, const MutParams& g, const MutParams& m, const MutParams& v, int64_t a0,
+                       int64_t a1, const uint8_t* row_mask, const clsp_adam_hparams& hp, hipStream_t s);
+hipError_t launch_zero_rows(const MutParams& g, int64_t a0, int64_t a1, hipStream_t s);
+
+}  // namespace clsp

@@ -1,0 +1,303 @@
+// Tile rasteriser: forward compositing, L1 loss gradient, and reverse compositing with
+// per-Gaussian gradient reduction (Supp. "Local Optimization Kernel", item 2: only the
+// tiles of the render mask are launched; Table tab:timings "Forward::Render" and
+// "Backward::Render").
+//
+// One 256-thread workgroup (four wave64s) per 16x16 tile, one pixel per thread.  The
+// tile's depth-ordered records are staged through LDS 256 at a time; every lane reads
+// the same LDS record, so the reads are broadcasts.  In the backward each wave sums its
+// 64 pixels' partials with DPP row operations, the four wave sums meet in LDS, and one
+// global float atomic per (record, component) is issued, only for changed Gaussians.
+#include "internal.hpp"
+
+namespace clsp {
+namespace {
+
+constexpr int NT = TILE_PIX;
+constexpr int C_TILES = 2;
+
+// Opacity of a record at a pixel centre, evaluated with explicitly rounded operations
+// so the forward and the backward take the same decisions bit for bit.
+// Returns false when the record is skipped (positive exponent or alpha < 1/255).
+__device__ __forceinline__ bool splat_alpha(const float4 a, const float4 b, float fx, float fy, float& dx, float& dy,
+                                            float& G, float& alpha, bool& clamped) {
+  dx = __fsub_rn(fx, a.x);
+  dy = __fsub_rn(fy, a.y);
+  // q = A dx^2 + 2 B dx dy + C dy^2
+  const float q = __fmaf_rn(__fmul_rn(a.z, dx), dx,
+                            __fmaf_rn(__fmul_rn(__fmul_rn(2.0f, a.w), dx), dy, __fmul_rn(__fmul_rn(b.x, dy), dy)));
+  const float power = __fmul_rn(-0.5f, q);
+  if (power > 0.0f) return false;
+  G = __expf(power);
+  const float oG = __fmul_rn(b.y, G);
+  clamped = !(oG < ALPHA_MAX);
+  alpha = clamped ? ALPHA_MAX : oG;
+  return alpha >= ALPHA_MIN;
+}
+
+__global__ void __launch_bounds__(NT) render_forward_kernel(const float* __restrict__ splat,
+                                                            const uint32_t* __restrict__ values,
+                                                            const uint2* __restrict__ ranges,
+                                                            const uint32_t* __restrict__ tile_list,
+                                                            const uint32_t* __restrict__ counters, int T, int TX,
+                                                            int W, int H, float bg0, float bg1, float bg2,
+                                                            float* __restrict__ image, float* __restrict__ T_final,
+                                                            uint32_t* __restrict__ n_contrib) {
+  if (blockIdx.x >= counters[C_TILES]) return;
+  __shared__ float4 s_a[NT];
+  __shared__ float4 s_b[NT];
+  __shared__ float s_c[NT];
+  const uint32_t gt = tile_list[blockIdx.x];
+  const int v = gt / T, t = gt % T;
+  const int px = (t % TX) * TILE + (threadIdx.x & 15);
+  const int py = (t / TX) * TILE + (threadIdx.x >> 4);
+  const bool inside = px < W && py < H;
+  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const uint2 rg = ranges[gt];
+  const int total = (int)(rg.y - rg.x);
+
+  float Tr = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+  uint32_t last = 0;
+  bool done = !inside;
+  for (int base = 0; base < total; base += NT) {
+    if (__syncthreads_count(done) == NT) break;
+    const int k = base + threadIdx.x;
+    if (k < total) {
+      const uint32_t e = values[rg.x + k];
+      const float4* sp = reinterpret_cast<const float4*>(splat + (size_t)e * SPLAT_STRIDE);
+      s_a[threadIdx.x] = sp[0];
+      s_b[threadIdx.x] = sp[1];
+      s_c[threadIdx.x] = sp[2].x;
+    }
+    __syncthreads();
+    if (!done) {
+      const int cnt = min(NT, total - base);
+      for (int j = 0; j < cnt; ++j) {
+        const float4 a = s_a[j], b = s_b[j];
+        float dx, dy, G, alpha;
+        bool clamped;
+        if (!splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped)) continue;
+        const float Tn = Tr * (1.0f - alpha);
+        if (Tn < T_STOP) {
+          done = true;
+          break;
+        }
+        const float w = alpha * Tr;
+        cr = fmaf(w, b.z, cr);
+        cg = fmaf(w, b.w, cg);
+        cb = fmaf(w, s_c[j], cb);
+        Tr = Tn;
+        last = (uint32_t)(base + j + 1);
+      }
+    }
+  }
+  if (inside) {
+    const size_t hw = (size_t)H * W;
+    const size_t pix = (size_t)py * W + px;
+    image[((size_t)v * 3 + 0) * hw + pix] = fmaf(Tr, bg0, cr);
+    image[((size_t)v * 3 + 1) * hw + pix] = fmaf(Tr, bg1, cg);
+    image[((size_t)v * 3 + 2) * hw + pix] = fmaf(Tr, bg2, cb);
+    T_final[(size_t)v * hw + pix] = Tr;
+    n_contrib[(size_t)v * hw + pix] = last;
+  }
+}
+
+__global__ void __launch_bounds__(NT) l1_loss_grad_kernel(const float* __restrict__ image,
+                                                          const float* __restrict__ target,
+                                                          const uint32_t* __restrict__ tile_list,
+                                                          const uint32_t* __restrict__ counters, int T, int TX, int W,
+                                                          int H, float* __restrict__ dL, float* __restrict__ loss_sum) {
+  if (blockIdx.x >= counters[C_TILES]) return;
+  __shared__ float s_sum[4];
+  const uint32_t gt = tile_list[blockIdx.x];
+  const int v = gt / T, t = gt % T;
+  const int px = (t % TX) * TILE + (threadIdx.x & 15);
+  const int py = (t / TX) * TILE + (threadIdx.x >> 4);
+  const float norm = 1.0f / (3.0f * (float)W * (float)H);
+  float acc = 0.0f;
+  if (px < W && py < H) {
+    const size_t hw = (size_t)H * W;
+    for (int c = 0; c < 3; ++c) {
+      const size_t idx = ((size_t)v * 3 + c) * hw + (size_t)py * W + px;
+      const float d = image[idx] - target[idx];
+      dL[idx] = d > 0.0f ? norm : (d < 0.0f ? -norm : 0.0f);
+      acc += fabsf(d);
+    }
+  }
+  if (loss_sum) {
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss_sum, (s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3]) * norm);
+  }
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
+}
+
+// Sum of v over the 64 lanes of the wave, valid in lane 63 (DPP row operations; every
+// lane of the wave must be active).
+__device__ __forceinline__ float wave_sum_lane63(float v) {
+  v += dpp_f<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f<0x141, 0xf>(v);  // row_half_mirror
+  v += dpp_f<0x140, 0xf>(v);  // row_mirror
+  v += dpp_f<0x142, 0xa>(v);  // row_bcast15 into rows 1 and 3
+  v += dpp_f<0x143, 0xc>(v);  // row_bcast31 into rows 2 and 3
+  return v;
+}
+
+__global__ void __launch_bounds__(NT) render_backward_kernel(
+    const float* __restrict__ splat, const uint32_t* __restrict__ values, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ tile_list, const uint32_t* __restrict__ counters, int T, int TX, int W, int H,
+    int64_t n, float bg0, float bg1, float bg2, int64_t a0, int64_t a1, const float* __restrict__ T_final,
+    const uint32_t* __restrict__ n_contrib, const float* __restrict__ dL, float* __restrict__ grad2d) {
+  if (blockIdx.x >= counters[C_TILES]) return;
+  __shared__ float4 s_a[NT];
+  __shared__ float4 s_b[NT];
+  __shared__ float s_c[NT];
+  __shared__ uint32_t s_e[NT];
+  __shared__ float s_g[NT][9];
+  __shared__ uint32_t s_max;
+
+  const uint32_t gt = tile_list[blockIdx.x];
+  const int v = gt / T, t = gt % T;
+  const int px = (t % TX) * TILE + (threadIdx.x & 15);
+  const int py = (t / TX) * TILE + (threadIdx.x >> 4);
+  const bool inside = px < W && py < H;
+  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const uint2 rg = ranges[gt];
+  const size_t hw = (size_t)H * W;
+  const size_t pix = (size_t)py * W + px;
+
+  float Tr = 1.0f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+  uint32_t last = 0;
+  if (inside) {
+    Tr = T_final[(size_t)v * hw + pix];
+    last = n_contrib[(size_t)v * hw + pix];
+    g0 = dL[((size_t)v * 3 + 0) * hw + pix];
+    g1 = dL[((size_t)v * 3 + 1) * hw + pix];
+    g2 = dL[((size_t)v * 3 + 2) * hw + pix];
+  }
+  // colour of everything behind the current record (starts with the background)
+  float S0 = Tr * bg0, S1 = Tr * bg1, S2 = Tr * bg2;
+  if (threadIdx.x == 0) s_max = 0;
+  __syncthreads();
+  atomicMax(&s_max, last);
+  __syncthreads();
+  const int maxlast = (int)s_max;
+  const int64_t na = a1 - a0;
+  const int64_t vbase = (int64_t)v * n;
+  const uint32_t lane = threadIdx.x & 63;
+
+  for (int end = maxlast; end > 0; end -= NT) {
+    const int beg = end > NT ? end - NT : 0;
+    const int cnt = end - beg;
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+      const uint32_t e = values[rg.x + beg + threadIdx.x];
+      const float4* sp = reinterpret_cast<const float4*>(splat + (size_t)e * SPLAT_STRIDE);
+      s_a[threadIdx.x] = sp[0];
+      s_b[threadIdx.x] = sp[1];
+      s_c[threadIdx.x] = sp[2].x;
+      s_e[threadIdx.x] = e;
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) s_g[threadIdx.x][c] = 0.0f;
+    __syncthreads();
+    for (int j = cnt - 1; j >= 0; --j) {
+      const int k = beg + j;
+      float p[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) p[c] = 0.0f;
+      bool contrib = false;
+      if (k < (int)last) {
+        const float4 a = s_a[j], b = s_b[j];
+        const float cb = s_c[j];
+        float dx, dy, G, alpha;
+        bool clamped;
+        if (splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped)) {
+          const float om = 1.0f - alpha;
+          const float Tj = Tr / om;
+          const float w = alpha * Tj;
+          const float io = 1.0f / om;
+          const float dLda = g0 * (Tj * b.z - S0 * io) + g1 * (Tj * b.w - S1 * io) + g2 * (Tj * cb - S2 * io);
+          S0 = fmaf(w, b.z, S0);
+          S1 = fmaf(w, b.w, S1);
+          S2 = fmaf(w, cb, S2);
+          Tr = Tj;
+          p[6] = w * g0;
+          p[7] = w * g1;
+          p[8] = w * g2;
+          if (!clamped) {
+            const float gp = alpha * dLda;  // dL/dpower
+            p[5] = G * dLda;                // dL/dopacity
+            p[0] = gp * (a.z * dx + a.w * dy);
+            p[1] = gp * (a.w * dx + b.x * dy);
+            p[2] = -0.5f * gp * dx * dx;
+            p[3] = -gp * dx * dy;
+            p[4] = -0.5f * gp * dy * dy;
+          }
+          contrib = true;
+        }
+      }
+      if (__ballot(contrib)) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          const float sum = wave_sum_lane63(p[c]);
+          if (lane == 63 && sum != 0.0f) atomicAdd(&s_g[j][c], sum);
+        }
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+      const int64_t gid = (int64_t)s_e[threadIdx.x] - vbase;
+      if (gid >= a0 && gid < a1) {
+        float* dst = grad2d + ((int64_t)v * na + (gid - a0)) * G2D_STRIDE;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          const float val = s_g[threadIdx.x][c];
+          if (val != 0.0f) atomicAdd(dst + c, val);
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_render_forward(const clsp_projected& proj, const clsp_bins& bins, int views, int W, int H, int TX,
+                                 int TY, const float bg[3], float* image, float* T_final, uint32_t* n_contrib,
+                                 hipStream_t s) {
+  const int T = TX * TY;
+  const int blocks = views * T;
+  hipLaunchKernelGGL(render_forward_kernel, dim3(blocks), dim3(NT), 0, s, proj.splat, bins.values,
+                     reinterpret_cast<const uint2*>(bins.ranges), bins.tile_list, bins.counters, T, TX, W, H, bg[0],
+                     bg[1], bg[2], image, T_final, n_contrib);
+  return hipGetLastError();
+}
+
+hipError_t launch_l1_loss_grad(const float* image, const float* target, const clsp_bins& bins, int views, int W, int H,
+                               int TX, int TY, float* dL, float* loss_sum, hipStream_t s) {
+  const int T = TX * TY;
+  hipLaunchKernelGGL(l1_loss_grad_kernel, dim3(views * T), dim3(NT), 0, s, image, target, bins.tile_list,
+                     bins.counters, T, TX, W, H, dL, loss_sum);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_backward(const clsp_projected& proj, const clsp_bins& bins, int views, int64_t n, int W,
+                                  int H, int TX, int TY, const float bg[3], int64_t a0, int64_t a1,
+                                  const float* T_final, const uint32_t* n_contrib, const float* dL, float* grad2d,
+                                  hipStream_t s) {
+  const int T = TX * TY;
+  hipError_t err = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, (a1 - a0) * views * G2D_STRIDE, s);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(render_backward_kernel, dim3(views * T), dim3(NT), 0, s, proj.splat, bins.values,
+                     reinterpret_cast<const uint2*>(bins.ranges), bins.tile_list, bins.counters, T, TX, W, H, n,
+                     bg[0], bg[1], bg[2], a0, a1, T_final, n_contrib, dL, grad2d);
+  return hipGetLastError();
+}
+
+}  // namespace clsp

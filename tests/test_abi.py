@@ -1,0 +1,128 @@
+"""The C-ABI library loads, exports every function include/clsplat.h declares, and
+rejects invalid arguments on the host (no GPU work is enqueued by these calls)."""
+import ctypes
+import re
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2506_21117_amd import _ffi, build
+    if not _ffi.LIB_PATH.exists():
+        build.build()
+    return _ffi.load()
+
+
+def declared_functions():
+    text = (ROOT / "include" / "clsplat.h").read_text()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(clsp_[a-z_0-9]+)\(", text, re.M)))
+
+
+def test_header_declares_the_five_hot_path_calls():
+    names = declared_functions()
+    for f in ("clsp_project_preprocess", "clsp_bin_and_sort", "clsp_render_forward", "clsp_render_backward",
+              "clsp_masked_adam_step"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    from paper_2506_21117_amd import _ffi
+    names = declared_functions()
+    assert set(names) == set(_ffi.EXPORTED)
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_version(L):
+    assert b"gfx950" in L.clsp_version()
+
+
+def test_struct_sizes_match_header():
+    from paper_2506_21117_amd import _ffi
+    assert ctypes.sizeof(_ffi.Camera) == 4 * 18
+    assert ctypes.sizeof(_ffi.Gaussians) == 6 * 8 + 8 + 8 + 4 + 4
+    assert ctypes.sizeof(_ffi.Params) == 5 * 8 + 8 + 4 + 4
+    assert ctypes.sizeof(_ffi.Bins) == 7 * 8
+    assert ctypes.sizeof(_ffi.AdamHParams) == 4 * 10
+
+
+def test_workspace_queries(L):
+    a = L.clsp_bin_and_sort_workspace_bytes(1000, 1, 128, 128, 10000)
+    b = L.clsp_bin_and_sort_workspace_bytes(1000, 1, 128, 128, 20000)
+    assert a > 0 and b >= a + 2 * 4 * 10000 - 512
+    assert L.clsp_bin_and_sort_workspace_bytes(-1, 1, 128, 128, 10) == 0
+    assert L.clsp_render_backward_workspace_bytes(100, 2) == 100 * 2 * 12 * 4
+    assert L.clsp_render_backward_workspace_bytes(-1, 1) == 0
+
+
+def _cam(w=64, h=48):
+    from paper_2506_21117_amd import _ffi
+    c = (_ffi.Camera * 1)()
+    c[0].R = (ctypes.c_float * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
+    c[0].t = (ctypes.c_float * 3)(0, 0, 4)
+    c[0].fx = c[0].fy = 64.0
+    c[0].cx, c[0].cy = w / 2, h / 2
+    c[0].width, c[0].height = w, h
+    return c
+
+
+def test_invalid_arguments_are_rejected_on_the_host(L):
+    from paper_2506_21117_amd import _ffi
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    g = _ffi.Gaussians(fake, fake, fake, fake, fake, None, 10, 10, 5, 0)   # sh_degree 5
+    proj = _ffi.Projected(fake, fake, fake, fake)
+    cam = _cam()
+    assert L.clsp_project_preprocess(ctypes.byref(g), cam, 1, ctypes.byref(proj), None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert b"sh_degree" in L.clsp_last_error()
+    g.sh_degree = 0
+    assert L.clsp_project_preprocess(ctypes.byref(g), cam, 0, ctypes.byref(proj), None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_project_preprocess(ctypes.byref(g), None, 1, ctypes.byref(proj), None) == _ffi.CLSP_ERR_INVALID_ARG
+    g.n_rows = 5    # fewer rows than Gaussians and no gather
+    assert L.clsp_project_preprocess(ctypes.byref(g), cam, 1, ctypes.byref(proj), None) == _ffi.CLSP_ERR_INVALID_ARG
+    g.n_rows = 10
+    two = (_ffi.Camera * 2)(cam[0], cam[0])
+    two[1].width = 32  # views of different sizes
+    assert L.clsp_project_preprocess(ctypes.byref(g), two, 2, ctypes.byref(proj), None) == _ffi.CLSP_ERR_INVALID_ARG
+    bad = _cam()
+    bad[0].fx = 0.0
+    assert L.clsp_project_preprocess(ctypes.byref(g), bad, 1, ctypes.byref(proj), None) == _ffi.CLSP_ERR_INVALID_ARG
+    big = _cam(16384, 16384)   # more than 65536 tiles per view
+    assert L.clsp_project_preprocess(ctypes.byref(g), big, 1, ctypes.byref(proj), None) == _ffi.CLSP_ERR_INVALID_ARG
+
+    bins = _ffi.Bins(fake, fake, fake, fake, fake, fake, 100)
+    ws_need = L.clsp_bin_and_sort_workspace_bytes(10, 1, 64, 48, 100)
+    # active range outside [0, n]
+    assert L.clsp_bin_and_sort(ctypes.byref(proj), 10, cam, 1, _ffi.Range(5, 11), 1, ctypes.byref(bins), fake,
+                               ws_need, None) == _ffi.CLSP_ERR_INVALID_ARG
+    # workspace too small
+    assert L.clsp_bin_and_sort(ctypes.byref(proj), 10, cam, 1, _ffi.Range(5, 10), 1, ctypes.byref(bins), fake,
+                               ws_need - 1, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert b"workspace" in L.clsp_last_error()
+    bins.capacity = 1 << 33
+    assert L.clsp_bin_and_sort(ctypes.byref(proj), 10, cam, 1, _ffi.Range(5, 10), 1, ctypes.byref(bins), fake,
+                               1 << 40, None) == _ffi.CLSP_ERR_INVALID_ARG
+
+    p = _ffi.Params(fake, fake, fake, fake, fake, 10, 0, 0)
+    hp = _ffi.AdamHParams()
+    hp.beta1, hp.beta2, hp.eps, hp.step = 0.9, 0.999, 1e-15, 0    # step 0
+    assert L.clsp_masked_adam_step(ctypes.byref(p), ctypes.byref(p), ctypes.byref(p), ctypes.byref(p),
+                                   _ffi.Range(0, 10), None, ctypes.byref(hp), None) == _ffi.CLSP_ERR_INVALID_ARG
+    hp.step = 1
+    q = _ffi.Params(fake, fake, fake, fake, fake, 11, 0, 0)   # moments of another size
+    assert L.clsp_masked_adam_step(ctypes.byref(p), ctypes.byref(p), ctypes.byref(q), ctypes.byref(p),
+                                   _ffi.Range(0, 10), None, ctypes.byref(hp), None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_zero_grads(ctypes.byref(p), _ffi.Range(3, 2), None) == _ffi.CLSP_ERR_INVALID_ARG
+    gathered = _ffi.Gaussians(fake, fake, fake, fake, fake, fake, 10, 10, 0, 0)
+    assert L.clsp_render_backward(ctypes.byref(gathered), ctypes.byref(proj), ctypes.byref(bins), cam, 1,
+                                  (ctypes.c_float * 3)(0, 0, 0), _ffi.Range(0, 10), fake, fake, fake,
+                                  ctypes.byref(p), fake, 1 << 20, None) == _ffi.CLSP_ERR_INVALID_ARG
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_2506_21117_amd import _ffi
+    with pytest.raises(_ffi.LibraryMissing):
+        _ffi.load(tmp_path / "nope.so")

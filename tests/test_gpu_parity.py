@@ -1,0 +1,369 @@
+"""Parity of every hot-path call (through the C-ABI) with the CPU reference.
+
+Binning is compared bit for bit against the reference binning run on the GPU's own
+float32 screen-space outputs; pixels within 1e-4 relative; gradients within 1e-3
+relative (plus the float32 summation-order term 1e-5 * sum of |per-pixel terms|);
+preprocess outputs within float32 rounding; Adam within 1e-6 of the step size.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+from gpu_helpers import (bin_reference_for, check_grads, check_pixels, gpu_preprocess, masked_pixels, to_np,
+                         unpack)
+from paper_2506_21117_amd import api
+
+pytestmark = pytest.mark.gpu
+
+
+# ------------------------------------------------------------------ workloads
+def _clamp_scene(seed=13):
+    """Gaussians off to the sides (Jacobian clamp), some behind the near plane, strong
+    SH bands (colour clamp), 100x37 ragged image."""
+    rng = np.random.default_rng(seed)
+    n = 400
+    means = np.stack([rng.uniform(-5, 5, n), rng.uniform(-2, 2, n), rng.uniform(-4.5, 1.5, n)]).astype(np.float32)
+    ls = rng.normal(-1.8, 0.5, (3, n)).astype(np.float32)
+    sh = rng.normal(0, 0.9, (4, 3, n)).astype(np.float32)
+    sc = scenes.Scene(means, ls, rng.normal(size=(4, n)), rng.normal(0, 1.5, n), sh, 1)
+    cam = scenes.Camera(np.eye(3), (0, 0, 4), 60, 60, 50, 18.5, 100, 37)
+    return sc, [cam]
+
+
+def workload(name):
+    if name == "tiny":
+        w = scenes.tiny()
+        return w.scene, w.cameras
+    if name == "sh3":
+        w = scenes.fd_scene(n=500, res=64)
+        return w.scene, w.cameras
+    if name == "clamp":
+        return _clamp_scene()
+    if name == "ring2":
+        w = scenes.full_scene(n=3000, n_views=2, res=96, fx=132.0)
+        return w.scene, w.cameras
+    raise KeyError(name)
+
+
+CASES = ["tiny", "sh3", "clamp", "ring2"]
+
+
+# ------------------------------------------------------------------ a1 preprocess
+@pytest.mark.parametrize("case", CASES)
+def test_preprocess_parity(dev, case):
+    sc, cams = workload(case)
+    g = api.GaussianTensors.from_scene(sc, dev)
+    proj = gpu_preprocess(g, cams)
+    for v, cam in enumerate(cams):
+        gp = unpack(proj, v)
+        ref = oracle.preprocess(sc, cam)
+        near = (ref["flags"] & oracle.F_NEAR) != 0
+        vis_g = (gp["flags"] & 1) != 0
+        assert np.all((vis_g == ref["visible"]) | near)
+        np.testing.assert_array_equal(gp["depth"].view(np.uint32), ref["z32"].view(np.uint32))
+        both = vis_g & ref["visible"] & ~near
+        assert both.sum() > 0.3 * sc.n or case == "clamp"
+
+        def close(k, rel, abs_=0.0, scale=None):
+            o = ref[k][both]
+            s = np.abs(o) if scale is None else scale
+            err = np.abs(gp[k][both].astype(np.float64) - o)
+            assert np.all(err <= rel * s + abs_), (k, float((err / (rel * s + abs_)).max()))
+
+        close("u", 2e-6, 1e-4)
+        close("v", 2e-6, 1e-4)
+        cn = np.sqrt(ref["A"] ** 2 + 2 * ref["B"] ** 2 + ref["C"] ** 2)[both]
+        for k in ("A", "B", "C"):
+            close(k, 1e-4, scale=cn)      # det = ac - b^2 cancels for thin ellipses
+        close("opacity", 1e-6)
+        for k in ("r", "g", "b"):
+            close(k, 1e-6, 2e-6)
+        close("rx", 1e-4, 1e-4)
+        close("ry", 1e-4, 1e-4)
+        clamp_bits = oracle.F_CLAMPX | oracle.F_CLAMPY | oracle.F_SHCLAMP_R | oracle.F_SHCLAMP_G | oracle.F_SHCLAMP_B
+        np.testing.assert_array_equal(gp["flags"][both] & clamp_bits, ref["flags"][both] & clamp_bits)
+        # the tile rectangle is the documented float32 formula of the GPU's own outputs
+        x0, x1, y0, y1 = oracle.tile_rects(gp["u"], gp["v"], gp["rx"], gp["ry"], cam.width, cam.height)
+        for a, b in ((gp["x0"], x0), (gp["x1"], x1), (gp["y0"], y0), (gp["y1"], y1)):
+            np.testing.assert_array_equal(a[vis_g].astype(np.int64), b[vis_g])
+
+
+# ------------------------------------------------------------------ a2, a3 binning
+def _check_bins(bins, proj, cams, active, use_mask):
+    c = bins.read_counters()
+    assert not c["overflow"]
+    n = proj.n
+    TX, TY = api.tile_grid(cams[0].width, cams[0].height)
+    T = TX * TY
+    values = to_np(bins.values).view(np.uint32)
+    keys = to_np(bins.keys).view(np.uint32)
+    ranges = to_np(bins.ranges).view(np.uint32).astype(np.int64)
+    mask_words = to_np(bins.tile_mask).view(np.uint32)
+    off = 0
+    total_tiles = []
+    for v, cam in enumerate(cams):
+        gp = unpack(proj, v)
+        ref = bin_reference_for(gp, cam, active, use_mask)
+        P = ref["n_pairs"]
+        np.testing.assert_array_equal(values[off:off + P].astype(np.int64), ref["values"] + v * n)
+        np.testing.assert_array_equal(keys[off:off + P].astype(np.int64), ref["tiles"] + v * T)
+        rv = ranges[v * T:(v + 1) * T]
+        exp = ref["ranges"].copy()
+        ne = exp[:, 1] > exp[:, 0]
+        exp[ne] += off
+        np.testing.assert_array_equal(rv, exp)
+        bits = np.array([(mask_words[v][t // 32] >> (t % 32)) & 1 for t in range(T)], bool)
+        np.testing.assert_array_equal(bits, ref["mask"])
+        total_tiles += [v * T + t for t in np.nonzero(ref["mask"])[0]]
+        off += P
+    assert c["pairs"] == off == c["written"]
+    np.testing.assert_array_equal(to_np(bins.tile_list)[:c["tiles"]], np.array(total_tiles, np.int64))
+    return off
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("use_mask", [False, True])
+def test_bin_and_sort_bit_exact(dev, case, use_mask):
+    sc, cams = workload(case)
+    g = api.GaussianTensors.from_scene(sc, dev)
+    proj = gpu_preprocess(g, cams)
+    active = (int(sc.n * 0.8), sc.n)
+    bins = api.bin_and_sort(proj, cams, active, use_mask, capacity=200_000)
+    torch.cuda.synchronize()
+    P = _check_bins(bins, proj, cams, active, use_mask)
+    assert P > 0
+
+
+def test_bin_and_sort_many_tile_bits(dev):
+    """3600 tiles per view (12 tile bits, two sort passes) plus views stacked (13 bits)."""
+    w = scenes.full_scene(n=4000, n_views=2, res=960, fx=1320.0)
+    cams = [scenes.Camera(c.R, c.t, 1280, 1280, 640, 360, 1280, 720) for c in w.cameras]
+    g = api.GaussianTensors.from_scene(w.scene, dev)
+    proj = gpu_preprocess(g, cams)
+    for use_mask in (False, True):
+        bins = api.bin_and_sort(proj, cams, (3000, 4000), use_mask, capacity=2_000_000)
+        torch.cuda.synchronize()
+        _check_bins(bins, proj, cams, (3000, 4000), use_mask)
+
+
+def test_capacity_overflow_is_reported_and_recoverable(dev):
+    sc, cams = workload("tiny")
+    g = api.GaussianTensors.from_scene(sc, dev)
+    proj = gpu_preprocess(g, cams)
+    small = api.bin_and_sort(proj, cams, capacity=100)
+    c = small.read_counters()
+    assert c["overflow"] and c["pairs"] > 100 and c["written"] == 0 and c["tiles"] == 0
+    assert to_np(small.counters)[5] == 1            # sticky
+    img, _, _ = api.render_forward(proj, small, cams)   # renders nothing, touches nothing
+    torch.cuda.synchronize()
+    assert float(img.abs().sum()) == 0.0
+    big = api.bin_and_sort(proj, cams, capacity=c["pairs"])
+    torch.cuda.synchronize()
+    _check_bins(big, proj, cams, None, False)
+
+
+# ------------------------------------------------------------------ a4 forward
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("bg", [(0.0, 0.0, 0.0), (0.2, 0.5, 0.9)])
+def test_render_forward_parity(dev, case, bg):
+    sc, cams = workload(case)
+    g = api.GaussianTensors.from_scene(sc, dev)
+    proj = gpu_preprocess(g, cams)
+    bins = api.bin_and_sort(proj, cams, capacity=400_000)
+    img, T, nc = api.render_forward(proj, bins, cams, bg)
+    torch.cuda.synchronize()
+    for v, cam in enumerate(cams):
+        ref = oracle.render(sc, cam, bg)
+        got = to_np(img[v]).transpose(1, 2, 0).reshape(-1, 3)
+        check_pixels(got, ref, f"{case} view {v}")
+        ok = ref["flag"] == 0
+        Tg = to_np(T[v]).reshape(-1)
+        assert np.all(np.abs(Tg - ref["T"])[ok] <= 1e-4 * ref["T"][ok] + 1e-7)
+        assert Tg.min() >= 1e-4
+
+
+def test_render_forward_empty_and_culled(dev):
+    cam = scenes.Camera(np.eye(3), (0, 0, 4), 40, 40, 20, 15, 40, 30)
+    bg = (0.3, 0.6, 0.9)
+    for n in (0, 5):
+        rng = np.random.default_rng(n)
+        # n = 5: all behind the camera
+        sc = scenes.Scene(np.tile([[0], [0], [-5.0]], (1, n)), np.full((3, n), -2.0), rng.normal(size=(4, n)),
+                          np.zeros(n), np.zeros((1, 3, n)), 0)
+        g = api.GaussianTensors.from_scene(sc, dev) if n else api.GaussianTensors.zeros(0, 0, dev)
+        proj = api.project_preprocess(g, [cam])
+        bins = api.bin_and_sort(proj, [cam], capacity=16)
+        img, T, nc = api.render_forward(proj, bins, [cam], bg)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(to_np(img[0]), np.broadcast_to(np.float32(bg)[:, None, None], (3, 30, 40)))
+        assert np.all(to_np(T) == 1.0) and np.all(to_np(nc) == 0)
+
+
+def test_single_tile_image(dev):
+    """16x16: one tile, zero tile-key bits, no pair sort pass."""
+    w = scenes.tiny(n=300, width=16, height=16)
+    cam = scenes.Camera(np.eye(3), (0, 0, 4), 16, 16, 8, 8, 16, 16)
+    g = api.GaussianTensors.from_scene(w.scene, dev)
+    proj = gpu_preprocess(g, [cam])
+    bins = api.bin_and_sort(proj, [cam], capacity=10_000)
+    img, _, _ = api.render_forward(proj, bins, [cam])
+    torch.cuda.synchronize()
+    _check_bins(bins, proj, [cam], None, False)
+    ref = oracle.render(w.scene, cam)
+    check_pixels(to_np(img[0]).transpose(1, 2, 0).reshape(-1, 3), ref, "single tile")
+
+
+# ------------------------------------------------------------------ a5 loss gradient
+def test_l1_loss_grad_exact(dev):
+    sc, cams = workload("clamp")
+    g = api.GaussianTensors.from_scene(sc, dev)
+    proj = gpu_preprocess(g, cams)
+    bins = api.bin_and_sort(proj, cams, capacity=100_000)
+    img, _, _ = api.render_forward(proj, bins, cams)
+    rng = np.random.default_rng(3)
+    tgt_np = rng.uniform(size=img.shape).astype(np.float32)
+    tgt_np[0, :, 5, 7] = to_np(img[0, :, 5, 7])      # exact ties give sign 0
+    tgt = torch.as_tensor(tgt_np, device=dev)
+    loss = torch.zeros(1, device=dev)
+    dL = api.l1_loss_grad(img, tgt, bins, cams, loss_sum=loss)
+    torch.cuda.synchronize()
+    ref_loss, ref_g = oracle.l1_loss_grad(to_np(img[0]), tgt_np[0])
+    np.testing.assert_array_equal(to_np(dL[0]), ref_g.astype(np.float32))
+    assert abs(float(loss) - ref_loss) <= 1e-5 * ref_loss
+
+
+# ------------------------------------------------------------------ a6, a7 backward
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("local", [False, True])
+def test_render_backward_parity(dev, case, local):
+    sc, cams = workload(case)
+    n = sc.n
+    a = (int(n * 0.75), n) if local else (0, n)
+    bg = (0.1, 0.3, 0.2)
+    g = api.GaussianTensors.from_scene(sc, dev)
+    proj = gpu_preprocess(g, cams)
+    bins = api.bin_and_sort(proj, cams, a, use_mask=local, capacity=400_000)
+    img, T, nc = api.render_forward(proj, bins, cams, bg)
+    rng = np.random.default_rng(21)
+    dl_np = rng.normal(size=img.shape).astype(np.float32)
+    dl = torch.as_tensor(dl_np, device=dev)
+    grads = g.zeros_like()
+    api.render_backward(g, proj, bins, cams, bg, a, T, nc, dl, grads)
+    torch.cuda.synchronize()
+    # the reference sees the full image with the same upstream gradient: for the
+    # changed Gaussians the local step must give the full-scene gradient
+    ref = oracle.gradients(sc, cams, [dl_np[v].astype(np.float64) for v in range(len(cams))], bg)
+    worst = check_grads(grads, ref, slice(a[0], a[1]), f"{case} local={local}")
+    # rows outside the change set are never written
+    for k in api.GaussianTensors.NAMES:
+        assert np.all(to_np(getattr(grads, k))[..., :a[0]] == 0)
+    print(f"{case} local={local}: worst gradient error / tolerance {worst:.3f}")
+
+
+def test_gradients_accumulate(dev):
+    """render_backward adds to the gradient buffers."""
+    sc, cams = workload("tiny")
+    g = api.GaussianTensors.from_scene(sc, dev)
+    proj = gpu_preprocess(g, cams)
+    bins = api.bin_and_sort(proj, cams, capacity=100_000)
+    img, T, nc = api.render_forward(proj, bins, cams)
+    dl = torch.randn_like(img)
+    g1 = g.zeros_like()
+    api.render_backward(g, proj, bins, cams, (0, 0, 0), None, T, nc, dl, g1)
+    g2 = g1.clone()
+    api.render_backward(g, proj, bins, cams, (0, 0, 0), None, T, nc, dl, g2)
+    torch.cuda.synchronize()
+    for k in api.GaussianTensors.NAMES:
+        a, b = to_np(getattr(g1, k)), to_np(getattr(g2, k))
+        np.testing.assert_allclose(b, 2 * a, rtol=1e-5, atol=1e-9)
+    api.zero_grads(g2, (100, 200))
+    torch.cuda.synchronize()
+    assert np.all(to_np(g2.means)[:, 100:200] == 0) and np.any(to_np(g2.means)[:, 200:] != 0)
+
+
+# ------------------------------------------------------------------ exactness of the local step on the GPU
+def test_local_step_equals_full_step_on_gpu(dev):
+    w = scenes.local_change(n=40_000, n_views=2, width=320, height=180, fx=320.0, radius=0.4)
+    sc, cams = w.scene, w.cameras[:1]
+    a = (w.active_begin, sc.n)
+    g = api.GaussianTensors.from_scene(sc, dev)
+    proj = gpu_preprocess(g, cams)
+    out = {}
+    for local in (False, True):
+        bins = api.bin_and_sort(proj, cams, a if local else None, use_mask=local, capacity=4_000_000)
+        img, T, nc = api.render_forward(proj, bins, cams)
+        tgt = torch.rand_like(img, generator=torch.Generator(device=dev).manual_seed(5))
+        dL = api.l1_loss_grad(img, tgt, bins, cams)
+        grads = g.zeros_like()
+        api.render_backward(g, proj, bins, cams, (0, 0, 0), a if local else None, T, nc, dL, grads)
+        torch.cuda.synchronize()
+        out[local] = (bins, to_np(img), grads)
+    pix, tiles = masked_pixels(out[True][0], cams[0])
+    assert 0 < len(tiles) < 0.5 * api.tile_grid(320, 180)[0] * api.tile_grid(320, 180)[1]
+    # forward on masked tiles: identical lists, identical arithmetic -> identical bits
+    li, fi = out[True][1][0], out[False][1][0]
+    np.testing.assert_array_equal(li[:, pix[:, 1], pix[:, 0]], fi[:, pix[:, 1], pix[:, 0]])
+    for k in api.GaussianTensors.NAMES:
+        gl = to_np(getattr(out[True][2], k))[..., a[0]:]
+        gf = to_np(getattr(out[False][2], k))[..., a[0]:]
+        scale = np.abs(gf).max()
+        np.testing.assert_allclose(gl, gf, rtol=1e-4, atol=1e-6 * scale)
+
+
+# ------------------------------------------------------------------ a8 masked Adam
+@pytest.mark.parametrize("sh_degree", [0, 3])
+@pytest.mark.parametrize("with_mask", [False, True])
+def test_masked_adam_parity(dev, sh_degree, with_mask):
+    rng = np.random.default_rng(sh_degree + 7)
+    n, a = 3000, (1200, 3000)
+    K = (sh_degree + 1) ** 2
+    shapes = {"means": (3, n), "log_scales": (3, n), "quats": (4, n), "opacity_logit": (n,), "sh": (K, 3, n)}
+    mk = lambda f: api.GaussianTensors(*[torch.as_tensor(f(s).astype(np.float32), device=dev)
+                                         for s in shapes.values()], sh_degree)
+    P = mk(lambda s: rng.normal(size=s))
+    G = mk(lambda s: rng.normal(size=s) * 0.1)
+    M = mk(lambda s: rng.normal(size=s) * 0.01)
+    V = mk(lambda s: rng.uniform(size=s) * 1e-3)
+    P0, M0, V0 = P.clone(), M.clone(), V.clone()
+    row_mask = None
+    rows = np.arange(a[0], a[1])
+    if with_mask:
+        rm = (rng.uniform(size=n) < 0.5).astype(np.uint8)
+        row_mask = torch.as_tensor(rm, device=dev)
+        rows = rows[rm[a[0]:a[1]] == 1]
+    lr = (1e-3, 2e-3, 3e-3, 4e-3, 5e-3, 6e-3)
+    step = 7
+    api.masked_adam_step(P, G, M, V, a, step, lr, row_mask=row_mask)
+    torch.cuda.synchronize()
+    names = api.GaussianTensors.NAMES
+    lrs = {"means": lr[0], "log_scales": lr[1], "quats": lr[2], "opacity_logit": lr[3]}
+    np_ = lambda T: {k: to_np(getattr(T, k)).astype(np.float64) for k in names}
+    p0, g0, m0, v0 = np_(P0), np_(G), np_(M0), np_(V0)
+    for k in names:
+        if k == "sh":
+            continue
+        rP, rM, rV = oracle.adam_step({k: p0[k]}, {k: g0[k]}, {k: m0[k]}, {k: v0[k]}, step, lrs, rows=rows)
+        got = to_np(getattr(P, k)).astype(np.float64)
+        step_size = np.abs(rP[k][..., rows] - p0[k][..., rows])
+        ulp = np.spacing(np.abs(rP[k][..., rows]).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(got[..., rows] - rP[k][..., rows]) <= 1e-6 * step_size + ulp), k
+        np.testing.assert_allclose(to_np(getattr(M, k))[..., rows], rM[k][..., rows], rtol=1e-6, atol=1e-12)
+        np.testing.assert_allclose(to_np(getattr(V, k))[..., rows], rV[k][..., rows], rtol=1e-6, atol=1e-15)
+    # sh: degree-0 rows with lr[4], the rest with lr[5]
+    for kk, lr_k in ((slice(0, 1), lr[4]), (slice(1, K), lr[5])):
+        if kk.start >= K:
+            continue
+        rP, _, _ = oracle.adam_step({"s": p0["sh"][kk]}, {"s": g0["sh"][kk]}, {"s": m0["sh"][kk]},
+                                    {"s": v0["sh"][kk]}, step, {"s": lr_k}, rows=rows)
+        got = to_np(P.sh).astype(np.float64)[kk]
+        step_size = np.abs(rP["s"][..., rows] - p0["sh"][kk][..., rows])
+        ulp = np.spacing(np.abs(rP["s"][..., rows]).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(got[..., rows] - rP["s"][..., rows]) <= 1e-6 * step_size + ulp)
+    # every other row is bit-for-bit untouched
+    frozen = np.ones(n, bool)
+    frozen[rows] = False
+    for T1, T0 in ((P, P0), (M, M0), (V, V0)):
+        for k in names:
+            np.testing.assert_array_equal(to_np(getattr(T1, k))[..., frozen], to_np(getattr(T0, k))[..., frozen])
