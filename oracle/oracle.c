@@ -93,6 +93,29 @@ void orc_sh_basis(const double d[3], double Y[16]) {
   Y[15] = SH_C3A * x * (x * x - 3.0 * y * y);
 }
 
+/* Magnitude of each basis polynomial above: its constant times the sum of the absolute
+ * values of its monomials.  A float32 evaluation of Y_k can be wrong by a few ulp of
+ * this magnitude (cancellation near the zeros of Y_k); it scales the error bounds. */
+static void sh_basis_mag(const double d[3], double M[16]) {
+  const double x = fabs(d[0]), y = fabs(d[1]), z = fabs(d[2]);
+  M[0] = SH_C0;
+  M[1] = SH_C1 * y;
+  M[2] = SH_C1 * z;
+  M[3] = SH_C1 * x;
+  M[4] = SH_C2A * x * y;
+  M[5] = SH_C2A * y * z;
+  M[6] = SH_C2B * (3.0 * z * z + 1.0);
+  M[7] = SH_C2A * x * z;
+  M[8] = SH_C2C * (x * x + y * y);
+  M[9] = SH_C3A * y * (3.0 * x * x + y * y);
+  M[10] = SH_C3B * x * y * z;
+  M[11] = SH_C3C * y * (5.0 * z * z + 1.0);
+  M[12] = SH_C3D * z * (5.0 * z * z + 3.0);
+  M[13] = SH_C3C * x * (5.0 * z * z + 1.0);
+  M[14] = SH_C3E * z * (x * x + y * y);
+  M[15] = SH_C3A * x * (x * x + 3.0 * y * y);
+}
+
 /* Gradient of each basis polynomial above with respect to (x, y, z), as written. */
 static void sh_basis_grad(const double d[3], double G[16][3]) {
   const double x = d[0], y = d[1], z = d[2];
@@ -548,7 +571,7 @@ int orc_render(int64_t n, int sh_degree, const double *means, const double *log_
  * Gaussian i to its raw parameters: means(3), log_scales(3), quats(4), opacity
  * logit(1), sh[k][ch] (3K), written to out[]. */
 static void backward_one(const scene_t *sc, int64_t i, const cam_t *cam, const gstate_t *g, const double d2[9],
-                         double *out) {
+                         double *out, int magnitude) {
   const int64_t n = sc->n;
   const int K = (sc->sh_degree + 1) * (sc->sh_degree + 1);
   const int P = 11 + 3 * K;
@@ -559,7 +582,7 @@ static void backward_one(const scene_t *sc, int64_t i, const cam_t *cam, const g
   /* colour -> SH coefficients and view direction */
   {
     double Yb[16], dY[16][3];
-    orc_sh_basis(g->dir, Yb);
+    if (magnitude) sh_basis_mag(g->dir, Yb); else orc_sh_basis(g->dir, Yb);
     sh_basis_grad(g->dir, dY);
     double ddir[3] = {0, 0, 0};
     for (int ch = 0; ch < 3; ++ch) {
@@ -665,7 +688,8 @@ static void backward_one(const scene_t *sc, int64_t i, const cam_t *cam, const g
 /*
  * grads[n][P] = chain rule of grad2d[n][9] (P = 11 + 3K raw parameters per Gaussian).
  * If s2d and s_raw are given, s_raw[n][P] = |Jac| s2d, an upper bound on the sum of
- * absolute per-pixel terms of each raw-parameter gradient.
+ * absolute per-pixel terms of each raw-parameter gradient (with each SH basis value
+ * replaced by its monomial magnitude, which bounds its float32 evaluation error).
  */
 int orc_preprocess_backward(int64_t n, int sh_degree, const double *means, const double *log_scales,
                             const double *quats, const double *opac, const double *sh, const double *camv,
@@ -679,7 +703,7 @@ int orc_preprocess_backward(int64_t n, int sh_degree, const double *means, const
   for (int64_t i = 0; i < n; ++i) {
     gstate_t g;
     project_one(&sc, i, &cam, &g);
-    backward_one(&sc, i, &cam, &g, grad2d + 9 * i, grads + (int64_t)P * i);
+    backward_one(&sc, i, &cam, &g, grad2d + 9 * i, grads + (int64_t)P * i, 0);
     if (s2d && s_raw) {
       double col[59];
       double *sr = s_raw + (int64_t)P * i;
@@ -687,7 +711,7 @@ int orc_preprocess_backward(int64_t n, int sh_degree, const double *means, const
       for (int c = 0; c < 9; ++c) {
         double e[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         e[c] = 1.0;
-        backward_one(&sc, i, &cam, &g, e, col);
+        backward_one(&sc, i, &cam, &g, e, col, 1);
         for (int k = 0; k < P; ++k) sr[k] += fabs(col[k]) * s2d[9 * i + c];
       }
     }

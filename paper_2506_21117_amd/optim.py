@@ -74,13 +74,39 @@ class SplatOptimizer:
         c[C_STICKY] = 0
         return flag
 
-    def step(self, view: int, stream=None):
+    def step_timed(self, view: int, events, stream=None):
+        """``step`` with the two events recorded around the forward render call on
+        the step's stream."""
+        self.step(view, stream, events)
+
+    def render_stats(self):
+        """Work of the last step's forward render: rendered tiles and pixels, pairs,
+        records each tile must read (the largest contributor count of its pixels) and
+        (pixel, record) evaluations (sum of contributor counts)."""
+        c = self.bins.read_counters()
+        W, H = self.cams[0].width, self.cams[0].height
+        TX, TY = api.tile_grid(W, H)
+        tiles = self.bins.tile_list[:c["tiles"]].long()
+        nc = torch.zeros(1, TY * 16, TX * 16, dtype=torch.int64, device=self.nc.device)
+        nc[:, :H, :W] = self.nc.long()
+        per_tile = nc.reshape(TY, 16, TX, 16).permute(0, 2, 1, 3).reshape(TY * TX, 256)[tiles]
+        inside = torch.zeros(TY * 16, TX * 16, dtype=torch.bool, device=nc.device)
+        inside[:H, :W] = True
+        pix = inside.reshape(TY, 16, TX, 16).permute(0, 2, 1, 3).reshape(TY * TX, 256)[tiles].sum()
+        return {"tiles": c["tiles"], "tiles_total": TX * TY, "pairs": c["pairs"], "pixels": int(pix),
+                "records": int(per_tile.max(dim=1).values.sum()), "pixel_records": int(per_tile.sum())}
+
+    def step(self, view: int, stream=None, events=None):
         cam = [self.cams[view]]
         a = self.active
         api.zero_grads(self.grads, a, stream)
         api.project_preprocess(self.params, cam, self.proj, stream=stream)
         api.bin_and_sort(self.proj, cam, a, self.local, self.bins, stream=stream)
+        if events is not None:
+            events[0].record(stream)
         api.render_forward(self.proj, self.bins, cam, self.bg, self.image, self.T, self.nc, stream=stream)
+        if events is not None:
+            events[1].record(stream)
         api.l1_loss_grad(self.image, self.targets[view:view + 1], self.bins, cam, self.dL, self.loss_sum,
                          stream=stream)
         api.render_backward(self.params, self.proj, self.bins, cam, self.bg, a, self.T, self.nc, self.dL, self.grads,

@@ -277,7 +277,8 @@ def test_gradients_accumulate(dev):
     torch.cuda.synchronize()
     for k in api.GaussianTensors.NAMES:
         a, b = to_np(getattr(g1, k)), to_np(getattr(g2, k))
-        np.testing.assert_allclose(b, 2 * a, rtol=1e-5, atol=1e-9)
+        # the two runs sum their float atomics in different orders
+        np.testing.assert_allclose(b, 2 * a, rtol=1e-4, atol=1e-6 * np.abs(a).max())
     api.zero_grads(g2, (100, 200))
     torch.cuda.synchronize()
     assert np.all(to_np(g2.means)[:, 100:200] == 0) and np.any(to_np(g2.means)[:, 200:] != 0)
@@ -335,32 +336,45 @@ def test_masked_adam_parity(dev, sh_degree, with_mask):
         rows = rows[rm[a[0]:a[1]] == 1]
     lr = (1e-3, 2e-3, 3e-3, 4e-3, 5e-3, 6e-3)
     step = 7
-    api.masked_adam_step(P, G, M, V, a, step, lr, row_mask=row_mask)
+    b1, b2, eps = 0.9, 0.999, 1e-15
+    api.masked_adam_step(P, G, M, V, a, step, lr, beta1=b1, beta2=b2, eps=eps, row_mask=row_mask)
     torch.cuda.synchronize()
     names = api.GaussianTensors.NAMES
-    lrs = {"means": lr[0], "log_scales": lr[1], "quats": lr[2], "opacity_logit": lr[3]}
     np_ = lambda T: {k: to_np(getattr(T, k)).astype(np.float64) for k in names}
     p0, g0, m0, v0 = np_(P0), np_(G), np_(M0), np_(V0)
+    e32 = float(np.finfo(np.float32).eps)
+    bc1, bc2 = 1 - b1 ** step, 1 - b2 ** step
+
+    def check(key, p, g, m, v, lr_k, got_p, got_m, got_v):
+        rP, rM, rV = oracle.adam_step({"x": p}, {"x": g}, {"x": m}, {"x": v}, step, {"x": lr_k}, b1, b2, eps,
+                                      rows=rows)
+        sl = (Ellipsis, rows)
+        # float32 rounding of the moment updates (cancellation in b m + (1 - b) g) ...
+        err_m = 4 * e32 * (b1 * np.abs(m[sl]) + (1 - b1) * np.abs(g[sl]))
+        err_v = 4 * e32 * (b2 * v[sl] + (1 - b2) * g[sl] ** 2)
+        np.testing.assert_array_less(np.abs(got_m[sl] - rM["x"][sl]), err_m + 1e-30)
+        np.testing.assert_array_less(np.abs(got_v[sl] - rV["x"][sl]), err_v + 1e-30)
+        # ... carried through the step: d/dm and d/dv of lr mhat / (sqrt(vhat) + eps)
+        sv = np.sqrt(rV["x"][sl] / bc2)
+        step_ = lr_k * (rM["x"][sl] / bc1) / (sv + eps)
+        dm = lr_k / bc1 / (sv + eps)
+        dv = np.abs(step_) / (sv + eps) / (2 * np.maximum(sv, 1e-30)) / bc2
+        ulp = np.spacing(np.abs(rP["x"][sl]).astype(np.float32)).astype(np.float64)
+        tol = 1e-6 * np.abs(step_) + dm * err_m + dv * err_v + ulp
+        err = np.abs(got_p[sl] - rP["x"][sl])
+        assert np.all(err <= tol), (key, float((err / tol).max()))
+
+    gp, gm, gv = np_(P), np_(M), np_(V)
+    lrs = {"means": lr[0], "log_scales": lr[1], "quats": lr[2], "opacity_logit": lr[3]}
     for k in names:
-        if k == "sh":
-            continue
-        rP, rM, rV = oracle.adam_step({k: p0[k]}, {k: g0[k]}, {k: m0[k]}, {k: v0[k]}, step, lrs, rows=rows)
-        got = to_np(getattr(P, k)).astype(np.float64)
-        step_size = np.abs(rP[k][..., rows] - p0[k][..., rows])
-        ulp = np.spacing(np.abs(rP[k][..., rows]).astype(np.float32)).astype(np.float64)
-        assert np.all(np.abs(got[..., rows] - rP[k][..., rows]) <= 1e-6 * step_size + ulp), k
-        np.testing.assert_allclose(to_np(getattr(M, k))[..., rows], rM[k][..., rows], rtol=1e-6, atol=1e-12)
-        np.testing.assert_allclose(to_np(getattr(V, k))[..., rows], rV[k][..., rows], rtol=1e-6, atol=1e-15)
+        if k != "sh":
+            check(k, p0[k], g0[k], m0[k], v0[k], lrs[k], gp[k], gm[k], gv[k])
     # sh: degree-0 rows with lr[4], the rest with lr[5]
     for kk, lr_k in ((slice(0, 1), lr[4]), (slice(1, K), lr[5])):
         if kk.start >= K:
             continue
-        rP, _, _ = oracle.adam_step({"s": p0["sh"][kk]}, {"s": g0["sh"][kk]}, {"s": m0["sh"][kk]},
-                                    {"s": v0["sh"][kk]}, step, {"s": lr_k}, rows=rows)
-        got = to_np(P.sh).astype(np.float64)[kk]
-        step_size = np.abs(rP["s"][..., rows] - p0["sh"][kk][..., rows])
-        ulp = np.spacing(np.abs(rP["s"][..., rows]).astype(np.float32)).astype(np.float64)
-        assert np.all(np.abs(got[..., rows] - rP["s"][..., rows]) <= 1e-6 * step_size + ulp)
+        check(f"sh{kk}", p0["sh"][kk], g0["sh"][kk], m0["sh"][kk], v0["sh"][kk], lr_k, gp["sh"][kk], gm["sh"][kk],
+              gv["sh"][kk])
     # every other row is bit-for-bit untouched
     frozen = np.ones(n, bool)
     frozen[rows] = False
