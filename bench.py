@@ -29,6 +29,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=1_000_000, help="Gaussians (default: the 1M workload)")
     ap.add_argument("--no-full", action="store_true", help="skip the full-scene comparison")
+    ap.add_argument("--only-full", action="store_true", help="time only the full-scene step (profiling)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
     ap.add_argument("--cpu-pixels", type=int, default=1024)
     return ap.parse_args()
@@ -98,6 +99,10 @@ def main():
         stats = opt.render_stats()
         return dt, fwd_ms, stats, opt
 
+    if args.only_full:
+        t_full, k_full, st_full, _ = run(False)
+        log(f"full: {args.steps / t_full:.1f} it/s, render_forward {k_full:.3f} ms, {st_full}")
+        return 0
     t_local, k_local, st_local, opt_local = run(True)
     it_local = args.steps / t_local
     log(f"local: {it_local:.1f} it/s, render_forward {k_local:.3f} ms, {st_local}")

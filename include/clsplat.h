@@ -177,11 +177,15 @@ typedef struct clsp_bins {
 
 /* Adam hyper-parameters (host).  lr per group: 0 means, 1 log_scales, 2 quats,
  * 3 opacity_logit, 4 sh degree-0 rows (k = 0), 5 higher sh rows (k >= 1).  step is the
- * 1-based step count used in the bias corrections. */
+ * 1-based step count used in the bias corrections.  When step_device (device int32[1])
+ * is not NULL the kernel reads the step count from there instead (and `step` is
+ * ignored), so a captured graph can replay the call while the caller advances the
+ * counter on the device. */
 typedef struct clsp_adam_hparams {
   float lr[6];
   float beta1, beta2, eps;
   int32_t step;
+  const int32_t *step_device;
 } clsp_adam_hparams;
 
 /* Library version string and the last error message of the calling host thread. */
@@ -221,10 +225,20 @@ clsp_status clsp_bin_and_sort(const clsp_projected *proj, int64_t n, const clsp_
  * unmasked tiles do no work).  bg: host float[3] background colour.  Writes image,
  * T_final and n_contrib (1 + position, within the tile's list, of the last Gaussian
  * blended at the pixel; 0 if none) for the pixels of rendered tiles only; other pixels
- * are left as they were. */
+ * are left as they were.
+ * state (nullable, device, clsp_render_state_bytes(n_views, width, height) bytes)
+ * receives the compositing state the backward needs: for each rendered tile (in
+ * tile_list order) the largest n_contrib of its pixels and, per pixel, the
+ * transmittance and the colour added by each chunk of CLSP_STATE_CHUNK consecutive
+ * list entries (at most CLSP_STATE_CHUNKS chunks; the last takes the remainder).  It
+ * lets the backward process the chunks of a tile in parallel.  Pass NULL when no
+ * backward follows. */
+#define CLSP_STATE_CHUNK 128
+#define CLSP_STATE_CHUNKS 8
+size_t clsp_render_state_bytes(int32_t n_views, int32_t width, int32_t height);
 clsp_status clsp_render_forward(const clsp_projected *proj, const clsp_bins *bins, const clsp_camera *cams,
                                 int32_t n_views, const float *bg, float *image, float *T_final, uint32_t *n_contrib,
-                                clsp_stream stream);
+                                void *state, size_t state_bytes, clsp_stream stream);
 
 /* ---------------------------------------------------------------------------------
  * L1 photometric loss gradient on the rendered tiles: dL_dimage = sign(image - target)
@@ -242,14 +256,19 @@ clsp_status clsp_l1_loss_grad(const float *image, const float *target, const cls
  * gradients for the Gaussians in `active` only, then the chain rule to raw parameters
  * runs for `active` only.  Gradients are ADDED to `grads` (layout of clsp_params,
  * n_rows = n, rows outside `active` never written).  g must be the parameters the
- * projection was made from; T_final and n_contrib come from clsp_render_forward.
+ * projection was made from; T_final, n_contrib and state (required here) come from the
+ * clsp_render_forward call on the same bins.  Each tile's list is split into the
+ * chunks of the forward's state and every (tile, chunk) is processed by its own
+ * workgroup, back to front from that chunk's stored transmittance and the colour of
+ * the chunks behind it.
  * ws: device workspace of clsp_render_backward_workspace_bytes(active.end -
  * active.begin, n_views) bytes. */
 size_t clsp_render_backward_workspace_bytes(int64_t n_active, int32_t n_views);
 clsp_status clsp_render_backward(const clsp_gaussians *g, const clsp_projected *proj, const clsp_bins *bins,
                                  const clsp_camera *cams, int32_t n_views, const float *bg, clsp_range active,
-                                 const float *T_final, const uint32_t *n_contrib, const float *dL_dimage,
-                                 const clsp_params *grads, void *ws, size_t ws_bytes, clsp_stream stream);
+                                 const float *T_final, const uint32_t *n_contrib, const void *state,
+                                 size_t state_bytes, const float *dL_dimage, const clsp_params *grads, void *ws,
+                                 size_t ws_bytes, clsp_stream stream);
 
 /* ---------------------------------------------------------------------------------
  * Masked Adam (Supp. "3DGS Optimization in Changed Regions": gradients and optimiser

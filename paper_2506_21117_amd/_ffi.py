@@ -18,7 +18,8 @@ C_PAIRS, C_OVERFLOW, C_TILES, C_WRITTEN, C_ENTRIES, C_STICKY = 0, 1, 2, 3, 4, 5
 
 EXPORTED = (
     "clsp_version", "clsp_last_error", "clsp_project_preprocess", "clsp_bin_and_sort_workspace_bytes",
-    "clsp_bin_and_sort", "clsp_render_forward", "clsp_l1_loss_grad", "clsp_render_backward_workspace_bytes",
+    "clsp_bin_and_sort", "clsp_render_state_bytes", "clsp_render_forward", "clsp_l1_loss_grad",
+    "clsp_render_backward_workspace_bytes",
     "clsp_render_backward", "clsp_masked_adam_step", "clsp_zero_grads",
 )
 
@@ -53,7 +54,8 @@ class Bins(ctypes.Structure):
 
 
 class AdamHParams(ctypes.Structure):
-    _fields_ = [("lr", c_float * 6), ("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("step", c_int32)]
+    _fields_ = [("lr", c_float * 6), ("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("step", c_int32),
+                ("step_device", c_void_p)]
 
 
 _lib = None
@@ -86,9 +88,11 @@ def load(path: Path | None = None):
     L.clsp_bin_and_sort.restype = st
     L.clsp_bin_and_sort.argtypes = [POINTER(Projected), c_int64, POINTER(Camera), c_int32, Range, c_int32,
                                     POINTER(Bins), c_void_p, c_size_t, c_void_p]
+    L.clsp_render_state_bytes.restype = c_size_t
+    L.clsp_render_state_bytes.argtypes = [c_int32, c_int32, c_int32]
     L.clsp_render_forward.restype = st
     L.clsp_render_forward.argtypes = [POINTER(Projected), POINTER(Bins), POINTER(Camera), c_int32, POINTER(c_float),
-                                      c_void_p, c_void_p, c_void_p, c_void_p]
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     L.clsp_l1_loss_grad.restype = st
     L.clsp_l1_loss_grad.argtypes = [c_void_p, c_void_p, POINTER(Bins), POINTER(Camera), c_int32, c_void_p, c_void_p,
                                     c_void_p]
@@ -96,8 +100,8 @@ def load(path: Path | None = None):
     L.clsp_render_backward_workspace_bytes.argtypes = [c_int64, c_int32]
     L.clsp_render_backward.restype = st
     L.clsp_render_backward.argtypes = [POINTER(Gaussians), POINTER(Projected), POINTER(Bins), POINTER(Camera), c_int32,
-                                       POINTER(c_float), Range, c_void_p, c_void_p, c_void_p, POINTER(Params),
-                                       c_void_p, c_size_t, c_void_p]
+                                       POINTER(c_float), Range, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p,
+                                       POINTER(Params), c_void_p, c_size_t, c_void_p]
     L.clsp_masked_adam_step.restype = st
     L.clsp_masked_adam_step.argtypes = [POINTER(Params), POINTER(Params), POINTER(Params), POINTER(Params), Range,
                                         c_void_p, POINTER(AdamHParams), c_void_p]

@@ -221,7 +221,16 @@ def bin_and_sort(proj: ProjectedBuffers, cams, active=None, use_mask=False, bins
     return bins
 
 
-def render_forward(proj, bins, cams, bg=(0.0, 0.0, 0.0), image=None, T_final=None, n_contrib=None, stream=None):
+def render_state(cams, device):
+    """Device buffer for the forward's compositing state (needed by the backward)."""
+    b = lib().clsp_render_state_bytes(len(cams), cams[0].width, cams[0].height)
+    return torch.empty(max(1, b), dtype=torch.uint8, device=device)
+
+
+def render_forward(proj, bins, cams, bg=(0.0, 0.0, 0.0), image=None, T_final=None, n_contrib=None, state=None,
+                   stream=None):
+    """Returns (image, T_final, n_contrib).  ``state`` (from ``render_state``) is
+    filled when given; pass it to ``render_backward``."""
     V, H, W = len(cams), cams[0].height, cams[0].width
     dev = proj.splat.device
     if image is None:
@@ -235,7 +244,8 @@ def render_forward(proj, bins, cams, bg=(0.0, 0.0, 0.0), image=None, T_final=Non
             raise ValueError(f"output of shape {tuple(t.shape)}, expected contiguous {shape}")
     bgc = (ctypes.c_float * 3)(*[float(x) for x in bg])
     check(lib().clsp_render_forward(ctypes.byref(proj.struct()), ctypes.byref(bins.struct()), camera_array(cams), V, bgc,
-                                    _ptr(image), _ptr(T_final), _ptr(n_contrib), _stream(stream)))
+                                    _ptr(image), _ptr(T_final), _ptr(n_contrib), _ptr(state),
+                                    0 if state is None else state.numel(), _stream(stream)))
     return image, T_final, n_contrib
 
 
@@ -254,15 +264,18 @@ def render_backward_workspace(n_active, views, device):
     return torch.empty(max(1, b), dtype=torch.uint8, device=device)
 
 
-def render_backward(g: GaussianTensors, proj, bins, cams, bg, active, T_final, n_contrib, dL, grads: GaussianTensors,
-                    ws=None, stream=None):
+def render_backward(g: GaussianTensors, proj, bins, cams, bg, active, T_final, n_contrib, state, dL,
+                    grads: GaussianTensors, ws=None, stream=None):
+    """Adds the gradients of the Gaussians in ``active`` to ``grads``; ``T_final``,
+    ``n_contrib`` and ``state`` come from the ``render_forward`` call on ``bins``."""
     a0, a1 = (0, g.n) if active is None else (int(active[0]), int(active[1]))
     if ws is None:
         ws = render_backward_workspace(a1 - a0, len(cams), g.means.device)
     bgc = (ctypes.c_float * 3)(*[float(x) for x in bg])
     check(lib().clsp_render_backward(ctypes.byref(g.as_gaussians()), ctypes.byref(proj.struct()),
                                      ctypes.byref(bins.struct()), camera_array(cams), len(cams), bgc,
-                                     _ffi.Range(a0, a1), _ptr(T_final), _ptr(n_contrib), _ptr(dL),
+                                     _ffi.Range(a0, a1), _ptr(T_final), _ptr(n_contrib), _ptr(state),
+                                     0 if state is None else state.numel(), _ptr(dL),
                                      ctypes.byref(grads.as_params()), _ptr(ws), ws.numel(), _stream(stream)))
     return grads
 
@@ -278,11 +291,17 @@ DEFAULT_LR = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3, 2.5e-3 / 20.0)
 
 
 def masked_adam_step(params: GaussianTensors, grads, exp_avg, exp_avg_sq, active, step, lr=DEFAULT_LR, beta1=0.9,
-                     beta2=0.999, eps=1e-15, row_mask=None, stream=None):
+                     beta2=0.999, eps=1e-15, row_mask=None, stream=None, step_device=None):
+    """``step`` (host int) or ``step_device`` (int32 device tensor [1]) gives the 1-based
+    step count of the bias corrections."""
     a0, a1 = (0, params.n) if active is None else (int(active[0]), int(active[1]))
     hp = _ffi.AdamHParams()
     hp.lr = (ctypes.c_float * 6)(*[float(x) for x in lr])
-    hp.beta1, hp.beta2, hp.eps, hp.step = float(beta1), float(beta2), float(eps), int(step)
+    hp.beta1, hp.beta2, hp.eps, hp.step = float(beta1), float(beta2), float(eps), int(step or 0)
+    if step_device is not None:
+        if step_device.dtype != torch.int32 or step_device.numel() != 1 or not step_device.is_cuda:
+            raise ValueError("step_device must be an int32 CUDA tensor of one element")
+        hp.step_device = step_device.data_ptr()
     if row_mask is not None and (row_mask.dtype != torch.uint8 or row_mask.numel() != params.n):
         raise ValueError("row_mask must be uint8 [N]")
     check(lib().clsp_masked_adam_step(ctypes.byref(params.as_params()), ctypes.byref(grads.as_params()),

@@ -3,8 +3,8 @@
 ``render(params..., cameras, bg, mode)`` returns images [V, 3, H, W] and differentiates
 with respect to the five raw parameter tensors.  In ``"recompute"`` mode the forward
 keeps only its inputs; the backward re-runs preprocess, binning and the forward render
-to rebuild the per-pixel compositing state (final transmittance and contributor count)
-and then runs the backward kernels — nothing of size pixels x views or pairs survives
+to rebuild the per-pixel compositing state (final transmittance, contributor count and
+the per-chunk state of the tile lists) and then runs the backward kernels — nothing of size pixels x views or pairs survives
 between the two passes.  ``"stored"`` keeps that state instead.
 
 All kernels run through the C-ABI on the current stream.
@@ -56,7 +56,8 @@ class RenderFunction(torch.autograd.Function):
                                 quats.detach().contiguous(), opacity_logit.detach().contiguous(),
                                 sh.detach().contiguous(), sh_degree)
         proj, bins = _RENDERER.project_and_bin(g, cams)
-        image, T, nc = api.render_forward(proj, bins, cams, bg)
+        state = api.render_state(cams, g.means.device) if mode == "stored" else None
+        image, T, nc = api.render_forward(proj, bins, cams, bg, state=state)
         ctx.cams, ctx.bg, ctx.sh_degree, ctx.mode = cams, bg, sh_degree, mode
         if mode == "stored":
             # keep private copies of the compositing state and the depth lists
@@ -65,7 +66,7 @@ class RenderFunction(torch.autograd.Function):
                          api.BinBuffers(bins.values.clone(), bins.keys.clone(), bins.ranges.clone(),
                                         bins.tile_mask.clone(), bins.tile_list.clone(), bins.counters.clone(),
                                         bins.ws[:1], bins.capacity, bins.n, bins.views, bins.width, bins.height),
-                         T, nc)
+                         T, nc, state)
         else:
             ctx.state = None
         ctx.save_for_backward(*g.tensors())
@@ -78,11 +79,12 @@ class RenderFunction(torch.autograd.Function):
         cams = ctx.cams
         if ctx.state is None:
             proj, bins = _RENDERER.project_and_bin(g, cams)
-            _, T, nc = api.render_forward(proj, bins, cams, ctx.bg)
+            state = api.render_state(cams, g.means.device)
+            _, T, nc = api.render_forward(proj, bins, cams, ctx.bg, state=state)
         else:
-            proj, bins, T, nc = ctx.state
+            proj, bins, T, nc, state = ctx.state
         grads = g.zeros_like()
-        api.render_backward(g, proj, bins, cams, ctx.bg, None, T, nc, grad_image.contiguous(), grads)
+        api.render_backward(g, proj, bins, cams, ctx.bg, None, T, nc, state, grad_image.contiguous(), grads)
         ctx.state = None
         return (grads.means, grads.log_scales, grads.quats, grads.opacity_logit, grads.sh, None, None, None, None)
 

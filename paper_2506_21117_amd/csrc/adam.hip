@@ -12,7 +12,8 @@ namespace {
 struct AdamConst {
   float lr[6];
   float b1, b2, eps;
-  float bc1, bc2;  // 1 - beta^step
+  float bc1, bc2;             // 1 - beta^step (host step count)
+  const int32_t* step_dev;    // device step count, or null
 };
 
 __device__ __forceinline__ void adam_one(float* p, const float* g, float* m, float* v, float lr, const AdamConst& h) {
@@ -29,6 +30,11 @@ __global__ void __launch_bounds__(256) adam_kernel(MutParams P, MutParams Gr, Mu
   const int64_t i = a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a1) return;
   if (row_mask && !row_mask[i]) return;
+  if (h.step_dev) {
+    const float t = (float)max(*h.step_dev, 1);
+    h.bc1 = 1.0f - powf(h.b1, t);
+    h.bc2 = 1.0f - powf(h.b2, t);
+  }
   const int64_t n = P.n;
   for (int c = 0; c < 3; ++c) adam_one(P.means + c * n + i, Gr.means + c * n + i, M.means + c * n + i, V.means + c * n + i, h.lr[0], h);
   for (int c = 0; c < 3; ++c)
@@ -67,6 +73,7 @@ hipError_t launch_adam(const MutParams& p, const MutParams& g, const MutParams& 
   h.eps = hp.eps;
   h.bc1 = (float)(1.0 - pow((double)hp.beta1, (double)hp.step));
   h.bc2 = (float)(1.0 - pow((double)hp.beta2, (double)hp.step));
+  h.step_dev = hp.step_device;
   hipLaunchKernelGGL(adam_kernel, dim3(ceil_div(a1 - a0, 256)), dim3(256), 0, s, p, g, m, v, a0, a1, row_mask, h);
   return hipGetLastError();
 }

@@ -386,29 +386,156 @@ __global__ void check_capacity_kernel(uint32_t* counters, uint64_t capacity) {
   if (over) counters[C_STICKY] = 1u;
 }
 
-__global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ order, const uint32_t* __restrict__ offs,
-                                                  const uint2* __restrict__ rect, const uint32_t* __restrict__ mask,
-                                                  const uint32_t* __restrict__ counters, int64_t n, int TX, int T,
-                                                  int wpv, int use_mask, uint32_t* __restrict__ pk,
-                                                  uint32_t* __restrict__ pv) {
+// Pairs staged in LDS per round of the masked emission.
+constexpr int EMIT_WIN = 4096;
+// Mask words kept in LDS by the masked emission (all views of the call).
+constexpr int EMIT_MASK_WORDS = 4096;
+
+// Full mode: every tile of every rectangle is a pair.  A block takes NT consecutive
+// entries of the depth order; their pairs form one contiguous output range, which the
+// block's threads fill position by position (consecutive threads, consecutive
+// positions): the owner entry of a position is found by binary search over the NT
+// offsets in LDS and its tile follows from the position inside the rectangle.  Every
+// thread does the same work whatever the rectangle sizes, and every store is coalesced.
+__global__ void __launch_bounds__(NT) emit_full_kernel(const uint32_t* __restrict__ order,
+                                                       const uint32_t* __restrict__ offs,
+                                                       const uint2* __restrict__ rect,
+                                                       const uint32_t* __restrict__ counters, int64_t n, int TX,
+                                                       int T, uint32_t* __restrict__ pk, uint32_t* __restrict__ pv) {
+  __shared__ uint32_t s_off[NT];
+  __shared__ uint32_t s_e[NT];
+  __shared__ uint32_t s_org[NT];   // global tile of the rectangle's first tile
+  __shared__ uint32_t s_w[NT];     // rectangle width
+  __shared__ float s_iw[NT];       // 1 / width
   if (counters[C_OVERFLOW]) return;
   const uint32_t m = counters[C_ENTRIES];
-  for (uint32_t j = blockIdx.x * NT + threadIdx.x; j < m; j += gridDim.x * NT) {
-    const uint32_t e = order[j];
-    const uint32_t v = (uint32_t)(e / n);
-    const uint2 r = rect[e];
-    const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
-    uint32_t o = offs[j];
-    const uint32_t* vm = mask + (int64_t)v * wpv;
-    const uint32_t gbase = v * (uint32_t)T;
-    for (uint32_t ty = y0; ty < y1; ++ty)
-      for (uint32_t tx = x0; tx < x1; ++tx) {
-        const uint32_t t = ty * TX + tx;
-        if (use_mask && !((vm[t >> 5] >> (t & 31)) & 1u)) continue;
-        pk[o] = gbase + t;
-        pv[o] = e;
+  const uint32_t P = counters[C_PAIRS];
+  for (uint32_t j0 = blockIdx.x * NT; j0 < m; j0 += gridDim.x * NT) {
+    const uint32_t j = j0 + threadIdx.x;
+    const uint32_t cnt = min((uint32_t)NT, m - j0);
+    __syncthreads();
+    if (j < m) {
+      const uint32_t e = order[j];
+      const uint2 r = rect[e];
+      const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu;
+      const uint32_t w = x1 - x0;
+      s_off[threadIdx.x] = offs[j];
+      s_e[threadIdx.x] = e;
+      s_org[threadIdx.x] = (uint32_t)(e / n) * (uint32_t)T + y0 * TX + x0;
+      s_w[threadIdx.x] = w;
+      s_iw[threadIdx.x] = 1.0f / (float)(w > 0 ? w : 1);
+    }
+    __syncthreads();
+    const uint32_t base = s_off[0];
+    const uint32_t end = j0 + NT < m ? offs[j0 + NT] : P;
+    for (uint32_t pos = base + threadIdx.x; pos < end; pos += NT) {
+      // owner: the last entry whose offset is <= pos (entries with no pairs are skipped
+      // naturally because the next entry has the same offset)
+      uint32_t lo = 0, hi = cnt;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_off[mid] <= pos) lo = mid; else hi = mid;
+      }
+      const uint32_t r = pos - s_off[lo];
+      const uint32_t w = s_w[lo];
+      uint32_t row = (uint32_t)((float)r * s_iw[lo]);
+      if (row * w > r) --row;
+      else if ((row + 1) * w <= r) ++row;
+      pk[pos] = s_org[lo] + row * TX + (r - row * w);
+      pv[pos] = s_e[lo];
+    }
+  }
+}
+
+// Masked mode: each thread walks the masked tiles of its rectangle row by row (set
+// bits of the LDS copy of the mask, so the cost follows the masked tiles, not the
+// rectangle's area) and stages its pairs in an LDS window that the block writes out
+// with coalesced stores.
+template <bool LDS_MASK>
+__global__ void __launch_bounds__(NT) emit_masked_kernel(const uint32_t* __restrict__ order,
+                                                         const uint32_t* __restrict__ offs,
+                                                         const uint32_t* __restrict__ cnt_sorted,
+                                                         const uint2* __restrict__ rect,
+                                                         const uint32_t* __restrict__ mask,
+                                                         const uint32_t* __restrict__ counters, int64_t n, int TX,
+                                                         int T, int wpv, int views, uint32_t* __restrict__ pk,
+                                                         uint32_t* __restrict__ pv) {
+  __shared__ uint32_t s_k[EMIT_WIN];
+  __shared__ uint32_t s_v[EMIT_WIN];
+  __shared__ uint32_t s_mask[LDS_MASK ? EMIT_MASK_WORDS : 1];
+  if (counters[C_OVERFLOW]) return;
+  if (LDS_MASK) {
+    for (int w = threadIdx.x; w < views * wpv; w += NT) s_mask[w] = mask[w];
+    __syncthreads();
+  }
+  const uint32_t m = counters[C_ENTRIES];
+  const uint32_t P = counters[C_PAIRS];
+  for (uint32_t j0 = blockIdx.x * NT; j0 < m; j0 += gridDim.x * NT) {
+    const uint32_t j = j0 + threadIdx.x;
+    const uint32_t base = offs[j0];
+    const uint32_t last = min(j0 + NT, m);
+    const uint32_t end = last < m ? offs[last] : P;
+    uint32_t o = 0, o_end = 0, e = 0, x0 = 0, x1 = 0, y1 = 0, ty = 0, gbase = 0, bits = 0, wcur = 0, wlast = 0;
+    const uint32_t* vm = LDS_MASK ? s_mask : mask;
+    if (j < m) {
+      e = order[j];
+      o = offs[j];
+      o_end = o + cnt_sorted[j];
+      const uint32_t v = (uint32_t)(e / n);
+      const uint2 r = rect[e];
+      x0 = r.x & 0xffffu;
+      x1 = r.x >> 16;
+      ty = r.y & 0xffffu;
+      y1 = r.y >> 16;
+      vm += (int64_t)v * wpv;
+      gbase = v * (uint32_t)T;
+      // first row's first word, restricted to [x0, x1)
+      wcur = (ty * TX + x0) >> 5;
+      wlast = (ty * TX + x1 - 1) >> 5;
+      bits = 0;
+    }
+    // bits of word wcur of row ty that lie in the rectangle and the mask
+    auto row_word = [&](uint32_t w) -> uint32_t {
+      const uint32_t lo = ty * TX + x0, hi = ty * TX + x1;  // tiles [lo, hi) of this row
+      uint32_t b = vm[w];
+      const uint32_t wlo = w << 5;
+      if (wlo < lo) b &= ~0u << (lo - wlo);
+      if (wlo + 32 > hi) b &= (hi - wlo >= 32) ? ~0u : ((1u << (hi - wlo)) - 1u);
+      return b;
+    };
+    if (j < m && o < o_end) bits = row_word(wcur);
+    for (uint32_t win = base; win < end; win += EMIT_WIN) {
+      const uint32_t win_end = min(win + (uint32_t)EMIT_WIN, end);
+      while (o < o_end && o < win_end) {
+        // advance to the next set bit (the count guarantees one exists; the row bound
+        // only stops a walk that could otherwise leave the rectangle)
+        while (bits == 0 && ty < y1) {
+          if (wcur < wlast) {
+            ++wcur;
+          } else {
+            if (++ty >= y1) break;
+            wcur = (ty * TX + x0) >> 5;
+            wlast = (ty * TX + x1 - 1) >> 5;
+          }
+          bits = row_word(wcur);
+        }
+        if (bits == 0) {
+          o = o_end;
+          break;
+        }
+        const uint32_t b = __ffs(bits) - 1;
+        bits &= bits - 1;
+        s_k[o - win] = gbase + (wcur << 5) + b;
+        s_v[o - win] = e;
         ++o;
       }
+      __syncthreads();
+      for (uint32_t p = threadIdx.x; p < win_end - win; p += NT) {
+        pk[win + p] = s_k[p];
+        pv[win + p] = s_v[p];
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -604,8 +731,16 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
     const int tpasses = passes_for(p.tile_bits);
     uint32_t* ek = (tpasses % 2 == 0) ? bins.keys : pairK;
     uint32_t* ev = (tpasses % 2 == 0) ? bins.values : pairV;
-    hipLaunchKernelGGL(emit_kernel, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, spare, rect, bins.tile_mask,
-                       counters, n, p.TX, p.T, wpv, use_mask, ek, ev);
+    if (!use_mask) {
+      hipLaunchKernelGGL(emit_full_kernel, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, spare, rect, counters,
+                         n, p.TX, p.T, ek, ev);
+    } else if ((int64_t)V * wpv <= EMIT_MASK_WORDS) {
+      hipLaunchKernelGGL(emit_masked_kernel<true>, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, spare, tmp,
+                         rect, bins.tile_mask, counters, n, p.TX, p.T, wpv, V, ek, ev);
+    } else {
+      hipLaunchKernelGGL(emit_masked_kernel<false>, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, spare, tmp,
+                         rect, bins.tile_mask, counters, n, p.TX, p.T, wpv, V, ek, ev);
+    }
     // 6. stable sort by global tile
     if (tpasses > 0) {
       uint32_t *k0 = ek, *v0 = ev, *k1 = (ek == bins.keys) ? pairK : bins.keys, *v1 = (ev == bins.values) ? pairV : bins.values;

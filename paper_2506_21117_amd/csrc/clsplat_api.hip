@@ -183,17 +183,26 @@ clsp_status clsp_bin_and_sort(const clsp_projected* proj, int64_t n, const clsp_
                     "bin_and_sort");
 }
 
+size_t clsp_render_state_bytes(int32_t n_views, int32_t width, int32_t height) {
+  if (n_views < 1 || width < 1 || height < 1) return 0;
+  return clsp::render_state_bytes(n_views, (width + CLSP_TILE - 1) / CLSP_TILE, (height + CLSP_TILE - 1) / CLSP_TILE);
+}
+
 clsp_status clsp_render_forward(const clsp_projected* proj, const clsp_bins* bins, const clsp_camera* cams,
                                 int32_t n_views, const float* bg, float* image, float* T_final, uint32_t* n_contrib,
-                                clsp_stream stream) {
+                                void* state, size_t state_bytes, clsp_stream stream) {
   CHECK(check_projected(proj));
   CHECK(check_bins(bins));
   CHECK(check_cams(cams, n_views));
   if (!bg || !image || !T_final || !n_contrib) return fail(CLSP_ERR_INVALID_ARG, "render_forward output or bg is NULL");
   const int W = cams[0].width, H = cams[0].height;
+  if (state && state_bytes < clsp_render_state_bytes(n_views, W, H))
+    return fail(CLSP_ERR_INVALID_ARG, "state of %zu bytes is smaller than the %zu needed", state_bytes,
+                clsp_render_state_bytes(n_views, W, H));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return hip_status(clsp::launch_render_forward(*proj, *bins, n_views, W, H, (W + CLSP_TILE - 1) / CLSP_TILE,
-                                                (H + CLSP_TILE - 1) / CLSP_TILE, bg, image, T_final, n_contrib, s),
+                                                (H + CLSP_TILE - 1) / CLSP_TILE, bg, image, T_final, n_contrib,
+                                                state, s),
                     "render_forward");
 }
 
@@ -216,8 +225,9 @@ size_t clsp_render_backward_workspace_bytes(int64_t n_active, int32_t n_views) {
 
 clsp_status clsp_render_backward(const clsp_gaussians* g, const clsp_projected* proj, const clsp_bins* bins,
                                  const clsp_camera* cams, int32_t n_views, const float* bg, clsp_range active,
-                                 const float* T_final, const uint32_t* n_contrib, const float* dL_dimage,
-                                 const clsp_params* grads, void* ws, size_t ws_bytes, clsp_stream stream) {
+                                 const float* T_final, const uint32_t* n_contrib, const void* state,
+                                 size_t state_bytes, const float* dL_dimage, const clsp_params* grads, void* ws,
+                                 size_t ws_bytes, clsp_stream stream) {
   CHECK(check_gaussians(g));
   if (g->gather) return fail(CLSP_ERR_INVALID_ARG, "render_backward needs un-gathered parameters");
   CHECK(check_projected(proj));
@@ -228,6 +238,9 @@ clsp_status clsp_render_backward(const clsp_gaussians* g, const clsp_projected* 
   if (grads->n != g->n || grads->sh_degree != g->sh_degree)
     return fail(CLSP_ERR_INVALID_ARG, "grads layout differs from the parameters");
   if (!bg || !T_final || !n_contrib || !dL_dimage) return fail(CLSP_ERR_INVALID_ARG, "render_backward input is NULL");
+  if (!state || state_bytes < clsp_render_state_bytes(n_views, cams[0].width, cams[0].height))
+    return fail(CLSP_ERR_INVALID_ARG, "render_backward needs the forward's state (%zu bytes)",
+                clsp_render_state_bytes(n_views, cams[0].width, cams[0].height));
   const int64_t na = active.end - active.begin;
   const size_t need = clsp_render_backward_workspace_bytes(na, n_views);
   if (na > 0 && (!ws || ws_bytes < need))
@@ -238,7 +251,8 @@ clsp_status clsp_render_backward(const clsp_gaussians* g, const clsp_projected* 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   float* g2d = static_cast<float*>(ws);
   CHECK(hip_status(clsp::launch_render_backward(*proj, *bins, n_views, g->n, W, H, TX, TY, bg, active.begin,
-                                                active.end, T_final, n_contrib, dL_dimage, g2d, s),
+                                                active.end, T_final, n_contrib, const_cast<void*>(state), dL_dimage,
+                                                g2d, s),
                    "render_backward"));
   const clsp::RawParams rp = raw_params(g);
   const clsp::MutParams gm = mut_params(grads);
@@ -262,7 +276,7 @@ clsp_status clsp_masked_adam_step(const clsp_params* params, const clsp_params* 
       exp_avg->sh_degree != params->sh_degree || exp_avg_sq->sh_degree != params->sh_degree)
     return fail(CLSP_ERR_INVALID_ARG, "params, grads and moments differ in layout");
   CHECK(check_range(active, n));
-  if (hp->step < 1) return fail(CLSP_ERR_INVALID_ARG, "step must be >= 1");
+  if (!hp->step_device && hp->step < 1) return fail(CLSP_ERR_INVALID_ARG, "step must be >= 1");
   if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f && hp->beta2 >= 0.f && hp->beta2 < 1.f && hp->eps >= 0.f))
     return fail(CLSP_ERR_INVALID_ARG, "invalid Adam betas or eps");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);

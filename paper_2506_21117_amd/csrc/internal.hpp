@@ -82,14 +82,15 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
                                const clsp_bins& bins, char* ws, hipStream_t s);
 
 // render.hip
+size_t render_state_bytes(int views, int TX, int TY);
 hipError_t launch_render_forward(const clsp_projected& proj, const clsp_bins& bins, int views, int W, int H,
                                  int TX, int TY, const float bg[3], float* image, float* T_final,
-                                 uint32_t* n_contrib, hipStream_t s);
+                                 uint32_t* n_contrib, void* state, hipStream_t s);
 hipError_t launch_l1_loss_grad(const float* image, const float* target, const clsp_bins& bins, int views, int W,
                                int H, int TX, int TY, float* dL, float* loss_sum, hipStream_t s);
 hipError_t launch_render_backward(const clsp_projected& proj, const clsp_bins& bins, int views, int64_t n, int W,
                                   int H, int TX, int TY, const float bg[3], int64_t a0, int64_t a1,
-                                  const float* T_final, const uint32_t* n_contrib, const float* dL,
+                                  const float* T_final, const uint32_t* n_contrib, void* state, const float* dL,
                                   float* grad2d, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 

@@ -35,6 +35,25 @@ __device__ __forceinline__ bool splat_alpha(const float4 a, const float4 b, floa
   return alpha >= ALPHA_MIN;
 }
 
+// Compositing state per rendered tile slot: the largest contributor count of its pixels,
+// then per (chunk, pixel) the transmittance after the chunk and the chunk's colour.
+struct StateView {
+  uint32_t* maxlast;   // [slots]
+  float4* chunks;      // [slots][CHUNKS][256]
+};
+
+__host__ __device__ inline size_t state_header_bytes(int64_t slots) { return ((size_t)slots * 4 + 255) & ~(size_t)255; }
+
+__device__ __forceinline__ StateView state_view(void* base, int64_t slots) {
+  StateView v;
+  v.maxlast = reinterpret_cast<uint32_t*>(base);
+  v.chunks = reinterpret_cast<float4*>(reinterpret_cast<char*>(base) + state_header_bytes(slots));
+  return v;
+}
+
+constexpr int CH = CLSP_STATE_CHUNK;
+constexpr int CHUNKS = CLSP_STATE_CHUNKS;
+
 __global__ void __launch_bounds__(NT) render_forward_kernel(const float* __restrict__ splat,
                                                             const uint32_t* __restrict__ values,
                                                             const uint2* __restrict__ ranges,
@@ -42,11 +61,13 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(const float* __restr
                                                             const uint32_t* __restrict__ counters, int T, int TX,
                                                             int W, int H, float bg0, float bg1, float bg2,
                                                             float* __restrict__ image, float* __restrict__ T_final,
-                                                            uint32_t* __restrict__ n_contrib) {
+                                                            uint32_t* __restrict__ n_contrib, void* state,
+                                                            int64_t slots) {
   if (blockIdx.x >= counters[C_TILES]) return;
   __shared__ float4 s_a[NT];
   __shared__ float4 s_b[NT];
   __shared__ float s_c[NT];
+  __shared__ uint32_t s_max;
   const uint32_t gt = tile_list[blockIdx.x];
   const int v = gt / T, t = gt % T;
   const int px = (t % TX) * TILE + (threadIdx.x & 15);
@@ -55,8 +76,14 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(const float* __restr
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
   const uint2 rg = ranges[gt];
   const int total = (int)(rg.y - rg.x);
+  const bool keep = state != nullptr;
+  StateView sv;
+  if (keep) sv = state_view(state, slots);
+  float4* my_chunks = keep ? sv.chunks + (size_t)blockIdx.x * CHUNKS * NT + threadIdx.x : nullptr;
 
-  float Tr = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+  float Tr = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;   // colour of the flushed chunks
+  float dr = 0.0f, dg = 0.0f, db = 0.0f;              // colour of the current chunk
+  int chunk = 0;
   uint32_t last = 0;
   bool done = !inside;
   for (int base = 0; base < total; base += NT) {
@@ -70,26 +97,49 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(const float* __restr
       s_c[threadIdx.x] = sp[2].x;
     }
     __syncthreads();
-    if (!done) {
-      const int cnt = min(NT, total - base);
-      for (int j = 0; j < cnt; ++j) {
-        const float4 a = s_a[j], b = s_b[j];
-        float dx, dy, G, alpha;
-        bool clamped;
-        if (!splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped)) continue;
-        const float Tn = Tr * (1.0f - alpha);
-        if (Tn < T_STOP) {
-          done = true;
-          break;
+    const int cnt = min(NT, total - base);
+    for (int half = 0; half < NT / CH; ++half) {
+      const int jhi = min(cnt, (half + 1) * CH);
+      if (!done) {
+        for (int j = half * CH; j < jhi; ++j) {
+          const float4 a = s_a[j], b = s_b[j];
+          float dx, dy, G, alpha;
+          bool clamped;
+          if (!splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped)) continue;
+          const float Tn = Tr * (1.0f - alpha);
+          if (Tn < T_STOP) {
+            done = true;
+            break;
+          }
+          const float w = alpha * Tr;
+          dr = fmaf(w, b.z, dr);
+          dg = fmaf(w, b.w, dg);
+          db = fmaf(w, s_c[j], db);
+          Tr = Tn;
+          last = (uint32_t)(base + j + 1);
         }
-        const float w = alpha * Tr;
-        cr = fmaf(w, b.z, cr);
-        cg = fmaf(w, b.w, cg);
-        cb = fmaf(w, s_c[j], cb);
-        Tr = Tn;
-        last = (uint32_t)(base + j + 1);
+      }
+      // a chunk boundary of the tile's list: record this pixel's state
+      if (base + (half + 1) * CH <= total && chunk < CHUNKS - 1) {
+        if (keep) my_chunks[(size_t)chunk * NT] = make_float4(Tr, dr, dg, db);
+        cr += dr;
+        cg += dg;
+        cb += db;
+        dr = dg = db = 0.0f;
+        ++chunk;
       }
     }
+  }
+  if (keep) my_chunks[(size_t)chunk * NT] = make_float4(Tr, dr, dg, db);
+  cr += dr;
+  cg += dg;
+  cb += db;
+  if (keep) {
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    atomicMax(&s_max, last);
+    __syncthreads();
+    if (threadIdx.x == 0) sv.maxlast[blockIdx.x] = s_max;
   }
   if (inside) {
     const size_t hw = (size_t)H * W;
@@ -149,20 +199,31 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
   return v;
 }
 
+// One workgroup per (rendered tile, chunk of its list): reverse traversal of the
+// chunk's entries from the chunk's stored end state.
 __global__ void __launch_bounds__(NT) render_backward_kernel(
     const float* __restrict__ splat, const uint32_t* __restrict__ values, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ tile_list, const uint32_t* __restrict__ counters, int T, int TX, int W, int H,
     int64_t n, float bg0, float bg1, float bg2, int64_t a0, int64_t a1, const float* __restrict__ T_final,
-    const uint32_t* __restrict__ n_contrib, const float* __restrict__ dL, float* __restrict__ grad2d) {
-  if (blockIdx.x >= counters[C_TILES]) return;
+    const uint32_t* __restrict__ n_contrib, void* state, int64_t slots, const float* __restrict__ dL,
+    float* __restrict__ grad2d) {
+  const uint32_t slot = blockIdx.x;
+  if (slot >= counters[C_TILES]) return;
+  const StateView sv = state_view(state, slots);
+  const int maxlast = (int)sv.maxlast[slot];
+  const int chunk = blockIdx.y;
+  const int k0 = chunk * CH;
+  if (k0 >= maxlast) return;
+  const int last_chunk = min(CHUNKS - 1, (maxlast - 1) / CH);
+  const int k1 = (chunk == last_chunk) ? maxlast : (chunk + 1) * CH;
+
   __shared__ float4 s_a[NT];
   __shared__ float4 s_b[NT];
   __shared__ float s_c[NT];
   __shared__ uint32_t s_e[NT];
   __shared__ float s_g[NT][9];
-  __shared__ uint32_t s_max;
 
-  const uint32_t gt = tile_list[blockIdx.x];
+  const uint32_t gt = tile_list[slot];
   const int v = gt / T, t = gt % T;
   const int px = (t % TX) * TILE + (threadIdx.x & 15);
   const int py = (t / TX) * TILE + (threadIdx.x >> 4);
@@ -174,26 +235,32 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
 
   float Tr = 1.0f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
   uint32_t last = 0;
+  float Tfin = 1.0f;
   if (inside) {
-    Tr = T_final[(size_t)v * hw + pix];
+    Tfin = T_final[(size_t)v * hw + pix];
     last = n_contrib[(size_t)v * hw + pix];
     g0 = dL[((size_t)v * 3 + 0) * hw + pix];
     g1 = dL[((size_t)v * 3 + 1) * hw + pix];
     g2 = dL[((size_t)v * 3 + 2) * hw + pix];
   }
-  // colour of everything behind the current record (starts with the background)
-  float S0 = Tr * bg0, S1 = Tr * bg1, S2 = Tr * bg2;
-  if (threadIdx.x == 0) s_max = 0;
-  __syncthreads();
-  atomicMax(&s_max, last);
-  __syncthreads();
-  const int maxlast = (int)s_max;
+  // state at the end of this chunk: transmittance, and the colour of everything behind
+  // it (later chunks plus the background)
+  const float4* my_chunks = sv.chunks + (size_t)slot * CHUNKS * NT + threadIdx.x;
+  float S0 = Tfin * bg0, S1 = Tfin * bg1, S2 = Tfin * bg2;
+  for (int c = last_chunk; c > chunk; --c) {
+    const float4 st = my_chunks[(size_t)c * NT];
+    S0 += st.y;
+    S1 += st.z;
+    S2 += st.w;
+  }
+  Tr = (chunk == last_chunk) ? Tfin : my_chunks[(size_t)chunk * NT].x;
+
   const int64_t na = a1 - a0;
   const int64_t vbase = (int64_t)v * n;
   const uint32_t lane = threadIdx.x & 63;
 
-  for (int end = maxlast; end > 0; end -= NT) {
-    const int beg = end > NT ? end - NT : 0;
+  for (int end = k1; end > k0; end -= NT) {
+    const int beg = max(k0, end - NT);
     const int cnt = end - beg;
     __syncthreads();
     if ((int)threadIdx.x < cnt) {
@@ -268,14 +335,19 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
 
 }  // namespace
 
+size_t render_state_bytes(int views, int TX, int TY) {
+  const int64_t slots = (int64_t)views * TX * TY;
+  return state_header_bytes(slots) + (size_t)slots * CHUNKS * NT * sizeof(float4);
+}
+
 hipError_t launch_render_forward(const clsp_projected& proj, const clsp_bins& bins, int views, int W, int H, int TX,
                                  int TY, const float bg[3], float* image, float* T_final, uint32_t* n_contrib,
-                                 hipStream_t s) {
+                                 void* state, hipStream_t s) {
   const int T = TX * TY;
   const int blocks = views * T;
   hipLaunchKernelGGL(render_forward_kernel, dim3(blocks), dim3(NT), 0, s, proj.splat, bins.values,
                      reinterpret_cast<const uint2*>(bins.ranges), bins.tile_list, bins.counters, T, TX, W, H, bg[0],
-                     bg[1], bg[2], image, T_final, n_contrib);
+                     bg[1], bg[2], image, T_final, n_contrib, state, (int64_t)blocks);
   return hipGetLastError();
 }
 
@@ -289,14 +361,14 @@ hipError_t launch_l1_loss_grad(const float* image, const float* target, const cl
 
 hipError_t launch_render_backward(const clsp_projected& proj, const clsp_bins& bins, int views, int64_t n, int W,
                                   int H, int TX, int TY, const float bg[3], int64_t a0, int64_t a1,
-                                  const float* T_final, const uint32_t* n_contrib, const float* dL, float* grad2d,
-                                  hipStream_t s) {
+                                  const float* T_final, const uint32_t* n_contrib, void* state, const float* dL,
+                                  float* grad2d, hipStream_t s) {
   const int T = TX * TY;
   hipError_t err = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, (a1 - a0) * views * G2D_STRIDE, s);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(render_backward_kernel, dim3(views * T), dim3(NT), 0, s, proj.splat, bins.values,
+  hipLaunchKernelGGL(render_backward_kernel, dim3(views * T, CHUNKS), dim3(NT), 0, s, proj.splat, bins.values,
                      reinterpret_cast<const uint2*>(bins.ranges), bins.tile_list, bins.counters, T, TX, W, H, n,
-                     bg[0], bg[1], bg[2], a0, a1, T_final, n_contrib, dL, grad2d);
+                     bg[0], bg[1], bg[2], a0, a1, T_final, n_contrib, state, (int64_t)views * T, dL, grad2d);
   return hipGetLastError();
 }
 

@@ -10,10 +10,12 @@ with no mask and every row active.
 """
 from __future__ import annotations
 
+import ctypes
+
 import torch
 
-from . import api
-from ._ffi import C_OVERFLOW, C_PAIRS, C_STICKY
+from . import _ffi, api
+from ._ffi import C_STICKY, check
 
 
 class SplatOptimizer:
@@ -42,6 +44,7 @@ class SplatOptimizer:
         self.dL = torch.zeros(1, 3, H, W, dtype=torch.float32, device=dev)
         self.loss_sum = torch.zeros(1, dtype=torch.float32, device=dev)
         self.bwd_ws = api.render_backward_workspace(self.active[1] - self.active[0], 1, dev)
+        self.state = api.render_state(self.cams[:1], dev)
         self.step_count = 0
         self.bins = None
         self._capacity = capacity
@@ -64,7 +67,30 @@ class SplatOptimizer:
             self.bins = api.BinBuffers.alloc(self.n, 1, self.cams[0].width, self.cams[0].height, cap,
                                              self.params.means.device)
         self.bins.counters.zero_()
+        self._prepare_calls()
         return need
+
+    def _prepare_calls(self):
+        """Build every ctypes argument of a step once (buffers never move)."""
+        a0, a1 = self.active
+        self._cams = [api.camera_array([c]) for c in self.cams]
+        self._g = self.params.as_gaussians()
+        self._pp = self.params.as_params()
+        self._gr = self.grads.as_params()
+        self._m = self.m.as_params()
+        self._v = self.v.as_params()
+        self._proj = self.proj.struct()
+        self._bins = self.bins.struct()
+        self._range = _ffi.Range(a0, a1)
+        self._bg = (ctypes.c_float * 3)(*self.bg)
+        self._hp = _ffi.AdamHParams()
+        self._hp.lr = (ctypes.c_float * 6)(*[float(x) for x in self.lr])
+        self._hp.beta1, self._hp.beta2, self._hp.eps = 0.9, 0.999, 1e-15
+        p = lambda t: ctypes.c_void_p(t.data_ptr())
+        self._ptrs = {"image": p(self.image), "T": p(self.T), "nc": p(self.nc), "dL": p(self.dL),
+                      "loss": p(self.loss_sum), "ws": p(self.bins.ws), "bws": p(self.bwd_ws), "state": p(self.state),
+                      "targets": [p(self.targets[v:v + 1]) for v in range(len(self.cams))]}
+        self._sizes = (self.bins.ws.numel(), self.bwd_ws.numel(), self.state.numel())
 
     def overflowed(self) -> bool:
         """True if any step since the last check ran out of pair capacity (sticky
@@ -77,7 +103,7 @@ class SplatOptimizer:
     def step_timed(self, view: int, events, stream=None):
         """``step`` with the two events recorded around the forward render call on
         the step's stream."""
-        self.step(view, stream, events)
+        self.step(view, stream if stream is not None else torch.cuda.current_stream(), events)
 
     def render_stats(self):
         """Work of the last step's forward render: rendered tiles and pixels, pairs,
@@ -97,19 +123,29 @@ class SplatOptimizer:
                 "records": int(per_tile.max(dim=1).values.sum()), "pixel_records": int(per_tile.sum())}
 
     def step(self, view: int, stream=None, events=None):
-        cam = [self.cams[view]]
-        a = self.active
-        api.zero_grads(self.grads, a, stream)
-        api.project_preprocess(self.params, cam, self.proj, stream=stream)
-        api.bin_and_sort(self.proj, cam, a, self.local, self.bins, stream=stream)
+        """One step on view ``view``: the C-ABI calls in order, all on ``stream``
+        (default: the current torch stream)."""
+        L = api.lib()
+        st = api._stream(stream)
+        cam = self._cams[view]
+        P = self._ptrs
+        by = ctypes.byref
+        use_mask = 1 if self.local else 0
+        check(L.clsp_zero_grads(by(self._gr), self._range, st))
+        check(L.clsp_project_preprocess(by(self._g), cam, 1, by(self._proj), st))
+        check(L.clsp_bin_and_sort(by(self._proj), self.n, cam, 1, self._range, use_mask, by(self._bins), P["ws"],
+                                  self._sizes[0], st))
         if events is not None:
             events[0].record(stream)
-        api.render_forward(self.proj, self.bins, cam, self.bg, self.image, self.T, self.nc, stream=stream)
+        check(L.clsp_render_forward(by(self._proj), by(self._bins), cam, 1, self._bg, P["image"], P["T"], P["nc"],
+                                    P["state"], self._sizes[2], st))
         if events is not None:
             events[1].record(stream)
-        api.l1_loss_grad(self.image, self.targets[view:view + 1], self.bins, cam, self.dL, self.loss_sum,
-                         stream=stream)
-        api.render_backward(self.params, self.proj, self.bins, cam, self.bg, a, self.T, self.nc, self.dL, self.grads,
-                            self.bwd_ws, stream=stream)
+        check(L.clsp_l1_loss_grad(P["image"], P["targets"][view], by(self._bins), cam, 1, P["dL"], P["loss"], st))
+        check(L.clsp_render_backward(by(self._g), by(self._proj), by(self._bins), cam, 1, self._bg, self._range, P["T"],
+                                     P["nc"], P["state"], self._sizes[2], P["dL"], by(self._gr), P["bws"],
+                                     self._sizes[1], st))
         self.step_count += 1
-        api.masked_adam_step(self.params, self.grads, self.m, self.v, a, self.step_count, self.lr, stream=stream)
+        self._hp.step = self.step_count
+        check(L.clsp_masked_adam_step(by(self._pp), by(self._gr), by(self._m), by(self._v), self._range, None,
+                                      by(self._hp), st))

@@ -47,7 +47,7 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(_ffi.Gaussians) == 6 * 8 + 8 + 8 + 4 + 4
     assert ctypes.sizeof(_ffi.Params) == 5 * 8 + 8 + 4 + 4
     assert ctypes.sizeof(_ffi.Bins) == 7 * 8
-    assert ctypes.sizeof(_ffi.AdamHParams) == 4 * 10
+    assert ctypes.sizeof(_ffi.AdamHParams) == 4 * 10 + 8
 
 
 def test_workspace_queries(L):
@@ -118,8 +118,15 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
     assert L.clsp_zero_grads(ctypes.byref(p), _ffi.Range(3, 2), None) == _ffi.CLSP_ERR_INVALID_ARG
     gathered = _ffi.Gaussians(fake, fake, fake, fake, fake, fake, 10, 10, 0, 0)
     assert L.clsp_render_backward(ctypes.byref(gathered), ctypes.byref(proj), ctypes.byref(bins), cam, 1,
-                                  (ctypes.c_float * 3)(0, 0, 0), _ffi.Range(0, 10), fake, fake, fake,
+                                  (ctypes.c_float * 3)(0, 0, 0), _ffi.Range(0, 10), fake, fake, fake, 1 << 30, fake,
                                   ctypes.byref(p), fake, 1 << 20, None) == _ffi.CLSP_ERR_INVALID_ARG
+    # the backward needs the forward's compositing state
+    g.n_rows, g.gather = 10, None
+    assert L.clsp_render_backward(ctypes.byref(g), ctypes.byref(proj), ctypes.byref(_ffi.Bins(fake, fake, fake, fake,
+                                  fake, fake, 100)), cam, 1, (ctypes.c_float * 3)(0, 0, 0), _ffi.Range(0, 10), fake,
+                                  fake, None, 0, fake, ctypes.byref(p), fake, 1 << 20, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert b"state" in L.clsp_last_error()
+    assert L.clsp_render_state_bytes(1, 64, 48) >= 12 * 8 * 256 * 16
 
 
 def test_missing_library_fails_loudly(tmp_path):

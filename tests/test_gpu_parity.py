@@ -245,12 +245,13 @@ def test_render_backward_parity(dev, case, local):
     g = api.GaussianTensors.from_scene(sc, dev)
     proj = gpu_preprocess(g, cams)
     bins = api.bin_and_sort(proj, cams, a, use_mask=local, capacity=400_000)
-    img, T, nc = api.render_forward(proj, bins, cams, bg)
+    state = api.render_state(cams, dev)
+    img, T, nc = api.render_forward(proj, bins, cams, bg, state=state)
     rng = np.random.default_rng(21)
     dl_np = rng.normal(size=img.shape).astype(np.float32)
     dl = torch.as_tensor(dl_np, device=dev)
     grads = g.zeros_like()
-    api.render_backward(g, proj, bins, cams, bg, a, T, nc, dl, grads)
+    api.render_backward(g, proj, bins, cams, bg, a, T, nc, state, dl, grads)
     torch.cuda.synchronize()
     # the reference sees the full image with the same upstream gradient: for the
     # changed Gaussians the local step must give the full-scene gradient
@@ -268,12 +269,13 @@ def test_gradients_accumulate(dev):
     g = api.GaussianTensors.from_scene(sc, dev)
     proj = gpu_preprocess(g, cams)
     bins = api.bin_and_sort(proj, cams, capacity=100_000)
-    img, T, nc = api.render_forward(proj, bins, cams)
+    state = api.render_state(cams, dev)
+    img, T, nc = api.render_forward(proj, bins, cams, state=state)
     dl = torch.randn_like(img)
     g1 = g.zeros_like()
-    api.render_backward(g, proj, bins, cams, (0, 0, 0), None, T, nc, dl, g1)
+    api.render_backward(g, proj, bins, cams, (0, 0, 0), None, T, nc, state, dl, g1)
     g2 = g1.clone()
-    api.render_backward(g, proj, bins, cams, (0, 0, 0), None, T, nc, dl, g2)
+    api.render_backward(g, proj, bins, cams, (0, 0, 0), None, T, nc, state, dl, g2)
     torch.cuda.synchronize()
     for k in api.GaussianTensors.NAMES:
         a, b = to_np(getattr(g1, k)), to_np(getattr(g2, k))
@@ -294,11 +296,12 @@ def test_local_step_equals_full_step_on_gpu(dev):
     out = {}
     for local in (False, True):
         bins = api.bin_and_sort(proj, cams, a if local else None, use_mask=local, capacity=4_000_000)
-        img, T, nc = api.render_forward(proj, bins, cams)
+        state = api.render_state(cams, dev)
+        img, T, nc = api.render_forward(proj, bins, cams, state=state)
         tgt = torch.rand_like(img, generator=torch.Generator(device=dev).manual_seed(5))
         dL = api.l1_loss_grad(img, tgt, bins, cams)
         grads = g.zeros_like()
-        api.render_backward(g, proj, bins, cams, (0, 0, 0), a if local else None, T, nc, dL, grads)
+        api.render_backward(g, proj, bins, cams, (0, 0, 0), a if local else None, T, nc, state, dL, grads)
         torch.cuda.synchronize()
         out[local] = (bins, to_np(img), grads)
     pix, tiles = masked_pixels(out[True][0], cams[0])
@@ -336,7 +339,9 @@ def test_masked_adam_parity(dev, sh_degree, with_mask):
         rows = rows[rm[a[0]:a[1]] == 1]
     lr = (1e-3, 2e-3, 3e-3, 4e-3, 5e-3, 6e-3)
     step = 7
-    b1, b2, eps = 0.9, 0.999, 1e-15
+    # the kernel receives float32 hyper-parameters; the reference gets the same values
+    b1, b2, eps = (float(np.float32(x)) for x in (0.9, 0.999, 1e-15))
+    lr = tuple(float(np.float32(x)) for x in lr)
     api.masked_adam_step(P, G, M, V, a, step, lr, beta1=b1, beta2=b2, eps=eps, row_mask=row_mask)
     torch.cuda.synchronize()
     names = api.GaussianTensors.NAMES
