@@ -149,30 +149,62 @@ typedef struct clsp_projected {
 #define CLSP_FLAG_CLAMP_Y 4u
 #define CLSP_FLAG_SHCLAMP_R 8u
 
-/* Per-tile depth-ordered lists (device).
- *   values    uint32[capacity]: entry index v*n + i of each (tile, Gaussian) pair,
- *             sorted by global tile, then depth key, then Gaussian index
- *   keys      uint32[capacity]: the global tile of each sorted pair
- *   ranges    uint32[n_views*T][2]: [start, end) of each tile's pairs; [0, 0) when a
- *             tile has none or is outside the render mask
+/* Per-tile depth-ordered lists (device buffers owned by the caller, plus host fields).
+ *
+ * A tile's list is every visible Gaussian whose tile rectangle contains the tile, in
+ * ascending (depth key, index) order.  Two ways to build it (`mode`):
+ *   CLSP_BINS_COMPLETE      clsp_bin_and_sort builds every rendered tile's full list.
+ *   CLSP_BINS_DEPTH_SLICED  clsp_bin_and_sort builds the lists of a first depth slab
+ *                           (the nearest 1/16 of the Gaussians that have pairs, at least
+ *                           16384 of them); clsp_render_forward renders it, then lists
+ *                           the remaining Gaussians only for tiles in which some pixel is
+ *                           still compositing, and continues those tiles.  Each list is
+ *                           then a prefix of the complete one that reaches at least as
+ *                           far as any pixel of the tile composites, so images and
+ *                           gradients are the same as with complete lists.
+ *   values    uint32[capacity]: entry index v*n + i of each (tile, Gaussian) pair
+ *   keys      uint32[capacity]: the global tile of each pair
+ *             Pairs [0, counters[7]) hold the first lists sorted by (global tile, depth,
+ *             index); in depth-sliced mode pairs [counters[7], counters[3]) hold the
+ *             second lists sorted the same way.
+ *   ranges    uint32[n_views*T][2]: [start, end) of each tile's first list
+ *   ranges2   uint32[n_views*T][2]: [start, end) of each tile's second list ([0, 0) in
+ *             complete mode); a tile's list is its first list followed by its second
  *   tile_mask uint32[n_views][ceil(T/32)]: bit (t % 32) of word t/32 of view v is set
  *             when tile t of view v is rendered
+ *   alive_mask uint32[n_views][ceil(T/32)]: tiles that needed the second list
  *   tile_list uint32[n_views*T]: the rendered global tiles, ascending
- *   counters  uint32[8]: [0] pairs needed P, [1] overflow (1 when P > capacity; then no
- *             list or range is valid, no tile is rendered, and the caller must grow
- *             `capacity` and call again), [2] number of rendered tiles, [3] pairs written
- *             (P, or 0 on overflow), [4] entries with at least one pair, [5] sticky
- *             overflow: set to 1 on overflow and never cleared by the library, so a
- *             caller can check once after many steps; [6], [7] reserved.  Slots 0-4 are
- *             rewritten by every call. */
+ *   counters  uint32[16]: [0] pairs needed P, [1] overflow (1 when P > capacity; then
+ *             the lists are not valid, tiles are not rendered or not finished, and the
+ *             caller must grow `capacity` and redo the binning and the forward),
+ *             [2] number of rendered tiles, [3] pairs written (P, or 0 on overflow),
+ *             [4] entries with at least one pair, [5] sticky overflow: set to 1 on
+ *             overflow and never cleared by the library, so a caller can check once after
+ *             many steps, [6] entries in the first slab, [7] pairs of the first lists,
+ *             [8] tiles that needed the second list; [9..15] reserved.  Slots other than
+ *             [5] are rewritten by every clsp_bin_and_sort call.
+ *   ws, ws_bytes: device workspace of clsp_bin_and_sort_workspace_bytes(...) bytes; it
+ *             belongs to these lists (the depth-sliced forward uses it too)
+ *   capacity: pairs the value and key buffers (and the workspace) hold
+ *   n:        Gaussians per view of the projection the lists are built from */
+#define CLSP_BINS_COMPLETE 0
+#define CLSP_BINS_DEPTH_SLICED 1
+#define CLSP_COUNTERS 16
 typedef struct clsp_bins {
   uint32_t *values;
   uint32_t *keys;
   uint32_t *ranges;
+  uint32_t *ranges2;
   uint32_t *tile_mask;
+  uint32_t *alive_mask;
   uint32_t *tile_list;
   uint32_t *counters;
+  void *ws;
+  size_t ws_bytes;
   int64_t capacity;
+  int64_t n;
+  int32_t mode;
+  int32_t reserved;
 } clsp_bins;
 
 /* Adam hyper-parameters (host).  lr per group: 0 means, 1 log_scales, 2 quats,
@@ -209,16 +241,16 @@ clsp_status clsp_project_preprocess(const clsp_gaussians *g, const clsp_camera *
  * Gaussian projects, reusing the projection for the per-tile depth ordering).
  * With use_mask != 0 the mask is the union of the tile rectangles of the visible
  * Gaussians in `active` and pairs are emitted only into masked tiles; with use_mask == 0
- * every tile is rendered.  Capacity overflow is reported on the device (counters[1]);
- * nothing is read back here.  ws: device workspace of at least
- * clsp_bin_and_sort_workspace_bytes(n, n_views, width, height, capacity) bytes.
- * Errors: as above, plus capacity not in 0..2^32-1, active outside [0, n],
- * workspace too small. */
+ * every tile is rendered.  bins->mode selects complete or depth-sliced lists (see
+ * clsp_bins); bins->n must equal the projection's n.  Capacity overflow is reported on
+ * the device (counters[1]); nothing is read back.
+ * Errors: as above, plus capacity not in 0..2^32-1, active outside [0, n], workspace
+ * smaller than clsp_bin_and_sort_workspace_bytes(n, n_views, width, height, capacity),
+ * unknown mode. */
 size_t clsp_bin_and_sort_workspace_bytes(int64_t n, int32_t n_views, int32_t width, int32_t height,
                                          int64_t capacity);
-clsp_status clsp_bin_and_sort(const clsp_projected *proj, int64_t n, const clsp_camera *cams, int32_t n_views,
-                              clsp_range active, int32_t use_mask, const clsp_bins *bins, void *ws, size_t ws_bytes,
-                              clsp_stream stream);
+clsp_status clsp_bin_and_sort(const clsp_projected *proj, const clsp_camera *cams, int32_t n_views, clsp_range active,
+                              int32_t use_mask, const clsp_bins *bins, clsp_stream stream);
 
 /* ---------------------------------------------------------------------------------
  * Forward rendering of the rendered tiles (Sec. 3.3 step 2; Supp. item 2: threads of
@@ -232,7 +264,9 @@ clsp_status clsp_bin_and_sort(const clsp_projected *proj, int64_t n, const clsp_
  * transmittance and the colour added by each chunk of CLSP_STATE_CHUNK consecutive
  * list entries (at most CLSP_STATE_CHUNKS chunks; the last takes the remainder).  It
  * lets the backward process the chunks of a tile in parallel.  Pass NULL when no
- * backward follows. */
+ * backward follows.  With depth-sliced bins this call also lists the second slab for
+ * the tiles that need it (using the bins' workspace) and finishes those tiles; `proj`
+ * must be the projection the bins were built from. */
 #define CLSP_STATE_CHUNK 128
 #define CLSP_STATE_CHUNKS 8
 size_t clsp_render_state_bytes(int32_t n_views, int32_t width, int32_t height);

@@ -14,7 +14,9 @@ CLSP_ERR_UNSUPPORTED = -4
 TILE = 16
 
 FLAG_VISIBLE, FLAG_CLAMP_X, FLAG_CLAMP_Y, FLAG_SHCLAMP_R = 1, 2, 4, 8
-C_PAIRS, C_OVERFLOW, C_TILES, C_WRITTEN, C_ENTRIES, C_STICKY = 0, 1, 2, 3, 4, 5
+C_PAIRS, C_OVERFLOW, C_TILES, C_WRITTEN, C_ENTRIES, C_STICKY, C_SLAB1, C_PAIRS1, C_ALIVE = 0, 1, 2, 3, 4, 5, 6, 7, 8
+N_COUNTERS = 16
+BINS_COMPLETE, BINS_DEPTH_SLICED = 0, 1
 
 EXPORTED = (
     "clsp_version", "clsp_last_error", "clsp_project_preprocess", "clsp_bin_and_sort_workspace_bytes",
@@ -49,8 +51,10 @@ class Projected(ctypes.Structure):
 
 
 class Bins(ctypes.Structure):
-    _fields_ = [("values", c_void_p), ("keys", c_void_p), ("ranges", c_void_p), ("tile_mask", c_void_p),
-                ("tile_list", c_void_p), ("counters", c_void_p), ("capacity", c_int64)]
+    _fields_ = [("values", c_void_p), ("keys", c_void_p), ("ranges", c_void_p), ("ranges2", c_void_p),
+                ("tile_mask", c_void_p), ("alive_mask", c_void_p), ("tile_list", c_void_p), ("counters", c_void_p),
+                ("ws", c_void_p), ("ws_bytes", c_size_t), ("capacity", c_int64), ("n", c_int64), ("mode", c_int32),
+                ("reserved", c_int32)]
 
 
 class AdamHParams(ctypes.Structure):
@@ -86,8 +90,8 @@ def load(path: Path | None = None):
     L.clsp_bin_and_sort_workspace_bytes.restype = c_size_t
     L.clsp_bin_and_sort_workspace_bytes.argtypes = [c_int64, c_int32, c_int32, c_int32, c_int64]
     L.clsp_bin_and_sort.restype = st
-    L.clsp_bin_and_sort.argtypes = [POINTER(Projected), c_int64, POINTER(Camera), c_int32, Range, c_int32,
-                                    POINTER(Bins), c_void_p, c_size_t, c_void_p]
+    L.clsp_bin_and_sort.argtypes = [POINTER(Projected), POINTER(Camera), c_int32, Range, c_int32, POINTER(Bins),
+                                    c_void_p]
     L.clsp_render_state_bytes.restype = c_size_t
     L.clsp_render_state_bytes.argtypes = [c_int32, c_int32, c_int32]
     L.clsp_render_forward.restype = st

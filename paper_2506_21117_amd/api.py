@@ -158,40 +158,48 @@ class ProjectedBuffers:
 
 @dataclass
 class BinBuffers:
-    values: torch.Tensor     # [capacity] int32 (entry index)
-    keys: torch.Tensor       # [capacity] int32 (global tile)
-    ranges: torch.Tensor     # [V*T, 2] int32
-    tile_mask: torch.Tensor  # [V, ceil(T/32)] int32
-    tile_list: torch.Tensor  # [V*T] int32
-    counters: torch.Tensor   # [8] int32
-    ws: torch.Tensor         # workspace bytes
+    values: torch.Tensor      # [capacity] int32 (entry index)
+    keys: torch.Tensor        # [capacity] int32 (global tile)
+    ranges: torch.Tensor      # [V*T, 2] int32, first lists
+    ranges2: torch.Tensor     # [V*T, 2] int32, second lists (depth-sliced mode)
+    tile_mask: torch.Tensor   # [V, ceil(T/32)] int32
+    alive_mask: torch.Tensor  # [V, ceil(T/32)] int32
+    tile_list: torch.Tensor   # [V*T] int32
+    counters: torch.Tensor    # [16] int32
+    ws: torch.Tensor          # workspace bytes
     capacity: int
     n: int
     views: int
     width: int
     height: int
+    mode: int = _ffi.BINS_DEPTH_SLICED
 
     @classmethod
-    def alloc(cls, n, views, width, height, capacity, device):
+    def alloc(cls, n, views, width, height, capacity, device, mode=_ffi.BINS_DEPTH_SLICED):
         TX, TY = tile_grid(width, height)
         T = TX * TY
         cap = max(1, int(capacity))
         wsb = lib().clsp_bin_and_sort_workspace_bytes(n, views, width, height, cap)
         i32 = lambda *s: torch.zeros(*s, dtype=torch.int32, device=device)
-        return cls(i32(cap), i32(cap), i32(views * T, 2), i32(views, (T + 31) // 32), i32(views * T), i32(8),
-                   torch.empty(max(1, wsb), dtype=torch.uint8, device=device), cap, n, views, width, height)
+        wpv = (T + 31) // 32
+        return cls(i32(cap), i32(cap), i32(views * T, 2), i32(views * T, 2), i32(views, wpv), i32(views, wpv),
+                   i32(views * T), i32(_ffi.N_COUNTERS), torch.empty(max(1, wsb), dtype=torch.uint8, device=device),
+                   cap, n, views, width, height, int(mode))
 
     def struct(self):
         b = _ffi.Bins()
-        b.values, b.keys, b.ranges = _ptr(self.values), _ptr(self.keys), _ptr(self.ranges)
-        b.tile_mask, b.tile_list, b.counters = _ptr(self.tile_mask), _ptr(self.tile_list), _ptr(self.counters)
-        b.capacity = self.capacity
+        b.values, b.keys, b.ranges, b.ranges2 = _ptr(self.values), _ptr(self.keys), _ptr(self.ranges), _ptr(self.ranges2)
+        b.tile_mask, b.alive_mask = _ptr(self.tile_mask), _ptr(self.alive_mask)
+        b.tile_list, b.counters = _ptr(self.tile_list), _ptr(self.counters)
+        b.ws, b.ws_bytes = _ptr(self.ws), self.ws.numel()
+        b.capacity, b.n, b.mode = self.capacity, self.n, self.mode
         return b
 
     def read_counters(self):
         c = self.counters.cpu().numpy().view(np.uint32)
         return {"pairs": int(c[_ffi.C_PAIRS]), "overflow": bool(c[_ffi.C_OVERFLOW]), "tiles": int(c[_ffi.C_TILES]),
-                "written": int(c[_ffi.C_WRITTEN]), "entries": int(c[_ffi.C_ENTRIES])}
+                "written": int(c[_ffi.C_WRITTEN]), "entries": int(c[_ffi.C_ENTRIES]), "slab1": int(c[_ffi.C_SLAB1]),
+                "pairs1": int(c[_ffi.C_PAIRS1]), "alive": int(c[_ffi.C_ALIVE])}
 
 
 # ------------------------------------------------------------------ calls
@@ -208,16 +216,19 @@ def project_preprocess(g: GaussianTensors, cams, out: ProjectedBuffers | None = 
 
 
 def bin_and_sort(proj: ProjectedBuffers, cams, active=None, use_mask=False, bins: BinBuffers | None = None,
-                 capacity=None, stream=None):
+                 capacity=None, mode=_ffi.BINS_DEPTH_SLICED, stream=None):
+    """Render mask and per-tile depth order.  With depth-sliced bins (the default) the
+    forward call completes the lists of the tiles that need more than the first slab."""
     n = proj.n
     a0, a1 = (0, n) if active is None else (int(active[0]), int(active[1]))
     if bins is None:
         cap = capacity if capacity is not None else max(1024, 64 * n * len(cams))
-        bins = BinBuffers.alloc(n, len(cams), cams[0].width, cams[0].height, cap, proj.splat.device)
+        bins = BinBuffers.alloc(n, len(cams), cams[0].width, cams[0].height, cap, proj.splat.device, mode)
+    if bins.n != n or bins.views != len(cams):
+        raise ValueError("bins sized for another projection")
     ca = camera_array(cams)
-    check(lib().clsp_bin_and_sort(ctypes.byref(proj.struct()), n, ca, len(cams), _ffi.Range(a0, a1),
-                                  1 if use_mask else 0, ctypes.byref(bins.struct()), _ptr(bins.ws), bins.ws.numel(),
-                                  _stream(stream)))
+    check(lib().clsp_bin_and_sort(ctypes.byref(proj.struct()), ca, len(cams), _ffi.Range(a0, a1), 1 if use_mask else 0,
+                                  ctypes.byref(bins.struct()), _stream(stream)))
     return bins
 
 

@@ -24,7 +24,9 @@ class _Renderer:
         self.proj = None
         self.bins = None
 
-    def project_and_bin(self, g, cams):
+    def render(self, g, cams, bg, state):
+        """Preprocess, depth-sliced binning and forward; grows the pair buffers and
+        renders again if they were too small."""
         dev = g.means.device
         key = (g.n, len(cams), cams[0].width, cams[0].height, str(dev))
         if key != self._key:
@@ -34,12 +36,13 @@ class _Renderer:
         api.project_preprocess(g, cams, self.proj)
         while True:
             if self.bins is None:
-                cap = max(1 << 20, 16 * g.n * len(cams))
+                cap = max(1 << 20, 4 * g.n * len(cams))
                 self.bins = api.BinBuffers.alloc(g.n, len(cams), cams[0].width, cams[0].height, cap, dev)
             api.bin_and_sort(self.proj, cams, None, False, self.bins)
+            out = api.render_forward(self.proj, self.bins, cams, bg, state=state)
             c = self.bins.read_counters()
             if not c["overflow"]:
-                return self.proj, self.bins
+                return self.proj, self.bins, out
             cap = int(c["pairs"] * 1.25) + 1024
             self.bins = api.BinBuffers.alloc(g.n, len(cams), cams[0].width, cams[0].height, cap, dev)
 
@@ -55,17 +58,17 @@ class RenderFunction(torch.autograd.Function):
         g = api.GaussianTensors(means.detach().contiguous(), log_scales.detach().contiguous(),
                                 quats.detach().contiguous(), opacity_logit.detach().contiguous(),
                                 sh.detach().contiguous(), sh_degree)
-        proj, bins = _RENDERER.project_and_bin(g, cams)
         state = api.render_state(cams, g.means.device) if mode == "stored" else None
-        image, T, nc = api.render_forward(proj, bins, cams, bg, state=state)
+        proj, bins, (image, T, nc) = _RENDERER.render(g, cams, bg, state)
         ctx.cams, ctx.bg, ctx.sh_degree, ctx.mode = cams, bg, sh_degree, mode
         if mode == "stored":
             # keep private copies of the compositing state and the depth lists
             ctx.state = (api.ProjectedBuffers(proj.splat.clone(), proj.depth.clone(), proj.rect.clone(),
                                               proj.flags.clone(), proj.n, proj.views),
                          api.BinBuffers(bins.values.clone(), bins.keys.clone(), bins.ranges.clone(),
-                                        bins.tile_mask.clone(), bins.tile_list.clone(), bins.counters.clone(),
-                                        bins.ws[:1], bins.capacity, bins.n, bins.views, bins.width, bins.height),
+                                        bins.ranges2.clone(), bins.tile_mask.clone(), bins.alive_mask.clone(),
+                                        bins.tile_list.clone(), bins.counters.clone(), bins.ws[:1], bins.capacity,
+                                        bins.n, bins.views, bins.width, bins.height, bins.mode),
                          T, nc, state)
         else:
             ctx.state = None
@@ -78,9 +81,8 @@ class RenderFunction(torch.autograd.Function):
         g = api.GaussianTensors(*tensors, ctx.sh_degree)
         cams = ctx.cams
         if ctx.state is None:
-            proj, bins = _RENDERER.project_and_bin(g, cams)
             state = api.render_state(cams, g.means.device)
-            _, T, nc = api.render_forward(proj, bins, cams, ctx.bg, state=state)
+            proj, bins, (_, T, nc) = _RENDERER.render(g, cams, ctx.bg, state)
         else:
             proj, bins, T, nc, state = ctx.state
         grads = g.zeros_like()

@@ -13,6 +13,11 @@
 //                are sorted instead of tile + 32 depth bits;
 //   7. ranges  : [start, end) per tile, and the compact list of tiles to render.
 // Every kernel reads its element count from device memory, so nothing is read back.
+//
+// Depth-sliced lists: steps 5-7 first run for the nearest slab of the depth order
+// only; after the forward pass has rendered it, they run again for the remaining
+// entries, emitting only into the tiles that still have compositing pixels (the
+// "alive" tiles), and the forward continues those tiles.
 #include "internal.hpp"
 
 namespace clsp {
@@ -28,7 +33,10 @@ constexpr int SCAN_CHUNK = NT * SCAN_ITEMS;
 constexpr int MAX_SCAN_BLOCKS = 1024;
 
 // Counter slots (see clsp_bins).
-constexpr int C_PAIRS = 0, C_OVERFLOW = 1, C_TILES = 2, C_WRITTEN = 3, C_ENTRIES = 4, C_STICKY = 5;
+constexpr int C_PAIRS = 0, C_OVERFLOW = 1, C_TILES = 2, C_WRITTEN = 3, C_ENTRIES = 4, C_STICKY = 5, C_SLAB1 = 6,
+              C_PAIRS1 = 7, C_ALIVE = 8;
+// scratch counter slots used while a slab is listed
+constexpr int C_SLAB_LO = 9, C_SLAB_N = 10, C_SLAB_PAIRS = 11, C_SLAB_BASE = 12;
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
@@ -230,11 +238,16 @@ __global__ void __launch_bounds__(NT) compact_kernel(const uint32_t* __restrict_
 }
 
 // ------------------------------------------------------------------ radix sort
+// All sort kernels work on keys[off + e], e < n, with n and off read from device memory.
+__device__ __forceinline__ uint32_t load_off(const uint32_t* p) { return p ? *p : 0u; }
+
 // Digit histogram of each block's span: hist[d * G + b].
 __global__ void __launch_bounds__(NT) rs_upsweep_kernel(const uint32_t* __restrict__ keys, const uint32_t* n_ptr,
-                                                        int shift, int bits, uint32_t* __restrict__ hist, int G) {
+                                                        const uint32_t* off_ptr, int shift, int bits,
+                                                        uint32_t* __restrict__ hist, int G) {
   __shared__ uint32_t h[4][256];
   const uint32_t n = *n_ptr;
+  keys += load_off(off_ptr);
   const int radix = 1 << bits;
   const uint32_t msk = (uint32_t)radix - 1u;
   for (int d = threadIdx.x; d < 4 * 256; d += NT) (&h[0][0])[d] = 0;
@@ -275,8 +288,8 @@ __global__ void __launch_bounds__(NT) rs_scan_kernel(uint32_t* __restrict__ hist
 __global__ void __launch_bounds__(NT) rs_downsweep_kernel(const uint32_t* __restrict__ kin,
                                                           const uint32_t* __restrict__ vin,
                                                           uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                          const uint32_t* n_ptr, int shift, int bits,
-                                                          const uint32_t* __restrict__ hist,
+                                                          const uint32_t* n_ptr, const uint32_t* off_ptr, int shift,
+                                                          int bits, const uint32_t* __restrict__ hist,
                                                           const uint32_t* __restrict__ tot, int G) {
   __shared__ uint32_t s_key[RS_CHUNK];
   __shared__ uint32_t s_val[RS_CHUNK];
@@ -287,6 +300,11 @@ __global__ void __launch_bounds__(NT) rs_downsweep_kernel(const uint32_t* __rest
   __shared__ uint32_t s4[4];
 
   const uint32_t n = *n_ptr;
+  const uint32_t off = load_off(off_ptr);
+  kin += off;
+  vin += off;
+  kout += off;
+  vout += off;
   uint32_t beg, end;
   block_span(n, G, blockIdx.x, RS_CHUNK, beg, end);
   if (beg >= end) return;
@@ -370,29 +388,72 @@ __global__ void __launch_bounds__(NT) rs_downsweep_kernel(const uint32_t* __rest
   }
 }
 
-// ------------------------------------------------------------------ 5. emission
-__global__ void __launch_bounds__(NT) gather_counts_kernel(const uint32_t* __restrict__ order,
-                                                           const uint32_t* __restrict__ cnt, const uint32_t* n_ptr,
-                                                           uint32_t* __restrict__ out) {
-  const uint32_t m = *n_ptr;
-  for (uint32_t j = blockIdx.x * NT + threadIdx.x; j < m; j += gridDim.x * NT) out[j] = cnt[order[j]];
+// ------------------------------------------------------------------ slabs of the depth order
+// counters[C_SLAB1] = entries of the first slab.
+__global__ void slab_bounds_kernel(uint32_t* counters, int sliced) {
+  const uint32_t m = counters[C_ENTRIES];
+  counters[C_SLAB1] = sliced ? min(m, max(m >> 4, 16384u)) : m;
 }
 
-__global__ void check_capacity_kernel(uint32_t* counters, uint64_t capacity) {
-  const uint32_t p = counters[C_PAIRS];
-  const bool over = (uint64_t)p > capacity;
+// Select slab `which` (1: [0, S1), 2: [S1, M)) of the depth order: its first sorted
+// entry, entry count and the first pair position.
+__global__ void slab_select_kernel(uint32_t* counters, int which) {
+  const uint32_t m = counters[C_ENTRIES], s1 = counters[C_SLAB1];
+  counters[C_SLAB_LO] = which == 1 ? 0u : s1;
+  // the second slab is listed only if some tile is still alive
+  counters[C_SLAB_N] = which == 1 ? s1 : (counters[C_ALIVE] ? m - s1 : 0u);
+  counters[C_SLAB_BASE] = which == 1 ? 0u : counters[C_PAIRS1];
+}
+
+// Pairs each slab entry emits: its count from the count pass (first slab) ...
+__global__ void __launch_bounds__(NT) gather_counts_kernel(const uint32_t* __restrict__ order,
+                                                           const uint32_t* __restrict__ cnt,
+                                                           const uint32_t* __restrict__ counters,
+                                                           uint32_t* __restrict__ out) {
+  const uint32_t lo = counters[C_SLAB_LO], m = counters[C_SLAB_N];
+  for (uint32_t j = blockIdx.x * NT + threadIdx.x; j < m; j += gridDim.x * NT) out[j] = cnt[order[lo + j]];
+}
+
+// ... or recounted against the tiles still alive (second slab).
+__global__ void __launch_bounds__(NT) recount_kernel(const uint32_t* __restrict__ order, const uint2* __restrict__ rect,
+                                                     const uint32_t* __restrict__ alive, const uint32_t* counters,
+                                                     int64_t n, int TX, int wpv, uint32_t* __restrict__ out) {
+  const uint32_t lo = counters[C_SLAB_LO], m = counters[C_SLAB_N];
+  for (uint32_t j = blockIdx.x * NT + threadIdx.x; j < m; j += gridDim.x * NT) {
+    const uint32_t e = order[lo + j];
+    const uint32_t* vm = alive + (uint32_t)(e / n) * (int64_t)wpv;
+    const uint2 r = rect[e];
+    const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
+    uint32_t c = 0;
+    for (uint32_t ty = y0; ty < y1; ++ty) c += count_bits(vm, ty * TX + x0, ty * TX + x1);
+    out[j] = c;
+  }
+}
+
+// Capacity check after a slab's pair count: P = first-slab pairs + this slab's pairs.
+__global__ void check_capacity_kernel(uint32_t* counters, uint64_t capacity, int which) {
+  const uint32_t sp = counters[C_SLAB_PAIRS];
+  const uint32_t p = (which == 1 ? 0u : counters[C_PAIRS1]) + sp;
+  if (which == 1) counters[C_PAIRS1] = sp;
+  const bool over = (uint64_t)p > capacity || counters[C_OVERFLOW];
+  counters[C_PAIRS] = p;
   counters[C_OVERFLOW] = over ? 1u : 0u;
   counters[C_WRITTEN] = over ? 0u : p;
-  if (over) counters[C_STICKY] = 1u;
+  if (over) {
+    counters[C_STICKY] = 1u;
+    counters[C_SLAB_PAIRS] = 0u;  // nothing is emitted or sorted
+    counters[C_SLAB_N] = 0u;
+  }
 }
 
+// ------------------------------------------------------------------ 5. emission
 // Pairs staged in LDS per round of the masked emission.
 constexpr int EMIT_WIN = 4096;
 // Mask words kept in LDS by the masked emission (all views of the call).
 constexpr int EMIT_MASK_WORDS = 4096;
 
 // Full mode: every tile of every rectangle is a pair.  A block takes NT consecutive
-// entries of the depth order; their pairs form one contiguous output range, which the
+// entries of the slab; their pairs form one contiguous output range, which the
 // block's threads fill position by position (consecutive threads, consecutive
 // positions): the owner entry of a position is found by binary search over the NT
 // offsets in LDS and its tile follows from the position inside the rectangle.  Every
@@ -408,8 +469,12 @@ __global__ void __launch_bounds__(NT) emit_full_kernel(const uint32_t* __restric
   __shared__ uint32_t s_w[NT];     // rectangle width
   __shared__ float s_iw[NT];       // 1 / width
   if (counters[C_OVERFLOW]) return;
-  const uint32_t m = counters[C_ENTRIES];
-  const uint32_t P = counters[C_PAIRS];
+  const uint32_t m = counters[C_SLAB_N];
+  const uint32_t P = counters[C_SLAB_PAIRS];
+  order += counters[C_SLAB_LO];
+  const uint32_t pbase = counters[C_SLAB_BASE];
+  pk += pbase;
+  pv += pbase;
   for (uint32_t j0 = blockIdx.x * NT; j0 < m; j0 += gridDim.x * NT) {
     const uint32_t j = j0 + threadIdx.x;
     const uint32_t cnt = min((uint32_t)NT, m - j0);
@@ -429,8 +494,8 @@ __global__ void __launch_bounds__(NT) emit_full_kernel(const uint32_t* __restric
     const uint32_t base = s_off[0];
     const uint32_t end = j0 + NT < m ? offs[j0 + NT] : P;
     for (uint32_t pos = base + threadIdx.x; pos < end; pos += NT) {
-      // owner: the last entry whose offset is <= pos (entries with no pairs are skipped
-      // naturally because the next entry has the same offset)
+      // owner: the last entry whose offset is <= pos (every slab entry has pairs, so
+      // offsets strictly increase)
       uint32_t lo = 0, hi = cnt;
       while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
@@ -447,10 +512,11 @@ __global__ void __launch_bounds__(NT) emit_full_kernel(const uint32_t* __restric
   }
 }
 
-// Masked mode: each thread walks the masked tiles of its rectangle row by row (set
-// bits of the LDS copy of the mask, so the cost follows the masked tiles, not the
-// rectangle's area) and stages its pairs in an LDS window that the block writes out
-// with coalesced stores.
+// Masked: each thread walks the tiles of its rectangle that are set in `mask`, row by
+// row (set bits of an LDS copy of the mask, so the cost follows those tiles, not the
+// rectangle's area), and stages its pairs in an LDS window that the block writes out
+// with coalesced stores.  Entries of the second slab may have no pair (their tiles are
+// no longer alive); they are skipped.
 template <bool LDS_MASK>
 __global__ void __launch_bounds__(NT) emit_masked_kernel(const uint32_t* __restrict__ order,
                                                          const uint32_t* __restrict__ offs,
@@ -464,12 +530,17 @@ __global__ void __launch_bounds__(NT) emit_masked_kernel(const uint32_t* __restr
   __shared__ uint32_t s_v[EMIT_WIN];
   __shared__ uint32_t s_mask[LDS_MASK ? EMIT_MASK_WORDS : 1];
   if (counters[C_OVERFLOW]) return;
+  const uint32_t m = counters[C_SLAB_N];
+  if (blockIdx.x * NT >= m) return;
   if (LDS_MASK) {
     for (int w = threadIdx.x; w < views * wpv; w += NT) s_mask[w] = mask[w];
     __syncthreads();
   }
-  const uint32_t m = counters[C_ENTRIES];
-  const uint32_t P = counters[C_PAIRS];
+  const uint32_t P = counters[C_SLAB_PAIRS];
+  order += counters[C_SLAB_LO];
+  const uint32_t pbase = counters[C_SLAB_BASE];
+  pk += pbase;
+  pv += pbase;
   for (uint32_t j0 = blockIdx.x * NT; j0 < m; j0 += gridDim.x * NT) {
     const uint32_t j = j0 + threadIdx.x;
     const uint32_t base = offs[j0];
@@ -489,12 +560,10 @@ __global__ void __launch_bounds__(NT) emit_masked_kernel(const uint32_t* __restr
       y1 = r.y >> 16;
       vm += (int64_t)v * wpv;
       gbase = v * (uint32_t)T;
-      // first row's first word, restricted to [x0, x1)
       wcur = (ty * TX + x0) >> 5;
       wlast = (ty * TX + x1 - 1) >> 5;
-      bits = 0;
     }
-    // bits of word wcur of row ty that lie in the rectangle and the mask
+    // bits of word w of row ty that lie in the rectangle and the mask
     auto row_word = [&](uint32_t w) -> uint32_t {
       const uint32_t lo = ty * TX + x0, hi = ty * TX + x1;  // tiles [lo, hi) of this row
       uint32_t b = vm[w];
@@ -540,13 +609,15 @@ __global__ void __launch_bounds__(NT) emit_masked_kernel(const uint32_t* __restr
 }
 
 // ------------------------------------------------------------------ 7. ranges, tile list
+// [start, end) of each tile's run among the slab's sorted pairs (absolute positions).
 __global__ void __launch_bounds__(NT) ranges_kernel(const uint32_t* __restrict__ keys,
                                                     const uint32_t* __restrict__ counters, uint2* __restrict__ ranges) {
-  const uint32_t P = counters[C_WRITTEN];
+  const uint32_t P = counters[C_SLAB_PAIRS], base = counters[C_SLAB_BASE];
   for (uint32_t p = blockIdx.x * NT + threadIdx.x; p < P; p += gridDim.x * NT) {
-    const uint32_t k = keys[p];
-    if (p == 0 || keys[p - 1] != k) ranges[k].x = p;
-    if (p + 1 == P || keys[p + 1] != k) ranges[k].y = p + 1;
+    const uint32_t q = base + p;
+    const uint32_t k = keys[q];
+    if (p == 0 || keys[q - 1] != k) ranges[k].x = q;
+    if (p + 1 == P || keys[q + 1] != k) ranges[k].y = q + 1;
   }
 }
 
@@ -601,10 +672,11 @@ hipError_t scan(const uint32_t* in, uint32_t* out, const uint32_t* n_ptr, uint32
   return hipGetLastError();
 }
 
-// Stable LSD radix sort of (keys, vals) on bits [0, total_bits); n from n_ptr.  Passes
-// alternate between (k0, v0) and (k1, v1); returns 0 when the result is in (k0, v0).
-int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_ptr, int64_t nmax,
-               int total_bits, uint32_t* hist, uint32_t* tot, hipStream_t s) {
+// Stable LSD radix sort of (keys, vals)[off + e], e < n, on bits [0, total_bits); n and
+// off read from device memory.  Passes alternate between (k0, v0) and (k1, v1); returns
+// 0 when the result is in (k0, v0).
+int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_ptr, const uint32_t* off_ptr,
+               int64_t nmax, int total_bits, uint32_t* hist, uint32_t* tot, hipStream_t s) {
   if (total_bits <= 0) return 0;
   const int passes = (total_bits + 7) / 8;
   const int per = (total_bits + passes - 1) / passes;
@@ -616,10 +688,10 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uin
     uint32_t* vi = cur ? v1 : v0;
     uint32_t* ko = cur ? k0 : k1;
     uint32_t* vo = cur ? v0 : v1;
-    hipLaunchKernelGGL(rs_upsweep_kernel, dim3(G), dim3(NT), 0, s, ki, n_ptr, shift, bits, hist, G);
+    hipLaunchKernelGGL(rs_upsweep_kernel, dim3(G), dim3(NT), 0, s, ki, n_ptr, off_ptr, shift, bits, hist, G);
     hipLaunchKernelGGL(rs_scan_kernel, dim3(1 << bits), dim3(NT), 0, s, hist, G, tot);
-    hipLaunchKernelGGL(rs_downsweep_kernel, dim3(G), dim3(NT), 0, s, ki, vi, ko, vo, n_ptr, shift, bits, hist, tot,
-                       G);
+    hipLaunchKernelGGL(rs_downsweep_kernel, dim3(G), dim3(NT), 0, s, ki, vi, ko, vo, n_ptr, off_ptr, shift, bits, hist,
+                       tot, G);
     shift += bits;
     cur ^= 1;
   }
@@ -627,6 +699,72 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uin
 }
 
 int passes_for(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
+
+struct WsPtrs {
+  uint32_t *cnt, *tmp, *keyA, *valA, *keyB, *valB, *blk, *hist, *dtot, *pairK, *pairV, *tflag, *tpos;
+};
+
+WsPtrs carve(const BinPlan& p, char* ws) {
+  WsPtrs w;
+  w.cnt = reinterpret_cast<uint32_t*>(ws + p.off_cnt);
+  w.tmp = reinterpret_cast<uint32_t*>(ws + p.off_flag);
+  w.keyA = reinterpret_cast<uint32_t*>(ws + p.off_keyA);
+  w.valA = reinterpret_cast<uint32_t*>(ws + p.off_valA);
+  w.keyB = reinterpret_cast<uint32_t*>(ws + p.off_keyB);
+  w.valB = reinterpret_cast<uint32_t*>(ws + p.off_valB);
+  w.blk = reinterpret_cast<uint32_t*>(ws + p.off_scanBlk);
+  w.hist = reinterpret_cast<uint32_t*>(ws + p.off_hist);
+  w.dtot = reinterpret_cast<uint32_t*>(ws + p.off_digit);
+  w.pairK = reinterpret_cast<uint32_t*>(ws + p.off_pairK);
+  w.pairV = reinterpret_cast<uint32_t*>(ws + p.off_pairV);
+  w.tflag = reinterpret_cast<uint32_t*>(ws + p.off_tflag);
+  w.tpos = w.tflag + ((int64_t)p.views * p.T + 1);
+  return w;
+}
+
+// Lists one slab of the depth order (order = valA after the 32-bit depth sort):
+// counts, offsets, capacity check, emission (into `mask`'s tiles), tile sort, ranges.
+hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bins& bins, const WsPtrs& w, int which,
+                     int use_mask, const uint32_t* mask, uint32_t* ranges, hipStream_t s) {
+  const int V = p.views;
+  const int64_t n = p.n, E = p.entries;
+  const int wpv = (p.T + 31) / 32;
+  const uint2* rect = reinterpret_cast<const uint2*>(proj.rect);
+  uint32_t* counters = bins.counters;
+  uint32_t* order = w.valA;
+  hipError_t err;
+  hipLaunchKernelGGL(slab_select_kernel, dim3(1), dim3(1), 0, s, counters, which);
+  if (which == 1)
+    hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(E)), dim3(NT), 0, s, order, w.cnt, counters, w.tmp);
+  else
+    hipLaunchKernelGGL(recount_kernel, dim3(grid_for(E)), dim3(NT), 0, s, order, rect, mask, counters, n, p.TX, wpv,
+                       w.tmp);
+  // offsets (relative to the slab's first pair) into valB
+  if ((err = scan(w.tmp, w.valB, counters + C_SLAB_N, 0u, E, w.blk, counters + C_SLAB_PAIRS, s)) != hipSuccess)
+    return err;
+  hipLaunchKernelGGL(check_capacity_kernel, dim3(1), dim3(1), 0, s, counters, (uint64_t)p.capacity, which);
+  const int tpasses = passes_for(p.tile_bits);
+  uint32_t* ek = (tpasses % 2 == 0) ? bins.keys : w.pairK;
+  uint32_t* ev = (tpasses % 2 == 0) ? bins.values : w.pairV;
+  if (which == 1 && !use_mask) {
+    hipLaunchKernelGGL(emit_full_kernel, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, w.valB, rect, counters, n,
+                       p.TX, p.T, ek, ev);
+  } else if ((int64_t)V * wpv <= EMIT_MASK_WORDS) {
+    hipLaunchKernelGGL(emit_masked_kernel<true>, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, w.valB, w.tmp, rect,
+                       mask, counters, n, p.TX, p.T, wpv, V, ek, ev);
+  } else {
+    hipLaunchKernelGGL(emit_masked_kernel<false>, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, w.valB, w.tmp,
+                       rect, mask, counters, n, p.TX, p.T, wpv, V, ek, ev);
+  }
+  if (tpasses > 0) {
+    uint32_t *k1 = (ek == bins.keys) ? w.pairK : bins.keys, *v1 = (ev == bins.values) ? w.pairV : bins.values;
+    radix_sort(ek, ev, k1, v1, counters + C_SLAB_PAIRS, counters + C_SLAB_BASE, p.capacity, p.tile_bits, w.hist,
+               w.dtot, s);
+  }
+  hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(p.capacity, 1 << 14)), dim3(NT), 0, s, bins.keys, counters,
+                     reinterpret_cast<uint2*>(ranges));
+  return hipGetLastError();
+}
 
 }  // namespace
 
@@ -672,6 +810,9 @@ BinPlan make_bin_plan(int64_t n, int views, int W, int H, int64_t capacity) {
   p.off_pairK = take(need_pair_buf ? (size_t)(capacity > 0 ? capacity : 1) * 4 : 4);
   p.off_pairV = take(need_pair_buf ? (size_t)(capacity > 0 ? capacity : 1) * 4 : 4);
   p.off_tflag = take((gt + 1) * 4 * 2);
+  // per rendered tile slot: alive flag, and per pixel the carried compositing state
+  p.off_alive = take(gt * 4);
+  p.off_carry = take((size_t)gt * TILE_PIX * CARRY_FIELDS * 4);
   p.total = off;
   return p;
 }
@@ -681,26 +822,17 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
   const int V = p.views;
   const int64_t n = p.n, E = p.entries, gt = (int64_t)V * p.T;
   const int wpv = (p.T + 31) / 32;
-  uint32_t* cnt = reinterpret_cast<uint32_t*>(ws + p.off_cnt);
-  uint32_t* tmp = reinterpret_cast<uint32_t*>(ws + p.off_flag);
-  uint32_t* keyA = reinterpret_cast<uint32_t*>(ws + p.off_keyA);
-  uint32_t* valA = reinterpret_cast<uint32_t*>(ws + p.off_valA);
-  uint32_t* keyB = reinterpret_cast<uint32_t*>(ws + p.off_keyB);
-  uint32_t* valB = reinterpret_cast<uint32_t*>(ws + p.off_valB);
-  uint32_t* blk = reinterpret_cast<uint32_t*>(ws + p.off_scanBlk);
-  uint32_t* hist = reinterpret_cast<uint32_t*>(ws + p.off_hist);
-  uint32_t* dtot = reinterpret_cast<uint32_t*>(ws + p.off_digit);
-  uint32_t* pairK = reinterpret_cast<uint32_t*>(ws + p.off_pairK);
-  uint32_t* pairV = reinterpret_cast<uint32_t*>(ws + p.off_pairV);
-  uint32_t* tflag = reinterpret_cast<uint32_t*>(ws + p.off_tflag);
-  uint32_t* tpos = tflag + (gt + 1);
+  const WsPtrs w = carve(p, ws);
   const uint2* rect = reinterpret_cast<const uint2*>(proj.rect);
   uint32_t* counters = bins.counters;
   hipError_t err;
 
   // clear outputs (counters[C_STICKY] is left alone: it remembers any overflow)
   if ((err = launch_fill_u32(counters, 0u, C_STICKY, s)) != hipSuccess) return err;
+  if ((err = launch_fill_u32(counters + C_STICKY + 1, 0u, CLSP_COUNTERS - C_STICKY - 1, s)) != hipSuccess) return err;
   if ((err = launch_fill_u32(bins.ranges, 0u, gt * 2, s)) != hipSuccess) return err;
+  if ((err = launch_fill_u32(bins.ranges2, 0u, gt * 2, s)) != hipSuccess) return err;
+  if ((err = launch_fill_u32(bins.alive_mask, 0u, (int64_t)V * wpv, s)) != hipSuccess) return err;
   // 1. mask
   if (use_mask) {
     if ((err = launch_fill_u32(bins.tile_mask, 0u, (int64_t)V * wpv, s)) != hipSuccess) return err;
@@ -715,47 +847,33 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
   if (E > 0) {
     // 2. counts
     hipLaunchKernelGGL(count_kernel, dim3(ceil_div(n, NT), V), dim3(NT), use_mask ? wpv * 4 : 0, s, rect, proj.flags,
-                       bins.tile_mask, n, p.TX, wpv, use_mask, cnt, tmp);
+                       bins.tile_mask, n, p.TX, wpv, use_mask, w.cnt, w.tmp);
     // 3. compaction of entries with pairs, keyed by depth
-    uint32_t* pos = keyB;  // scratch until the sort needs it
-    if ((err = scan(tmp, pos, nullptr, (uint32_t)E, E, blk, counters + C_ENTRIES, s)) != hipSuccess) return err;
-    hipLaunchKernelGGL(compact_kernel, dim3(ceil_div(E, NT)), dim3(NT), 0, s, tmp, pos, proj.depth, E, keyA, valA);
-    // 4. depth order (32 key bits, 4 passes -> result back in A)
-    const int where = radix_sort(keyA, valA, keyB, valB, counters + C_ENTRIES, E, 32, hist, dtot, s);
-    uint32_t* order = where ? valB : valA;
-    uint32_t* spare = where ? valA : valB;
-    // 5. offsets of each entry's pairs in depth order, capacity check, emission
-    hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(E)), dim3(NT), 0, s, order, cnt, counters + C_ENTRIES, tmp);
-    if ((err = scan(tmp, spare, counters + C_ENTRIES, 0u, E, blk, counters + C_PAIRS, s)) != hipSuccess) return err;
-    hipLaunchKernelGGL(check_capacity_kernel, dim3(1), dim3(1), 0, s, counters, (uint64_t)p.capacity);
-    const int tpasses = passes_for(p.tile_bits);
-    uint32_t* ek = (tpasses % 2 == 0) ? bins.keys : pairK;
-    uint32_t* ev = (tpasses % 2 == 0) ? bins.values : pairV;
-    if (!use_mask) {
-      hipLaunchKernelGGL(emit_full_kernel, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, spare, rect, counters,
-                         n, p.TX, p.T, ek, ev);
-    } else if ((int64_t)V * wpv <= EMIT_MASK_WORDS) {
-      hipLaunchKernelGGL(emit_masked_kernel<true>, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, spare, tmp,
-                         rect, bins.tile_mask, counters, n, p.TX, p.T, wpv, V, ek, ev);
-    } else {
-      hipLaunchKernelGGL(emit_masked_kernel<false>, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, spare, tmp,
-                         rect, bins.tile_mask, counters, n, p.TX, p.T, wpv, V, ek, ev);
-    }
-    // 6. stable sort by global tile
-    if (tpasses > 0) {
-      uint32_t *k0 = ek, *v0 = ev, *k1 = (ek == bins.keys) ? pairK : bins.keys, *v1 = (ev == bins.values) ? pairV : bins.values;
-      radix_sort(k0, v0, k1, v1, counters + C_WRITTEN, p.capacity, p.tile_bits, hist, dtot, s);
-    }
-    // 7. ranges
-    hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(p.capacity, 1 << 14)), dim3(NT), 0, s, bins.keys, counters,
-                       reinterpret_cast<uint2*>(bins.ranges));
+    uint32_t* pos = w.keyB;  // scratch until the sort needs it
+    if ((err = scan(w.tmp, pos, nullptr, (uint32_t)E, E, w.blk, counters + C_ENTRIES, s)) != hipSuccess) return err;
+    hipLaunchKernelGGL(compact_kernel, dim3(ceil_div(E, NT)), dim3(NT), 0, s, w.tmp, pos, proj.depth, E, w.keyA, w.valA);
+    // 4. depth order: 32 key bits, 4 passes, the result back in (keyA, valA)
+    radix_sort(w.keyA, w.valA, w.keyB, w.valB, counters + C_ENTRIES, nullptr, E, 32, w.hist, w.dtot, s);
+    hipLaunchKernelGGL(slab_bounds_kernel, dim3(1), dim3(1), 0, s, counters, bins.mode == CLSP_BINS_DEPTH_SLICED);
+    // 5-7 for the first slab (the whole order for complete lists)
+    if ((err = list_slab(p, proj, bins, w, 1, use_mask, bins.tile_mask, bins.ranges, s)) != hipSuccess) return err;
   }
   // tile list (masked tiles; all tiles in full mode)
   hipLaunchKernelGGL(tile_flags_kernel, dim3(ceil_div(gt, NT)), dim3(NT), 0, s, bins.tile_mask, V, p.T, wpv, counters,
-                     tflag);
-  if ((err = scan(tflag, tpos, nullptr, (uint32_t)gt, gt, blk, counters + C_TILES, s)) != hipSuccess) return err;
-  hipLaunchKernelGGL(tile_list_kernel, dim3(ceil_div(gt, NT)), dim3(NT), 0, s, tflag, tpos, gt, bins.tile_list);
+                     w.tflag);
+  if ((err = scan(w.tflag, w.tpos, nullptr, (uint32_t)gt, gt, w.blk, counters + C_TILES, s)) != hipSuccess) return err;
+  hipLaunchKernelGGL(tile_list_kernel, dim3(ceil_div(gt, NT)), dim3(NT), 0, s, w.tflag, w.tpos, gt, bins.tile_list);
   return hipGetLastError();
 }
+
+hipError_t launch_list_second_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bins& bins, char* ws,
+                                   hipStream_t s) {
+  if (p.entries == 0) return hipSuccess;
+  const WsPtrs w = carve(p, ws);
+  return list_slab(p, proj, bins, w, 2, 1, bins.alive_mask, bins.ranges2, s);
+}
+
+uint32_t* bin_alive_flags(const BinPlan& p, char* ws) { return reinterpret_cast<uint32_t*>(ws + p.off_alive); }
+float* bin_carry(const BinPlan& p, char* ws) { return reinterpret_cast<float*>(ws + p.off_carry); }
 
 }  // namespace clsp

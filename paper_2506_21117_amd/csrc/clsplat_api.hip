@@ -126,9 +126,21 @@ clsp_status check_projected(const clsp_projected* p) {
 }
 
 clsp_status check_bins(const clsp_bins* b) {
-  if (!b || !b->values || !b->keys || !b->ranges || !b->tile_mask || !b->tile_list || !b->counters)
+  if (!b || !b->values || !b->keys || !b->ranges || !b->ranges2 || !b->tile_mask || !b->alive_mask || !b->tile_list ||
+      !b->counters)
     return fail(CLSP_ERR_INVALID_ARG, "bins buffers missing");
   if (b->capacity < 0 || b->capacity > MAX_ENTRIES) return fail(CLSP_ERR_INVALID_ARG, "capacity not in 0..2^32-1");
+  if (b->mode != CLSP_BINS_COMPLETE && b->mode != CLSP_BINS_DEPTH_SLICED)
+    return fail(CLSP_ERR_INVALID_ARG, "unknown bins mode %d", b->mode);
+  if (b->n < 0) return fail(CLSP_ERR_INVALID_ARG, "bins n < 0");
+  return CLSP_OK;
+}
+
+// The bins' workspace must hold the plan for these views and this capacity.
+clsp_status check_bins_ws(const clsp_bins* b, const clsp::BinPlan& plan) {
+  if (!b->ws || b->ws_bytes < plan.total)
+    return fail(CLSP_ERR_INVALID_ARG, "bins workspace of %zu bytes is smaller than the %zu needed", b->ws_bytes,
+                plan.total);
   return CLSP_OK;
 }
 
@@ -165,21 +177,19 @@ size_t clsp_bin_and_sort_workspace_bytes(int64_t n, int32_t n_views, int32_t wid
   return clsp::make_bin_plan(n, n_views, width, height, capacity).total;
 }
 
-clsp_status clsp_bin_and_sort(const clsp_projected* proj, int64_t n, const clsp_camera* cams, int32_t n_views,
-                              clsp_range active, int32_t use_mask, const clsp_bins* bins, void* ws, size_t ws_bytes,
-                              clsp_stream stream) {
+clsp_status clsp_bin_and_sort(const clsp_projected* proj, const clsp_camera* cams, int32_t n_views, clsp_range active,
+                              int32_t use_mask, const clsp_bins* bins, clsp_stream stream) {
   CHECK(check_projected(proj));
   CHECK(check_cams(cams, n_views));
   CHECK(check_bins(bins));
-  if (n < 0) return fail(CLSP_ERR_INVALID_ARG, "n < 0");
+  const int64_t n = bins->n;
   if ((int64_t)n_views * n > MAX_ENTRIES) return fail(CLSP_ERR_INVALID_ARG, "n_views * n >= 2^32");
   CHECK(check_range(active, n));
   const clsp::BinPlan plan = clsp::make_bin_plan(n, n_views, cams[0].width, cams[0].height, bins->capacity);
-  if (!ws || ws_bytes < plan.total)
-    return fail(CLSP_ERR_INVALID_ARG, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, plan.total);
+  CHECK(check_bins_ws(bins, plan));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return hip_status(clsp::launch_bin_and_sort(plan, *proj, active.begin, active.end, use_mask ? 1 : 0, *bins,
-                                              static_cast<char*>(ws), s),
+                                              static_cast<char*>(bins->ws), s),
                     "bin_and_sort");
 }
 
@@ -199,6 +209,7 @@ clsp_status clsp_render_forward(const clsp_projected* proj, const clsp_bins* bin
   if (state && state_bytes < clsp_render_state_bytes(n_views, W, H))
     return fail(CLSP_ERR_INVALID_ARG, "state of %zu bytes is smaller than the %zu needed", state_bytes,
                 clsp_render_state_bytes(n_views, W, H));
+  CHECK(check_bins_ws(bins, clsp::make_bin_plan(bins->n, n_views, W, H, bins->capacity)));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return hip_status(clsp::launch_render_forward(*proj, *bins, n_views, W, H, (W + CLSP_TILE - 1) / CLSP_TILE,
                                                 (H + CLSP_TILE - 1) / CLSP_TILE, bg, image, T_final, n_contrib,

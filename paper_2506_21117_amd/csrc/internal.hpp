@@ -20,6 +20,9 @@ constexpr float T_STOP = 1e-4f;
 constexpr float NEAR_Z = 0.2f;
 constexpr float LOWPASS = 0.3f;
 constexpr float EXTENT_MARGIN = 1.0f + 1.0f / 4096.0f;
+// Per-pixel compositing state carried from the first to the second depth slab:
+// T, colour of the flushed chunks (3), colour of the current chunk (3), last, done.
+constexpr int CARRY_FIELDS = 9;
 
 // Camera as the kernels take it (by value): the C-ABI camera plus derived constants.
 struct DevCam {
@@ -73,13 +76,18 @@ struct BinPlan {
   int64_t entries;    // views * n
   // workspace carve-up (byte offsets)
   size_t off_cnt, off_flag, off_keyA, off_valA, off_keyB, off_valB, off_scanBlk, off_hist, off_digit,
-      off_pairK, off_pairV, off_tflag, total;
+      off_pairK, off_pairV, off_tflag, off_alive, off_carry, total;
   int scan_blocks;
   int sort_blocks_gauss, sort_blocks_pairs;
 };
 BinPlan make_bin_plan(int64_t n, int views, int W, int H, int64_t capacity);
 hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int64_t a0, int64_t a1, int use_mask,
                                const clsp_bins& bins, char* ws, hipStream_t s);
+// Depth-sliced lists: list the second slab into the alive tiles (bins.alive_mask).
+hipError_t launch_list_second_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bins& bins, char* ws,
+                                   hipStream_t s);
+uint32_t* bin_alive_flags(const BinPlan& p, char* ws);
+float* bin_carry(const BinPlan& p, char* ws);
 
 // render.hip
 size_t render_state_bytes(int views, int TX, int TY);

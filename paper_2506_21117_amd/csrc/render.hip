@@ -14,7 +14,7 @@ namespace clsp {
 namespace {
 
 constexpr int NT = TILE_PIX;
-constexpr int C_TILES = 2;
+constexpr int C_OVERFLOW = 1, C_TILES = 2, C_ALIVE = 8;
 
 // Opacity of a record at a pixel centre, evaluated with explicitly rounded operations
 // so the forward and the backward take the same decisions bit for bit.
@@ -54,55 +54,85 @@ __device__ __forceinline__ StateView state_view(void* base, int64_t slots) {
 constexpr int CH = CLSP_STATE_CHUNK;
 constexpr int CHUNKS = CLSP_STATE_CHUNKS;
 
-__global__ void __launch_bounds__(NT) render_forward_kernel(const float* __restrict__ splat,
-                                                            const uint32_t* __restrict__ values,
-                                                            const uint2* __restrict__ ranges,
-                                                            const uint32_t* __restrict__ tile_list,
-                                                            const uint32_t* __restrict__ counters, int T, int TX,
-                                                            int W, int H, float bg0, float bg1, float bg2,
-                                                            float* __restrict__ image, float* __restrict__ T_final,
-                                                            uint32_t* __restrict__ n_contrib, void* state,
-                                                            int64_t slots) {
-  if (blockIdx.x >= counters[C_TILES]) return;
+// Entry of list position k of a tile whose list is [r1.x, r1.y) followed by [r2.x, r2.y).
+__device__ __forceinline__ uint32_t list_entry(const uint32_t* __restrict__ values, uint2 r1, uint2 r2, int k) {
+  const int len1 = (int)(r1.y - r1.x);
+  return k < len1 ? values[r1.x + k] : values[r2.x + (k - len1)];
+}
+
+// PHASE 1 composites each rendered tile's first list (the whole list for complete
+// bins).  With `sliced`, tiles in which a pixel is still compositing at the end are
+// marked alive and their per-pixel state is saved in `carry`; PHASE 2 continues the
+// alive tiles with their second lists from that state.  Chunk boundaries (every CH
+// list positions) and all arithmetic are the same as in one pass over the whole list,
+// so the outputs are identical bit for bit.
+template <int PHASE>
+__global__ void __launch_bounds__(NT) render_forward_kernel(
+    const float* __restrict__ splat, const uint32_t* __restrict__ values, const uint2* __restrict__ ranges,
+    const uint2* __restrict__ ranges2, const uint32_t* __restrict__ tile_list, uint32_t* __restrict__ counters, int T,
+    int TX, int W, int H, float bg0, float bg1, float bg2, float* __restrict__ image, float* __restrict__ T_final,
+    uint32_t* __restrict__ n_contrib, void* state, int64_t slots, int sliced, uint32_t* __restrict__ alive,
+    uint32_t* __restrict__ alive_mask, int wpv, float* __restrict__ carry) {
+  const uint32_t slot = blockIdx.x;
+  if (slot >= counters[C_TILES]) return;
+  if (PHASE == 2 && (counters[C_OVERFLOW] || !alive[slot])) return;
   __shared__ float4 s_a[NT];
   __shared__ float4 s_b[NT];
   __shared__ float s_c[NT];
   __shared__ uint32_t s_max;
-  const uint32_t gt = tile_list[blockIdx.x];
+  const uint32_t gt = tile_list[slot];
   const int v = gt / T, t = gt % T;
   const int px = (t % TX) * TILE + (threadIdx.x & 15);
   const int py = (t / TX) * TILE + (threadIdx.x >> 4);
   const bool inside = px < W && py < H;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  const uint2 rg = ranges[gt];
-  const int total = (int)(rg.y - rg.x);
+  const uint2 r1 = ranges[gt];
+  const uint2 r2 = PHASE == 2 ? ranges2[gt] : make_uint2(0u, 0u);
+  const int len1 = (int)(r1.y - r1.x);
+  const int k_begin = PHASE == 1 ? 0 : len1;
+  const int k_end = PHASE == 1 ? len1 : len1 + (int)(r2.y - r2.x);
   const bool keep = state != nullptr;
   StateView sv;
   if (keep) sv = state_view(state, slots);
-  float4* my_chunks = keep ? sv.chunks + (size_t)blockIdx.x * CHUNKS * NT + threadIdx.x : nullptr;
+  float4* my_chunks = keep ? sv.chunks + (size_t)slot * CHUNKS * NT + threadIdx.x : nullptr;
+  float* my_carry = carry + (size_t)slot * CARRY_FIELDS * NT + threadIdx.x;
 
   float Tr = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;   // colour of the flushed chunks
   float dr = 0.0f, dg = 0.0f, db = 0.0f;              // colour of the current chunk
-  int chunk = 0;
   uint32_t last = 0;
   bool done = !inside;
-  for (int base = 0; base < total; base += NT) {
+  int chunk = 0;
+  if (PHASE == 2) {
+    Tr = my_carry[0 * NT];
+    cr = my_carry[1 * NT];
+    cg = my_carry[2 * NT];
+    cb = my_carry[3 * NT];
+    dr = my_carry[4 * NT];
+    dg = my_carry[5 * NT];
+    db = my_carry[6 * NT];
+    last = __float_as_uint(my_carry[7 * NT]);
+    done = my_carry[8 * NT] != 0.0f;
+    chunk = min(len1 / CH, CHUNKS - 1);
+  }
+  for (int kb = k_begin; kb < k_end; kb += NT) {
     if (__syncthreads_count(done) == NT) break;
-    const int k = base + threadIdx.x;
-    if (k < total) {
-      const uint32_t e = values[rg.x + k];
+    const int k = kb + threadIdx.x;
+    if (k < k_end) {
+      const uint32_t e = list_entry(values, r1, r2, k);
       const float4* sp = reinterpret_cast<const float4*>(splat + (size_t)e * SPLAT_STRIDE);
       s_a[threadIdx.x] = sp[0];
       s_b[threadIdx.x] = sp[1];
       s_c[threadIdx.x] = sp[2].x;
     }
     __syncthreads();
-    const int cnt = min(NT, total - base);
-    for (int half = 0; half < NT / CH; ++half) {
-      const int jhi = min(cnt, (half + 1) * CH);
+    const int cnt = min(NT, k_end - kb);
+    // segments of the batch between chunk boundaries of the list
+    for (int j = 0; j < cnt;) {
+      const int next_b = ((kb + j) / CH + 1) * CH;
+      const int jhi = min(cnt, next_b - kb);
       if (!done) {
-        for (int j = half * CH; j < jhi; ++j) {
-          const float4 a = s_a[j], b = s_b[j];
+        for (int jj = j; jj < jhi; ++jj) {
+          const float4 a = s_a[jj], b = s_b[jj];
           float dx, dy, G, alpha;
           bool clamped;
           if (!splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped)) continue;
@@ -114,19 +144,42 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(const float* __restr
           const float w = alpha * Tr;
           dr = fmaf(w, b.z, dr);
           dg = fmaf(w, b.w, dg);
-          db = fmaf(w, s_c[j], db);
+          db = fmaf(w, s_c[jj], db);
           Tr = Tn;
-          last = (uint32_t)(base + j + 1);
+          last = (uint32_t)(kb + jj + 1);
         }
       }
       // a chunk boundary of the tile's list: record this pixel's state
-      if (base + (half + 1) * CH <= total && chunk < CHUNKS - 1) {
+      if (kb + jhi == next_b && chunk < CHUNKS - 1) {
         if (keep) my_chunks[(size_t)chunk * NT] = make_float4(Tr, dr, dg, db);
         cr += dr;
         cg += dg;
         cb += db;
         dr = dg = db = 0.0f;
         ++chunk;
+      }
+      j = jhi;
+    }
+  }
+  if (PHASE == 1 && sliced) {
+    const bool more = __syncthreads_count(done) < NT;
+    if (more) {
+      // save the state; the second list continues this tile
+      my_carry[0 * NT] = Tr;
+      my_carry[1 * NT] = cr;
+      my_carry[2 * NT] = cg;
+      my_carry[3 * NT] = cb;
+      my_carry[4 * NT] = dr;
+      my_carry[5 * NT] = dg;
+      my_carry[6 * NT] = db;
+      my_carry[7 * NT] = __uint_as_float(last);
+      my_carry[8 * NT] = done ? 1.0f : 0.0f;
+    }
+    if (threadIdx.x == 0) {
+      alive[slot] = more ? 1u : 0u;
+      if (more) {
+        atomicOr(&alive_mask[(int64_t)v * wpv + (t >> 5)], 1u << (t & 31));
+        atomicAdd(&counters[C_ALIVE], 1u);
       }
     }
   }
@@ -139,7 +192,7 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(const float* __restr
     __syncthreads();
     atomicMax(&s_max, last);
     __syncthreads();
-    if (threadIdx.x == 0) sv.maxlast[blockIdx.x] = s_max;
+    if (threadIdx.x == 0) sv.maxlast[slot] = s_max;
   }
   if (inside) {
     const size_t hw = (size_t)H * W;
@@ -203,10 +256,10 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
 // chunk's entries from the chunk's stored end state.
 __global__ void __launch_bounds__(NT) render_backward_kernel(
     const float* __restrict__ splat, const uint32_t* __restrict__ values, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ tile_list, const uint32_t* __restrict__ counters, int T, int TX, int W, int H,
-    int64_t n, float bg0, float bg1, float bg2, int64_t a0, int64_t a1, const float* __restrict__ T_final,
-    const uint32_t* __restrict__ n_contrib, void* state, int64_t slots, const float* __restrict__ dL,
-    float* __restrict__ grad2d) {
+    const uint2* __restrict__ ranges2, const uint32_t* __restrict__ tile_list, const uint32_t* __restrict__ counters,
+    int T, int TX, int W, int H, int64_t n, float bg0, float bg1, float bg2, int64_t a0, int64_t a1,
+    const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib, void* state, int64_t slots,
+    const float* __restrict__ dL, float* __restrict__ grad2d) {
   const uint32_t slot = blockIdx.x;
   if (slot >= counters[C_TILES]) return;
   const StateView sv = state_view(state, slots);
@@ -229,7 +282,7 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
   const int py = (t / TX) * TILE + (threadIdx.x >> 4);
   const bool inside = px < W && py < H;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  const uint2 rg = ranges[gt];
+  const uint2 r1 = ranges[gt], r2 = ranges2[gt];
   const size_t hw = (size_t)H * W;
   const size_t pix = (size_t)py * W + px;
 
@@ -264,7 +317,7 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
     const int cnt = end - beg;
     __syncthreads();
     if ((int)threadIdx.x < cnt) {
-      const uint32_t e = values[rg.x + beg + threadIdx.x];
+      const uint32_t e = list_entry(values, r1, r2, beg + (int)threadIdx.x);
       const float4* sp = reinterpret_cast<const float4*>(splat + (size_t)e * SPLAT_STRIDE);
       s_a[threadIdx.x] = sp[0];
       s_b[threadIdx.x] = sp[1];
@@ -345,9 +398,23 @@ hipError_t launch_render_forward(const clsp_projected& proj, const clsp_bins& bi
                                  void* state, hipStream_t s) {
   const int T = TX * TY;
   const int blocks = views * T;
-  hipLaunchKernelGGL(render_forward_kernel, dim3(blocks), dim3(NT), 0, s, proj.splat, bins.values,
-                     reinterpret_cast<const uint2*>(bins.ranges), bins.tile_list, bins.counters, T, TX, W, H, bg[0],
-                     bg[1], bg[2], image, T_final, n_contrib, state, (int64_t)blocks);
+  const int sliced = bins.mode == CLSP_BINS_DEPTH_SLICED;
+  const BinPlan plan = make_bin_plan(bins.n, views, W, H, bins.capacity);
+  char* ws = static_cast<char*>(bins.ws);
+  uint32_t* alive = bin_alive_flags(plan, ws);
+  float* carry = bin_carry(plan, ws);
+  const int wpv = (T + 31) / 32;
+  hipLaunchKernelGGL(render_forward_kernel<1>, dim3(blocks), dim3(NT), 0, s, proj.splat, bins.values,
+                     reinterpret_cast<const uint2*>(bins.ranges), reinterpret_cast<const uint2*>(bins.ranges2),
+                     bins.tile_list, bins.counters, T, TX, W, H, bg[0], bg[1], bg[2], image, T_final, n_contrib, state,
+                     (int64_t)blocks, sliced, alive, bins.alive_mask, wpv, carry);
+  if (!sliced) return hipGetLastError();
+  hipError_t err = launch_list_second_slab(plan, proj, bins, ws, s);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(render_forward_kernel<2>, dim3(blocks), dim3(NT), 0, s, proj.splat, bins.values,
+                     reinterpret_cast<const uint2*>(bins.ranges), reinterpret_cast<const uint2*>(bins.ranges2),
+                     bins.tile_list, bins.counters, T, TX, W, H, bg[0], bg[1], bg[2], image, T_final, n_contrib, state,
+                     (int64_t)blocks, sliced, alive, bins.alive_mask, wpv, carry);
   return hipGetLastError();
 }
 
@@ -367,7 +434,8 @@ hipError_t launch_render_backward(const clsp_projected& proj, const clsp_bins& b
   hipError_t err = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, (a1 - a0) * views * G2D_STRIDE, s);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(render_backward_kernel, dim3(views * T, CHUNKS), dim3(NT), 0, s, proj.splat, bins.values,
-                     reinterpret_cast<const uint2*>(bins.ranges), bins.tile_list, bins.counters, T, TX, W, H, n,
+                     reinterpret_cast<const uint2*>(bins.ranges), reinterpret_cast<const uint2*>(bins.ranges2),
+                     bins.tile_list, bins.counters, T, TX, W, H, n,
                      bg[0], bg[1], bg[2], a0, a1, T_final, n_contrib, state, (int64_t)views * T, dL, grad2d);
   return hipGetLastError();
 }

@@ -52,20 +52,28 @@ class SplatOptimizer:
 
     def ensure_capacity(self, headroom=1.15):
         """Size the pair buffers for every view at the current parameters (reads the
-        device pair counts once per view; not part of a step)."""
+        device pair counts once per view; not part of a step).  The complete lists'
+        pair count bounds the depth-sliced lists' for the same parameters."""
         need = 1
+        dev = self.params.means.device
+        W, H = self.cams[0].width, self.cams[0].height
+        probe = None
         for vi in range(len(self.cams)):
             cam = [self.cams[vi]]
             api.project_preprocess(self.params, cam, self.proj)
-            b = self.bins if self.bins is not None else api.BinBuffers.alloc(
-                self.n, 1, cam[0].width, cam[0].height, self._capacity or 1 << 20, self.params.means.device)
-            api.bin_and_sort(self.proj, cam, self.active, self.local, b)
-            need = max(need, b.read_counters()["pairs"])
-            self.bins = b
-        if self.bins.capacity < need:
-            cap = int(need * headroom) + 1024
-            self.bins = api.BinBuffers.alloc(self.n, 1, self.cams[0].width, self.cams[0].height, cap,
-                                             self.params.means.device)
+            if probe is None:
+                probe = api.BinBuffers.alloc(self.n, 1, W, H, self._capacity or 1 << 20, dev, _ffi.BINS_COMPLETE)
+            while True:
+                api.bin_and_sort(self.proj, cam, self.active, self.local, probe)
+                c = probe.read_counters()
+                if not c["overflow"]:
+                    break
+                probe = api.BinBuffers.alloc(self.n, 1, W, H, int(c["pairs"] * 1.05) + 1024, dev, _ffi.BINS_COMPLETE)
+            need = max(need, c["pairs"])
+        del probe
+        cap = int(need * headroom) + 1024
+        if self.bins is None or self.bins.capacity < cap:
+            self.bins = api.BinBuffers.alloc(self.n, 1, W, H, cap, dev)
         self.bins.counters.zero_()
         self._prepare_calls()
         return need
@@ -133,8 +141,7 @@ class SplatOptimizer:
         use_mask = 1 if self.local else 0
         check(L.clsp_zero_grads(by(self._gr), self._range, st))
         check(L.clsp_project_preprocess(by(self._g), cam, 1, by(self._proj), st))
-        check(L.clsp_bin_and_sort(by(self._proj), self.n, cam, 1, self._range, use_mask, by(self._bins), P["ws"],
-                                  self._sizes[0], st))
+        check(L.clsp_bin_and_sort(by(self._proj), cam, 1, self._range, use_mask, by(self._bins), st))
         if events is not None:
             events[0].record(stream)
         check(L.clsp_render_forward(by(self._proj), by(self._bins), cam, 1, self._bg, P["image"], P["T"], P["nc"],

@@ -229,7 +229,7 @@ class GpuBackend:
     def _capacity(self, reqs):
         key = reqs[0].key
         n = len(self.store.gathers[key[0]])
-        per = self.pairs_per_view.get(key, 24 * n)
+        per = self.pairs_per_view.get(key, 4 * n)
         return int(per * len(reqs) * 1.2) + 4096
 
     def estimate_bytes(self, reqs):
@@ -240,7 +240,7 @@ class GpuBackend:
         ws = self.api.lib().clsp_bin_and_sort_workspace_bytes(n, V, W, H, cap)
         TX, TY = self.api.tile_grid(W, H)
         proj = n * V * (48 + 4 + 8 + 4)
-        bins = cap * 8 + V * TX * TY * 16 + 64
+        bins = cap * 8 + V * TX * TY * 24 + 128
         images = V * H * W * (12 + 4 + 4)
         return int(proj + bins + ws + images)
 
@@ -283,12 +283,11 @@ class GpuBackend:
         cap = self._capacity([req])
         while True:
             bins = api.bin_and_sort(proj, [req.camera], capacity=cap)
+            img, _, _ = api.render_forward(proj, bins, [req.camera], self.bg)
             c = bins.read_counters()
             if not c["overflow"]:
-                break
+                return img[0]
             cap = int(c["pairs"] * 1.2) + 4096
-        img, _, _ = api.render_forward(proj, bins, [req.camera], self.bg)
-        return img[0]
 
 
 def poisson_requests(rng, n_requests, qps, timesteps, resolutions, camera_fn):

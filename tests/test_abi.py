@@ -46,7 +46,7 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(_ffi.Camera) == 4 * 18
     assert ctypes.sizeof(_ffi.Gaussians) == 6 * 8 + 8 + 8 + 4 + 4
     assert ctypes.sizeof(_ffi.Params) == 5 * 8 + 8 + 4 + 4
-    assert ctypes.sizeof(_ffi.Bins) == 7 * 8
+    assert ctypes.sizeof(_ffi.Bins) == 9 * 8 + 8 + 8 + 8 + 4 + 4
     assert ctypes.sizeof(_ffi.AdamHParams) == 4 * 10 + 8
 
 
@@ -93,18 +93,30 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
     big = _cam(16384, 16384)   # more than 65536 tiles per view
     assert L.clsp_project_preprocess(ctypes.byref(g), big, 1, ctypes.byref(proj), None) == _ffi.CLSP_ERR_INVALID_ARG
 
-    bins = _ffi.Bins(fake, fake, fake, fake, fake, fake, 100)
     ws_need = L.clsp_bin_and_sort_workspace_bytes(10, 1, 64, 48, 100)
+    bins = _ffi.Bins(fake, fake, fake, fake, fake, fake, fake, fake, fake, ws_need, 100, 10, 1, 0)
     # active range outside [0, n]
-    assert L.clsp_bin_and_sort(ctypes.byref(proj), 10, cam, 1, _ffi.Range(5, 11), 1, ctypes.byref(bins), fake,
-                               ws_need, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_bin_and_sort(ctypes.byref(proj), cam, 1, _ffi.Range(5, 11), 1, ctypes.byref(bins),
+                               None) == _ffi.CLSP_ERR_INVALID_ARG
     # workspace too small
-    assert L.clsp_bin_and_sort(ctypes.byref(proj), 10, cam, 1, _ffi.Range(5, 10), 1, ctypes.byref(bins), fake,
-                               ws_need - 1, None) == _ffi.CLSP_ERR_INVALID_ARG
+    bins.ws_bytes = ws_need - 1
+    assert L.clsp_bin_and_sort(ctypes.byref(proj), cam, 1, _ffi.Range(5, 10), 1, ctypes.byref(bins),
+                               None) == _ffi.CLSP_ERR_INVALID_ARG
     assert b"workspace" in L.clsp_last_error()
+    bins.ws_bytes = 1 << 40
+    bins.mode = 7
+    assert L.clsp_bin_and_sort(ctypes.byref(proj), cam, 1, _ffi.Range(5, 10), 1, ctypes.byref(bins),
+                               None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert b"mode" in L.clsp_last_error()
+    bins.mode = 0
     bins.capacity = 1 << 33
-    assert L.clsp_bin_and_sort(ctypes.byref(proj), 10, cam, 1, _ffi.Range(5, 10), 1, ctypes.byref(bins), fake,
-                               1 << 40, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_bin_and_sort(ctypes.byref(proj), cam, 1, _ffi.Range(5, 10), 1, ctypes.byref(bins),
+                               None) == _ffi.CLSP_ERR_INVALID_ARG
+    bins.capacity = 100
+    bins.ranges2 = None
+    assert L.clsp_bin_and_sort(ctypes.byref(proj), cam, 1, _ffi.Range(5, 10), 1, ctypes.byref(bins),
+                               None) == _ffi.CLSP_ERR_INVALID_ARG
+    bins.ranges2 = fake
 
     p = _ffi.Params(fake, fake, fake, fake, fake, 10, 0, 0)
     hp = _ffi.AdamHParams()
@@ -122,9 +134,9 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
                                   ctypes.byref(p), fake, 1 << 20, None) == _ffi.CLSP_ERR_INVALID_ARG
     # the backward needs the forward's compositing state
     g.n_rows, g.gather = 10, None
-    assert L.clsp_render_backward(ctypes.byref(g), ctypes.byref(proj), ctypes.byref(_ffi.Bins(fake, fake, fake, fake,
-                                  fake, fake, 100)), cam, 1, (ctypes.c_float * 3)(0, 0, 0), _ffi.Range(0, 10), fake,
-                                  fake, None, 0, fake, ctypes.byref(p), fake, 1 << 20, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_render_backward(ctypes.byref(g), ctypes.byref(proj), ctypes.byref(bins), cam, 1,
+                                  (ctypes.c_float * 3)(0, 0, 0), _ffi.Range(0, 10), fake, fake, None, 0, fake,
+                                  ctypes.byref(p), fake, 1 << 20, None) == _ffi.CLSP_ERR_INVALID_ARG
     assert b"state" in L.clsp_last_error()
     assert L.clsp_render_state_bytes(1, 64, 48) >= 12 * 8 * 256 * 16
 

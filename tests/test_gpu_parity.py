@@ -14,6 +14,7 @@ import scenes
 from gpu_helpers import (bin_reference_for, check_grads, check_pixels, gpu_preprocess, masked_pixels, to_np,
                          unpack)
 from paper_2506_21117_amd import api
+from paper_2506_21117_amd._ffi import BINS_COMPLETE as COMPLETE
 
 pytestmark = pytest.mark.gpu
 
@@ -48,6 +49,17 @@ def workload(name):
 
 
 CASES = ["tiny", "sh3", "clamp", "ring2"]
+
+
+def _sliced_case(name):
+    if name == "local":
+        w = scenes.local_change(n=60_000, n_views=2, width=320, height=180, fx=320.0)
+        return w.scene, w.cameras[:1], (w.active_begin, w.scene.n)
+    if name == "cloud":
+        w = scenes.full_scene(n=40_000, n_views=2, res=160, fx=220.0)
+        return w.scene, w.cameras, (36_000, 40_000)
+    sc, cams = workload(name)
+    return sc, cams, (int(sc.n * 0.8), sc.n)
 
 
 # ------------------------------------------------------------------ a1 preprocess
@@ -130,7 +142,7 @@ def test_bin_and_sort_bit_exact(dev, case, use_mask):
     g = api.GaussianTensors.from_scene(sc, dev)
     proj = gpu_preprocess(g, cams)
     active = (int(sc.n * 0.8), sc.n)
-    bins = api.bin_and_sort(proj, cams, active, use_mask, capacity=200_000)
+    bins = api.bin_and_sort(proj, cams, active, use_mask, capacity=200_000, mode=COMPLETE)
     torch.cuda.synchronize()
     P = _check_bins(bins, proj, cams, active, use_mask)
     assert P > 0
@@ -143,7 +155,7 @@ def test_bin_and_sort_many_tile_bits(dev):
     g = api.GaussianTensors.from_scene(w.scene, dev)
     proj = gpu_preprocess(g, cams)
     for use_mask in (False, True):
-        bins = api.bin_and_sort(proj, cams, (3000, 4000), use_mask, capacity=2_000_000)
+        bins = api.bin_and_sort(proj, cams, (3000, 4000), use_mask, capacity=2_000_000, mode=COMPLETE)
         torch.cuda.synchronize()
         _check_bins(bins, proj, cams, (3000, 4000), use_mask)
 
@@ -152,16 +164,31 @@ def test_capacity_overflow_is_reported_and_recoverable(dev):
     sc, cams = workload("tiny")
     g = api.GaussianTensors.from_scene(sc, dev)
     proj = gpu_preprocess(g, cams)
-    small = api.bin_and_sort(proj, cams, capacity=100)
+    small = api.bin_and_sort(proj, cams, capacity=100, mode=COMPLETE)
     c = small.read_counters()
     assert c["overflow"] and c["pairs"] > 100 and c["written"] == 0 and c["tiles"] == 0
     assert to_np(small.counters)[5] == 1            # sticky
     img, _, _ = api.render_forward(proj, small, cams)   # renders nothing, touches nothing
     torch.cuda.synchronize()
     assert float(img.abs().sum()) == 0.0
-    big = api.bin_and_sort(proj, cams, capacity=c["pairs"])
+    big = api.bin_and_sort(proj, cams, capacity=c["pairs"], mode=COMPLETE)
     torch.cuda.synchronize()
     _check_bins(big, proj, cams, None, False)
+    # depth-sliced lists: an overflow in the first slab ...
+    sl = api.bin_and_sort(proj, cams, capacity=c["pairs"] // 3)
+    api.render_forward(proj, sl, cams)
+    assert sl.read_counters()["overflow"] and to_np(sl.counters)[5] == 1
+    # ... and in the second (a sparse cloud: more than one slab, edge tiles still alive)
+    sc2, cams2, _ = _sliced_case("cloud")
+    proj2 = gpu_preprocess(api.GaussianTensors.from_scene(sc2, dev), cams2)
+    ok = api.bin_and_sort(proj2, cams2, capacity=20_000_000)
+    api.render_forward(proj2, ok, cams2)
+    r = ok.read_counters()
+    assert not r["overflow"] and r["alive"] > 0 and r["pairs"] > r["pairs1"]
+    tight = api.bin_and_sort(proj2, cams2, capacity=r["pairs1"] + 1)
+    api.render_forward(proj2, tight, cams2)
+    t2 = tight.read_counters()
+    assert t2["overflow"] and t2["alive"] > 0 and t2["pairs"] == r["pairs"]
 
 
 # ------------------------------------------------------------------ a4 forward
@@ -207,7 +234,7 @@ def test_single_tile_image(dev):
     cam = scenes.Camera(np.eye(3), (0, 0, 4), 16, 16, 8, 8, 16, 16)
     g = api.GaussianTensors.from_scene(w.scene, dev)
     proj = gpu_preprocess(g, [cam])
-    bins = api.bin_and_sort(proj, [cam], capacity=10_000)
+    bins = api.bin_and_sort(proj, [cam], capacity=10_000, mode=COMPLETE)
     img, _, _ = api.render_forward(proj, bins, [cam])
     torch.cuda.synchronize()
     _check_bins(bins, proj, [cam], None, False)
@@ -386,3 +413,69 @@ def test_masked_adam_parity(dev, sh_degree, with_mask):
     for T1, T0 in ((P, P0), (M, M0), (V, V0)):
         for k in names:
             np.testing.assert_array_equal(to_np(getattr(T1, k))[..., frozen], to_np(getattr(T0, k))[..., frozen])
+
+
+# ------------------------------------------------------------------ depth-sliced lists
+@pytest.mark.parametrize("case", ["tiny", "ring2", "local", "cloud"])
+@pytest.mark.parametrize("local", [False, True])
+def test_depth_sliced_lists_match_complete_lists(dev, case, local):
+    """Every sliced list is a prefix of the complete list (the complete list itself for
+    tiles that needed the second slab), and images, transmittance, contributor counts
+    are bit-identical; gradients agree up to float32 summation order."""
+    sc, cams, a = _sliced_case(case)
+    act = a if local else None
+    g = api.GaussianTensors.from_scene(sc, dev)
+    proj = gpu_preprocess(g, cams)
+    out = {}
+    for mode in (COMPLETE, api._ffi.BINS_DEPTH_SLICED):
+        bins = api.bin_and_sort(proj, cams, act, local, capacity=8_000_000, mode=mode)
+        state = api.render_state(cams, dev)
+        img, T, nc = api.render_forward(proj, bins, cams, (0.1, 0.2, 0.3), state=state)
+        dl = torch.as_tensor(np.random.default_rng(4).normal(size=img.shape).astype(np.float32), device=dev)
+        grads = g.zeros_like()
+        api.render_backward(g, proj, bins, cams, (0.1, 0.2, 0.3), act, T, nc, state, dl, grads)
+        torch.cuda.synchronize()
+        c = bins.read_counters()
+        assert not c["overflow"]
+        out[mode] = (bins, to_np(img), to_np(T), to_np(nc), grads, c)
+    cb, ci, cT, cn, cg, cc = out[COMPLETE]
+    sb, si, sT, sn, sg, scn = out[api._ffi.BINS_DEPTH_SLICED]
+    np.testing.assert_array_equal(si, ci)
+    np.testing.assert_array_equal(sT, cT)
+    np.testing.assert_array_equal(sn, cn)
+    assert scn["pairs"] <= cc["pairs"] and scn["tiles"] == cc["tiles"]
+    vals_c, vals_s = to_np(cb.values).view(np.uint32), to_np(sb.values).view(np.uint32)
+    rc = to_np(cb.ranges).view(np.uint32).astype(np.int64)
+    r1 = to_np(sb.ranges).view(np.uint32).astype(np.int64)
+    r2 = to_np(sb.ranges2).view(np.uint32).astype(np.int64)
+    alive = to_np(sb.alive_mask).view(np.uint32)
+    TX, TY = api.tile_grid(cams[0].width, cams[0].height)
+    T_ = TX * TY
+    maxnc = {}
+    for gt in to_np(cb.tile_list)[:cc["tiles"]]:
+        full = vals_c[rc[gt, 0]:rc[gt, 1]]
+        lst = np.concatenate([vals_s[r1[gt, 0]:r1[gt, 1]], vals_s[r2[gt, 0]:r2[gt, 1]]])
+        np.testing.assert_array_equal(lst, full[:len(lst)])
+        v, t = divmod(int(gt), T_)
+        if (alive[v][t // 32] >> (t % 32)) & 1:
+            assert len(lst) == len(full)
+    # the sliced lists reach every pixel's last contributor
+    for v in range(len(cams)):
+        ncv = cn[v]
+        for gt in to_np(cb.tile_list)[:cc["tiles"]]:
+            vv, t = divmod(int(gt), T_)
+            if vv != v:
+                continue
+            ty, tx = divmod(t, TX)
+            m = int(ncv[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16].max(initial=0))
+            assert (r1[gt, 1] - r1[gt, 0]) + (r2[gt, 1] - r2[gt, 0]) >= m
+    rows = slice(a[0], a[1]) if local else slice(0, sc.n)
+    for k in api.GaussianTensors.NAMES:
+        x = to_np(getattr(sg, k))[..., rows].astype(np.float64)
+        y = to_np(getattr(cg, k))[..., rows].astype(np.float64)
+        scale = np.sqrt((y ** 2).mean()) + 1e-30
+        assert np.abs(x - y).max() <= 1e-4 * np.abs(y).max() + 1e-3 * scale, k
+    if case == "local":
+        assert scn["pairs"] < cc["pairs"]           # the dense local scene terminates early
+    if case == "cloud" and not local:
+        assert scn["alive"] > 0                     # some tiles needed the second slab

@@ -27,7 +27,7 @@ def test_gathered_state_equals_snapshot(dev, store_and_states):
     for k in (0, 2, len(states) - 1):
         snap = api.GaussianTensors.from_scene(states[k], dev)
         proj = api.project_preprocess(snap, [cam])
-        bins = api.bin_and_sort(proj, [cam], capacity=4_000_000)
+        bins = api.bin_and_sort(proj, [cam], capacity=4_000_000, mode=api._ffi.BINS_COMPLETE)
         ref, _, _ = api.render_forward(proj, bins, [cam])
         from paper_2506_21117_amd.serve import Request
         got = be.render_alone(Request(0, k, cam))
