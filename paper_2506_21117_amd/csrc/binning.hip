@@ -441,16 +441,15 @@ __global__ void check_capacity_kernel(uint32_t* counters, uint64_t capacity, int
   counters[C_WRITTEN] = over ? 0u : p;
   if (over) {
     counters[C_STICKY] = 1u;
+    if (which == 1) counters[C_TILES] = 0u;  // no tile is rendered
     counters[C_SLAB_PAIRS] = 0u;  // nothing is emitted or sorted
     counters[C_SLAB_N] = 0u;
   }
 }
 
 // ------------------------------------------------------------------ 5. emission
-// Pairs staged in LDS per round of the masked emission.
-constexpr int EMIT_WIN = 4096;
-// Mask words kept in LDS by the masked emission (all views of the call).
-constexpr int EMIT_MASK_WORDS = 4096;
+// Mask words up to which the masked emission stages mask and word prefix in LDS.
+constexpr int EMIT_MASK_WORDS = 8192;
 
 // Full mode: every tile of every rectangle is a pair.  A block takes NT consecutive
 // entries of the slab; their pairs form one contiguous output range, which the
@@ -512,30 +511,48 @@ __global__ void __launch_bounds__(NT) emit_full_kernel(const uint32_t* __restric
   }
 }
 
-// Masked: each thread walks the tiles of its rectangle that are set in `mask`, row by
-// row (set bits of an LDS copy of the mask, so the cost follows those tiles, not the
-// rectangle's area), and stages its pairs in an LDS window that the block writes out
-// with coalesced stores.  Entries of the second slab may have no pair (their tiles are
-// no longer alive); they are skipped.
-template <bool LDS_MASK>
+// Masked: the same cooperative fill as the full mode, with the tiles of a rectangle
+// restricted to the set bits of `mask`.  The tiles of row ty of a rectangle that are in
+// the mask are a contiguous run of the mask's sorted tile list (`list`): from rank
+// rank(ty, x0) to rank(ty, x1), where rank(t) is the number of mask bits before tile t
+// of the view (the word prefix `wpre` plus a popcount inside the word).  A position
+// is mapped to its tile by walking the owner's rows, so the cost per pair follows the
+// rectangle's height, never a per-thread serial walk over another entry's pairs.
+// Entries of the second slab may have no pair (their tiles are no longer alive): they
+// own no position.  `LDS`: mask and word prefix are staged in LDS (dynamic size).
+__device__ __forceinline__ uint32_t mask_rank(const uint32_t* mk, const uint32_t* wp, uint32_t wv, uint32_t t) {
+  const uint32_t w = wv + (t >> 5), b = t & 31u;
+  return wp[w] + (b ? __popc(mk[w] & ((1u << b) - 1u)) : 0u);
+}
+
+template <bool LDS>
 __global__ void __launch_bounds__(NT) emit_masked_kernel(const uint32_t* __restrict__ order,
                                                          const uint32_t* __restrict__ offs,
-                                                         const uint32_t* __restrict__ cnt_sorted,
                                                          const uint2* __restrict__ rect,
                                                          const uint32_t* __restrict__ mask,
+                                                         const uint32_t* __restrict__ wpre,
+                                                         const uint32_t* __restrict__ list,
                                                          const uint32_t* __restrict__ counters, int64_t n, int TX,
-                                                         int T, int wpv, int views, uint32_t* __restrict__ pk,
+                                                         int wpv, int views, uint32_t* __restrict__ pk,
                                                          uint32_t* __restrict__ pv) {
-  __shared__ uint32_t s_k[EMIT_WIN];
-  __shared__ uint32_t s_v[EMIT_WIN];
-  __shared__ uint32_t s_mask[LDS_MASK ? EMIT_MASK_WORDS : 1];
+  extern __shared__ uint32_t s_tab[];  // LDS: mask words, then the word prefix
+  __shared__ uint32_t s_off[NT];
+  __shared__ uint32_t s_e[NT];
+  __shared__ uint2 s_r[NT];
+  __shared__ uint32_t s_wv[NT];  // first mask word of the entry's view
   if (counters[C_OVERFLOW]) return;
   const uint32_t m = counters[C_SLAB_N];
   if (blockIdx.x * NT >= m) return;
-  if (LDS_MASK) {
-    for (int w = threadIdx.x; w < views * wpv; w += NT) s_mask[w] = mask[w];
-    __syncthreads();
+  const uint32_t nw = (uint32_t)views * (uint32_t)wpv;
+  if (LDS) {
+    for (uint32_t w = threadIdx.x; w < nw; w += NT) {
+      s_tab[w] = mask[w];
+      s_tab[nw + w] = wpre[w];
+    }
+    if (threadIdx.x == 0) s_tab[2 * nw] = wpre[nw];
   }
+  const uint32_t* mk = LDS ? s_tab : mask;
+  const uint32_t* wp = LDS ? s_tab + nw : wpre;
   const uint32_t P = counters[C_SLAB_PAIRS];
   order += counters[C_SLAB_LO];
   const uint32_t pbase = counters[C_SLAB_BASE];
@@ -543,67 +560,42 @@ __global__ void __launch_bounds__(NT) emit_masked_kernel(const uint32_t* __restr
   pv += pbase;
   for (uint32_t j0 = blockIdx.x * NT; j0 < m; j0 += gridDim.x * NT) {
     const uint32_t j = j0 + threadIdx.x;
-    const uint32_t base = offs[j0];
-    const uint32_t last = min(j0 + NT, m);
-    const uint32_t end = last < m ? offs[last] : P;
-    uint32_t o = 0, o_end = 0, e = 0, x0 = 0, x1 = 0, y1 = 0, ty = 0, gbase = 0, bits = 0, wcur = 0, wlast = 0;
-    const uint32_t* vm = LDS_MASK ? s_mask : mask;
+    const uint32_t cnt = min((uint32_t)NT, m - j0);
+    __syncthreads();
     if (j < m) {
-      e = order[j];
-      o = offs[j];
-      o_end = o + cnt_sorted[j];
-      const uint32_t v = (uint32_t)(e / n);
-      const uint2 r = rect[e];
-      x0 = r.x & 0xffffu;
-      x1 = r.x >> 16;
-      ty = r.y & 0xffffu;
-      y1 = r.y >> 16;
-      vm += (int64_t)v * wpv;
-      gbase = v * (uint32_t)T;
-      wcur = (ty * TX + x0) >> 5;
-      wlast = (ty * TX + x1 - 1) >> 5;
+      const uint32_t e = order[j];
+      s_off[threadIdx.x] = offs[j];
+      s_e[threadIdx.x] = e;
+      s_r[threadIdx.x] = rect[e];
+      s_wv[threadIdx.x] = (uint32_t)(e / n) * (uint32_t)wpv;
     }
-    // bits of word w of row ty that lie in the rectangle and the mask
-    auto row_word = [&](uint32_t w) -> uint32_t {
-      const uint32_t lo = ty * TX + x0, hi = ty * TX + x1;  // tiles [lo, hi) of this row
-      uint32_t b = vm[w];
-      const uint32_t wlo = w << 5;
-      if (wlo < lo) b &= ~0u << (lo - wlo);
-      if (wlo + 32 > hi) b &= (hi - wlo >= 32) ? ~0u : ((1u << (hi - wlo)) - 1u);
-      return b;
-    };
-    if (j < m && o < o_end) bits = row_word(wcur);
-    for (uint32_t win = base; win < end; win += EMIT_WIN) {
-      const uint32_t win_end = min(win + (uint32_t)EMIT_WIN, end);
-      while (o < o_end && o < win_end) {
-        // advance to the next set bit (the count guarantees one exists; the row bound
-        // only stops a walk that could otherwise leave the rectangle)
-        while (bits == 0 && ty < y1) {
-          if (wcur < wlast) {
-            ++wcur;
-          } else {
-            if (++ty >= y1) break;
-            wcur = (ty * TX + x0) >> 5;
-            wlast = (ty * TX + x1 - 1) >> 5;
-          }
-          bits = row_word(wcur);
-        }
-        if (bits == 0) {
-          o = o_end;
+    __syncthreads();
+    const uint32_t base = s_off[0];
+    const uint32_t end = j0 + NT < m ? offs[j0 + NT] : P;
+    for (uint32_t pos = base + threadIdx.x; pos < end; pos += NT) {
+      // owner: the last entry whose offset is <= pos (an entry without pairs shares
+      // its offset with the next entry, which is then the owner)
+      uint32_t lo = 0, hi = cnt;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_off[mid] <= pos) lo = mid; else hi = mid;
+      }
+      uint32_t r = pos - s_off[lo];
+      const uint2 rc = s_r[lo];
+      const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu, y1 = rc.y >> 16;
+      const uint32_t wv = s_wv[lo];
+      uint32_t tile = 0;
+      for (uint32_t ty = y0; ty < y1; ++ty) {
+        const uint32_t a = mask_rank(mk, wp, wv, ty * TX + x0);
+        const uint32_t c = mask_rank(mk, wp, wv, ty * TX + x1) - a;
+        if (r < c) {
+          tile = list[a + r];
           break;
         }
-        const uint32_t b = __ffs(bits) - 1;
-        bits &= bits - 1;
-        s_k[o - win] = gbase + (wcur << 5) + b;
-        s_v[o - win] = e;
-        ++o;
+        r -= c;
       }
-      __syncthreads();
-      for (uint32_t p = threadIdx.x; p < win_end - win; p += NT) {
-        pk[win + p] = s_k[p];
-        pv[win + p] = s_v[p];
-      }
-      __syncthreads();
+      pk[pos] = tile;
+      pv[pos] = s_e[lo];
     }
   }
 }
@@ -621,21 +613,57 @@ __global__ void __launch_bounds__(NT) ranges_kernel(const uint32_t* __restrict__
   }
 }
 
-__global__ void __launch_bounds__(NT) tile_flags_kernel(const uint32_t* __restrict__ mask, int views, int T, int wpv,
-                                                        const uint32_t* __restrict__ counters,
-                                                        uint32_t* __restrict__ tflag) {
-  const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (g >= (int64_t)views * T) return;
-  const int v = (int)(g / T), t = (int)(g % T);
-  // no tile is rendered when the pair lists overflowed
-  tflag[g] = (!counters[C_OVERFLOW] && ((mask[(int64_t)v * wpv + (t >> 5)] >> (t & 31)) & 1u)) ? 1u : 0u;
-}
+// Index of a tile bitmap (V views of wpv words): wpre[w] = set bits in words [0, w)
+// (wpre[V*wpv] = total), and list = the set tiles as global indices v*T + t in
+// ascending order.  One block of MI_NT threads walks the words in chunks with a
+// running carry; the total goes to *count_out when given.
+constexpr int MI_NT = 1024;
+constexpr int MI_ITEMS = 4;
 
-__global__ void __launch_bounds__(NT) tile_list_kernel(const uint32_t* __restrict__ tflag,
-                                                       const uint32_t* __restrict__ tpos, int64_t count,
-                                                       uint32_t* __restrict__ list) {
-  const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (g < count && tflag[g]) list[tpos[g]] = (uint32_t)g;
+__global__ void __launch_bounds__(MI_NT) mask_index_kernel(const uint32_t* __restrict__ mask, int views, int wpv, int T,
+                                                           uint32_t* __restrict__ wpre, uint32_t* __restrict__ list,
+                                                           uint32_t* __restrict__ count_out) {
+  __shared__ uint32_t s_w[MI_NT / 64];
+  __shared__ uint32_t s_carry;
+  const uint32_t nw = (uint32_t)views * (uint32_t)wpv;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < nw; base += MI_NT * MI_ITEMS) {
+    uint32_t wd[MI_ITEMS];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < MI_ITEMS; ++k) {
+      const uint32_t idx = base + threadIdx.x * MI_ITEMS + k;
+      wd[k] = idx < nw ? mask[idx] : 0u;
+      sum += __popc(wd[k]);
+    }
+    const uint32_t inc = wave_incl_scan(sum);
+    const int wave = threadIdx.x >> 6;
+    if (lane_id() == 63) s_w[wave] = inc;
+    __syncthreads();
+    uint32_t off = 0, total = 0;
+    for (int k = 0; k < MI_NT / 64; ++k) {
+      if (k < wave) off += s_w[k];
+      total += s_w[k];
+    }
+    uint32_t run = s_carry + off + inc - sum;
+#pragma unroll
+    for (int k = 0; k < MI_ITEMS; ++k) {
+      const uint32_t idx = base + threadIdx.x * MI_ITEMS + k;
+      if (idx < nw) {
+        wpre[idx] = run;
+        const uint32_t v = idx / (uint32_t)wpv, t0 = (idx % (uint32_t)wpv) * 32u;
+        for (uint32_t bits = wd[k]; bits; bits &= bits - 1u) list[run++] = v * (uint32_t)T + t0 + (__ffs(bits) - 1u);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    wpre[nw] = s_carry;
+    if (count_out) *count_out = s_carry;
+  }
 }
 
 // ------------------------------------------------------------------ host helpers
@@ -701,7 +729,7 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uin
 int passes_for(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
 
 struct WsPtrs {
-  uint32_t *cnt, *tmp, *keyA, *valA, *keyB, *valB, *blk, *hist, *dtot, *pairK, *pairV, *tflag, *tpos;
+  uint32_t *cnt, *tmp, *keyA, *valA, *keyB, *valB, *blk, *hist, *dtot, *pairK, *pairV, *wpre, *tlist;
 };
 
 WsPtrs carve(const BinPlan& p, char* ws) {
@@ -717,15 +745,23 @@ WsPtrs carve(const BinPlan& p, char* ws) {
   w.dtot = reinterpret_cast<uint32_t*>(ws + p.off_digit);
   w.pairK = reinterpret_cast<uint32_t*>(ws + p.off_pairK);
   w.pairV = reinterpret_cast<uint32_t*>(ws + p.off_pairV);
-  w.tflag = reinterpret_cast<uint32_t*>(ws + p.off_tflag);
-  w.tpos = w.tflag + ((int64_t)p.views * p.T + 1);
+  w.wpre = reinterpret_cast<uint32_t*>(ws + p.off_tflag);
+  w.tlist = w.wpre + ((int64_t)p.views * p.T + 1);
   return w;
 }
 
+// Index of `mask` (word prefix into w.wpre, sorted tile list into `list`).
+void index_mask(const BinPlan& p, const uint32_t* mask, const WsPtrs& w, uint32_t* list, uint32_t* count_out,
+                hipStream_t s) {
+  const int wpv = (p.T + 31) / 32;
+  hipLaunchKernelGGL(mask_index_kernel, dim3(1), dim3(MI_NT), 0, s, mask, p.views, wpv, p.T, w.wpre, list, count_out);
+}
+
 // Lists one slab of the depth order (order = valA after the 32-bit depth sort):
-// counts, offsets, capacity check, emission (into `mask`'s tiles), tile sort, ranges.
+// counts, offsets, capacity check, emission (into `mask`'s tiles, whose index
+// w.wpre / `mlist` is built), tile sort, ranges.
 hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bins& bins, const WsPtrs& w, int which,
-                     int use_mask, const uint32_t* mask, uint32_t* ranges, hipStream_t s) {
+                     int use_mask, const uint32_t* mask, const uint32_t* mlist, uint32_t* ranges, hipStream_t s) {
   const int V = p.views;
   const int64_t n = p.n, E = p.entries;
   const int wpv = (p.T + 31) / 32;
@@ -750,11 +786,12 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
     hipLaunchKernelGGL(emit_full_kernel, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, w.valB, rect, counters, n,
                        p.TX, p.T, ek, ev);
   } else if ((int64_t)V * wpv <= EMIT_MASK_WORDS) {
-    hipLaunchKernelGGL(emit_masked_kernel<true>, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, w.valB, w.tmp, rect,
-                       mask, counters, n, p.TX, p.T, wpv, V, ek, ev);
+    const size_t lds = (size_t)(2 * V * wpv + 1) * 4;
+    hipLaunchKernelGGL(emit_masked_kernel<true>, dim3(grid_for(E, 1 << 16)), dim3(NT), lds, s, order, w.valB, rect,
+                       mask, w.wpre, mlist, counters, n, p.TX, wpv, V, ek, ev);
   } else {
-    hipLaunchKernelGGL(emit_masked_kernel<false>, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, w.valB, w.tmp,
-                       rect, mask, counters, n, p.TX, p.T, wpv, V, ek, ev);
+    hipLaunchKernelGGL(emit_masked_kernel<false>, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, w.valB, rect,
+                       mask, w.wpre, mlist, counters, n, p.TX, wpv, V, ek, ev);
   }
   if (tpasses > 0) {
     uint32_t *k1 = (ek == bins.keys) ? w.pairK : bins.keys, *v1 = (ev == bins.values) ? w.pairV : bins.values;
@@ -833,7 +870,7 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
   if ((err = launch_fill_u32(bins.ranges, 0u, gt * 2, s)) != hipSuccess) return err;
   if ((err = launch_fill_u32(bins.ranges2, 0u, gt * 2, s)) != hipSuccess) return err;
   if ((err = launch_fill_u32(bins.alive_mask, 0u, (int64_t)V * wpv, s)) != hipSuccess) return err;
-  // 1. mask
+  // 1. mask, and its index: the sorted list of tiles to render (all tiles in full mode)
   if (use_mask) {
     if ((err = launch_fill_u32(bins.tile_mask, 0u, (int64_t)V * wpv, s)) != hipSuccess) return err;
     if (a1 > a0) {
@@ -844,6 +881,7 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
     hipLaunchKernelGGL(mask_all_kernel, dim3(grid_for((int64_t)V * wpv, 1 << 20)), dim3(NT), 0, s, bins.tile_mask, V,
                        p.T, wpv);
   }
+  index_mask(p, bins.tile_mask, w, bins.tile_list, counters + C_TILES, s);
   if (E > 0) {
     // 2. counts
     hipLaunchKernelGGL(count_kernel, dim3(ceil_div(n, NT), V), dim3(NT), use_mask ? wpv * 4 : 0, s, rect, proj.flags,
@@ -856,13 +894,9 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
     radix_sort(w.keyA, w.valA, w.keyB, w.valB, counters + C_ENTRIES, nullptr, E, 32, w.hist, w.dtot, s);
     hipLaunchKernelGGL(slab_bounds_kernel, dim3(1), dim3(1), 0, s, counters, bins.mode == CLSP_BINS_DEPTH_SLICED);
     // 5-7 for the first slab (the whole order for complete lists)
-    if ((err = list_slab(p, proj, bins, w, 1, use_mask, bins.tile_mask, bins.ranges, s)) != hipSuccess) return err;
+    if ((err = list_slab(p, proj, bins, w, 1, use_mask, bins.tile_mask, bins.tile_list, bins.ranges, s)) != hipSuccess)
+      return err;
   }
-  // tile list (masked tiles; all tiles in full mode)
-  hipLaunchKernelGGL(tile_flags_kernel, dim3(ceil_div(gt, NT)), dim3(NT), 0, s, bins.tile_mask, V, p.T, wpv, counters,
-                     w.tflag);
-  if ((err = scan(w.tflag, w.tpos, nullptr, (uint32_t)gt, gt, w.blk, counters + C_TILES, s)) != hipSuccess) return err;
-  hipLaunchKernelGGL(tile_list_kernel, dim3(ceil_div(gt, NT)), dim3(NT), 0, s, w.tflag, w.tpos, gt, bins.tile_list);
   return hipGetLastError();
 }
 
@@ -870,7 +904,8 @@ hipError_t launch_list_second_slab(const BinPlan& p, const clsp_projected& proj,
                                    hipStream_t s) {
   if (p.entries == 0) return hipSuccess;
   const WsPtrs w = carve(p, ws);
-  return list_slab(p, proj, bins, w, 2, 1, bins.alive_mask, bins.ranges2, s);
+  index_mask(p, bins.alive_mask, w, w.tlist, nullptr, s);
+  return list_slab(p, proj, bins, w, 2, 1, bins.alive_mask, w.tlist, bins.ranges2, s);
 }
 
 uint32_t* bin_alive_flags(const BinPlan& p, char* ws) { return reinterpret_cast<uint32_t*>(ws + p.off_alive); }

@@ -274,6 +274,7 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
   __shared__ float4 s_b[NT];
   __shared__ float s_c[NT];
   __shared__ uint32_t s_e[NT];
+  __shared__ uint32_t s_act[NT];  // the record's Gaussian is in the active range
   __shared__ float s_g[NT][9];
 
   const uint32_t gt = tile_list[slot];
@@ -323,12 +324,31 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
       s_b[threadIdx.x] = sp[1];
       s_c[threadIdx.x] = sp[2].x;
       s_e[threadIdx.x] = e;
+      const int64_t gid = (int64_t)e - vbase;
+      s_act[threadIdx.x] = (gid >= a0 && gid < a1) ? 1u : 0u;
     }
 #pragma unroll
     for (int c = 0; c < 9; ++c) s_g[threadIdx.x][c] = 0.0f;
     __syncthreads();
     for (int j = cnt - 1; j >= 0; --j) {
       const int k = beg + j;
+      if (!s_act[j]) {
+        // a frozen Gaussian: only the transmittance and the colour behind move on
+        if (k < (int)last) {
+          const float4 a = s_a[j], b = s_b[j];
+          float dx, dy, G, alpha;
+          bool clamped;
+          if (splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped)) {
+            const float Tj = Tr / (1.0f - alpha);
+            const float w = alpha * Tj;
+            S0 = fmaf(w, b.z, S0);
+            S1 = fmaf(w, b.w, S1);
+            S2 = fmaf(w, s_c[j], S2);
+            Tr = Tj;
+          }
+        }
+        continue;
+      }
       float p[9];
 #pragma unroll
       for (int c = 0; c < 9; ++c) p[c] = 0.0f;
@@ -374,7 +394,7 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
     __syncthreads();
     if ((int)threadIdx.x < cnt) {
       const int64_t gid = (int64_t)s_e[threadIdx.x] - vbase;
-      if (gid >= a0 && gid < a1) {
+      if (s_act[threadIdx.x]) {
         float* dst = grad2d + ((int64_t)v * na + (gid - a0)) * G2D_STRIDE;
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
