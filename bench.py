@@ -30,8 +30,14 @@ def parse():
     ap.add_argument("--n", type=int, default=1_000_000, help="Gaussians (default: the 1M workload)")
     ap.add_argument("--no-full", action="store_true", help="skip the full-scene comparison")
     ap.add_argument("--only-full", action="store_true", help="time only the full-scene step (profiling)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
-    ap.add_argument("--cpu-pixels", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="time budget of the CPU oracle timing")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving latency leg")
+    ap.add_argument("--qps", type=float, default=100.0, help="arrival rate of the serving leg")
+    ap.add_argument("--requests", type=int, default=400, help="requests of the serving leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy 10 times (the reference kernel of known size for "
+                         "the HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -53,6 +59,14 @@ def main():
     from paper_2506_21117_amd.optim import SplatOptimizer
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 10 copies of 256 MiB (268435456 B read and written per copy)")
+        return 0
     t0 = time.time()
     w = scenes.local_change(n=args.n)
     sc, cams = w.scene, w.cameras
@@ -76,6 +90,7 @@ def main():
     log("targets rendered")
 
     order = np.random.default_rng(0).permutation(len(cams))
+    calls = SplatOptimizer.TIMED_CALLS
 
     def run(local):
         params = api.GaussianTensors.from_scene(sc, dev)
@@ -84,8 +99,9 @@ def main():
         for i in range(args.warmup):
             opt.step(int(order[i % len(order)]))
         torch.cuda.synchronize()
-        # HIP events around the dominant kernel's call, on the stream it runs on
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        # HIP events around each timed C-ABI call, on the stream the calls run on
+        mk = lambda: torch.cuda.Event(enable_timing=True)
+        ev = [{c: (mk(), mk()) for c in calls} for _ in range(args.steps)]
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         for i in range(args.steps):
@@ -94,39 +110,36 @@ def main():
         dt = time.perf_counter() - t_start
         if opt.overflowed():
             raise RuntimeError("pair capacity overflow during the timed steps")
-        fwd_ms = float(np.mean([s.elapsed_time(e) for s, e in ev]))
-        # algorithmic units of the timed kernel, from the last step's state
+        call_ms = {c: float(np.mean([e[c][0].elapsed_time(e[c][1]) for e in ev])) for c in calls}
+        # algorithmic units of the timed calls, from the last step's state
         stats = opt.render_stats()
-        return dt, fwd_ms, stats, opt
+        return dt, call_ms, stats, opt
 
     if args.only_full:
-        t_full, k_full, st_full, _ = run(False)
-        log(f"full: {args.steps / t_full:.1f} it/s, render_forward {k_full:.3f} ms, {st_full}")
+        t_full, ms_full, st_full, _ = run(False)
+        log(f"full: {args.steps / t_full:.1f} it/s, calls {ms_full}, {st_full}")
         return 0
-    t_local, k_local, st_local, opt_local = run(True)
+    t_local, ms_local, st_local, opt_local = run(True)
     it_local = args.steps / t_local
-    log(f"local: {it_local:.1f} it/s, render_forward {k_local:.3f} ms, {st_local}")
+    log(f"local: {it_local:.1f} it/s, calls {ms_local}, {st_local}")
     res_full = None
     if not args.no_full:
         del opt_local
         torch.cuda.empty_cache()
-        t_full, k_full, st_full, opt_full = run(False)
-        res_full = (args.steps / t_full, k_full, st_full)
-        log(f"full: {res_full[0]:.1f} it/s, render_forward {k_full:.3f} ms, {st_full}")
+        t_full, ms_full, st_full, opt_full = run(False)
+        res_full = (args.steps / t_full, ms_full, st_full)
+        log(f"full: {res_full[0]:.1f} it/s, calls {ms_full}, {st_full}")
         del opt_full
+    del targets
+    torch.cuda.empty_cache()
 
-    # roofline of render_forward (local step): algorithmic bytes per launch =
-    # records read (40 B each: 4 B id + 36 B record) + 20 B written per pixel
-    bytes_local = st_local["records"] * 40 + st_local["pixels"] * 20
-    achieved = bytes_local / (k_local * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "render_forward_kernel", "achieved": round(achieved, 2),
-                "peak": 8000.0, "unit": "GB/s", "frac": round(achieved / 8000.0, 5), "traffic": None,
-                "alu_achieved_tflops": round(st_local["pixel_records"] * 20 / (k_local * 1e-3) / 1e12, 3),
-                "alu_peak_tflops": 78.6}
-
+    roofline = roofline_of(ms_local, st_local, sc.n)
+    serving = None
+    if not args.no_serve:
+        serving = serving_leg(dev, args.qps, args.requests, log)
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(sc, cams, a, targets, args.cpu_pixels, opt_stats=st_local, log=log)
+        cpu = cpu_baseline(sc, cams, a, w.scene_gt, order, args.cpu_seconds, log)
 
     mpix = st_local["pixels"] * it_local / 1e6
     out = {
@@ -150,6 +163,10 @@ def main():
         "full_it_s": None if res_full is None else round(res_full[0], 3),
         "local_over_full": None if res_full is None else round(it_local / res_full[0], 3),
         "full_pairs": None if res_full is None else res_full[2]["pairs"],
+        "local_stats": st_local,
+        "call_ms_local": {k: round(v, 4) for k, v in ms_local.items()},
+        "call_ms_full": None if res_full is None else {k: round(v, 4) for k, v in res_full[1].items()},
+        "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -157,50 +174,134 @@ def main():
     return 0
 
 
-def cpu_baseline(sc, cams, a, targets, n_pix, opt_stats, log):
-    """The CPU reference (float64 brute force) on a bounded sample of one local step:
-    forward + backward of `n_pix` seeded pixels of view 0's render mask, scaled to the
-    full masked region of the step."""
+# FP32 operations per (pixel, record) evaluation, counted from the model's formulas:
+# the Gaussian weight (offset 2, quadratic form 9, exp 1, opacity product and clamp 2),
+# the transmittance update (2) and the colour sums (3 multiply-adds = 6) ...
+FLOP_EVAL = 22
+# ... and, for a record of the active range in the backward, its gradient terms: dL/dalpha
+# (3 x (2 mul + 1 sub) + 2 add + 1 reciprocal = 12), colour (3), opacity (1), power (1),
+# centre (2 x 4), conic (8) and the reduction over the pixels of the tile (9 adds per
+# pixel) = 42.
+FLOP_GRAD = 42
+# Peak of the FP32 vector units without packed math: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 (FMA) x 2.4 GHz.
+ALU_PEAK_TFLOPS = 78.6
+
+
+def roofline_of(ms, st, n):
+    """Roofline of the local step's dominant call (by measured time)."""
+    dom = max(ms, key=ms.get)
+    t = ms[dom] * 1e-3
+    if dom == "render_backward":
+        flops = FLOP_EVAL * st["pixel_records"] + FLOP_GRAD * st["pixel_records_active"]
+        ach = flops / t / 1e12
+        return {"bound": "alu", "kernel": "render_backward (raster backward + preprocess backward)",
+                "achieved": round(ach, 3), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / ALU_PEAK_TFLOPS, 5), "traffic": None,
+                "units": {"pixel_records": st["pixel_records"], "pixel_records_active": st["pixel_records_active"],
+                          "flop_per_eval": FLOP_EVAL, "flop_per_active_eval": FLOP_GRAD}}
+    if dom == "render_forward":
+        flops = FLOP_EVAL * st["pixel_records"]
+        ach = flops / t / 1e12
+        return {"bound": "alu", "kernel": "render_forward (both depth slabs)", "achieved": round(ach, 3),
+                "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / ALU_PEAK_TFLOPS, 5), "traffic": None,
+                "units": {"pixel_records": st["pixel_records"], "flop_per_eval": FLOP_EVAL}}
+    # binning: read the projected rectangles, flags and depths of all N entries
+    # (16 B), then per pair 44 B (emit 12 B, one sort read + write 24 B, range scan 8 B)
+    byts = 16 * n + 44 * st["pairs"]
+    ach = byts / t / 1e9
+    return {"bound": "hbm", "kernel": "bin_and_sort", "achieved": round(ach, 2), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(ach / 8000.0, 5), "traffic": None, "units": {"entries": n, "pairs": st["pairs"]}}
+
+
+def serving_leg(dev, qps, n_requests, log):
+    """Render latency of stored scene states under Poisson arrivals (the 2M-Gaussian
+    base with 7 change steps; resolutions 640x480, 1280x720, 1920x1080)."""
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2506_21117_amd.serve import Engine, GpuBackend, StateStore, poisson_requests
+
+    t0 = time.time()
+    states, history = scenes.serving_history(seed=5)
+    store = StateStore.from_history(states[-1], history)
+    del states, history
+    store.to_device(dev)
+    log(f"serving store: {store.n_rows} resident rows, {store.timesteps} timesteps, built in {time.time() - t0:.1f}s")
+    camfn = lambda r, W, H: scenes.sphere_camera(r, 4.0, width=W, height=H, fx=H / (2 * np.tan(np.radians(20))))
+    be = GpuBackend(store, dev, max_slots=4)
+    eng = Engine(be, hbm_budget_bytes=64 << 30, max_slots=4, max_batch=4)
+    # warm-up: one request per (timestep, resolution) learns the pair capacities
+    rng = np.random.default_rng(50)
+    warm = [poisson_requests(rng, 1, 0.0, 1, [res], camfn)[0] for res in scenes.RESOLUTIONS]
+    warm = [type(r)(i, k, r.camera, 0.0) for i, (k, r) in enumerate((k, r) for k in range(store.timesteps)
+                                                                      for r in warm)]
+    eng.run(warm)
+    torch.cuda.synchronize()
+    reqs = poisson_requests(np.random.default_rng(51), n_requests, qps, store.timesteps, scenes.RESOLUTIONS, camfn)
+    _, st = eng.run(reqs)
+    torch.cuda.synchronize()
+    s = st.summary()
+    log(f"serving at {qps} QPS: {s}")
+    return {"qps": qps, "requests": n_requests, "p50_ms": round(s["p50_ms"], 3), "p99_ms": round(s["p99_ms"], 3),
+            "mean_ms": round(s["mean_ms"], 3), "frames_per_s": round(s["frames_per_s"], 1), "groups": s["groups"],
+            "retries": s["retries"], "workload": "2M-Gaussian base + 7 change steps, SH3, resolutions "
+                                                 "640x480/1280x720/1920x1080, Poisson arrivals, max 4 views per call"}
+
+
+def cpu_baseline(sc, cams, a, scene_gt, order, budget_s, log):
+    """The CPU oracle (float64, brute force per pixel) running complete local steps of
+    the same workload until ``budget_s`` seconds have passed: project every Gaussian,
+    build the render mask from the change set, render every masked pixel, L1 gradient
+    against the oracle's own render of the unchanged scene at those pixels, render again
+    with that gradient, preprocess backward, Adam on the change set."""
     import numpy as np
 
     import oracle
-    from paper_2506_21117_amd import api
 
-    cam = cams[0]
-    # the render mask of view 0, from the reference's own projection (same formula)
-    pp = oracle.preprocess(sc, cam)
-    f32 = lambda k: pp[k].astype(np.float32)
-    TX, TY = api.tile_grid(cam.width, cam.height)
-    x0, x1, y0, y1 = oracle.tile_rects(f32("u"), f32("v"), f32("rx"), f32("ry"), cam.width, cam.height)
-    mask = np.zeros((TY, TX), bool)
-    for i in range(a[0], a[1]):
-        if pp["visible"][i] and x1[i] > x0[i] and y1[i] > y0[i]:
-            mask[y0[i]:y1[i], x0[i]:x1[i]] = True
-    ys, xs = np.nonzero(np.kron(mask, np.ones((16, 16), bool))[:cam.height, :cam.width])
-    all_pix = np.stack([xs, ys], 1).astype(np.int32)
-    rng = np.random.default_rng(7)
-    pix = all_pix[rng.choice(len(all_pix), size=min(n_pix, len(all_pix)), replace=False)]
-    dl = np.sign(rng.normal(size=(len(pix), 3))) / (3.0 * cam.width * cam.height)
+    names = ("means", "log_scales", "quats", "opacity_logit", "sh")
+    lrs = {"means": 1.6e-4, "log_scales": 5e-3, "quats": 1e-3, "opacity_logit": 5e-2, "sh": 2.5e-3}
+    params = {k: np.asarray(x, dtype=np.float64) for k, x in zip(names, sc.param_arrays())}
+    m = {k: np.zeros_like(x) for k, x in params.items()}
+    v = {k: np.zeros_like(x) for k, x in params.items()}
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    # fixed part of a step: projection and depth order of all Gaussians (one pixel)
-    t0 = time.perf_counter()
-    oracle.render(sc, cam, pixels=pix[:1])
-    t_fixed = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    r = oracle.render(sc, cam, pixels=pix, dL_dC=dl)
-    t_pix = max(0.0, time.perf_counter() - t0 - t_fixed)
-    t0 = time.perf_counter()
-    oracle.preprocess_backward(sc, cam, r["grad2d"])
-    t_pb = time.perf_counter() - t0
-    scale = len(all_pix) / len(pix)
-    per_step = t_fixed + t_pix * scale + t_pb
-    log(f"cpu reference: projection+sort {t_fixed:.1f}s, {len(pix)} of {len(all_pix)} masked pixels fwd+bwd "
-        f"{t_pix:.1f}s, preprocess backward {t_pb:.1f}s -> {per_step:.1f}s per local step")
-    return {"value": round(1.0 / per_step, 6), "unit": "it/s", "cores": threads, "kind": "oracle",
-            "sample": f"fp64 brute-force fwd+bwd of {len(pix)} seeded pixels of view 0's render mask "
-                      f"({len(all_pix)} masked pixels) of the 1M-Gaussian 1280x720 scene; per-pixel time scaled "
-                      f"by {scale:.1f}, plus one projection+depth sort and one preprocess backward of all "
-                      f"Gaussians (measured {t_fixed + t_pix + t_pb:.1f}s)"}
+    rows = slice(a[0], a[1])
+    steps = 0
+    t_start = time.perf_counter()
+    t_target = 0.0
+    while True:
+        cam = cams[int(order[steps % len(order)])]
+        pt = tuple(params[k] for k in names)
+        # the target pixels are rendered from the unchanged scene (not timed)
+        pp = oracle.preprocess(sc, cam, params=pt)
+        f32 = lambda k: pp[k].astype(np.float32)
+        x0, x1, y0, y1 = oracle.tile_rects(f32("u"), f32("v"), f32("rx"), f32("ry"), cam.width, cam.height)
+        TX, TY = oracle.tile_grid(cam.width, cam.height)
+        mask = np.zeros((TY, TX), bool)
+        for i in np.nonzero(pp["visible"][a[0]:a[1]])[0] + a[0]:
+            mask[y0[i]:y1[i], x0[i]:x1[i]] = True
+        ys, xs = np.nonzero(np.kron(mask, np.ones((16, 16), bool))[:cam.height, :cam.width])
+        pix = np.stack([xs, ys], 1).astype(np.int32)
+        t1 = time.perf_counter()
+        tgt = oracle.render(scene_gt, cam, pixels=pix)["rgb"]
+        t_target += time.perf_counter() - t1
+        img = oracle.render(sc, cam, pixels=pix, params=pt)["rgb"]
+        dl = np.sign(img - tgt) / (3.0 * cam.width * cam.height)
+        r = oracle.render(sc, cam, pixels=pix, dL_dC=dl, params=pt)
+        g = oracle.preprocess_backward(sc, cam, r["grad2d"], params=pt)
+        params, m, v = oracle.adam_step(params, g, m, v, steps + 1, lrs, rows=rows)
+        steps += 1
+        if time.perf_counter() - t_start - t_target >= budget_s:
+            break
+    dt = time.perf_counter() - t_start - t_target
+    log(f"cpu oracle: {steps} complete local steps in {dt:.1f}s ({threads} threads)")
+    return {"value": round(steps / dt, 6), "unit": "it/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} complete local steps (views in the bench's order) of the 1M-Gaussian 1280x720 "
+                      f"workload: fp64 projection of all Gaussians, render mask of the change set, brute-force "
+                      f"forward of every masked pixel, L1 gradient, brute-force forward+backward, preprocess "
+                      f"backward, Adam on the change set; {dt:.1f}s measured, no extrapolation (the render of "
+                      f"the targets at the masked pixels is excluded)"}
 
 
 if __name__ == "__main__":

@@ -18,6 +18,8 @@
 // only; after the forward pass has rendered it, they run again for the remaining
 // entries, emitting only into the tiles that still have compositing pixels (the
 // "alive" tiles), and the forward continues those tiles.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace clsp {
@@ -78,6 +80,24 @@ __device__ __forceinline__ void block_span(uint32_t n, int G, int b, uint32_t qu
 }
 
 // ------------------------------------------------------------------ fills
+// Zero up to CLEAR_SEGS buffers in one launch.
+constexpr int CLEAR_SEGS = 6;
+struct ClearList {
+  uint32_t* p[CLEAR_SEGS];
+  int64_t n[CLEAR_SEGS];
+  int k;
+};
+
+__global__ void clear_kernel(ClearList c) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;; i += (int64_t)gridDim.x * NT) {
+    int64_t j = i;
+    int s = 0;
+    while (s < c.k && j >= c.n[s]) j -= c.n[s++];
+    if (s == c.k) return;
+    c.p[s][j] = 0u;
+  }
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t value, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < count; i += (int64_t)gridDim.x * NT) p[i] = value;
 }
@@ -133,16 +153,29 @@ __device__ __forceinline__ uint32_t count_bits(const uint32_t* m, uint32_t lo, u
   return c;
 }
 
+// Corner table of a tile bitmap (built by mask_index_kernel): for view v, row ty in
+// [0, TY] and column x in [0, TX], tab[(v*(TY+1) + ty)*(TX+1) + x] = set tiles in rows
+// < ty and columns < x.  The set tiles of a rectangle, and the rank of a tile among
+// the view's set tiles in row-major order, follow from four and three entries.
+__device__ __forceinline__ uint32_t tab_rect(const uint32_t* tab, uint32_t vrow, uint32_t TXp, uint32_t x0, uint32_t x1,
+                                             uint32_t ya, uint32_t yb) {
+  const uint32_t* a = tab + (size_t)(vrow + ya) * TXp;
+  const uint32_t* b = tab + (size_t)(vrow + yb) * TXp;
+  return (b[x1] - b[x0]) - (a[x1] - a[x0]);
+}
+
+// Set tiles of the view before (ty, x), row-major (TX = TXp - 1).
+__device__ __forceinline__ uint32_t tab_rank(const uint32_t* tab, uint32_t vrow, uint32_t TXp, uint32_t ty, uint32_t x) {
+  const uint32_t* a = tab + (size_t)(vrow + ty) * TXp;
+  return a[TXp - 1] + (a[TXp + x] - a[x]);
+}
+
 // ------------------------------------------------------------------ 2. counts
+// Pairs of each entry: the rectangle's area, or its set tiles in the mask (corner table).
 __global__ void __launch_bounds__(NT) count_kernel(const uint2* __restrict__ rect, const uint32_t* __restrict__ flags,
-                                                   const uint32_t* __restrict__ mask, int64_t n, int TX, int wpv,
+                                                   const uint32_t* __restrict__ tab, int64_t n, int TX, int TY,
                                                    int use_mask, uint32_t* __restrict__ cnt, uint32_t* __restrict__ has) {
-  extern __shared__ uint32_t smask[];
   const int v = blockIdx.y;
-  if (use_mask) {
-    for (int w = threadIdx.x; w < wpv; w += NT) smask[w] = mask[(int64_t)v * wpv + w];
-    __syncthreads();
-  }
   const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (i >= n) return;
   const int64_t e = (int64_t)v * n + i;
@@ -154,7 +187,7 @@ __global__ void __launch_bounds__(NT) count_kernel(const uint2* __restrict__ rec
       if (!use_mask) {
         c = (x1 - x0) * (y1 - y0);
       } else {
-        for (uint32_t ty = y0; ty < y1; ++ty) c += count_bits(smask, ty * TX + x0, ty * TX + x1);
+        c = tab_rect(tab, (uint32_t)v * (uint32_t)(TY + 1), (uint32_t)(TX + 1), x0, x1, y0, y1);
       }
     }
   }
@@ -389,16 +422,13 @@ __global__ void __launch_bounds__(NT) rs_downsweep_kernel(const uint32_t* __rest
 }
 
 // ------------------------------------------------------------------ slabs of the depth order
-// counters[C_SLAB1] = entries of the first slab.
-__global__ void slab_bounds_kernel(uint32_t* counters, int sliced) {
-  const uint32_t m = counters[C_ENTRIES];
-  counters[C_SLAB1] = sliced ? min(m, max(m >> 4, 16384u)) : m;
-}
-
 // Select slab `which` (1: [0, S1), 2: [S1, M)) of the depth order: its first sorted
 // entry, entry count and the first pair position.
-__global__ void slab_select_kernel(uint32_t* counters, int which) {
-  const uint32_t m = counters[C_ENTRIES], s1 = counters[C_SLAB1];
+__global__ void slab_select_kernel(uint32_t* counters, int which, int sliced) {
+  const uint32_t m = counters[C_ENTRIES];
+  // the first slab: the nearest max(M/16, 16384) entries (all of them for complete lists)
+  if (which == 1) counters[C_SLAB1] = sliced ? min(m, max(m >> 4, 16384u)) : m;
+  const uint32_t s1 = counters[C_SLAB1];
   counters[C_SLAB_LO] = which == 1 ? 0u : s1;
   // the second slab is listed only if some tile is still alive
   counters[C_SLAB_N] = which == 1 ? s1 : (counters[C_ALIVE] ? m - s1 : 0u);
@@ -416,17 +446,15 @@ __global__ void __launch_bounds__(NT) gather_counts_kernel(const uint32_t* __res
 
 // ... or recounted against the tiles still alive (second slab).
 __global__ void __launch_bounds__(NT) recount_kernel(const uint32_t* __restrict__ order, const uint2* __restrict__ rect,
-                                                     const uint32_t* __restrict__ alive, const uint32_t* counters,
-                                                     int64_t n, int TX, int wpv, uint32_t* __restrict__ out) {
+                                                     const uint32_t* __restrict__ tab, const uint32_t* counters,
+                                                     int64_t n, int TX, int TY, uint32_t* __restrict__ out) {
   const uint32_t lo = counters[C_SLAB_LO], m = counters[C_SLAB_N];
   for (uint32_t j = blockIdx.x * NT + threadIdx.x; j < m; j += gridDim.x * NT) {
     const uint32_t e = order[lo + j];
-    const uint32_t* vm = alive + (uint32_t)(e / n) * (int64_t)wpv;
+    const uint32_t v = (uint32_t)(e / n);
     const uint2 r = rect[e];
     const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
-    uint32_t c = 0;
-    for (uint32_t ty = y0; ty < y1; ++ty) c += count_bits(vm, ty * TX + x0, ty * TX + x1);
-    out[j] = c;
+    out[j] = tab_rect(tab, v * (uint32_t)(TY + 1), (uint32_t)(TX + 1), x0, x1, y0, y1);
   }
 }
 
@@ -448,154 +476,172 @@ __global__ void check_capacity_kernel(uint32_t* counters, uint64_t capacity, int
 }
 
 // ------------------------------------------------------------------ 5. emission
-// Mask words up to which the masked emission stages mask and word prefix in LDS.
-constexpr int EMIT_MASK_WORDS = 8192;
+// Words (corner table + tile list) up to which the masked emission stages both in LDS
+// (with the static arrays, within 64 KB).
+constexpr int EMIT_TAB_WORDS = 10240;
+// Pairs one thread emits per round: a contiguous run, so the owner search and the
+// row search are paid once per run.
+constexpr int EMIT_RUN = 8;
+constexpr int EMIT_ROUND = NT * EMIT_RUN;
+// Entries per block: the first slab holds the nearest (largest) footprints, so its
+// entries are spread over more blocks.
+constexpr int EMIT_EPB_NEAR = 16;
+constexpr int EMIT_EPB = NT;
 
-// Full mode: every tile of every rectangle is a pair.  A block takes NT consecutive
-// entries of the slab; their pairs form one contiguous output range, which the
-// block's threads fill position by position (consecutive threads, consecutive
-// positions): the owner entry of a position is found by binary search over the NT
-// offsets in LDS and its tile follows from the position inside the rectangle.  Every
-// thread does the same work whatever the rectangle sizes, and every store is coalesced.
-__global__ void __launch_bounds__(NT) emit_full_kernel(const uint32_t* __restrict__ order,
-                                                       const uint32_t* __restrict__ offs,
-                                                       const uint2* __restrict__ rect,
-                                                       const uint32_t* __restrict__ counters, int64_t n, int TX,
-                                                       int T, uint32_t* __restrict__ pk, uint32_t* __restrict__ pv) {
-  __shared__ uint32_t s_off[NT];
-  __shared__ uint32_t s_e[NT];
-  __shared__ uint32_t s_org[NT];   // global tile of the rectangle's first tile
-  __shared__ uint32_t s_w[NT];     // rectangle width
-  __shared__ float s_iw[NT];       // 1 / width
-  if (counters[C_OVERFLOW]) return;
-  const uint32_t m = counters[C_SLAB_N];
-  const uint32_t P = counters[C_SLAB_PAIRS];
-  order += counters[C_SLAB_LO];
-  const uint32_t pbase = counters[C_SLAB_BASE];
-  pk += pbase;
-  pv += pbase;
-  for (uint32_t j0 = blockIdx.x * NT; j0 < m; j0 += gridDim.x * NT) {
-    const uint32_t j = j0 + threadIdx.x;
-    const uint32_t cnt = min((uint32_t)NT, m - j0);
-    __syncthreads();
-    if (j < m) {
-      const uint32_t e = order[j];
-      const uint2 r = rect[e];
-      const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu;
-      const uint32_t w = x1 - x0;
-      s_off[threadIdx.x] = offs[j];
-      s_e[threadIdx.x] = e;
-      s_org[threadIdx.x] = (uint32_t)(e / n) * (uint32_t)T + y0 * TX + x0;
-      s_w[threadIdx.x] = w;
-      s_iw[threadIdx.x] = 1.0f / (float)(w > 0 ? w : 1);
-    }
-    __syncthreads();
-    const uint32_t base = s_off[0];
-    const uint32_t end = j0 + NT < m ? offs[j0 + NT] : P;
-    for (uint32_t pos = base + threadIdx.x; pos < end; pos += NT) {
-      // owner: the last entry whose offset is <= pos (every slab entry has pairs, so
-      // offsets strictly increase)
-      uint32_t lo = 0, hi = cnt;
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_off[mid] <= pos) lo = mid; else hi = mid;
-      }
-      const uint32_t r = pos - s_off[lo];
-      const uint32_t w = s_w[lo];
-      uint32_t row = (uint32_t)((float)r * s_iw[lo]);
-      if (row * w > r) --row;
-      else if ((row + 1) * w <= r) ++row;
-      pk[pos] = s_org[lo] + row * TX + (r - row * w);
-      pv[pos] = s_e[lo];
-    }
-  }
-}
+// LDS slot of run position p (runs padded to EMIT_RUN + 1 words against bank conflicts).
+__device__ __forceinline__ uint32_t run_slot(uint32_t p) { return (p / EMIT_RUN) * (EMIT_RUN + 1) + p % EMIT_RUN; }
 
-// Masked: the same cooperative fill as the full mode, with the tiles of a rectangle
-// restricted to the set bits of `mask`.  The tiles of row ty of a rectangle that are in
-// the mask are a contiguous run of the mask's sorted tile list (`list`): from rank
-// rank(ty, x0) to rank(ty, x1), where rank(t) is the number of mask bits before tile t
-// of the view (the word prefix `wpre` plus a popcount inside the word).  A position
-// is mapped to its tile by walking the owner's rows, so the cost per pair follows the
-// rectangle's height, never a per-thread serial walk over another entry's pairs.
-// Entries of the second slab may have no pair (their tiles are no longer alive): they
-// own no position.  `LDS`: mask and word prefix are staged in LDS (dynamic size).
-__device__ __forceinline__ uint32_t mask_rank(const uint32_t* mk, const uint32_t* wp, uint32_t wv, uint32_t t) {
-  const uint32_t w = wv + (t >> 5), b = t & 31u;
-  return wp[w] + (b ? __popc(mk[w] & ((1u << b) - 1u)) : 0u);
-}
-
-template <bool LDS>
-__global__ void __launch_bounds__(NT) emit_masked_kernel(const uint32_t* __restrict__ order,
-                                                         const uint32_t* __restrict__ offs,
-                                                         const uint2* __restrict__ rect,
-                                                         const uint32_t* __restrict__ mask,
-                                                         const uint32_t* __restrict__ wpre,
-                                                         const uint32_t* __restrict__ list,
-                                                         const uint32_t* __restrict__ counters, int64_t n, int TX,
-                                                         int wpv, int views, uint32_t* __restrict__ pk,
-                                                         uint32_t* __restrict__ pv) {
-  extern __shared__ uint32_t s_tab[];  // LDS: mask words, then the word prefix
-  __shared__ uint32_t s_off[NT];
+// Emission of one slab: entry j of the slab (in depth order) writes (global tile,
+// entry) for its tiles at positions [offs[j], offs[j] + count).  Without MASKED every
+// tile of the rectangle is a pair (row-major); with MASKED only the tiles set in the
+// mask: those of row ty are the run [rank(ty, x0), rank(ty, x1)) of the mask's sorted
+// tile list `list`, ranks taken from the corner table `tab` plus the view's first list
+// position `vfirst[v]`.  A block takes `epb` consecutive entries; its threads take
+// contiguous runs of EMIT_RUN positions of the block's pair range, find the run's
+// owner entry (the last one whose offset is <= the position: an entry without pairs
+// shares its offset with the next one) and the pair's row (binary search over the
+// rectangle's rows on the table's prefix counts), and step through the row's tiles,
+// searching the row again whenever a row or an entry is exhausted.  Runs are staged in LDS and written out with coalesced stores.
+// LDS_TAB: the corner table and the first V*T words of the list are copied into
+// dynamic LDS.
+template <bool MASKED, bool LDS_TAB>
+__global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ order, const uint32_t* __restrict__ offs,
+                                                  const uint2* __restrict__ rect, const uint32_t* __restrict__ tab,
+                                                  const uint32_t* __restrict__ vfirst, const uint32_t* __restrict__ list,
+                                                  const uint32_t* __restrict__ counters, int64_t n, int TX, int TY,
+                                                  int views, int epb, uint32_t* __restrict__ pk,
+                                                  uint32_t* __restrict__ pv) {
+  extern __shared__ uint32_t s_tab[];  // LDS_TAB: the corner table, then the tile list
+  __shared__ uint32_t s_off[NT + 1];
   __shared__ uint32_t s_e[NT];
   __shared__ uint2 s_r[NT];
-  __shared__ uint32_t s_wv[NT];  // first mask word of the entry's view
+  __shared__ uint32_t s_vb[NT];  // MASKED: first table row of the view; else first global tile
+  __shared__ uint32_t s_vf[NT];  // MASKED: the view's first list position
+  __shared__ uint32_t s_k[NT * (EMIT_RUN + 1)];
+  __shared__ uint32_t s_v[NT * (EMIT_RUN + 1)];
   if (counters[C_OVERFLOW]) return;
   const uint32_t m = counters[C_SLAB_N];
-  if (blockIdx.x * NT >= m) return;
-  const uint32_t nw = (uint32_t)views * (uint32_t)wpv;
-  if (LDS) {
-    for (uint32_t w = threadIdx.x; w < nw; w += NT) {
-      s_tab[w] = mask[w];
-      s_tab[nw + w] = wpre[w];
+  if ((uint64_t)blockIdx.x * epb >= m) return;
+  const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
+  const uint32_t tab_words = (uint32_t)views * TYp * TXp;
+  if (MASKED && LDS_TAB) {
+    // eight loads in flight per thread
+    const uint32_t words = tab_words + (uint32_t)views * (uint32_t)(TX * TY);
+    for (uint32_t w0 = threadIdx.x; w0 < words; w0 += 8 * NT) {
+      uint32_t t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t w = w0 + u * NT;
+        t[u] = w < tab_words ? tab[w] : (w < words ? list[w - tab_words] : 0u);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (w0 + u * NT < words) s_tab[w0 + u * NT] = t[u];
     }
-    if (threadIdx.x == 0) s_tab[2 * nw] = wpre[nw];
   }
-  const uint32_t* mk = LDS ? s_tab : mask;
-  const uint32_t* wp = LDS ? s_tab + nw : wpre;
+  const uint32_t* tb = LDS_TAB ? s_tab : tab;
+  const uint32_t* tl = LDS_TAB ? s_tab + tab_words : list;
   const uint32_t P = counters[C_SLAB_PAIRS];
   order += counters[C_SLAB_LO];
   const uint32_t pbase = counters[C_SLAB_BASE];
   pk += pbase;
   pv += pbase;
-  for (uint32_t j0 = blockIdx.x * NT; j0 < m; j0 += gridDim.x * NT) {
-    const uint32_t j = j0 + threadIdx.x;
-    const uint32_t cnt = min((uint32_t)NT, m - j0);
+  // tiles of row ty of the current rectangle: global tiles a + [0, c) (full) or list
+  // entries a + [0, c) (masked)
+  auto row_span = [&](uint32_t vb, uint32_t vf, uint32_t ty, uint32_t x0, uint32_t x1, uint32_t& a, uint32_t& c) {
+    if (MASKED) {
+      a = vf + tab_rank(tb, vb, TXp, ty, x0);
+      c = vf + tab_rank(tb, vb, TXp, ty, x1) - a;
+    } else {
+      a = vb + ty * TX + x0;
+      c = x1 - x0;
+    }
+  };
+  for (uint32_t j0 = blockIdx.x * epb; j0 < m; j0 += gridDim.x * epb) {
+    const uint32_t cnt = min((uint32_t)epb, m - j0);
     __syncthreads();
-    if (j < m) {
-      const uint32_t e = order[j];
-      s_off[threadIdx.x] = offs[j];
+    if (threadIdx.x < cnt) {
+      const uint32_t e = order[j0 + threadIdx.x];
+      const uint32_t v = (uint32_t)(e / n);
+      s_off[threadIdx.x] = offs[j0 + threadIdx.x];
       s_e[threadIdx.x] = e;
       s_r[threadIdx.x] = rect[e];
-      s_wv[threadIdx.x] = (uint32_t)(e / n) * (uint32_t)wpv;
+      s_vb[threadIdx.x] = MASKED ? v * TYp : v * (uint32_t)(TX * TY);
+      s_vf[threadIdx.x] = MASKED ? vfirst[v] : 0u;
     }
+    if (threadIdx.x == 0) s_off[cnt] = j0 + cnt < m ? offs[j0 + cnt] : P;
     __syncthreads();
-    const uint32_t base = s_off[0];
-    const uint32_t end = j0 + NT < m ? offs[j0 + NT] : P;
-    for (uint32_t pos = base + threadIdx.x; pos < end; pos += NT) {
-      // owner: the last entry whose offset is <= pos (an entry without pairs shares
-      // its offset with the next entry, which is then the owner)
-      uint32_t lo = 0, hi = cnt;
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_off[mid] <= pos) lo = mid; else hi = mid;
-      }
-      uint32_t r = pos - s_off[lo];
-      const uint2 rc = s_r[lo];
-      const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu, y1 = rc.y >> 16;
-      const uint32_t wv = s_wv[lo];
-      uint32_t tile = 0;
-      for (uint32_t ty = y0; ty < y1; ++ty) {
-        const uint32_t a = mask_rank(mk, wp, wv, ty * TX + x0);
-        const uint32_t c = mask_rank(mk, wp, wv, ty * TX + x1) - a;
-        if (r < c) {
-          tile = list[a + r];
-          break;
+    const uint32_t base = s_off[0], end = s_off[cnt];
+    for (uint32_t rb = base; rb < end; rb += EMIT_ROUND) {
+      const uint32_t q0 = rb + threadIdx.x * EMIT_RUN;
+      const uint32_t q1 = min(q0 + EMIT_RUN, end);
+      if (q0 < q1) {
+        uint32_t lo = 0, hi = cnt;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (s_off[mid] <= q0) lo = mid; else hi = mid;
         }
-        r -= c;
+        // state of the current pair: entry lo, its rectangle, the pair's index re among
+        // the entry's pairs, its row ty, the row's tiles a + [0, c) and the index r in it
+        uint32_t x0 = 0, x1 = 0, y0 = 0, y1 = 0, vb = 0, vf = 0, e = 0, ne = 0;
+        uint32_t re = q0 - s_off[lo], ty = 0, a = 0, c = 0, r = 0;
+        auto load_entry = [&]() {
+          const uint2 rc = s_r[lo];
+          x0 = rc.x & 0xffffu;
+          x1 = rc.x >> 16;
+          y0 = rc.y & 0xffffu;
+          y1 = rc.y >> 16;
+          vb = s_vb[lo];
+          vf = s_vf[lo];
+          e = s_e[lo];
+          ne = s_off[lo + 1] - s_off[lo];
+        };
+        // the row holding pair re of the entry
+        auto locate = [&]() {
+          if (MASKED) {
+            // largest row t in [y0, y1) with (set tiles of rows [y0, t)) <= re
+            uint32_t ylo = y0, yhi = y1;
+            while (yhi - ylo > 1) {
+              const uint32_t mid = (ylo + yhi) >> 1;
+              if (tab_rect(tb, vb, TXp, x0, x1, y0, mid) <= re) ylo = mid; else yhi = mid;
+            }
+            ty = ylo;
+            r = re - tab_rect(tb, vb, TXp, x0, x1, y0, ty);
+          } else {
+            const uint32_t w = x1 - x0;
+            ty = y0 + re / w;
+            r = re % w;
+          }
+          row_span(vb, vf, ty, x0, x1, a, c);
+        };
+        load_entry();
+        locate();
+        for (uint32_t q = q0; q < q1; ++q) {
+          const uint32_t slot = run_slot(q - rb);
+          s_k[slot] = MASKED ? tl[a + r] : a + r;
+          s_v[slot] = e;
+          ++re;
+          if (++r < c || q + 1 == q1) continue;
+          if (re == ne) {
+            // the entry is done: the owner of position q + 1 (entries without pairs
+            // share their offset with it)
+            ++lo;
+            while (lo + 1 < cnt && s_off[lo + 1] <= q + 1) ++lo;
+            if (lo >= cnt) break;  // cannot happen with consistent counts
+            load_entry();
+            re = 0;
+          }
+          locate();
+        }
       }
-      pk[pos] = tile;
-      pv[pos] = s_e[lo];
+      __syncthreads();
+      const uint32_t len = min((uint32_t)EMIT_ROUND, end - rb);
+      for (uint32_t p = threadIdx.x; p < len; p += NT) {
+        const uint32_t slot = run_slot(p);
+        pk[rb + p] = s_k[slot];
+        pv[rb + p] = s_v[slot];
+      }
+      __syncthreads();
     }
   }
 }
@@ -613,16 +659,23 @@ __global__ void __launch_bounds__(NT) ranges_kernel(const uint32_t* __restrict__
   }
 }
 
-// Index of a tile bitmap (V views of wpv words): wpre[w] = set bits in words [0, w)
-// (wpre[V*wpv] = total), and list = the set tiles as global indices v*T + t in
-// ascending order.  One block of MI_NT threads walks the words in chunks with a
-// running carry; the total goes to *count_out when given.
+// Index of a tile bitmap (V views of TX x TY tiles, wpv words per view): `list` = the
+// set tiles as global indices v*T + t in ascending order, vfirst[v] = the list
+// position of view v's first set tile, and the corner table `tab` (see tab_rect).
+// One block of MI_NT threads walks the words in chunks with a running carry (wpre[w]
+// = set bits in words [0, w) is kept as scratch), then builds the table column by
+// column; the total goes to *count_out when given.
 constexpr int MI_NT = 1024;
 constexpr int MI_ITEMS = 4;
+constexpr int MI_TAB_WORDS = 12288;  // corner tables up to 48 KB are built in LDS
 
-__global__ void __launch_bounds__(MI_NT) mask_index_kernel(const uint32_t* __restrict__ mask, int views, int wpv, int T,
-                                                           uint32_t* __restrict__ wpre, uint32_t* __restrict__ list,
-                                                           uint32_t* __restrict__ count_out) {
+__global__ void __launch_bounds__(MI_NT) mask_index_kernel(const uint32_t* __restrict__ mask, int views, int wpv,
+                                                           int TX, int TY, uint32_t* __restrict__ wpre,
+                                                           uint32_t* __restrict__ list, uint32_t* __restrict__ vfirst,
+                                                           uint32_t* __restrict__ tab, uint32_t* __restrict__ count_out,
+                                                           int lds_tab) {
+  extern __shared__ uint32_t s_tab[];  // lds_tab: the corner table under construction
+  const int T = TX * TY;
   __shared__ uint32_t s_w[MI_NT / 64];
   __shared__ uint32_t s_carry;
   const uint32_t nw = (uint32_t)views * (uint32_t)wpv;
@@ -663,6 +716,30 @@ __global__ void __launch_bounds__(MI_NT) mask_index_kernel(const uint32_t* __res
   if (threadIdx.x == 0) {
     wpre[nw] = s_carry;
     if (count_out) *count_out = s_carry;
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < views; v += MI_NT) vfirst[v] = wpre[(uint32_t)v * wpv];
+  // corner table, built in LDS when it fits (lds_tab): first each row's prefix counts
+  // (all rows in parallel), then running sums down each column
+  const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
+  const uint32_t words = (uint32_t)views * TYp * TXp;
+  uint32_t* tb = lds_tab ? s_tab : tab;
+  for (uint32_t i = threadIdx.x; i < words; i += MI_NT) {
+    const uint32_t x = i % TXp, row = i / TXp, v = row / TYp, ty = row % TYp;
+    tb[i] = ty == 0 ? 0u : count_bits(mask + (size_t)v * wpv, (ty - 1) * TX, (ty - 1) * TX + x);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < (uint32_t)views * TXp; i += MI_NT) {
+    uint32_t* col = tb + (size_t)(i / TXp) * TYp * TXp + i % TXp;
+    uint32_t acc = 0;
+    for (uint32_t ty = 1; ty < TYp; ++ty) {
+      acc += col[(size_t)ty * TXp];
+      col[(size_t)ty * TXp] = acc;
+    }
+  }
+  if (lds_tab) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < words; i += MI_NT) tab[i] = s_tab[i];
   }
 }
 
@@ -729,7 +806,7 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uin
 int passes_for(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
 
 struct WsPtrs {
-  uint32_t *cnt, *tmp, *keyA, *valA, *keyB, *valB, *blk, *hist, *dtot, *pairK, *pairV, *wpre, *tlist;
+  uint32_t *cnt, *tmp, *keyA, *valA, *keyB, *valB, *blk, *hist, *dtot, *pairK, *pairV, *wpre, *tlist, *vfirst, *tab;
 };
 
 WsPtrs carve(const BinPlan& p, char* ws) {
@@ -747,14 +824,20 @@ WsPtrs carve(const BinPlan& p, char* ws) {
   w.pairV = reinterpret_cast<uint32_t*>(ws + p.off_pairV);
   w.wpre = reinterpret_cast<uint32_t*>(ws + p.off_tflag);
   w.tlist = w.wpre + ((int64_t)p.views * p.T + 1);
+  w.vfirst = reinterpret_cast<uint32_t*>(ws + p.off_vfirst);
+  w.tab = reinterpret_cast<uint32_t*>(ws + p.off_tab);
   return w;
 }
 
-// Index of `mask` (word prefix into w.wpre, sorted tile list into `list`).
+// Index of `mask`: sorted tile list into `list`, view first positions and corner table
+// into w.vfirst and w.tab.
 void index_mask(const BinPlan& p, const uint32_t* mask, const WsPtrs& w, uint32_t* list, uint32_t* count_out,
                 hipStream_t s) {
   const int wpv = (p.T + 31) / 32;
-  hipLaunchKernelGGL(mask_index_kernel, dim3(1), dim3(MI_NT), 0, s, mask, p.views, wpv, p.T, w.wpre, list, count_out);
+  const int64_t words = (int64_t)p.views * (p.TY + 1) * (p.TX + 1);
+  const int lds = words <= MI_TAB_WORDS;
+  hipLaunchKernelGGL(mask_index_kernel, dim3(1), dim3(MI_NT), lds ? (size_t)words * 4 : 0, s, mask, p.views, wpv, p.TX,
+                     p.TY, w.wpre, list, w.vfirst, w.tab, count_out, lds);
 }
 
 // Lists one slab of the depth order (order = valA after the 32-bit depth sort):
@@ -769,11 +852,12 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
   uint32_t* counters = bins.counters;
   uint32_t* order = w.valA;
   hipError_t err;
-  hipLaunchKernelGGL(slab_select_kernel, dim3(1), dim3(1), 0, s, counters, which);
+  hipLaunchKernelGGL(slab_select_kernel, dim3(1), dim3(1), 0, s, counters, which,
+                     bins.mode == CLSP_BINS_DEPTH_SLICED ? 1 : 0);
   if (which == 1)
     hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(E)), dim3(NT), 0, s, order, w.cnt, counters, w.tmp);
   else
-    hipLaunchKernelGGL(recount_kernel, dim3(grid_for(E)), dim3(NT), 0, s, order, rect, mask, counters, n, p.TX, wpv,
+    hipLaunchKernelGGL(recount_kernel, dim3(grid_for(E)), dim3(NT), 0, s, order, rect, w.tab, counters, n, p.TX, p.TY,
                        w.tmp);
   // offsets (relative to the slab's first pair) into valB
   if ((err = scan(w.tmp, w.valB, counters + C_SLAB_N, 0u, E, w.blk, counters + C_SLAB_PAIRS, s)) != hipSuccess)
@@ -782,16 +866,24 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
   const int tpasses = passes_for(p.tile_bits);
   uint32_t* ek = (tpasses % 2 == 0) ? bins.keys : w.pairK;
   uint32_t* ev = (tpasses % 2 == 0) ? bins.values : w.pairV;
+  const int epb = which == 1 ? EMIT_EPB_NEAR : EMIT_EPB;
+  // blocks for the most entries the slab can hold (the first slab of depth-sliced
+  // lists holds at most max(E/16, 16384)); blocks loop beyond the grid
+  const int64_t slab_max = (which == 1 && bins.mode == CLSP_BINS_DEPTH_SLICED)
+                               ? std::min<int64_t>(E, std::max<int64_t>(E >> 4, 16384))
+                               : E;
+  // at most two blocks per CU: each block's copy of the mask index serves many groups
+  const int eg = (int)std::min<int64_t>(std::max<int64_t>((slab_max + epb - 1) / epb, 1), 512);
+  const int64_t tab_words = (int64_t)V * (p.TY + 1) * (p.TX + 1) + (int64_t)V * p.T;
   if (which == 1 && !use_mask) {
-    hipLaunchKernelGGL(emit_full_kernel, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, w.valB, rect, counters, n,
-                       p.TX, p.T, ek, ev);
-  } else if ((int64_t)V * wpv <= EMIT_MASK_WORDS) {
-    const size_t lds = (size_t)(2 * V * wpv + 1) * 4;
-    hipLaunchKernelGGL(emit_masked_kernel<true>, dim3(grid_for(E, 1 << 16)), dim3(NT), lds, s, order, w.valB, rect,
-                       mask, w.wpre, mlist, counters, n, p.TX, wpv, V, ek, ev);
+    hipLaunchKernelGGL((emit_kernel<false, false>), dim3(eg), dim3(NT), 0, s, order, w.valB, rect, w.tab, w.vfirst,
+                       mlist, counters, n, p.TX, p.TY, V, epb, ek, ev);
+  } else if (tab_words <= EMIT_TAB_WORDS) {
+    hipLaunchKernelGGL((emit_kernel<true, true>), dim3(eg), dim3(NT), (size_t)tab_words * 4, s, order, w.valB, rect,
+                       w.tab, w.vfirst, mlist, counters, n, p.TX, p.TY, V, epb, ek, ev);
   } else {
-    hipLaunchKernelGGL(emit_masked_kernel<false>, dim3(grid_for(E, 1 << 16)), dim3(NT), 0, s, order, w.valB, rect,
-                       mask, w.wpre, mlist, counters, n, p.TX, wpv, V, ek, ev);
+    hipLaunchKernelGGL((emit_kernel<true, false>), dim3(eg), dim3(NT), 0, s, order, w.valB, rect, w.tab, w.vfirst,
+                       mlist, counters, n, p.TX, p.TY, V, epb, ek, ev);
   }
   if (tpasses > 0) {
     uint32_t *k1 = (ek == bins.keys) ? w.pairK : bins.keys, *v1 = (ev == bins.values) ? w.pairV : bins.values;
@@ -847,6 +939,8 @@ BinPlan make_bin_plan(int64_t n, int views, int W, int H, int64_t capacity) {
   p.off_pairK = take(need_pair_buf ? (size_t)(capacity > 0 ? capacity : 1) * 4 : 4);
   p.off_pairV = take(need_pair_buf ? (size_t)(capacity > 0 ? capacity : 1) * 4 : 4);
   p.off_tflag = take((gt + 1) * 4 * 2);
+  p.off_vfirst = take((size_t)views * 4);
+  p.off_tab = take((size_t)views * (p.TY + 1) * (p.TX + 1) * 4);
   // per rendered tile slot: alive flag, and per pixel the carried compositing state
   p.off_alive = take(gt * 4);
   p.off_carry = take((size_t)gt * TILE_PIX * CARRY_FIELDS * 4);
@@ -865,14 +959,24 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
   hipError_t err;
 
   // clear outputs (counters[C_STICKY] is left alone: it remembers any overflow)
-  if ((err = launch_fill_u32(counters, 0u, C_STICKY, s)) != hipSuccess) return err;
-  if ((err = launch_fill_u32(counters + C_STICKY + 1, 0u, CLSP_COUNTERS - C_STICKY - 1, s)) != hipSuccess) return err;
-  if ((err = launch_fill_u32(bins.ranges, 0u, gt * 2, s)) != hipSuccess) return err;
-  if ((err = launch_fill_u32(bins.ranges2, 0u, gt * 2, s)) != hipSuccess) return err;
-  if ((err = launch_fill_u32(bins.alive_mask, 0u, (int64_t)V * wpv, s)) != hipSuccess) return err;
+  {
+    ClearList c{};
+    auto add = [&](uint32_t* ptr, int64_t cnt) {
+      c.p[c.k] = ptr;
+      c.n[c.k++] = cnt;
+    };
+    add(counters, C_STICKY);
+    add(counters + C_STICKY + 1, CLSP_COUNTERS - C_STICKY - 1);
+    add(bins.ranges, gt * 2);
+    add(bins.ranges2, gt * 2);
+    add(bins.alive_mask, (int64_t)V * wpv);
+    if (use_mask) add(bins.tile_mask, (int64_t)V * wpv);
+    int64_t total = 0;
+    for (int i = 0; i < c.k; ++i) total += c.n[i];
+    hipLaunchKernelGGL(clear_kernel, dim3(grid_for(total, 2048)), dim3(NT), 0, s, c);
+  }
   // 1. mask, and its index: the sorted list of tiles to render (all tiles in full mode)
   if (use_mask) {
-    if ((err = launch_fill_u32(bins.tile_mask, 0u, (int64_t)V * wpv, s)) != hipSuccess) return err;
     if (a1 > a0) {
       hipLaunchKernelGGL(mask_kernel, dim3(ceil_div(a1 - a0, NT), V), dim3(NT), wpv * 4, s, rect, proj.flags, n, a0,
                          a1, p.TX, wpv, bins.tile_mask);
@@ -884,15 +988,14 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
   index_mask(p, bins.tile_mask, w, bins.tile_list, counters + C_TILES, s);
   if (E > 0) {
     // 2. counts
-    hipLaunchKernelGGL(count_kernel, dim3(ceil_div(n, NT), V), dim3(NT), use_mask ? wpv * 4 : 0, s, rect, proj.flags,
-                       bins.tile_mask, n, p.TX, wpv, use_mask, w.cnt, w.tmp);
+    hipLaunchKernelGGL(count_kernel, dim3(ceil_div(n, NT), V), dim3(NT), 0, s, rect, proj.flags, w.tab, n, p.TX, p.TY,
+                       use_mask, w.cnt, w.tmp);
     // 3. compaction of entries with pairs, keyed by depth
     uint32_t* pos = w.keyB;  // scratch until the sort needs it
     if ((err = scan(w.tmp, pos, nullptr, (uint32_t)E, E, w.blk, counters + C_ENTRIES, s)) != hipSuccess) return err;
     hipLaunchKernelGGL(compact_kernel, dim3(ceil_div(E, NT)), dim3(NT), 0, s, w.tmp, pos, proj.depth, E, w.keyA, w.valA);
     // 4. depth order: 32 key bits, 4 passes, the result back in (keyA, valA)
     radix_sort(w.keyA, w.valA, w.keyB, w.valB, counters + C_ENTRIES, nullptr, E, 32, w.hist, w.dtot, s);
-    hipLaunchKernelGGL(slab_bounds_kernel, dim3(1), dim3(1), 0, s, counters, bins.mode == CLSP_BINS_DEPTH_SLICED);
     // 5-7 for the first slab (the whole order for complete lists)
     if ((err = list_slab(p, proj, bins, w, 1, use_mask, bins.tile_mask, bins.tile_list, bins.ranges, s)) != hipSuccess)
       return err;

@@ -27,12 +27,12 @@ __device__ __forceinline__ bool splat_alpha(const float4 a, const float4 b, floa
   const float q = __fmaf_rn(__fmul_rn(a.z, dx), dx,
                             __fmaf_rn(__fmul_rn(__fmul_rn(2.0f, a.w), dx), dy, __fmul_rn(__fmul_rn(b.x, dy), dy)));
   const float power = __fmul_rn(-0.5f, q);
-  if (power > 0.0f) return false;
+  // branch-free, so that the weights of neighbouring records can be computed together
   G = __expf(power);
   const float oG = __fmul_rn(b.y, G);
   clamped = !(oG < ALPHA_MAX);
   alpha = clamped ? ALPHA_MAX : oG;
-  return alpha >= ALPHA_MIN;
+  return !(power > 0.0f) && alpha >= ALPHA_MIN;
 }
 
 // Compositing state per rendered tile slot: the largest contributor count of its pixels,
@@ -131,22 +131,42 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
       const int next_b = ((kb + j) / CH + 1) * CH;
       const int jhi = min(cnt, next_b - kb);
       if (!done) {
-        for (int jj = j; jj < jhi; ++jj) {
-          const float4 a = s_a[jj], b = s_b[jj];
-          float dx, dy, G, alpha;
-          bool clamped;
-          if (!splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped)) continue;
+        // blend record jj (weight alpha); false once the pixel stops before it
+        auto blend = [&](int jj, float alpha, float4 b, float c) -> bool {
           const float Tn = Tr * (1.0f - alpha);
-          if (Tn < T_STOP) {
-            done = true;
-            break;
-          }
+          if (Tn < T_STOP) return false;
           const float w = alpha * Tr;
           dr = fmaf(w, b.z, dr);
           dg = fmaf(w, b.w, dg);
-          db = fmaf(w, s_c[jj], db);
+          db = fmaf(w, c, db);
           Tr = Tn;
           last = (uint32_t)(kb + jj + 1);
+          return true;
+        };
+        int jj = j;
+        // two records per iteration: their weights are independent, only the blending
+        // is sequential
+        for (; jj + 1 < jhi; jj += 2) {
+          const float4 a0 = s_a[jj], b0 = s_b[jj], a1 = s_a[jj + 1], b1 = s_b[jj + 1];
+          const float c0 = s_c[jj], c1 = s_c[jj + 1];
+          float dx0, dy0, G0, al0, dx1, dy1, G1, al1;
+          bool cl0, cl1;
+          const bool ok0 = splat_alpha(a0, b0, fx, fy, dx0, dy0, G0, al0, cl0);
+          const bool ok1 = splat_alpha(a1, b1, fx, fy, dx1, dy1, G1, al1, cl1);
+          if (ok0 && !blend(jj, al0, b0, c0)) {
+            done = true;
+            break;
+          }
+          if (ok1 && !blend(jj + 1, al1, b1, c1)) {
+            done = true;
+            break;
+          }
+        }
+        if (!done && jj < jhi) {
+          const float4 a = s_a[jj], b = s_b[jj];
+          float dx, dy, G, alpha;
+          bool clamped;
+          if (splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped) && !blend(jj, alpha, b, s_c[jj])) done = true;
         }
       }
       // a chunk boundary of the tile's list: record this pixel's state
@@ -330,22 +350,36 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
 #pragma unroll
     for (int c = 0; c < 9; ++c) s_g[threadIdx.x][c] = 0.0f;
     __syncthreads();
+    // a frozen Gaussian's record: only the transmittance and the colour behind move on
+    auto unblend = [&](bool ok, float alpha, float4 b, float c) {
+      if (!ok) return;
+      const float Tj = Tr / (1.0f - alpha);
+      const float w = alpha * Tj;
+      S0 = fmaf(w, b.z, S0);
+      S1 = fmaf(w, b.w, S1);
+      S2 = fmaf(w, c, S2);
+      Tr = Tj;
+    };
     for (int j = cnt - 1; j >= 0; --j) {
       const int k = beg + j;
       if (!s_act[j]) {
-        // a frozen Gaussian: only the transmittance and the colour behind move on
-        if (k < (int)last) {
+        if (j >= 1 && !s_act[j - 1]) {
+          // two frozen records: weights together, then undone in reverse order
+          const float4 a0 = s_a[j], b0 = s_b[j], a1 = s_a[j - 1], b1 = s_b[j - 1];
+          const float c0 = s_c[j], c1 = s_c[j - 1];
+          float dx0, dy0, G0, al0, dx1, dy1, G1, al1;
+          bool cl0, cl1;
+          const bool ok0 = splat_alpha(a0, b0, fx, fy, dx0, dy0, G0, al0, cl0) && k < (int)last;
+          const bool ok1 = splat_alpha(a1, b1, fx, fy, dx1, dy1, G1, al1, cl1) && k - 1 < (int)last;
+          unblend(ok0, al0, b0, c0);
+          unblend(ok1, al1, b1, c1);
+          --j;
+        } else {
           const float4 a = s_a[j], b = s_b[j];
           float dx, dy, G, alpha;
           bool clamped;
-          if (splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped)) {
-            const float Tj = Tr / (1.0f - alpha);
-            const float w = alpha * Tj;
-            S0 = fmaf(w, b.z, S0);
-            S1 = fmaf(w, b.w, S1);
-            S2 = fmaf(w, s_c[j], S2);
-            Tr = Tj;
-          }
+          const bool ok = splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped) && k < (int)last;
+          unblend(ok, alpha, b, s_c[j]);
         }
         continue;
       }

@@ -108,27 +108,47 @@ class SplatOptimizer:
         c[C_STICKY] = 0
         return flag
 
+    TIMED_CALLS = ("bin_and_sort", "render_forward", "render_backward")
+
     def step_timed(self, view: int, events, stream=None):
-        """``step`` with the two events recorded around the forward render call on
-        the step's stream."""
+        """``step`` with a pair of events recorded around each call named in
+        ``events`` (a dict: call name -> (start, end); names from TIMED_CALLS), on the
+        step's stream."""
         self.step(view, stream if stream is not None else torch.cuda.current_stream(), events)
 
     def render_stats(self):
-        """Work of the last step's forward render: rendered tiles and pixels, pairs,
-        records each tile must read (the largest contributor count of its pixels) and
-        (pixel, record) evaluations (sum of contributor counts)."""
+        """Work of the last step: rendered tiles and pixels, pairs, entries (views x
+        Gaussians with at least one pair), records each tile must read (the largest
+        contributor count of its pixels), (pixel, record) evaluations (sum of
+        contributor counts) and those of them whose record belongs to the active range
+        (the evaluations whose gradient the backward computes)."""
         c = self.bins.read_counters()
         W, H = self.cams[0].width, self.cams[0].height
         TX, TY = api.tile_grid(W, H)
+        dev = self.nc.device
         tiles = self.bins.tile_list[:c["tiles"]].long()
-        nc = torch.zeros(1, TY * 16, TX * 16, dtype=torch.int64, device=self.nc.device)
+        nc = torch.zeros(1, TY * 16, TX * 16, dtype=torch.int64, device=dev)
         nc[:, :H, :W] = self.nc.long()
         per_tile = nc.reshape(TY, 16, TX, 16).permute(0, 2, 1, 3).reshape(TY * TX, 256)[tiles]
-        inside = torch.zeros(TY * 16, TX * 16, dtype=torch.bool, device=nc.device)
+        inside = torch.zeros(TY * 16, TX * 16, dtype=torch.bool, device=dev)
         inside[:H, :W] = True
         pix = inside.reshape(TY, 16, TX, 16).permute(0, 2, 1, 3).reshape(TY * TX, 256)[tiles].sum()
-        return {"tiles": c["tiles"], "tiles_total": TX * TY, "pairs": c["pairs"], "pixels": int(pix),
-                "records": int(per_tile.max(dim=1).values.sum()), "pixel_records": int(per_tile.sum())}
+        # active records among each pixel's first n_contrib list entries: prefix counts
+        # of the active flag over the pair buffer, read at the two ranges of the list
+        a0, a1 = self.active
+        vals = self.bins.values[:max(c["pairs"], 1)].long()
+        act = ((vals >= a0) & (vals < a1)).long()
+        cum = torch.zeros(act.numel() + 1, dtype=torch.int64, device=dev)
+        cum[1:] = torch.cumsum(act, 0)
+        r1 = self.bins.ranges.view(-1, 2)[tiles].long()
+        r2 = self.bins.ranges2.view(-1, 2)[tiles].long()
+        len1 = (r1[:, 1] - r1[:, 0])[:, None]
+        k1 = torch.minimum(per_tile, len1)
+        k2 = (per_tile - len1).clamp(min=0)
+        n_act = (cum[r1[:, 0:1] + k1] - cum[r1[:, 0:1]]) + (cum[r2[:, 0:1] + k2] - cum[r2[:, 0:1]])
+        return {"tiles": c["tiles"], "tiles_total": TX * TY, "pairs": c["pairs"], "entries": c["entries"],
+                "pixels": int(pix), "records": int(per_tile.max(dim=1).values.sum()),
+                "pixel_records": int(per_tile.sum()), "pixel_records_active": int(n_act.sum())}
 
     def step(self, view: int, stream=None, events=None):
         """One step on view ``view``: the C-ABI calls in order, all on ``stream``
@@ -141,17 +161,21 @@ class SplatOptimizer:
         use_mask = 1 if self.local else 0
         check(L.clsp_zero_grads(by(self._gr), self._range, st))
         check(L.clsp_project_preprocess(by(self._g), cam, 1, by(self._proj), st))
+        ev = events or {}
+        mark = lambda name, i: ev[name][i].record(stream) if name in ev else None
+        mark("bin_and_sort", 0)
         check(L.clsp_bin_and_sort(by(self._proj), cam, 1, self._range, use_mask, by(self._bins), st))
-        if events is not None:
-            events[0].record(stream)
+        mark("bin_and_sort", 1)
+        mark("render_forward", 0)
         check(L.clsp_render_forward(by(self._proj), by(self._bins), cam, 1, self._bg, P["image"], P["T"], P["nc"],
                                     P["state"], self._sizes[2], st))
-        if events is not None:
-            events[1].record(stream)
+        mark("render_forward", 1)
         check(L.clsp_l1_loss_grad(P["image"], P["targets"][view], by(self._bins), cam, 1, P["dL"], P["loss"], st))
+        mark("render_backward", 0)
         check(L.clsp_render_backward(by(self._g), by(self._proj), by(self._bins), cam, 1, self._bg, self._range, P["T"],
                                      P["nc"], P["state"], self._sizes[2], P["dL"], by(self._gr), P["bws"],
                                      self._sizes[1], st))
+        mark("render_backward", 1)
         self.step_count += 1
         self._hp.step = self.step_count
         check(L.clsp_masked_adam_step(by(self._pp), by(self._gr), by(self._m), by(self._v), self._range, None,
