@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="time budget of the CPU oracle timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving latency leg")
+    ap.add_argument("--no-visible", action="store_true",
+                    help="skip the local leg whose change ball sits on the cube face z = +1 (visible)")
     ap.add_argument("--qps", type=float, default=100.0, help="arrival rate of the serving leg")
     ap.add_argument("--requests", type=int, default=400, help="requests of the serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -73,26 +75,29 @@ def main():
     a = (w.active_begin, sc.n)
     log(f"scene {w.name}: N={sc.n} active={a[1] - a[0]} built in {time.time() - t0:.1f}s")
 
-    # targets: renders of the unchanged scene (inputs, not timed)
-    gt = api.GaussianTensors.from_scene(w.scene_gt, dev)
-    targets = torch.zeros(len(cams), 3, cams[0].height, cams[0].width, device=dev)
-    proj = api.ProjectedBuffers.alloc(sc.n, 1, dev)
-    bins = None
-    for v, cam in enumerate(cams):
-        api.project_preprocess(gt, [cam], proj)
-        bins = api.bin_and_sort(proj, [cam], bins=bins, capacity=120_000_000)
-        api.render_forward(proj, bins, [cam], image=targets[v:v + 1],
-                           T_final=torch.empty(1, cam.height, cam.width, device=dev),
-                           n_contrib=torch.empty(1, cam.height, cam.width, dtype=torch.int32, device=dev))
-        assert not bins.read_counters()["overflow"]
-    del bins, gt
-    torch.cuda.synchronize()
+    def render_targets(wl):
+        """Renders of the unchanged scene (inputs, not timed)."""
+        gt = api.GaussianTensors.from_scene(wl.scene_gt, dev)
+        tg = torch.zeros(len(wl.cameras), 3, wl.cameras[0].height, wl.cameras[0].width, device=dev)
+        proj = api.ProjectedBuffers.alloc(wl.scene.n, 1, dev)
+        bins = None
+        for v, cam in enumerate(wl.cameras):
+            api.project_preprocess(gt, [cam], proj)
+            bins = api.bin_and_sort(proj, [cam], bins=bins, capacity=120_000_000)
+            api.render_forward(proj, bins, [cam], image=tg[v:v + 1],
+                               T_final=torch.empty(1, cam.height, cam.width, device=dev),
+                               n_contrib=torch.empty(1, cam.height, cam.width, dtype=torch.int32, device=dev))
+            assert not bins.read_counters()["overflow"]
+        torch.cuda.synchronize()
+        return tg
+
+    targets = render_targets(w)
     log("targets rendered")
 
     order = np.random.default_rng(0).permutation(len(cams))
     calls = SplatOptimizer.TIMED_CALLS
 
-    def run(local):
+    def run(local, sc=sc, targets=targets, a=a, steps=args.steps):
         params = api.GaussianTensors.from_scene(sc, dev)
         opt = SplatOptimizer(params, cams, targets, active=a, local=local)
         stream = torch.cuda.current_stream()
@@ -101,10 +106,10 @@ def main():
         torch.cuda.synchronize()
         # HIP events around each timed C-ABI call, on the stream the calls run on
         mk = lambda: torch.cuda.Event(enable_timing=True)
-        ev = [{c: (mk(), mk()) for c in calls} for _ in range(args.steps)]
+        ev = [{c: (mk(), mk()) for c in calls} for _ in range(steps)]
         torch.cuda.synchronize()
         t_start = time.perf_counter()
-        for i in range(args.steps):
+        for i in range(steps):
             opt.step_timed(int(order[(args.warmup + i) % len(order)]), ev[i], stream)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t_start
@@ -132,6 +137,20 @@ def main():
         del opt_full
     del targets
     torch.cuda.empty_cache()
+
+    visible = None
+    if not args.no_visible:
+        wv = scenes.local_change(n=args.n, center=(0.0, 0.0, 1.0))
+        tv = render_targets(wv)
+        av = (wv.active_begin, wv.scene.n)
+        t_v, ms_v, st_v, opt_v = run(True, sc=wv.scene, targets=tv, a=av, steps=max(args.steps // 2, 1))
+        it_v = max(args.steps // 2, 1) / t_v
+        log(f"visible change set {wv.name}: {it_v:.1f} it/s, calls {ms_v}, {st_v}")
+        visible = {"workload": wv.name, "active_gaussians": av[1] - av[0], "it_s": round(it_v, 3),
+                   "over_full": None if res_full is None else round(it_v / res_full[0], 3),
+                   "call_ms": {k: round(v, 4) for k, v in ms_v.items()}, "stats": st_v}
+        del opt_v, tv
+        torch.cuda.empty_cache()
 
     roofline = roofline_of(ms_local, st_local, sc.n)
     serving = None
@@ -164,6 +183,7 @@ def main():
         "local_over_full": None if res_full is None else round(it_local / res_full[0], 3),
         "full_pairs": None if res_full is None else res_full[2]["pairs"],
         "local_stats": st_local,
+        "visible_change_variant": visible,
         "call_ms_local": {k: round(v, 4) for k, v in ms_local.items()},
         "call_ms_full": None if res_full is None else {k: round(v, 4) for k, v in res_full[1].items()},
         "serving": serving,

@@ -246,14 +246,15 @@ def full_scene(seed=2, n=200_000, n_views=8, res=800, fx=1100.0) -> Workload:
 
 
 def local_change(seed=3, n=1_000_000, n_views=16, width=1280, height=720, fx=1280.0,
-                 radius=0.4, reinit="sfm") -> Workload:
-    """1M Gaussians as in ``tiny``; the Gaussians within ``radius`` of the origin form
-    the change set and are re-initialised, then the scene is reordered static-first.
-    16 ring views of 1280x720.  ``scene_gt`` holds the unchanged scene in the same
-    order (its renders are the targets)."""
+                 radius=0.4, reinit="sfm", center=(0.0, 0.0, 0.0)) -> Workload:
+    """1M Gaussians as in ``tiny``; the Gaussians within ``radius`` of ``center`` (the
+    origin by default) form the change set and are re-initialised, then the scene is
+    reordered static-first.  16 ring views of 1280x720.  ``scene_gt`` holds the
+    unchanged scene in the same order (its renders are the targets)."""
     rng = np.random.default_rng(seed)
     gt = uniform_cube_scene(rng, n, sh_degree=0)
-    active = np.linalg.norm(gt.means.astype(np.float64), axis=0) <= radius
+    c = np.asarray(center, dtype=np.float64).reshape(3, 1)
+    active = np.linalg.norm(gt.means.astype(np.float64) - c, axis=0) <= radius
     gt_sorted, a0, perm = static_first(gt, active)
     idx = np.arange(a0, n)
     if reinit == "sfm":
@@ -265,7 +266,8 @@ def local_change(seed=3, n=1_000_000, n_views=16, width=1280, height=720, fx=128
         for a, b in zip(start.param_arrays(), fresh.param_arrays()):
             a[..., a0:] = b
     cams = ring_cameras(n_views, 4.0, width=width, height=height, fx=fx)
-    return Workload(f"local-{n // 1000}k-{width}x{height}-{n_views}v", start, cams, a0, None, gt_sorted,
+    tag = "" if not np.any(c) else "-c" + ",".join(f"{x:g}" for x in c.ravel())
+    return Workload(f"local-{n // 1000}k-{width}x{height}-{n_views}v{tag}", start, cams, a0, None, gt_sorted,
                     {"perm": perm})
 
 
