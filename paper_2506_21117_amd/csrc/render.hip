@@ -130,44 +130,33 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
     for (int j = 0; j < cnt;) {
       const int next_b = ((kb + j) / CH + 1) * CH;
       const int jhi = min(cnt, next_b - kb);
-      if (!done) {
-        // blend record jj (weight alpha); false once the pixel stops before it
-        auto blend = [&](int jj, float alpha, float4 b, float c) -> bool {
-          const float Tn = Tr * (1.0f - alpha);
-          if (Tn < T_STOP) return false;
-          const float w = alpha * Tr;
-          dr = fmaf(w, b.z, dr);
-          dg = fmaf(w, b.w, dg);
-          db = fmaf(w, c, db);
-          Tr = Tn;
-          last = (uint32_t)(kb + jj + 1);
-          return true;
-        };
-        int jj = j;
-        // two records per iteration: their weights are independent, only the blending
-        // is sequential
-        for (; jj + 1 < jhi; jj += 2) {
-          const float4 a0 = s_a[jj], b0 = s_b[jj], a1 = s_a[jj + 1], b1 = s_b[jj + 1];
-          const float c0 = s_c[jj], c1 = s_c[jj + 1];
-          float dx0, dy0, G0, al0, dx1, dy1, G1, al1;
-          bool cl0, cl1;
-          const bool ok0 = splat_alpha(a0, b0, fx, fy, dx0, dy0, G0, al0, cl0);
-          const bool ok1 = splat_alpha(a1, b1, fx, fy, dx1, dy1, G1, al1, cl1);
-          if (ok0 && !blend(jj, al0, b0, c0)) {
-            done = true;
-            break;
-          }
-          if (ok1 && !blend(jj + 1, al1, b1, c1)) {
-            done = true;
-            break;
-          }
-        }
-        if (!done && jj < jhi) {
-          const float4 a = s_a[jj], b = s_b[jj];
-          float dx, dy, G, alpha;
-          bool clamped;
-          if (splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped) && !blend(jj, alpha, b, s_c[jj])) done = true;
-        }
+      // Branch-free blending, two records per iteration: both weights are computed
+      // first, then applied in order with selects; a lane that has stopped keeps its
+      // state (the same values as stopping with a branch).  The wave leaves the
+      // segment once all its lanes have stopped.
+      auto blend = [&](bool ok, float alpha, float4 b, float c, uint32_t k1) {
+        const float Tn = Tr * (1.0f - alpha);
+        const bool stop = ok && Tn < T_STOP;
+        const bool use = ok && !stop;
+        const float w = alpha * Tr;
+        dr = use ? fmaf(w, b.z, dr) : dr;
+        dg = use ? fmaf(w, b.w, dg) : dg;
+        db = use ? fmaf(w, c, db) : db;
+        Tr = use ? Tn : Tr;
+        last = use ? k1 : last;
+        done = done || stop;
+      };
+      for (int jj = j; jj < jhi; jj += 2) {
+        if (__ballot(!done) == 0ull) break;
+        const int j1 = min(jj + 1, jhi - 1);
+        const float4 a0 = s_a[jj], b0 = s_b[jj], a1 = s_a[j1], b1 = s_b[j1];
+        const float c0 = s_c[jj], c1 = s_c[j1];
+        float dx0, dy0, G0, al0, dx1, dy1, G1, al1;
+        bool cl0, cl1;
+        const bool ok0 = splat_alpha(a0, b0, fx, fy, dx0, dy0, G0, al0, cl0);
+        const bool ok1 = splat_alpha(a1, b1, fx, fy, dx1, dy1, G1, al1, cl1) && jj + 1 < jhi;
+        blend(ok0 && !done, al0, b0, c0, (uint32_t)(kb + jj + 1));
+        blend(ok1 && !done, al1, b1, c1, (uint32_t)(kb + jj + 2));
       }
       // a chunk boundary of the tile's list: record this pixel's state
       if (kb + jhi == next_b && chunk < CHUNKS - 1) {
@@ -383,40 +372,34 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
         }
         continue;
       }
+      // branch-free: every lane evaluates the record, the ones it does not reach or
+      // that skip it keep their state and contribute zeros
+      const float4 a = s_a[j], b = s_b[j];
+      const float cb = s_c[j];
+      float dx, dy, G, alpha;
+      bool clamped;
+      const bool contrib = splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped) && k < (int)last;
+      const float om = 1.0f - alpha;
+      const float Tj = Tr / om;
+      const float w = alpha * Tj;
+      const float io = 1.0f / om;
+      const float dLda = g0 * (Tj * b.z - S0 * io) + g1 * (Tj * b.w - S1 * io) + g2 * (Tj * cb - S2 * io);
+      S0 = contrib ? fmaf(w, b.z, S0) : S0;
+      S1 = contrib ? fmaf(w, b.w, S1) : S1;
+      S2 = contrib ? fmaf(w, cb, S2) : S2;
+      Tr = contrib ? Tj : Tr;
+      const bool geo = contrib && !clamped;  // the 0.99 clamp has zero derivative
+      const float gp = alpha * dLda;         // dL/dpower
       float p[9];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) p[c] = 0.0f;
-      bool contrib = false;
-      if (k < (int)last) {
-        const float4 a = s_a[j], b = s_b[j];
-        const float cb = s_c[j];
-        float dx, dy, G, alpha;
-        bool clamped;
-        if (splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped)) {
-          const float om = 1.0f - alpha;
-          const float Tj = Tr / om;
-          const float w = alpha * Tj;
-          const float io = 1.0f / om;
-          const float dLda = g0 * (Tj * b.z - S0 * io) + g1 * (Tj * b.w - S1 * io) + g2 * (Tj * cb - S2 * io);
-          S0 = fmaf(w, b.z, S0);
-          S1 = fmaf(w, b.w, S1);
-          S2 = fmaf(w, cb, S2);
-          Tr = Tj;
-          p[6] = w * g0;
-          p[7] = w * g1;
-          p[8] = w * g2;
-          if (!clamped) {
-            const float gp = alpha * dLda;  // dL/dpower
-            p[5] = G * dLda;                // dL/dopacity
-            p[0] = gp * (a.z * dx + a.w * dy);
-            p[1] = gp * (a.w * dx + b.x * dy);
-            p[2] = -0.5f * gp * dx * dx;
-            p[3] = -gp * dx * dy;
-            p[4] = -0.5f * gp * dy * dy;
-          }
-          contrib = true;
-        }
-      }
+      p[0] = geo ? gp * (a.z * dx + a.w * dy) : 0.0f;
+      p[1] = geo ? gp * (a.w * dx + b.x * dy) : 0.0f;
+      p[2] = geo ? -0.5f * gp * dx * dx : 0.0f;
+      p[3] = geo ? -gp * dx * dy : 0.0f;
+      p[4] = geo ? -0.5f * gp * dy * dy : 0.0f;
+      p[5] = geo ? G * dLda : 0.0f;  // dL/dopacity
+      p[6] = contrib ? w * g0 : 0.0f;
+      p[7] = contrib ? w * g1 : 0.0f;
+      p[8] = contrib ? w * g2 : 0.0f;
       if (__ballot(contrib)) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
