@@ -195,6 +195,23 @@ __global__ void __launch_bounds__(NT) count_kernel(const uint2* __restrict__ rec
   has[e] = c > 0 ? 1u : 0u;
 }
 
+// Capacity check after a slab's pair count: P = first-slab pairs + this slab's pairs.
+__device__ void capacity_check(uint32_t* counters, uint64_t capacity, int which) {
+  const uint32_t sp = counters[C_SLAB_PAIRS];
+  const uint32_t p = (which == 1 ? 0u : counters[C_PAIRS1]) + sp;
+  if (which == 1) counters[C_PAIRS1] = sp;
+  const bool over = (uint64_t)p > capacity || counters[C_OVERFLOW];
+  counters[C_PAIRS] = p;
+  counters[C_OVERFLOW] = over ? 1u : 0u;
+  counters[C_WRITTEN] = over ? 0u : p;
+  if (over) {
+    counters[C_STICKY] = 1u;
+    if (which == 1) counters[C_TILES] = 0u;  // no tile is rendered
+    counters[C_SLAB_PAIRS] = 0u;  // nothing is emitted or sorted
+    counters[C_SLAB_N] = 0u;
+  }
+}
+
 // ------------------------------------------------------------------ generic exclusive scan
 __global__ void __launch_bounds__(NT) scan_reduce_kernel(const uint32_t* __restrict__ in, const uint32_t* n_ptr,
                                                          uint32_t n_host, uint32_t* __restrict__ blk, int G) {
@@ -209,8 +226,10 @@ __global__ void __launch_bounds__(NT) scan_reduce_kernel(const uint32_t* __restr
   if (threadIdx.x == 0) blk[blockIdx.x] = tot;
 }
 
-// One block: exclusive scan of the G block sums in place; total -> *total_out.
-__global__ void __launch_bounds__(NT) scan_blocks_kernel(uint32_t* __restrict__ blk, int G, uint32_t* total_out) {
+// One block: exclusive scan of the G block sums in place; total -> *total_out.  With
+// check_which (1 or 2) the total is a slab's pair count and the capacity check follows.
+__global__ void __launch_bounds__(NT) scan_blocks_kernel(uint32_t* __restrict__ blk, int G, uint32_t* total_out,
+                                                         uint32_t* counters, uint64_t capacity, int check_which) {
   __shared__ uint32_t s4[4];
   constexpr int PER = MAX_SCAN_BLOCKS / NT;
   uint32_t v[PER];
@@ -227,7 +246,10 @@ __global__ void __launch_bounds__(NT) scan_blocks_kernel(uint32_t* __restrict__ 
     if (idx < G) blk[idx] = off;
     off += v[k];
   }
-  if (threadIdx.x == 0 && total_out) *total_out = tot;
+  if (threadIdx.x == 0) {
+    if (total_out) *total_out = tot;
+    if (check_which) capacity_check(counters, capacity, check_which);
+  }
 }
 
 __global__ void __launch_bounds__(NT) scan_apply_kernel(const uint32_t* __restrict__ in, const uint32_t* n_ptr,
@@ -258,18 +280,40 @@ __global__ void __launch_bounds__(NT) scan_apply_kernel(const uint32_t* __restri
   }
 }
 
-// ------------------------------------------------------------------ 3. compaction
-__global__ void __launch_bounds__(NT) compact_kernel(const uint32_t* __restrict__ has,
-                                                     const uint32_t* __restrict__ pos,
-                                                     const float* __restrict__ depth, int64_t count,
-                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (e >= count || !has[e]) return;
-  const uint32_t p = pos[e];
-  keys[p] = __float_as_uint(depth[e]);  // depth > 0.2: the bit pattern orders like the value
-  vals[p] = (uint32_t)e;
+// The final scan step of the has-pairs flags as a compaction: entry e with a pair
+// goes to position p (its exclusive prefix) as (depth key, e).
+__global__ void __launch_bounds__(NT) scan_compact_kernel(const uint32_t* __restrict__ has, uint32_t n,
+                                                          const uint32_t* __restrict__ blk, int G,
+                                                          const float* __restrict__ depth, uint32_t* __restrict__ keys,
+                                                          uint32_t* __restrict__ vals) {
+  __shared__ uint32_t s4[4];
+  uint32_t beg, end;
+  block_span(n, G, blockIdx.x, SCAN_CHUNK, beg, end);
+  uint32_t base = blk[blockIdx.x];
+  for (uint32_t c = beg; c < end; c += SCAN_CHUNK) {
+    uint32_t v[SCAN_ITEMS];
+    uint32_t sum = 0;
+    const uint32_t t0 = c + threadIdx.x * SCAN_ITEMS;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      v[k] = (t0 + k < end) ? has[t0 + k] : 0u;
+      sum += v[k];
+    }
+    uint32_t tot;
+    uint32_t off = base + block_excl_scan(sum, s4, tot);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      if (v[k]) {
+        keys[off] = __float_as_uint(depth[t0 + k]);  // depth > 0.2: the bit pattern orders like the value
+        vals[off] = t0 + k;
+      }
+      off += v[k];
+    }
+    base += tot;
+  }
 }
 
+// ------------------------------------------------------------------ 3. compaction
 // ------------------------------------------------------------------ radix sort
 // All sort kernels work on keys[off + e], e < n, with n and off read from device memory.
 __device__ __forceinline__ uint32_t load_off(const uint32_t* p) { return p ? *p : 0u; }
@@ -422,56 +466,45 @@ __global__ void __launch_bounds__(NT) rs_downsweep_kernel(const uint32_t* __rest
 }
 
 // ------------------------------------------------------------------ slabs of the depth order
-// Select slab `which` (1: [0, S1), 2: [S1, M)) of the depth order: its first sorted
-// entry, entry count and the first pair position.
-__global__ void slab_select_kernel(uint32_t* counters, int which, int sliced) {
-  const uint32_t m = counters[C_ENTRIES];
-  // the first slab: the nearest max(M/16, 16384) entries (all of them for complete lists)
-  if (which == 1) counters[C_SLAB1] = sliced ? min(m, max(m >> 4, 16384u)) : m;
-  const uint32_t s1 = counters[C_SLAB1];
-  counters[C_SLAB_LO] = which == 1 ? 0u : s1;
-  // the second slab is listed only if some tile is still alive
-  counters[C_SLAB_N] = which == 1 ? s1 : (counters[C_ALIVE] ? m - s1 : 0u);
-  counters[C_SLAB_BASE] = which == 1 ? 0u : counters[C_PAIRS1];
+// Slab `which` (1: [0, S1), 2: [S1, M)) of the depth order: its first sorted entry lo,
+// entry count m and first pair position base.  The first slab is the nearest
+// max(M/16, 16384) entries (all of them for complete lists); the second is listed only
+// if some tile is still alive.  The kernel that computes it first (gather_counts or
+// recount) also stores it in the counters for the kernels after it.
+__device__ __forceinline__ void slab_params(uint32_t* counters, int which, int sliced, uint32_t& lo, uint32_t& m) {
+  const uint32_t M = counters[C_ENTRIES];
+  const uint32_t s1 = which == 1 ? (sliced ? min(M, max(M >> 4, 16384u)) : M) : counters[C_SLAB1];
+  lo = which == 1 ? 0u : s1;
+  m = which == 1 ? s1 : (counters[C_ALIVE] ? M - s1 : 0u);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (which == 1) counters[C_SLAB1] = s1;
+    counters[C_SLAB_LO] = lo;
+    counters[C_SLAB_N] = m;
+    counters[C_SLAB_BASE] = which == 1 ? 0u : counters[C_PAIRS1];
+  }
 }
 
 // Pairs each slab entry emits: its count from the count pass (first slab) ...
 __global__ void __launch_bounds__(NT) gather_counts_kernel(const uint32_t* __restrict__ order,
-                                                           const uint32_t* __restrict__ cnt,
-                                                           const uint32_t* __restrict__ counters,
-                                                           uint32_t* __restrict__ out) {
-  const uint32_t lo = counters[C_SLAB_LO], m = counters[C_SLAB_N];
+                                                           const uint32_t* __restrict__ cnt, uint32_t* counters,
+                                                           int sliced, uint32_t* __restrict__ out) {
+  uint32_t lo, m;
+  slab_params(counters, 1, sliced, lo, m);
   for (uint32_t j = blockIdx.x * NT + threadIdx.x; j < m; j += gridDim.x * NT) out[j] = cnt[order[lo + j]];
 }
 
 // ... or recounted against the tiles still alive (second slab).
 __global__ void __launch_bounds__(NT) recount_kernel(const uint32_t* __restrict__ order, const uint2* __restrict__ rect,
-                                                     const uint32_t* __restrict__ tab, const uint32_t* counters,
-                                                     int64_t n, int TX, int TY, uint32_t* __restrict__ out) {
-  const uint32_t lo = counters[C_SLAB_LO], m = counters[C_SLAB_N];
+                                                     const uint32_t* __restrict__ tab, uint32_t* counters, int64_t n,
+                                                     int TX, int TY, uint32_t* __restrict__ out) {
+  uint32_t lo, m;
+  slab_params(counters, 2, 1, lo, m);
   for (uint32_t j = blockIdx.x * NT + threadIdx.x; j < m; j += gridDim.x * NT) {
     const uint32_t e = order[lo + j];
     const uint32_t v = (uint32_t)(e / n);
     const uint2 r = rect[e];
     const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
     out[j] = tab_rect(tab, v * (uint32_t)(TY + 1), (uint32_t)(TX + 1), x0, x1, y0, y1);
-  }
-}
-
-// Capacity check after a slab's pair count: P = first-slab pairs + this slab's pairs.
-__global__ void check_capacity_kernel(uint32_t* counters, uint64_t capacity, int which) {
-  const uint32_t sp = counters[C_SLAB_PAIRS];
-  const uint32_t p = (which == 1 ? 0u : counters[C_PAIRS1]) + sp;
-  if (which == 1) counters[C_PAIRS1] = sp;
-  const bool over = (uint64_t)p > capacity || counters[C_OVERFLOW];
-  counters[C_PAIRS] = p;
-  counters[C_OVERFLOW] = over ? 1u : 0u;
-  counters[C_WRITTEN] = over ? 0u : p;
-  if (over) {
-    counters[C_STICKY] = 1u;
-    if (which == 1) counters[C_TILES] = 0u;  // no tile is rendered
-    counters[C_SLAB_PAIRS] = 0u;  // nothing is emitted or sorted
-    counters[C_SLAB_N] = 0u;
   }
 }
 
@@ -769,10 +802,11 @@ int grid_for(int64_t count, int cap = 8192) {
 
 // Exclusive scan of in[0, n) (n from n_ptr if given) into out; total -> *total_out.
 hipError_t scan(const uint32_t* in, uint32_t* out, const uint32_t* n_ptr, uint32_t n_host, int64_t nmax,
-                uint32_t* blk, uint32_t* total_out, hipStream_t s) {
+                uint32_t* blk, uint32_t* total_out, hipStream_t s, uint32_t* counters = nullptr,
+                uint64_t capacity = 0, int check_which = 0) {
   const int G = scan_blocks(nmax);
   hipLaunchKernelGGL(scan_reduce_kernel, dim3(G), dim3(NT), 0, s, in, n_ptr, n_host, blk, G);
-  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(NT), 0, s, blk, G, total_out);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(NT), 0, s, blk, G, total_out, counters, capacity, check_which);
   hipLaunchKernelGGL(scan_apply_kernel, dim3(G), dim3(NT), 0, s, in, n_ptr, n_host, blk, G, out);
   return hipGetLastError();
 }
@@ -852,17 +886,16 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
   uint32_t* counters = bins.counters;
   uint32_t* order = w.valA;
   hipError_t err;
-  hipLaunchKernelGGL(slab_select_kernel, dim3(1), dim3(1), 0, s, counters, which,
-                     bins.mode == CLSP_BINS_DEPTH_SLICED ? 1 : 0);
   if (which == 1)
-    hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(E)), dim3(NT), 0, s, order, w.cnt, counters, w.tmp);
+    hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(E)), dim3(NT), 0, s, order, w.cnt, counters,
+                       bins.mode == CLSP_BINS_DEPTH_SLICED ? 1 : 0, w.tmp);
   else
     hipLaunchKernelGGL(recount_kernel, dim3(grid_for(E)), dim3(NT), 0, s, order, rect, w.tab, counters, n, p.TX, p.TY,
                        w.tmp);
-  // offsets (relative to the slab's first pair) into valB
-  if ((err = scan(w.tmp, w.valB, counters + C_SLAB_N, 0u, E, w.blk, counters + C_SLAB_PAIRS, s)) != hipSuccess)
+  // offsets (relative to the slab's first pair) into valB; the capacity check
+  if ((err = scan(w.tmp, w.valB, counters + C_SLAB_N, 0u, E, w.blk, counters + C_SLAB_PAIRS, s, counters,
+                  (uint64_t)p.capacity, which)) != hipSuccess)
     return err;
-  hipLaunchKernelGGL(check_capacity_kernel, dim3(1), dim3(1), 0, s, counters, (uint64_t)p.capacity, which);
   const int tpasses = passes_for(p.tile_bits);
   uint32_t* ek = (tpasses % 2 == 0) ? bins.keys : w.pairK;
   uint32_t* ev = (tpasses % 2 == 0) ? bins.values : w.pairV;
@@ -991,9 +1024,14 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
     hipLaunchKernelGGL(count_kernel, dim3(ceil_div(n, NT), V), dim3(NT), 0, s, rect, proj.flags, w.tab, n, p.TX, p.TY,
                        use_mask, w.cnt, w.tmp);
     // 3. compaction of entries with pairs, keyed by depth
-    uint32_t* pos = w.keyB;  // scratch until the sort needs it
-    if ((err = scan(w.tmp, pos, nullptr, (uint32_t)E, E, w.blk, counters + C_ENTRIES, s)) != hipSuccess) return err;
-    hipLaunchKernelGGL(compact_kernel, dim3(ceil_div(E, NT)), dim3(NT), 0, s, w.tmp, pos, proj.depth, E, w.keyA, w.valA);
+    {
+      const int G = scan_blocks(E);
+      hipLaunchKernelGGL(scan_reduce_kernel, dim3(G), dim3(NT), 0, s, w.tmp, nullptr, (uint32_t)E, w.blk, G);
+      hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(NT), 0, s, w.blk, G, counters + C_ENTRIES, nullptr,
+                         (uint64_t)0, 0);
+      hipLaunchKernelGGL(scan_compact_kernel, dim3(G), dim3(NT), 0, s, w.tmp, (uint32_t)E, w.blk, G, proj.depth,
+                         w.keyA, w.valA);
+    }
     // 4. depth order: 32 key bits, 4 passes, the result back in (keyA, valA)
     radix_sort(w.keyA, w.valA, w.keyB, w.valB, counters + C_ENTRIES, nullptr, E, 32, w.hist, w.dtot, s);
     // 5-7 for the first slab (the whole order for complete lists)
