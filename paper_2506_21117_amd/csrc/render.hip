@@ -19,20 +19,36 @@ constexpr int C_OVERFLOW = 1, C_TILES = 2, C_ALIVE = 8;
 // Opacity of a record at a pixel centre, evaluated with explicitly rounded operations
 // so the forward and the backward take the same decisions bit for bit.
 // Returns false when the record is skipped (positive exponent or alpha < 1/255).
+// Records are staged in LDS with the conic in base-2 exponent units:
+// a = (u, v, A2, B2), b = (C2, o, r, g) with A2 = -A log2(e)/2, B2 = -B log2(e),
+// C2 = -C log2(e)/2, so that the Gaussian's exponent (A dx^2 + 2B dx dy + C dy^2)(-1/2)
+// is p2 / log2(e) with p2 = A2 dx^2 + B2 dx dy + C2 dy^2, and G = 2^p2.
+constexpr float LOG2E = 1.4426950408889634f;
+constexpr float K_AC = -0.5f * LOG2E;
+constexpr float K_B = -LOG2E;
+
+__device__ __forceinline__ void stage_record(const float* __restrict__ splat, uint32_t e, float4& a, float4& b,
+                                             float& c) {
+  const float4* sp = reinterpret_cast<const float4*>(splat + (size_t)e * SPLAT_STRIDE);
+  const float4 r0 = sp[0], r1 = sp[1];
+  a = make_float4(r0.x, r0.y, r0.z * K_AC, r0.w * K_B);
+  b = make_float4(r1.x * K_AC, r1.y, r1.z, r1.w);
+  c = sp[2].x;
+}
+
+// Weight of a staged record at pixel centre (fx, fy): false if the exponent is positive
+// or alpha = min(0.99, o G) < 1/255 (branch-free, so that the weights of neighbouring
+// records can be computed together).
 __device__ __forceinline__ bool splat_alpha(const float4 a, const float4 b, float fx, float fy, float& dx, float& dy,
                                             float& G, float& alpha, bool& clamped) {
   dx = __fsub_rn(fx, a.x);
   dy = __fsub_rn(fy, a.y);
-  // q = A dx^2 + 2 B dx dy + C dy^2
-  const float q = __fmaf_rn(__fmul_rn(a.z, dx), dx,
-                            __fmaf_rn(__fmul_rn(__fmul_rn(2.0f, a.w), dx), dy, __fmul_rn(__fmul_rn(b.x, dy), dy)));
-  const float power = __fmul_rn(-0.5f, q);
-  // branch-free, so that the weights of neighbouring records can be computed together
-  G = __expf(power);
+  const float p2 = __fmaf_rn(__fmul_rn(a.z, dx), dx, __fmaf_rn(__fmul_rn(a.w, dx), dy, __fmul_rn(__fmul_rn(b.x, dy), dy)));
+  G = __builtin_amdgcn_exp2f(p2);
   const float oG = __fmul_rn(b.y, G);
   clamped = !(oG < ALPHA_MAX);
   alpha = clamped ? ALPHA_MAX : oG;
-  return !(power > 0.0f) && alpha >= ALPHA_MIN;
+  return !(p2 > 0.0f) && alpha >= ALPHA_MIN;
 }
 
 // Compositing state per rendered tile slot: the largest contributor count of its pixels,
@@ -119,10 +135,7 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
     const int k = kb + threadIdx.x;
     if (k < k_end) {
       const uint32_t e = list_entry(values, r1, r2, k);
-      const float4* sp = reinterpret_cast<const float4*>(splat + (size_t)e * SPLAT_STRIDE);
-      s_a[threadIdx.x] = sp[0];
-      s_b[threadIdx.x] = sp[1];
-      s_c[threadIdx.x] = sp[2].x;
+      stage_record(splat, e, s_a[threadIdx.x], s_b[threadIdx.x], s_c[threadIdx.x]);
     }
     __syncthreads();
     const int cnt = min(NT, k_end - kb);
@@ -138,10 +151,10 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
         const float Tn = Tr * (1.0f - alpha);
         const bool stop = ok && Tn < T_STOP;
         const bool use = ok && !stop;
-        const float w = alpha * Tr;
-        dr = use ? fmaf(w, b.z, dr) : dr;
-        dg = use ? fmaf(w, b.w, dg) : dg;
-        db = use ? fmaf(w, c, db) : db;
+        const float w = use ? alpha * Tr : 0.0f;  // colours are finite and >= 0: adding 0*c is exact
+        dr = fmaf(w, b.z, dr);
+        dg = fmaf(w, b.w, dg);
+        db = fmaf(w, c, db);
         Tr = use ? Tn : Tr;
         last = use ? k1 : last;
         done = done || stop;
@@ -328,10 +341,7 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
     __syncthreads();
     if ((int)threadIdx.x < cnt) {
       const uint32_t e = list_entry(values, r1, r2, beg + (int)threadIdx.x);
-      const float4* sp = reinterpret_cast<const float4*>(splat + (size_t)e * SPLAT_STRIDE);
-      s_a[threadIdx.x] = sp[0];
-      s_b[threadIdx.x] = sp[1];
-      s_c[threadIdx.x] = sp[2].x;
+      stage_record(splat, e, s_a[threadIdx.x], s_b[threadIdx.x], s_c[threadIdx.x]);
       s_e[threadIdx.x] = e;
       const int64_t gid = (int64_t)e - vbase;
       s_act[threadIdx.x] = (gid >= a0 && gid < a1) ? 1u : 0u;
@@ -372,35 +382,40 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
         }
         continue;
       }
-      // branch-free: every lane evaluates the record, the ones it does not reach or
-      // that skip it keep their state and contribute zeros
+      // Every lane evaluates the record's weight; if some lane of the wave is touched,
+      // the gradient terms are computed branch-free, masked by 0/1 factors (exact: the
+      // unmasked terms are multiplied by 1, the masked ones add zeros), and reduced.
       const float4 a = s_a[j], b = s_b[j];
       const float cb = s_c[j];
       float dx, dy, G, alpha;
       bool clamped;
       const bool contrib = splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped) && k < (int)last;
-      const float om = 1.0f - alpha;
-      const float Tj = Tr / om;
-      const float w = alpha * Tj;
-      const float io = 1.0f / om;
-      const float dLda = g0 * (Tj * b.z - S0 * io) + g1 * (Tj * b.w - S1 * io) + g2 * (Tj * cb - S2 * io);
-      S0 = contrib ? fmaf(w, b.z, S0) : S0;
-      S1 = contrib ? fmaf(w, b.w, S1) : S1;
-      S2 = contrib ? fmaf(w, cb, S2) : S2;
-      Tr = contrib ? Tj : Tr;
-      const bool geo = contrib && !clamped;  // the 0.99 clamp has zero derivative
-      const float gp = alpha * dLda;         // dL/dpower
-      float p[9];
-      p[0] = geo ? gp * (a.z * dx + a.w * dy) : 0.0f;
-      p[1] = geo ? gp * (a.w * dx + b.x * dy) : 0.0f;
-      p[2] = geo ? -0.5f * gp * dx * dx : 0.0f;
-      p[3] = geo ? -gp * dx * dy : 0.0f;
-      p[4] = geo ? -0.5f * gp * dy * dy : 0.0f;
-      p[5] = geo ? G * dLda : 0.0f;  // dL/dopacity
-      p[6] = contrib ? w * g0 : 0.0f;
-      p[7] = contrib ? w * g1 : 0.0f;
-      p[8] = contrib ? w * g2 : 0.0f;
       if (__ballot(contrib)) {
+        const float om = 1.0f - alpha;
+        const float Tj = Tr / om;
+        const float w = alpha * Tj;
+        const float io = 1.0f / om;
+        const float dLda = g0 * (Tj * b.z - S0 * io) + g1 * (Tj * b.w - S1 * io) + g2 * (Tj * cb - S2 * io);
+        S0 = contrib ? fmaf(w, b.z, S0) : S0;
+        S1 = contrib ? fmaf(w, b.w, S1) : S1;
+        S2 = contrib ? fmaf(w, cb, S2) : S2;
+        Tr = contrib ? Tj : Tr;
+        const float cf = contrib ? 1.0f : 0.0f;
+        const float gf = (contrib && !clamped) ? 1.0f : 0.0f;  // the 0.99 clamp has zero derivative
+        const float gp = alpha * dLda * gf;                     // dL/dpower
+        // dL/du = gp (A dx + B dy), dL/dv = gp (B dx + C dy); in staged units A = A2 / K_AC,
+        // B = B2 / K_B = B2 / (2 K_AC), C = C2 / K_AC
+        const float gk = gp * (1.0f / K_AC);
+        float p[9];
+        p[0] = gk * (a.z * dx + 0.5f * a.w * dy);
+        p[1] = gk * (0.5f * a.w * dx + b.x * dy);
+        p[2] = -0.5f * gp * dx * dx;
+        p[3] = -gp * dx * dy;
+        p[4] = -0.5f * gp * dy * dy;
+        p[5] = G * dLda * gf;  // dL/dopacity
+        p[6] = w * g0 * cf;
+        p[7] = w * g1 * cf;
+        p[8] = w * g2 * cf;
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
           const float sum = wave_sum_lane63(p[c]);
