@@ -485,24 +485,33 @@ __device__ __forceinline__ void slab_params(uint32_t* counters, int which, int s
 }
 
 // Pairs each slab entry emits: its count from the count pass (first slab) ...
+// Both also copy the slab entries' rectangles into depth order (rsort) for the emission.
 __global__ void __launch_bounds__(NT) gather_counts_kernel(const uint32_t* __restrict__ order,
-                                                           const uint32_t* __restrict__ cnt, uint32_t* counters,
-                                                           int sliced, uint32_t* __restrict__ out) {
+                                                           const uint32_t* __restrict__ cnt,
+                                                           const uint2* __restrict__ rect, uint32_t* counters,
+                                                           int sliced, uint32_t* __restrict__ out,
+                                                           uint2* __restrict__ rsort) {
   uint32_t lo, m;
   slab_params(counters, 1, sliced, lo, m);
-  for (uint32_t j = blockIdx.x * NT + threadIdx.x; j < m; j += gridDim.x * NT) out[j] = cnt[order[lo + j]];
+  for (uint32_t j = blockIdx.x * NT + threadIdx.x; j < m; j += gridDim.x * NT) {
+    const uint32_t e = order[lo + j];
+    out[j] = cnt[e];
+    rsort[j] = rect[e];
+  }
 }
 
 // ... or recounted against the tiles still alive (second slab).
 __global__ void __launch_bounds__(NT) recount_kernel(const uint32_t* __restrict__ order, const uint2* __restrict__ rect,
                                                      const uint32_t* __restrict__ tab, uint32_t* counters, int64_t n,
-                                                     int TX, int TY, uint32_t* __restrict__ out) {
+                                                     int TX, int TY, uint32_t* __restrict__ out,
+                                                     uint2* __restrict__ rsort) {
   uint32_t lo, m;
   slab_params(counters, 2, 1, lo, m);
   for (uint32_t j = blockIdx.x * NT + threadIdx.x; j < m; j += gridDim.x * NT) {
     const uint32_t e = order[lo + j];
     const uint32_t v = (uint32_t)(e / n);
     const uint2 r = rect[e];
+    rsort[j] = r;
     const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
     out[j] = tab_rect(tab, v * (uint32_t)(TY + 1), (uint32_t)(TX + 1), x0, x1, y0, y1);
   }
@@ -518,7 +527,7 @@ constexpr int EMIT_RUN = 8;
 constexpr int EMIT_ROUND = NT * EMIT_RUN;
 // Entries per block: the first slab holds the nearest (largest) footprints, so its
 // entries are spread over more blocks.
-constexpr int EMIT_EPB_NEAR = 16;
+constexpr int EMIT_EPB_NEAR = 64;
 constexpr int EMIT_EPB = NT;
 
 // LDS slot of run position p (runs padded to EMIT_RUN + 1 words against bank conflicts).
@@ -539,7 +548,7 @@ __device__ __forceinline__ uint32_t run_slot(uint32_t p) { return (p / EMIT_RUN)
 // dynamic LDS.
 template <bool MASKED, bool LDS_TAB>
 __global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ order, const uint32_t* __restrict__ offs,
-                                                  const uint2* __restrict__ rect, const uint32_t* __restrict__ tab,
+                                                  const uint2* __restrict__ rsort, const uint32_t* __restrict__ tab,
                                                   const uint32_t* __restrict__ vfirst, const uint32_t* __restrict__ list,
                                                   const uint32_t* __restrict__ counters, int64_t n, int TX, int TY,
                                                   int views, int epb, uint32_t* __restrict__ pk,
@@ -598,7 +607,7 @@ __global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ o
       const uint32_t v = (uint32_t)(e / n);
       s_off[threadIdx.x] = offs[j0 + threadIdx.x];
       s_e[threadIdx.x] = e;
-      s_r[threadIdx.x] = rect[e];
+      s_r[threadIdx.x] = rsort[j0 + threadIdx.x];
       s_vb[threadIdx.x] = MASKED ? v * TYp : v * (uint32_t)(TX * TY);
       s_vf[threadIdx.x] = MASKED ? vfirst[v] : 0u;
     }
@@ -841,6 +850,7 @@ int passes_for(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
 
 struct WsPtrs {
   uint32_t *cnt, *tmp, *keyA, *valA, *keyB, *valB, *blk, *hist, *dtot, *pairK, *pairV, *wpre, *tlist, *vfirst, *tab;
+  uint2* rsort;
 };
 
 WsPtrs carve(const BinPlan& p, char* ws) {
@@ -860,6 +870,7 @@ WsPtrs carve(const BinPlan& p, char* ws) {
   w.tlist = w.wpre + ((int64_t)p.views * p.T + 1);
   w.vfirst = reinterpret_cast<uint32_t*>(ws + p.off_vfirst);
   w.tab = reinterpret_cast<uint32_t*>(ws + p.off_tab);
+  w.rsort = reinterpret_cast<uint2*>(ws + p.off_rsort);
   return w;
 }
 
@@ -887,11 +898,11 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
   uint32_t* order = w.valA;
   hipError_t err;
   if (which == 1)
-    hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(E)), dim3(NT), 0, s, order, w.cnt, counters,
-                       bins.mode == CLSP_BINS_DEPTH_SLICED ? 1 : 0, w.tmp);
+    hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(E)), dim3(NT), 0, s, order, w.cnt, rect, counters,
+                       bins.mode == CLSP_BINS_DEPTH_SLICED ? 1 : 0, w.tmp, w.rsort);
   else
     hipLaunchKernelGGL(recount_kernel, dim3(grid_for(E)), dim3(NT), 0, s, order, rect, w.tab, counters, n, p.TX, p.TY,
-                       w.tmp);
+                       w.tmp, w.rsort);
   // offsets (relative to the slab's first pair) into valB; the capacity check
   if ((err = scan(w.tmp, w.valB, counters + C_SLAB_N, 0u, E, w.blk, counters + C_SLAB_PAIRS, s, counters,
                   (uint64_t)p.capacity, which)) != hipSuccess)
@@ -905,17 +916,17 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
   const int64_t slab_max = (which == 1 && bins.mode == CLSP_BINS_DEPTH_SLICED)
                                ? std::min<int64_t>(E, std::max<int64_t>(E >> 4, 16384))
                                : E;
-  // at most two blocks per CU: each block's copy of the mask index serves many groups
-  const int eg = (int)std::min<int64_t>(std::max<int64_t>((slab_max + epb - 1) / epb, 1), 512);
+  // at most four blocks per CU: each block's copy of the mask index serves many groups
+  const int eg = (int)std::min<int64_t>(std::max<int64_t>((slab_max + epb - 1) / epb, 1), 1024);
   const int64_t tab_words = (int64_t)V * (p.TY + 1) * (p.TX + 1) + (int64_t)V * p.T;
   if (which == 1 && !use_mask) {
-    hipLaunchKernelGGL((emit_kernel<false, false>), dim3(eg), dim3(NT), 0, s, order, w.valB, rect, w.tab, w.vfirst,
+    hipLaunchKernelGGL((emit_kernel<false, false>), dim3(eg), dim3(NT), 0, s, order, w.valB, w.rsort, w.tab, w.vfirst,
                        mlist, counters, n, p.TX, p.TY, V, epb, ek, ev);
   } else if (tab_words <= EMIT_TAB_WORDS) {
-    hipLaunchKernelGGL((emit_kernel<true, true>), dim3(eg), dim3(NT), (size_t)tab_words * 4, s, order, w.valB, rect,
+    hipLaunchKernelGGL((emit_kernel<true, true>), dim3(eg), dim3(NT), (size_t)tab_words * 4, s, order, w.valB, w.rsort,
                        w.tab, w.vfirst, mlist, counters, n, p.TX, p.TY, V, epb, ek, ev);
   } else {
-    hipLaunchKernelGGL((emit_kernel<true, false>), dim3(eg), dim3(NT), 0, s, order, w.valB, rect, w.tab, w.vfirst,
+    hipLaunchKernelGGL((emit_kernel<true, false>), dim3(eg), dim3(NT), 0, s, order, w.valB, w.rsort, w.tab, w.vfirst,
                        mlist, counters, n, p.TX, p.TY, V, epb, ek, ev);
   }
   if (tpasses > 0) {
@@ -974,6 +985,7 @@ BinPlan make_bin_plan(int64_t n, int views, int W, int H, int64_t capacity) {
   p.off_tflag = take((gt + 1) * 4 * 2);
   p.off_vfirst = take((size_t)views * 4);
   p.off_tab = take((size_t)views * (p.TY + 1) * (p.TX + 1) * 4);
+  p.off_rsort = take(E * 8);
   // per rendered tile slot: alive flag, and per pixel the carried compositing state
   p.off_alive = take(gt * 4);
   p.off_carry = take((size_t)gt * TILE_PIX * CARRY_FIELDS * 4);
