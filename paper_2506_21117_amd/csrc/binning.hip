@@ -174,7 +174,7 @@ __device__ __forceinline__ uint32_t tab_rank(const uint32_t* tab, uint32_t vrow,
 // Pairs of each entry: the rectangle's area, or its set tiles in the mask (corner table).
 __global__ void __launch_bounds__(NT) count_kernel(const uint2* __restrict__ rect, const uint32_t* __restrict__ flags,
                                                    const uint32_t* __restrict__ tab, int64_t n, int TX, int TY,
-                                                   int use_mask, uint32_t* __restrict__ cnt, uint32_t* __restrict__ has) {
+                                                   int use_mask, uint32_t* __restrict__ cnt) {
   const int v = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (i >= n) return;
@@ -192,7 +192,6 @@ __global__ void __launch_bounds__(NT) count_kernel(const uint2* __restrict__ rec
     }
   }
   cnt[e] = c;
-  has[e] = c > 0 ? 1u : 0u;
 }
 
 // Capacity check after a slab's pair count: P = first-slab pairs + this slab's pairs.
@@ -213,6 +212,8 @@ __device__ void capacity_check(uint32_t* counters, uint64_t capacity, int which)
 }
 
 // ------------------------------------------------------------------ generic exclusive scan
+// FLAGS: sum (in[e] != 0) instead of in[e].
+template <bool FLAGS = false>
 __global__ void __launch_bounds__(NT) scan_reduce_kernel(const uint32_t* __restrict__ in, const uint32_t* n_ptr,
                                                          uint32_t n_host, uint32_t* __restrict__ blk, int G) {
   __shared__ uint32_t s4[4];
@@ -220,7 +221,7 @@ __global__ void __launch_bounds__(NT) scan_reduce_kernel(const uint32_t* __restr
   uint32_t beg, end;
   block_span(n, G, blockIdx.x, SCAN_CHUNK, beg, end);
   uint32_t acc = 0;
-  for (uint32_t e = beg + threadIdx.x; e < end; e += NT) acc += in[e];
+  for (uint32_t e = beg + threadIdx.x; e < end; e += NT) acc += FLAGS ? (in[e] != 0u ? 1u : 0u) : in[e];
   uint32_t tot;
   block_excl_scan(acc, s4, tot);
   if (threadIdx.x == 0) blk[blockIdx.x] = tot;
@@ -280,9 +281,10 @@ __global__ void __launch_bounds__(NT) scan_apply_kernel(const uint32_t* __restri
   }
 }
 
-// The final scan step of the has-pairs flags as a compaction: entry e with a pair
-// goes to position p (its exclusive prefix) as (depth key, e).
-__global__ void __launch_bounds__(NT) scan_compact_kernel(const uint32_t* __restrict__ has, uint32_t n,
+// The final scan step over the entries' has-pairs flags (pair count > 0) as a
+// compaction: entry e with a pair goes to position p (its exclusive prefix) as
+// (depth key, e).
+__global__ void __launch_bounds__(NT) scan_compact_kernel(const uint32_t* __restrict__ cnt, uint32_t n,
                                                           const uint32_t* __restrict__ blk, int G,
                                                           const float* __restrict__ depth, uint32_t* __restrict__ keys,
                                                           uint32_t* __restrict__ vals) {
@@ -296,7 +298,7 @@ __global__ void __launch_bounds__(NT) scan_compact_kernel(const uint32_t* __rest
     const uint32_t t0 = c + threadIdx.x * SCAN_ITEMS;
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
-      v[k] = (t0 + k < end) ? has[t0 + k] : 0u;
+      v[k] = (t0 + k < end && cnt[t0 + k] != 0u) ? 1u : 0u;
       sum += v[k];
     }
     uint32_t tot;
@@ -318,29 +320,39 @@ __global__ void __launch_bounds__(NT) scan_compact_kernel(const uint32_t* __rest
 // All sort kernels work on keys[off + e], e < n, with n and off read from device memory.
 __device__ __forceinline__ uint32_t load_off(const uint32_t* p) { return p ? *p : 0u; }
 
-// Digit histogram of each block's span: hist[d * G + b].
+// Blocks that hold keys: one chunk each up to G (the grid), more per block beyond.
+__device__ __forceinline__ int rs_blocks(uint32_t n, int G) {
+  const uint32_t c = (n + RS_CHUNK - 1) / RS_CHUNK;
+  return (int)min((uint32_t)G, max(c, 1u));
+}
+
+// Digit histogram of each block's span: hist[d * Ge + b], Ge = rs_blocks(n, G).
 __global__ void __launch_bounds__(NT) rs_upsweep_kernel(const uint32_t* __restrict__ keys, const uint32_t* n_ptr,
                                                         const uint32_t* off_ptr, int shift, int bits,
                                                         uint32_t* __restrict__ hist, int G) {
   __shared__ uint32_t h[4][256];
   const uint32_t n = *n_ptr;
+  const int Ge = rs_blocks(n, G);
+  if ((int)blockIdx.x >= Ge) return;
   keys += load_off(off_ptr);
   const int radix = 1 << bits;
   const uint32_t msk = (uint32_t)radix - 1u;
   for (int d = threadIdx.x; d < 4 * 256; d += NT) (&h[0][0])[d] = 0;
   __syncthreads();
   uint32_t beg, end;
-  block_span(n, G, blockIdx.x, RS_CHUNK, beg, end);
+  block_span(n, Ge, blockIdx.x, RS_CHUNK, beg, end);
   const int w = threadIdx.x >> 6;
   for (uint32_t e = beg + threadIdx.x; e < end; e += NT) atomicAdd(&h[w][(keys[e] >> shift) & msk], 1u);
   __syncthreads();
-  for (int d = threadIdx.x; d < radix; d += NT) hist[(int64_t)d * G + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+  for (int d = threadIdx.x; d < radix; d += NT) hist[(int64_t)d * Ge + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
 // Block d: exclusive scan over blocks of digit d's counts; digit total -> tot[d].
-__global__ void __launch_bounds__(NT) rs_scan_kernel(uint32_t* __restrict__ hist, int G, uint32_t* __restrict__ tot) {
+__global__ void __launch_bounds__(NT) rs_scan_kernel(uint32_t* __restrict__ hist, const uint32_t* n_ptr, int G,
+                                                     uint32_t* __restrict__ tot) {
   __shared__ uint32_t s4[4];
   constexpr int PER = MAX_SORT_BLOCKS / NT;
+  G = rs_blocks(*n_ptr, G);
   uint32_t* row = hist + (int64_t)blockIdx.x * G;
   uint32_t v[PER];
   uint32_t sum = 0;
@@ -382,6 +394,8 @@ __global__ void __launch_bounds__(NT) rs_downsweep_kernel(const uint32_t* __rest
   vin += off;
   kout += off;
   vout += off;
+  G = rs_blocks(n, G);
+  if ((int)blockIdx.x >= G) return;
   uint32_t beg, end;
   block_span(n, G, blockIdx.x, RS_CHUNK, beg, end);
   if (beg >= end) return;
@@ -814,7 +828,7 @@ hipError_t scan(const uint32_t* in, uint32_t* out, const uint32_t* n_ptr, uint32
                 uint32_t* blk, uint32_t* total_out, hipStream_t s, uint32_t* counters = nullptr,
                 uint64_t capacity = 0, int check_which = 0) {
   const int G = scan_blocks(nmax);
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3(G), dim3(NT), 0, s, in, n_ptr, n_host, blk, G);
+  hipLaunchKernelGGL(scan_reduce_kernel<false>, dim3(G), dim3(NT), 0, s, in, n_ptr, n_host, blk, G);
   hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(NT), 0, s, blk, G, total_out, counters, capacity, check_which);
   hipLaunchKernelGGL(scan_apply_kernel, dim3(G), dim3(NT), 0, s, in, n_ptr, n_host, blk, G, out);
   return hipGetLastError();
@@ -837,7 +851,7 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uin
     uint32_t* ko = cur ? k0 : k1;
     uint32_t* vo = cur ? v0 : v1;
     hipLaunchKernelGGL(rs_upsweep_kernel, dim3(G), dim3(NT), 0, s, ki, n_ptr, off_ptr, shift, bits, hist, G);
-    hipLaunchKernelGGL(rs_scan_kernel, dim3(1 << bits), dim3(NT), 0, s, hist, G, tot);
+    hipLaunchKernelGGL(rs_scan_kernel, dim3(1 << bits), dim3(NT), 0, s, hist, n_ptr, G, tot);
     hipLaunchKernelGGL(rs_downsweep_kernel, dim3(G), dim3(NT), 0, s, ki, vi, ko, vo, n_ptr, off_ptr, shift, bits, hist,
                        tot, G);
     shift += bits;
@@ -1034,14 +1048,14 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
   if (E > 0) {
     // 2. counts
     hipLaunchKernelGGL(count_kernel, dim3(ceil_div(n, NT), V), dim3(NT), 0, s, rect, proj.flags, w.tab, n, p.TX, p.TY,
-                       use_mask, w.cnt, w.tmp);
+                       use_mask, w.cnt);
     // 3. compaction of entries with pairs, keyed by depth
     {
       const int G = scan_blocks(E);
-      hipLaunchKernelGGL(scan_reduce_kernel, dim3(G), dim3(NT), 0, s, w.tmp, nullptr, (uint32_t)E, w.blk, G);
+      hipLaunchKernelGGL(scan_reduce_kernel<true>, dim3(G), dim3(NT), 0, s, w.cnt, nullptr, (uint32_t)E, w.blk, G);
       hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(NT), 0, s, w.blk, G, counters + C_ENTRIES, nullptr,
                          (uint64_t)0, 0);
-      hipLaunchKernelGGL(scan_compact_kernel, dim3(G), dim3(NT), 0, s, w.tmp, (uint32_t)E, w.blk, G, proj.depth,
+      hipLaunchKernelGGL(scan_compact_kernel, dim3(G), dim3(NT), 0, s, w.cnt, (uint32_t)E, w.blk, G, proj.depth,
                          w.keyA, w.valA);
     }
     // 4. depth order: 32 key bits, 4 passes, the result back in (keyA, valA)
