@@ -12,6 +12,7 @@ Prints ONE JSON line.  `value` is local steps per second.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -194,6 +195,31 @@ def main():
     return 0
 
 
+# HBM bytes per call of the local step, from two rocprofv3 counter runs (FETCH_SIZE, then
+# WRITE_SIZE, summed over the call's kernels and averaged over 10 steps), each scaled by
+# what the counter reads for a plain 256 MiB device copy (fetch x2.000, write x1.000).
+# They describe the kernels whose sources hash to `source_sha256` and are reported only
+# while the sources still do (profiles/traffic_local_step_1M_1280x720.txt).
+MEASURED_TRAFFIC = {
+    "source_sha256": "877edc3f64a8895221c5130e918c42f4e6bfdf0d6a553ebf174a2d74356cc8ea",
+    "bytes": {"bin_and_sort": 183.066e6, "render_forward": 13.541e6, "render_backward": 15.237e6},
+}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in sorted((ROOT / "paper_2506_21117_amd" / "csrc").glob("*")) + [ROOT / "include" / "clsplat.h"]:
+        h.update(p.name.encode())
+        h.update(p.read_bytes())
+    return h.hexdigest()
+
+
+def measured_traffic(call):
+    if MEASURED_TRAFFIC["source_sha256"] != kernel_source_hash():
+        return None
+    return MEASURED_TRAFFIC["bytes"].get(call)
+
+
 # FP32 operations per (pixel, record) evaluation, counted from the model's formulas:
 # the Gaussian weight (offset 2, quadratic form 9, exp 1, opacity product and clamp 2),
 # the transmittance update (2) and the colour sums (3 multiply-adds = 6) ...
@@ -217,21 +243,23 @@ def roofline_of(ms, st, n):
         ach = flops / t / 1e12
         return {"bound": "alu", "kernel": "render_backward (raster backward + preprocess backward)",
                 "achieved": round(ach, 3), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / ALU_PEAK_TFLOPS, 5), "traffic": None,
+                "frac": round(ach / ALU_PEAK_TFLOPS, 5), "traffic": measured_traffic(dom),
                 "units": {"pixel_records": st["pixel_records"], "pixel_records_active": st["pixel_records_active"],
                           "flop_per_eval": FLOP_EVAL, "flop_per_active_eval": FLOP_GRAD}}
     if dom == "render_forward":
         flops = FLOP_EVAL * st["pixel_records"]
         ach = flops / t / 1e12
         return {"bound": "alu", "kernel": "render_forward (both depth slabs)", "achieved": round(ach, 3),
-                "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / ALU_PEAK_TFLOPS, 5), "traffic": None,
+                "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / ALU_PEAK_TFLOPS, 5),
+                "traffic": measured_traffic(dom),
                 "units": {"pixel_records": st["pixel_records"], "flop_per_eval": FLOP_EVAL}}
     # binning: read the projected rectangles, flags and depths of all N entries
     # (16 B), then per pair 44 B (emit 12 B, one sort read + write 24 B, range scan 8 B)
     byts = 16 * n + 44 * st["pairs"]
     ach = byts / t / 1e9
     return {"bound": "hbm", "kernel": "bin_and_sort", "achieved": round(ach, 2), "peak": 8000.0, "unit": "GB/s",
-            "frac": round(ach / 8000.0, 5), "traffic": None, "units": {"entries": n, "pairs": st["pairs"]}}
+            "frac": round(ach / 8000.0, 5), "traffic": measured_traffic(dom),
+            "units": {"entries": n, "pairs": st["pairs"], "algorithmic_bytes": byts}}
 
 
 def serving_leg(dev, qps, n_requests, log):
