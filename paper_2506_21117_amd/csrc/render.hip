@@ -19,6 +19,13 @@ constexpr int C_OVERFLOW = 1, C_TILES = 2, C_ALIVE = 8;
 // Opacity of a record at a pixel centre, evaluated with explicitly rounded operations
 // so the forward and the backward take the same decisions bit for bit.
 // Returns false when the record is skipped (positive exponent or alpha < 1/255).
+// Pixel of thread t in its 16x16 tile: each wave64 takes an 8x8 quadrant (t bits 0-2:
+// x, 3-5: y, 6: quadrant x, 7: quadrant y), so a wave's pixels are compact and tend to
+// finish compositing together.  Every kernel that keeps per-thread state of a tile
+// (compositing chunks, carries) uses this same map.
+__device__ __forceinline__ int pixel_x(uint32_t t) { return (int)((((t >> 6) & 1u) << 3) | (t & 7u)); }
+__device__ __forceinline__ int pixel_y(uint32_t t) { return (int)((((t >> 7) & 1u) << 3) | ((t >> 3) & 7u)); }
+
 // Records are staged in LDS with the conic in base-2 exponent units:
 // a = (u, v, A2, B2), b = (C2, o, r, g) with A2 = -A log2(e)/2, B2 = -B log2(e),
 // C2 = -C log2(e)/2, so that the Gaussian's exponent (A dx^2 + 2B dx dy + C dy^2)(-1/2)
@@ -98,8 +105,8 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
   __shared__ uint32_t s_max;
   const uint32_t gt = tile_list[slot];
   const int v = gt / T, t = gt % T;
-  const int px = (t % TX) * TILE + (threadIdx.x & 15);
-  const int py = (t / TX) * TILE + (threadIdx.x >> 4);
+  const int px = (t % TX) * TILE + pixel_x(threadIdx.x);
+  const int py = (t / TX) * TILE + pixel_y(threadIdx.x);
   const bool inside = px < W && py < H;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
   const uint2 r1 = ranges[gt];
@@ -236,8 +243,8 @@ __global__ void __launch_bounds__(NT) l1_loss_grad_kernel(const float* __restric
   __shared__ float s_sum[4];
   const uint32_t gt = tile_list[blockIdx.x];
   const int v = gt / T, t = gt % T;
-  const int px = (t % TX) * TILE + (threadIdx.x & 15);
-  const int py = (t / TX) * TILE + (threadIdx.x >> 4);
+  const int px = (t % TX) * TILE + pixel_x(threadIdx.x);
+  const int py = (t / TX) * TILE + pixel_y(threadIdx.x);
   const float norm = 1.0f / (3.0f * (float)W * (float)H);
   float acc = 0.0f;
   if (px < W && py < H) {
@@ -301,8 +308,8 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
 
   const uint32_t gt = tile_list[slot];
   const int v = gt / T, t = gt % T;
-  const int px = (t % TX) * TILE + (threadIdx.x & 15);
-  const int py = (t / TX) * TILE + (threadIdx.x >> 4);
+  const int px = (t % TX) * TILE + pixel_x(threadIdx.x);
+  const int py = (t / TX) * TILE + pixel_y(threadIdx.x);
   const bool inside = px < W && py < H;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
   const uint2 r1 = ranges[gt], r2 = ranges2[gt];
