@@ -1020,7 +1020,12 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
   // clear outputs (counters[C_STICKY] is left alone: it remembers any overflow)
   {
     ClearList c{};
+    bool full = false;
     auto add = [&](uint32_t* ptr, int64_t cnt) {
+      if (c.k == CLEAR_SEGS) {
+        full = true;
+        return;
+      }
       c.p[c.k] = ptr;
       c.n[c.k++] = cnt;
     };
@@ -1030,6 +1035,7 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
     add(bins.ranges2, gt * 2);
     add(bins.alive_mask, (int64_t)V * wpv);
     if (use_mask) add(bins.tile_mask, (int64_t)V * wpv);
+    if (full) return hipErrorInvalidValue;  // more buffers than the clear kernel's list holds
     int64_t total = 0;
     for (int i = 0; i < c.k; ++i) total += c.n[i];
     hipLaunchKernelGGL(clear_kernel, dim3(grid_for(total, 2048)), dim3(NT), 0, s, c);
