@@ -146,7 +146,8 @@ class SplatOptimizer:
         k1 = torch.minimum(per_tile, len1)
         k2 = (per_tile - len1).clamp(min=0)
         n_act = (cum[r1[:, 0:1] + k1] - cum[r1[:, 0:1]]) + (cum[r2[:, 0:1] + k2] - cum[r2[:, 0:1]])
-        return {"tiles": c["tiles"], "tiles_total": TX * TY, "pairs": c["pairs"], "entries": c["entries"],
+        return {"tiles": c["tiles"], "tiles_total": TX * TY, "pairs": c["pairs"], "pairs_first_slab": c["pairs1"],
+                "entries_first_slab": c["slab1"], "tiles_second_slab": c["alive"], "entries": c["entries"],
                 "pixels": int(pix), "records": int(per_tile.max(dim=1).values.sum()),
                 "pixel_records": int(per_tile.sum()), "pixel_records_active": int(n_act.sum())}
 
