@@ -208,8 +208,8 @@ def main():
 # They describe the kernels whose sources hash to `source_sha256` and are reported only
 # while the sources still do (profiles/traffic_local_step_1M_1280x720.txt).
 MEASURED_TRAFFIC = {
-    "source_sha256": "877edc3f64a8895221c5130e918c42f4e6bfdf0d6a553ebf174a2d74356cc8ea",
-    "bytes": {"bin_and_sort": 183.066e6, "render_forward": 13.541e6, "render_backward": 15.237e6},
+    "source_sha256": "785adaec9b317b781d972763fe7790839048bbd97617e3f5e91862b58457b68d",
+    "bytes": {"bin_and_sort": 183.065e6, "render_forward": 13.541e6, "render_backward": 15.236e6},
 }
 
 
