@@ -2,7 +2,10 @@
 //
 // Pipeline for V views of n Gaussians (entry e = v*n + i):
 //   1. mask    : tiles covered by the rectangles of the changed Gaussians (LDS bitmap per
-//                block, OR-ed into the global bitmap), or all tiles in full mode;
+//                block, OR-ed into the global bitmap), or all tiles in full mode; then
+//                its index: the sorted list of set tiles (the tiles to render) and a
+//                corner table of prefix counts that gives the set tiles of any
+//                rectangle in O(1);
 //   2. count   : pairs each entry emits = masked tiles of its rectangle;
 //   3. compact : entries with at least one pair, keyed by their float32 depth bits;
 //   4. sort    : stable LSD radix sort of those keys (equal depths keep entry order);
@@ -11,13 +14,13 @@
 //   6. sort    : stable LSD radix sort of the pairs by global tile only — the depth
 //                order within a tile comes from step 4, so only ceil(log2(V*T)) key bits
 //                are sorted instead of tile + 32 depth bits;
-//   7. ranges  : [start, end) per tile, and the compact list of tiles to render.
+//   7. ranges  : [start, end) of each tile's run.
 // Every kernel reads its element count from device memory, so nothing is read back.
 //
 // Depth-sliced lists: steps 5-7 first run for the nearest slab of the depth order
 // only; after the forward pass has rendered it, they run again for the remaining
 // entries, emitting only into the tiles that still have compositing pixels (the
-// "alive" tiles), and the forward continues those tiles.
+// "alive" tiles, indexed like the mask), and the forward continues those tiles.
 #include <algorithm>
 
 #include "internal.hpp"
