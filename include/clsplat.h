@@ -212,12 +212,16 @@ typedef struct clsp_bins {
  * 1-based step count used in the bias corrections.  When step_device (device int32[1])
  * is not NULL the kernel reads the step count from there instead (and `step` is
  * ignored), so a captured graph can replay the call while the caller advances the
- * counter on the device. */
+ * counter on the device.  With zero_grads != 0 the call also sets the gradient rows of
+ * `active` to zero after using them (all of them, row_mask or not), which replaces a
+ * separate clsp_zero_grads before the next step's backward. */
 typedef struct clsp_adam_hparams {
   float lr[6];
   float beta1, beta2, eps;
   int32_t step;
   const int32_t *step_device;
+  int32_t zero_grads;
+  int32_t reserved;
 } clsp_adam_hparams;
 
 /* Library version string and the last error message of the calling host thread. */

@@ -302,13 +302,15 @@ DEFAULT_LR = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3, 2.5e-3 / 20.0)
 
 
 def masked_adam_step(params: GaussianTensors, grads, exp_avg, exp_avg_sq, active, step, lr=DEFAULT_LR, beta1=0.9,
-                     beta2=0.999, eps=1e-15, row_mask=None, stream=None, step_device=None):
+                     beta2=0.999, eps=1e-15, row_mask=None, stream=None, step_device=None, zero_grads=False):
     """``step`` (host int) or ``step_device`` (int32 device tensor [1]) gives the 1-based
-    step count of the bias corrections."""
+    step count of the bias corrections.  With ``zero_grads`` the gradient rows of
+    ``active`` are set to zero after use."""
     a0, a1 = (0, params.n) if active is None else (int(active[0]), int(active[1]))
     hp = _ffi.AdamHParams()
     hp.lr = (ctypes.c_float * 6)(*[float(x) for x in lr])
     hp.beta1, hp.beta2, hp.eps, hp.step = float(beta1), float(beta2), float(eps), int(step or 0)
+    hp.zero_grads = 1 if zero_grads else 0
     if step_device is not None:
         if step_device.dtype != torch.int32 or step_device.numel() != 1 or not step_device.is_cuda:
             raise ValueError("step_device must be an int32 CUDA tensor of one element")

@@ -14,10 +14,12 @@ struct AdamConst {
   float b1, b2, eps;
   float bc1, bc2;             // 1 - beta^step (host step count)
   const int32_t* step_dev;    // device step count, or null
+  int zero_grads;             // clear the gradient rows after use
 };
 
-__device__ __forceinline__ void adam_one(float* p, const float* g, float* m, float* v, float lr, const AdamConst& h) {
+__device__ __forceinline__ void adam_one(float* p, float* g, float* m, float* v, float lr, const AdamConst& h) {
   const float gg = *g;
+  if (h.zero_grads) *g = 0.0f;
   const float mm = h.b1 * (*m) + (1.0f - h.b1) * gg;
   const float vv = h.b2 * (*v) + (1.0f - h.b2) * gg * gg;
   *m = mm;
@@ -29,7 +31,18 @@ __global__ void __launch_bounds__(256) adam_kernel(MutParams P, MutParams Gr, Mu
                                                    int64_t a1, const uint8_t* __restrict__ row_mask, AdamConst h) {
   const int64_t i = a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a1) return;
-  if (row_mask && !row_mask[i]) return;
+  if (row_mask && !row_mask[i]) {
+    if (h.zero_grads) {
+      const int64_t n = Gr.n;
+      for (int c = 0; c < 3; ++c) Gr.means[c * n + i] = 0.0f;
+      for (int c = 0; c < 3; ++c) Gr.log_scales[c * n + i] = 0.0f;
+      for (int c = 0; c < 4; ++c) Gr.quats[c * n + i] = 0.0f;
+      Gr.opac[i] = 0.0f;
+      const int K3 = 3 * (Gr.sh_degree + 1) * (Gr.sh_degree + 1);
+      for (int c = 0; c < K3; ++c) Gr.sh[(int64_t)c * n + i] = 0.0f;
+    }
+    return;
+  }
   if (h.step_dev) {
     const float t = (float)max(*h.step_dev, 1);
     h.bc1 = 1.0f - powf(h.b1, t);
@@ -74,6 +87,7 @@ hipError_t launch_adam(const MutParams& p, const MutParams& g, const MutParams& 
   h.bc1 = (float)(1.0 - pow((double)hp.beta1, (double)hp.step));
   h.bc2 = (float)(1.0 - pow((double)hp.beta2, (double)hp.step));
   h.step_dev = hp.step_device;
+  h.zero_grads = hp.zero_grads;
   hipLaunchKernelGGL(adam_kernel, dim3(ceil_div(a1 - a0, 256)), dim3(256), 0, s, p, g, m, v, a0, a1, row_mask, h);
   return hipGetLastError();
 }

@@ -1,10 +1,10 @@
 """Local and full-scene optimisation steps over the C-ABI.
 
 One step (one view, the 3D Gaussian Splatting convention) runs, all on one stream:
-zero the change set's gradient rows -> project all Gaussians -> render mask and per-tile
-depth order (masked tiles only in local mode) -> forward render -> L1 loss gradient ->
-backward render and preprocess backward for the change set -> masked Adam on the
-change set.  This is the local optimisation of CL-Splats (Sec. 3.3 "Local Optimization
+project all Gaussians -> render mask and per-tile depth order (masked tiles only in
+local mode) -> forward render -> L1 loss gradient -> backward render and preprocess
+backward for the change set -> masked Adam on the change set, which also clears the
+change set's gradient rows for the next step.  This is the local optimisation of CL-Splats (Sec. 3.3 "Local Optimization
 Kernel"; Supp. "3DGS Optimization in Changed Regions"); the full-scene step is the same
 with no mask and every row active.
 """
@@ -94,6 +94,9 @@ class SplatOptimizer:
         self._hp = _ffi.AdamHParams()
         self._hp.lr = (ctypes.c_float * 6)(*[float(x) for x in self.lr])
         self._hp.beta1, self._hp.beta2, self._hp.eps = 0.9, 0.999, 1e-15
+        # Adam clears the gradient rows it used, so every step starts from zero gradients
+        # (they start at zero) without a separate clearing launch
+        self._hp.zero_grads = 1
         p = lambda t: ctypes.c_void_p(t.data_ptr())
         self._ptrs = {"image": p(self.image), "T": p(self.T), "nc": p(self.nc), "dL": p(self.dL),
                       "loss": p(self.loss_sum), "ws": p(self.bins.ws), "bws": p(self.bwd_ws), "state": p(self.state),
@@ -160,7 +163,6 @@ class SplatOptimizer:
         P = self._ptrs
         by = ctypes.byref
         use_mask = 1 if self.local else 0
-        check(L.clsp_zero_grads(by(self._gr), self._range, st))
         check(L.clsp_project_preprocess(by(self._g), cam, 1, by(self._proj), st))
         ev = events or {}
         mark = lambda name, i: ev[name][i].record(stream) if name in ev else None

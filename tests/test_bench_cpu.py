@@ -19,6 +19,7 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_measured_traffic_only_for_the_measured_kernels(monkeypatch):
+    monkeypatch.setitem(bench.MEASURED_TRAFFIC, "source_sha256", bench.kernel_source_hash())
     assert bench.measured_traffic("bin_and_sort") == bench.MEASURED_TRAFFIC["bytes"]["bin_and_sort"]
     monkeypatch.setitem(bench.MEASURED_TRAFFIC, "source_sha256", "0" * 64)
     assert bench.measured_traffic("bin_and_sort") is None

@@ -415,6 +415,37 @@ def test_masked_adam_parity(dev, sh_degree, with_mask):
             np.testing.assert_array_equal(to_np(getattr(T1, k))[..., frozen], to_np(getattr(T0, k))[..., frozen])
 
 
+@pytest.mark.parametrize("with_mask", [False, True])
+def test_masked_adam_clears_gradients_when_asked(dev, with_mask):
+    """zero_grads leaves the update bit for bit the same, zeroes every gradient row of
+    the active range (masked-out rows too) and no other row."""
+    rng = np.random.default_rng(17)
+    n, a, sh_degree = 2000, (700, 1900), 1
+    K = (sh_degree + 1) ** 2
+    shapes = {"means": (3, n), "log_scales": (3, n), "quats": (4, n), "opacity_logit": (n,), "sh": (K, 3, n)}
+    mk = lambda f: api.GaussianTensors(*[torch.as_tensor(f(s).astype(np.float32), device=dev)
+                                         for s in shapes.values()], sh_degree)
+    P, G = mk(lambda s: rng.normal(size=s)), mk(lambda s: rng.normal(size=s) * 0.1)
+    M, V = mk(lambda s: rng.normal(size=s) * 0.01), mk(lambda s: rng.uniform(size=s) * 1e-3)
+    row_mask = torch.as_tensor((rng.uniform(size=n) < 0.5).astype(np.uint8), device=dev) if with_mask else None
+    outs = []
+    for zero in (False, True):
+        p, g, m, v = P.clone(), G.clone(), M.clone(), V.clone()
+        api.masked_adam_step(p, g, m, v, a, 3, row_mask=row_mask, zero_grads=zero)
+        outs.append((p, g, m, v))
+    torch.cuda.synchronize()
+    (p0, g0, m0, v0), (p1, g1, m1, v1) = outs
+    inside = np.zeros(n, bool)
+    inside[a[0]:a[1]] = True
+    for k in api.GaussianTensors.NAMES:
+        for X0, X1 in ((p0, p1), (m0, m1), (v0, v1)):
+            np.testing.assert_array_equal(to_np(getattr(X1, k)), to_np(getattr(X0, k)))
+        got, before = to_np(getattr(g1, k)), to_np(getattr(G, k))
+        assert not np.any(got[..., inside])
+        np.testing.assert_array_equal(got[..., ~inside], before[..., ~inside])
+        np.testing.assert_array_equal(to_np(getattr(g0, k)), before)
+
+
 # ------------------------------------------------------------------ depth-sliced lists
 @pytest.mark.parametrize("case", ["tiny", "ring2", "local", "cloud"])
 @pytest.mark.parametrize("local", [False, True])
