@@ -359,7 +359,9 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
     // a frozen Gaussian's record: only the transmittance and the colour behind move on
     auto unblend = [&](bool ok, float alpha, float4 b, float c) {
       if (!ok) return;
-      const float Tj = Tr / (1.0f - alpha);
+      // 1 - alpha is in [0.01, 1]: the hardware reciprocal (about 1 ulp) in place of a
+      // division
+      const float Tj = Tr * __builtin_amdgcn_rcpf(1.0f - alpha);
       const float w = alpha * Tj;
       S0 = fmaf(w, b.z, S0);
       S1 = fmaf(w, b.w, S1);
@@ -399,9 +401,9 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
       const bool contrib = splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped) && k < (int)last;
       if (__ballot(contrib)) {
         const float om = 1.0f - alpha;
-        const float Tj = Tr / om;
+        const float io = __builtin_amdgcn_rcpf(om);  // om in [0.01, 1]
+        const float Tj = Tr * io;
         const float w = alpha * Tj;
-        const float io = 1.0f / om;
         const float dLda = g0 * (Tj * b.z - S0 * io) + g1 * (Tj * b.w - S1 * io) + g2 * (Tj * cb - S2 * io);
         S0 = contrib ? fmaf(w, b.z, S0) : S0;
         S1 = contrib ? fmaf(w, b.w, S1) : S1;
