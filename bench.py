@@ -41,6 +41,14 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 10 times (the reference kernel of known size for "
                          "the HBM byte counters) and exit")
+    ap.add_argument("--summarize-trace", metavar="DB",
+                    help="print per-step kernel averages and per-call sums from the results database of a "
+                         "rocprofv3 --kernel-trace run of this script, and exit")
+    ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="print per-call HBM bytes from the output folders of four rocprofv3 --pmc runs "
+                         "(FETCH_SIZE and WRITE_SIZE of this script, then of --copy-calibration), and exit")
+    ap.add_argument("--summary-steps", type=int, default=10, help="steps (the last ones) a summary averages over")
+    ap.add_argument("--summary-note", action="append", default=[], help="a header line of the summary (repeatable)")
     return ap.parse_args()
 
 
@@ -50,6 +58,12 @@ def log(msg):
 
 def main():
     args = parse()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace, args.summary_steps, args.summary_note))
+        return 0
+    if args.summarize_traffic:
+        print(summarize_traffic(*args.summarize_traffic, k=args.summary_steps, notes=args.summary_note))
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this build runs on a single "
               "MI355X; see the design notes for how the step would shard).", file=sys.stderr)
@@ -208,8 +222,8 @@ def main():
 # They describe the kernels whose sources hash to `source_sha256` and are reported only
 # while the sources still do (profiles/traffic_local_step_1M_1280x720.txt).
 MEASURED_TRAFFIC = {
-    "source_sha256": "8f3fec841d4ca194bb4c9085eda2fad4e7242f901fdc60bb19eaa8cd6cae757e",
-    "bytes": {"bin_and_sort": 183.065e6, "render_forward": 13.541e6, "render_backward": 15.236e6},
+    "source_sha256": "e839be756c94dc89d8600e1cc39ed9e18a07eaa07bed84bb79eff0cb932666ed",
+    "bytes": {"bin_and_sort": 183.066e6, "render_forward": 13.531e6, "render_backward": 15.233e6},
 }
 
 
@@ -362,6 +376,136 @@ def cpu_baseline(sc, cams, a, scene_gt, order, budget_s, log):
                       f"forward of every masked pixel, L1 gradient, brute-force forward+backward, preprocess "
                       f"backward, Adam on the change set; {dt:.1f}s measured, no extrapolation (the render of "
                       f"the targets at the masked pixels is excluded)"}
+
+
+# ---- summaries of rocprofv3 output (host only) ----------------------------------------
+# A step of this script's timed loop starts at preprocess_kernel and ends at adam_kernel.
+# Within it the C-ABI calls are: bin_and_sort = the kernels after preprocess_kernel up to
+# the first render_forward_kernel<1>; render_forward = that one up to the last
+# render_forward_kernel (the second depth slab's listing runs between the two phases);
+# render_backward = the kernels after l1_loss_grad_kernel up to preprocess_backward_kernel.
+CALLS = ("bin_and_sort", "render_forward", "render_backward")
+
+
+def short_kernel_name(name):
+    return name.replace("clsp::(anonymous namespace)::", "").split("(")[0].replace("void ", "").strip()
+
+
+def split_steps(seq, k):
+    """``seq``: dispatches in order, each a tuple whose first item is the short kernel name.
+    Returns the last ``k`` complete steps, each as (all dispatches, {call: dispatches})."""
+    seq = [x for x in seq if not (x[0].startswith("at::") or "rocclr" in x[0])]
+    starts = [i for i, x in enumerate(seq) if x[0] == "preprocess_kernel"]
+    out = []
+    for j, s0 in enumerate(starts):
+        s1 = starts[j + 1] if j + 1 < len(starts) else len(seq)
+        st = seq[s0:s1]
+        names = [x[0] for x in st]
+        if "adam_kernel" not in names:
+            continue
+        st = st[:names.index("adam_kernel") + 1]
+        names = names[:len(st)]
+        try:
+            i_f1 = names.index("render_forward_kernel<1>")
+            i_f2 = max(i for i, nm in enumerate(names) if nm.startswith("render_forward_kernel"))
+            i_l1 = names.index("l1_loss_grad_kernel")
+            i_pb = names.index("preprocess_backward_kernel")
+        except ValueError:
+            continue
+        out.append((st, {"bin_and_sort": st[1:i_f1], "render_forward": st[i_f1:i_f2 + 1],
+                         "render_backward": st[i_l1 + 1:i_pb + 1]}))
+    return out[-k:]
+
+
+def summarize_trace(db, k, notes=()):
+    """Per-step kernel averages of a kernel trace (rocprofv3 results database)."""
+    import collections
+    import sqlite3
+
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, start, end, duration from kernels order by start").fetchall()
+    con.close()
+    steps = split_steps([(short_kernel_name(n), s, e, d) for n, s, e, d in rows], k)
+    if not steps:
+        raise SystemExit(f"{db}: no complete step found")
+    k = len(steps)
+    st = collections.defaultdict(lambda: [0, 0, float("inf"), 0])
+    for disp, _ in steps:
+        for n, _, _, d in disp:
+            x = st[n]
+            x[0] += 1; x[1] += d; x[2] = min(x[2], d); x[3] = max(x[3], d)
+    tot = sum(v[1] for v in st.values())
+    span = sum(disp[-1][2] - disp[0][1] for disp, _ in steps)
+    lines = [f"# {n}" for n in notes]
+    lines.append(f"# rocprofv3 kernel trace; averages over the last {k} steps "
+                 f"({sum(len(d) for d, _ in steps)} dispatches)")
+    lines.append(f"# GPU time per step (sum of kernel durations): {tot / k / 1e3:.1f} us; "
+                 f"span per step (first start -> last end): {span / k / 1e3:.1f} us")
+    lines.append(f"{'kernel':34s} {'calls/step':>10s} {'us/step':>9s} {'avg_us':>8s} {'min_us':>8s} "
+                 f"{'max_us':>8s} {'share':>6s}")
+    for n, (c, d, mn, mx) in sorted(st.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"{n:34s} {c / k:10.1f} {d / k / 1e3:9.1f} {d / c / 1e3:8.1f} {mn / 1e3:8.1f} "
+                     f"{mx / 1e3:8.1f} {100 * d / tot:5.1f}%")
+    lines.append("# per call (average over steps): kernels, sum of kernel durations, span first start -> last end")
+    for call in CALLS:
+        segs = [c[call] for _, c in steps]
+        lines.append(f"#   {call:16s} {sum(len(s) for s in segs) / k:5.1f} kernels  "
+                     f"sum {sum(sum(x[3] for x in s) for s in segs) / k / 1e3:8.1f} us  "
+                     f"span {sum(s[-1][2] - s[0][1] for s in segs) / k / 1e3:8.1f} us")
+    return "\n".join(lines)
+
+
+def read_counter_csv(folder, counter):
+    """Dispatches in order as (short kernel name, counter value) from the
+    counter_collection.csv that rocprofv3 --pmc --output-format csv wrote under ``folder``."""
+    import csv
+
+    files = sorted(Path(folder).rglob("*counter_collection.csv"))
+    if not files:
+        raise SystemExit(f"{folder}: no counter_collection.csv")
+    rows = {}
+    with open(files[0]) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] == counter:
+                rows[int(r["Dispatch_Id"])] = (short_kernel_name(r["Kernel_Name"]), float(r["Counter_Value"]))
+    return [rows[i] for i in sorted(rows)]
+
+
+COPY_KIB = 262144.0  # the 256 MiB calibration copy, in KiB
+
+
+def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, k=10, notes=()):
+    """HBM bytes per C-ABI call of the step: FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
+    summed over each call's kernels, averaged over the last ``k`` steps, and scaled by the
+    factor that makes the counter read 256 MiB for a plain 256 MiB device copy."""
+    def per_call(folder, counter):
+        steps = split_steps(read_counter_csv(folder, counter), k)
+        if not steps:
+            raise SystemExit(f"{folder}: no complete step found")
+        avg = {c: sum(sum(v for _, v in cs[c]) for _, cs in steps) / len(steps) for c in CALLS}
+        avg["step"] = sum(sum(v for _, v in d) for d, _ in steps) / len(steps)
+        return avg, len(steps)
+
+    def factor(folder, counter):
+        v = [x for n, x in read_counter_csv(folder, counter) if "copyBuffer" in n]
+        if not v:
+            raise SystemExit(f"{folder}: no copy dispatch")
+        m = sum(v) / len(v)
+        return COPY_KIB / m, m
+
+    ff, fm = factor(copy_fetch_dir, "FETCH_SIZE")
+    wf, wm = factor(copy_write_dir, "WRITE_SIZE")
+    fetch, kf = per_call(fetch_dir, "FETCH_SIZE")
+    write, kw = per_call(write_dir, "WRITE_SIZE")
+    lines = [f"# {n}" for n in notes]
+    lines.append(f"# copy calibration: 256 MiB device copy reads FETCH_SIZE {fm:.0f} KiB (factor {ff:.3f}), "
+                 f"WRITE_SIZE {wm:.0f} KiB (factor {wf:.3f})")
+    lines.append(f"# averages over {min(kf, kw)} steps; bytes = KiB x 1024 x factor")
+    for call in CALLS + ("step",):
+        f = fetch[call] * 1024 * ff
+        w = write[call] * 1024 * wf
+        lines.append(f"{call:16s} fetch {f / 1e6:9.3f} MB  write {w / 1e6:9.3f} MB  total {(f + w) / 1e6:9.3f} MB")
+    return "\n".join(lines)
 
 
 if __name__ == "__main__":
