@@ -15,6 +15,7 @@ namespace {
 
 constexpr int NT = TILE_PIX;
 constexpr int C_OVERFLOW = 1, C_TILES = 2, C_ALIVE = 8;
+constexpr int FW_UNROLL = 4;  // records whose weights the forward computes together
 
 // Opacity of a record at a pixel centre, evaluated with explicitly rounded operations
 // so the forward and the backward take the same decisions bit for bit.
@@ -150,10 +151,10 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
     for (int j = 0; j < cnt;) {
       const int next_b = ((kb + j) / CH + 1) * CH;
       const int jhi = min(cnt, next_b - kb);
-      // Branch-free blending, two records per iteration: both weights are computed
-      // first, then applied in order with selects; a lane that has stopped keeps its
-      // state (the same values as stopping with a branch).  The wave leaves the
-      // segment once all its lanes have stopped.
+      // Branch-free blending, FW_UNROLL records per iteration: their weights are
+      // computed first, then applied in order with selects; a lane that has stopped
+      // keeps its state (the same values as stopping with a branch).  The wave leaves
+      // the segment once all its lanes have stopped.
       auto blend = [&](bool ok, float alpha, float4 b, float c, uint32_t k1) {
         const float Tn = Tr * (1.0f - alpha);
         const bool stop = ok && Tn < T_STOP;
@@ -166,17 +167,23 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
         last = use ? k1 : last;
         done = done || stop;
       };
-      for (int jj = j; jj < jhi; jj += 2) {
+      for (int jj = j; jj < jhi; jj += FW_UNROLL) {
         if (__ballot(!done) == 0ull) break;
-        const int j1 = min(jj + 1, jhi - 1);
-        const float4 a0 = s_a[jj], b0 = s_b[jj], a1 = s_a[j1], b1 = s_b[j1];
-        const float c0 = s_c[jj], c1 = s_c[j1];
-        float dx0, dy0, G0, al0, dx1, dy1, G1, al1;
-        bool cl0, cl1;
-        const bool ok0 = splat_alpha(a0, b0, fx, fy, dx0, dy0, G0, al0, cl0);
-        const bool ok1 = splat_alpha(a1, b1, fx, fy, dx1, dy1, G1, al1, cl1) && jj + 1 < jhi;
-        blend(ok0 && !done, al0, b0, c0, (uint32_t)(kb + jj + 1));
-        blend(ok1 && !done, al1, b1, c1, (uint32_t)(kb + jj + 2));
+        float al[FW_UNROLL], cq[FW_UNROLL];
+        float4 bq[FW_UNROLL];
+        bool okq[FW_UNROLL];
+#pragma unroll
+        for (int u = 0; u < FW_UNROLL; ++u) {
+          const int ju = min(jj + u, jhi - 1);  // past the segment end: a masked-out copy of its last record
+          const float4 aq = s_a[ju];
+          bq[u] = s_b[ju];
+          cq[u] = s_c[ju];
+          float dx, dy, G;
+          bool cl;
+          okq[u] = splat_alpha(aq, bq[u], fx, fy, dx, dy, G, al[u], cl) && jj + u < jhi;
+        }
+#pragma unroll
+        for (int u = 0; u < FW_UNROLL; ++u) blend(okq[u] && !done, al[u], bq[u], cq[u], (uint32_t)(kb + jj + u + 1));
       }
       // a chunk boundary of the tile's list: record this pixel's state
       if (kb + jhi == next_b && chunk < CHUNKS - 1) {
