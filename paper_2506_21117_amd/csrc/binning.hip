@@ -175,26 +175,36 @@ __device__ __forceinline__ uint32_t tab_rank(const uint32_t* tab, uint32_t vrow,
 
 // ------------------------------------------------------------------ 2. counts
 // Pairs of each entry: the rectangle's area, or its set tiles in the mask (corner table).
+// Block b takes the span block_span(E, G, b, NT) of entries e = v*n + i, and also
+// writes how many of them have pairs to blk[b]: the first step of the compaction's
+// exclusive scan (scan_compact_kernel uses the same spans).
 __global__ void __launch_bounds__(NT) count_kernel(const uint2* __restrict__ rect, const uint32_t* __restrict__ flags,
-                                                   const uint32_t* __restrict__ tab, int64_t n, int TX, int TY,
-                                                   int use_mask, uint32_t* __restrict__ cnt) {
-  const int v = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (i >= n) return;
-  const int64_t e = (int64_t)v * n + i;
-  uint32_t c = 0;
-  if (flags[e] & CLSP_FLAG_VISIBLE) {
-    const uint2 r = rect[e];
-    const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
-    if (x1 > x0 && y1 > y0) {
-      if (!use_mask) {
-        c = (x1 - x0) * (y1 - y0);
-      } else {
-        c = tab_rect(tab, (uint32_t)v * (uint32_t)(TY + 1), (uint32_t)(TX + 1), x0, x1, y0, y1);
+                                                   const uint32_t* __restrict__ tab, uint32_t n, uint32_t E, int G,
+                                                   int TX, int TY, int use_mask, uint32_t* __restrict__ cnt,
+                                                   uint32_t* __restrict__ blk) {
+  __shared__ uint32_t s4[4];
+  uint32_t beg, end;
+  block_span(E, G, blockIdx.x, NT, beg, end);
+  uint32_t has = 0;
+  for (uint32_t e = beg + threadIdx.x; e < end; e += NT) {
+    uint32_t c = 0;
+    if (flags[e] & CLSP_FLAG_VISIBLE) {
+      const uint2 r = rect[e];
+      const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
+      if (x1 > x0 && y1 > y0) {
+        if (!use_mask) {
+          c = (x1 - x0) * (y1 - y0);
+        } else {
+          c = tab_rect(tab, (e / n) * (uint32_t)(TY + 1), (uint32_t)(TX + 1), x0, x1, y0, y1);
+        }
       }
     }
+    cnt[e] = c;
+    has += c != 0u ? 1u : 0u;
   }
-  cnt[e] = c;
+  uint32_t tot;
+  block_excl_scan(has, s4, tot);
+  if (threadIdx.x == 0) blk[blockIdx.x] = tot;
 }
 
 // Capacity check after a slab's pair count: P = first-slab pairs + this slab's pairs.
@@ -214,73 +224,41 @@ __device__ void capacity_check(uint32_t* counters, uint64_t capacity, int which)
   }
 }
 
-// ------------------------------------------------------------------ generic exclusive scan
-// FLAGS: sum (in[e] != 0) instead of in[e].
-template <bool FLAGS = false>
-__global__ void __launch_bounds__(NT) scan_reduce_kernel(const uint32_t* __restrict__ in, const uint32_t* n_ptr,
-                                                         uint32_t n_host, uint32_t* __restrict__ blk, int G) {
-  __shared__ uint32_t s4[4];
-  const uint32_t n = load_count(n_ptr, n_host);
-  uint32_t beg, end;
-  block_span(n, G, blockIdx.x, SCAN_CHUNK, beg, end);
-  uint32_t acc = 0;
-  for (uint32_t e = beg + threadIdx.x; e < end; e += NT) acc += FLAGS ? (in[e] != 0u ? 1u : 0u) : in[e];
-  uint32_t tot;
-  block_excl_scan(acc, s4, tot);
-  if (threadIdx.x == 0) blk[blockIdx.x] = tot;
-}
+// ------------------------------------------------------------------ exclusive scan of partial sums
+// One block: exclusive scan in place of the G partial sums blk[0, G), G = ceil(*n_ptr /
+// per) when n_ptr is given (per items per partial sum); the total goes to *total_out.
+// With check_which (1 or 2) the total is a slab's pair count and the capacity check
+// follows.
+constexpr int PSCAN_ITEMS = 16;
 
-// One block: exclusive scan of the G block sums in place; total -> *total_out.  With
-// check_which (1 or 2) the total is a slab's pair count and the capacity check follows.
-__global__ void __launch_bounds__(NT) scan_blocks_kernel(uint32_t* __restrict__ blk, int G, uint32_t* total_out,
-                                                         uint32_t* counters, uint64_t capacity, int check_which) {
+__global__ void __launch_bounds__(NT) scan_partials_kernel(uint32_t* __restrict__ blk, int G, const uint32_t* n_ptr,
+                                                           uint32_t per, uint32_t* total_out, uint32_t* counters,
+                                                           uint64_t capacity, int check_which) {
   __shared__ uint32_t s4[4];
-  constexpr int PER = MAX_SCAN_BLOCKS / NT;
-  uint32_t v[PER];
-  uint32_t sum = 0;
-  for (int k = 0; k < PER; ++k) {
-    const int idx = threadIdx.x * PER + k;
-    v[k] = idx < G ? blk[idx] : 0u;
-    sum += v[k];
-  }
-  uint32_t tot;
-  uint32_t off = block_excl_scan(sum, s4, tot);
-  for (int k = 0; k < PER; ++k) {
-    const int idx = threadIdx.x * PER + k;
-    if (idx < G) blk[idx] = off;
-    off += v[k];
-  }
-  if (threadIdx.x == 0) {
-    if (total_out) *total_out = tot;
-    if (check_which) capacity_check(counters, capacity, check_which);
-  }
-}
-
-__global__ void __launch_bounds__(NT) scan_apply_kernel(const uint32_t* __restrict__ in, const uint32_t* n_ptr,
-                                                        uint32_t n_host, const uint32_t* __restrict__ blk, int G,
-                                                        uint32_t* __restrict__ out) {
-  __shared__ uint32_t s4[4];
-  const uint32_t n = load_count(n_ptr, n_host);
-  uint32_t beg, end;
-  block_span(n, G, blockIdx.x, SCAN_CHUNK, beg, end);
-  uint32_t base = blk[blockIdx.x];
-  for (uint32_t c = beg; c < end; c += SCAN_CHUNK) {
-    uint32_t v[SCAN_ITEMS];
+  const uint32_t g = n_ptr ? (*n_ptr + per - 1) / per : (uint32_t)G;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < g; base += NT * PSCAN_ITEMS) {
+    uint32_t v[PSCAN_ITEMS];
     uint32_t sum = 0;
-    const uint32_t t0 = c + threadIdx.x * SCAN_ITEMS;
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-      v[k] = (t0 + k < end) ? in[t0 + k] : 0u;
+    for (int k = 0; k < PSCAN_ITEMS; ++k) {
+      const uint32_t idx = base + threadIdx.x * PSCAN_ITEMS + k;
+      v[k] = idx < g ? blk[idx] : 0u;
       sum += v[k];
     }
     uint32_t tot;
-    uint32_t off = base + block_excl_scan(sum, s4, tot);
+    uint32_t off = carry + block_excl_scan(sum, s4, tot);
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-      if (t0 + k < end) out[t0 + k] = off;
+    for (int k = 0; k < PSCAN_ITEMS; ++k) {
+      const uint32_t idx = base + threadIdx.x * PSCAN_ITEMS + k;
+      if (idx < g) blk[idx] = off;
       off += v[k];
     }
-    base += tot;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    if (total_out) *total_out = carry;
+    if (check_which) capacity_check(counters, capacity, check_which);
   }
 }
 
@@ -293,7 +271,7 @@ __global__ void __launch_bounds__(NT) scan_compact_kernel(const uint32_t* __rest
                                                           uint32_t* __restrict__ vals) {
   __shared__ uint32_t s4[4];
   uint32_t beg, end;
-  block_span(n, G, blockIdx.x, SCAN_CHUNK, beg, end);
+  block_span(n, G, blockIdx.x, NT, beg, end);
   uint32_t base = blk[blockIdx.x];
   for (uint32_t c = beg; c < end; c += SCAN_CHUNK) {
     uint32_t v[SCAN_ITEMS];
@@ -501,36 +479,71 @@ __device__ __forceinline__ void slab_params(uint32_t* counters, int which, int s
   }
 }
 
+// Sum of x over groups of `group` consecutive threads (64 or NT), valid in every thread
+// of the group; every thread of the block calls it.
+__device__ __forceinline__ uint32_t group_sum(uint32_t x, int group, uint32_t* s4) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  if (group == 64) return x;
+  if (lane_id() == 0) s4[threadIdx.x >> 6] = x;
+  __syncthreads();
+  x = s4[0] + s4[1] + s4[2] + s4[3];
+  __syncthreads();
+  return x;
+}
+
+// The slab's entries are taken in chunks of `epb` (the emission's entries per block):
+// chunk q = slab entries [q*epb, (q+1)*epb), its pair count -> blk[q] (the first step of
+// the exclusive scan that gives the emission offsets; scan_partials_kernel follows).
 // Pairs each slab entry emits: its count from the count pass (first slab) ...
 // Both also copy the slab entries' rectangles into depth order (rsort) for the emission.
 __global__ void __launch_bounds__(NT) gather_counts_kernel(const uint32_t* __restrict__ order,
                                                            const uint32_t* __restrict__ cnt,
                                                            const uint2* __restrict__ rect, uint32_t* counters,
-                                                           int sliced, uint32_t* __restrict__ out,
-                                                           uint2* __restrict__ rsort) {
+                                                           int sliced, int epb, uint32_t* __restrict__ out,
+                                                           uint2* __restrict__ rsort, uint32_t* __restrict__ blk) {
+  __shared__ uint32_t s4[4];
   uint32_t lo, m;
   slab_params(counters, 1, sliced, lo, m);
-  for (uint32_t j = blockIdx.x * NT + threadIdx.x; j < m; j += gridDim.x * NT) {
-    const uint32_t e = order[lo + j];
-    out[j] = cnt[e];
-    rsort[j] = rect[e];
+  const uint32_t nq = (m + epb - 1) / epb, per_iter = NT / epb;
+  const uint32_t g = threadIdx.x / epb, t = threadIdx.x % epb;
+  for (uint32_t q0 = blockIdx.x * per_iter; q0 < nq; q0 += gridDim.x * per_iter) {
+    const uint32_t q = q0 + g, j = q * epb + t;
+    uint32_t c = 0;
+    if (q < nq && j < m) {
+      const uint32_t e = order[lo + j];
+      c = cnt[e];
+      out[j] = c;
+      rsort[j] = rect[e];
+    }
+    c = group_sum(c, epb, s4);
+    if (t == 0 && q < nq) blk[q] = c;
   }
 }
 
 // ... or recounted against the tiles still alive (second slab).
 __global__ void __launch_bounds__(NT) recount_kernel(const uint32_t* __restrict__ order, const uint2* __restrict__ rect,
-                                                     const uint32_t* __restrict__ tab, uint32_t* counters, int64_t n,
-                                                     int TX, int TY, uint32_t* __restrict__ out,
-                                                     uint2* __restrict__ rsort) {
+                                                     const uint32_t* __restrict__ tab, uint32_t* counters, uint32_t n,
+                                                     int TX, int TY, int epb, uint32_t* __restrict__ out,
+                                                     uint2* __restrict__ rsort, uint32_t* __restrict__ blk) {
+  __shared__ uint32_t s4[4];
   uint32_t lo, m;
   slab_params(counters, 2, 1, lo, m);
-  for (uint32_t j = blockIdx.x * NT + threadIdx.x; j < m; j += gridDim.x * NT) {
-    const uint32_t e = order[lo + j];
-    const uint32_t v = (uint32_t)(e / n);
-    const uint2 r = rect[e];
-    rsort[j] = r;
-    const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
-    out[j] = tab_rect(tab, v * (uint32_t)(TY + 1), (uint32_t)(TX + 1), x0, x1, y0, y1);
+  const uint32_t nq = (m + epb - 1) / epb, per_iter = NT / epb;
+  const uint32_t g = threadIdx.x / epb, t = threadIdx.x % epb;
+  for (uint32_t q0 = blockIdx.x * per_iter; q0 < nq; q0 += gridDim.x * per_iter) {
+    const uint32_t q = q0 + g, j = q * epb + t;
+    uint32_t c = 0;
+    if (q < nq && j < m) {
+      const uint32_t e = order[lo + j];
+      const uint2 r = rect[e];
+      rsort[j] = r;
+      const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
+      c = tab_rect(tab, (e / n) * (uint32_t)(TY + 1), (uint32_t)(TX + 1), x0, x1, y0, y1);
+      out[j] = c;
+    }
+    c = group_sum(c, epb, s4);
+    if (t == 0 && q < nq) blk[q] = c;
   }
 }
 
@@ -564,8 +577,9 @@ __device__ __forceinline__ uint32_t run_slot(uint32_t p) { return (p / EMIT_RUN)
 // LDS_TAB: the corner table and the first V*T words of the list are copied into
 // dynamic LDS.
 template <bool MASKED, bool LDS_TAB>
-__global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ order, const uint32_t* __restrict__ offs,
-                                                  const uint2* __restrict__ rsort, const uint32_t* __restrict__ tab,
+__global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ order, const uint32_t* __restrict__ counts,
+                                                  const uint32_t* __restrict__ qoff, const uint2* __restrict__ rsort,
+                                                  const uint32_t* __restrict__ tab,
                                                   const uint32_t* __restrict__ vfirst, const uint32_t* __restrict__ list,
                                                   const uint32_t* __restrict__ counters, int64_t n, int TX, int TY,
                                                   int views, int epb, uint32_t* __restrict__ pk,
@@ -578,6 +592,7 @@ __global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ o
   __shared__ uint32_t s_vf[NT];  // MASKED: the view's first list position
   __shared__ uint32_t s_k[NT * (EMIT_RUN + 1)];
   __shared__ uint32_t s_v[NT * (EMIT_RUN + 1)];
+  __shared__ uint32_t s4[4];
   if (counters[C_OVERFLOW]) return;
   const uint32_t m = counters[C_SLAB_N];
   if ((uint64_t)blockIdx.x * epb >= m) return;
@@ -600,7 +615,6 @@ __global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ o
   }
   const uint32_t* tb = LDS_TAB ? s_tab : tab;
   const uint32_t* tl = LDS_TAB ? s_tab + tab_words : list;
-  const uint32_t P = counters[C_SLAB_PAIRS];
   order += counters[C_SLAB_LO];
   const uint32_t pbase = counters[C_SLAB_BASE];
   pk += pbase;
@@ -619,16 +633,21 @@ __global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ o
   for (uint32_t j0 = blockIdx.x * epb; j0 < m; j0 += gridDim.x * epb) {
     const uint32_t cnt = min((uint32_t)epb, m - j0);
     __syncthreads();
+    // the entries' pair offsets: the chunk's offset plus an exclusive scan of its counts
+    const uint32_t ce = threadIdx.x < cnt ? counts[j0 + threadIdx.x] : 0u;
+    uint32_t ctot;
+    const uint32_t ex = block_excl_scan(ce, s4, ctot);
+    const uint32_t qb = qoff[j0 / epb];
     if (threadIdx.x < cnt) {
       const uint32_t e = order[j0 + threadIdx.x];
       const uint32_t v = (uint32_t)(e / n);
-      s_off[threadIdx.x] = offs[j0 + threadIdx.x];
+      s_off[threadIdx.x] = qb + ex;
       s_e[threadIdx.x] = e;
       s_r[threadIdx.x] = rsort[j0 + threadIdx.x];
       s_vb[threadIdx.x] = MASKED ? v * TYp : v * (uint32_t)(TX * TY);
       s_vf[threadIdx.x] = MASKED ? vfirst[v] : 0u;
     }
-    if (threadIdx.x == 0) s_off[cnt] = j0 + cnt < m ? offs[j0 + cnt] : P;
+    if (threadIdx.x == 0) s_off[cnt] = qb + ctot;
     __syncthreads();
     const uint32_t base = s_off[0], end = s_off[cnt];
     for (uint32_t rb = base; rb < end; rb += EMIT_ROUND) {
@@ -812,8 +831,9 @@ int sort_blocks(int64_t nmax) {
   return (int)g;
 }
 
-int scan_blocks(int64_t nmax) {
-  int64_t g = (nmax + SCAN_CHUNK - 1) / SCAN_CHUNK;
+// Blocks of the count pass and of the compaction (spans of whole NT groups).
+int count_blocks(int64_t nmax) {
+  int64_t g = (nmax + NT - 1) / NT;
   if (g < 1) g = 1;
   if (g > MAX_SCAN_BLOCKS) g = MAX_SCAN_BLOCKS;
   return (int)g;
@@ -824,17 +844,6 @@ int grid_for(int64_t count, int cap = 8192) {
   if (g < 1) g = 1;
   if (g > cap) g = cap;
   return (int)g;
-}
-
-// Exclusive scan of in[0, n) (n from n_ptr if given) into out; total -> *total_out.
-hipError_t scan(const uint32_t* in, uint32_t* out, const uint32_t* n_ptr, uint32_t n_host, int64_t nmax,
-                uint32_t* blk, uint32_t* total_out, hipStream_t s, uint32_t* counters = nullptr,
-                uint64_t capacity = 0, int check_which = 0) {
-  const int G = scan_blocks(nmax);
-  hipLaunchKernelGGL(scan_reduce_kernel<false>, dim3(G), dim3(NT), 0, s, in, n_ptr, n_host, blk, G);
-  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(NT), 0, s, blk, G, total_out, counters, capacity, check_which);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3(G), dim3(NT), 0, s, in, n_ptr, n_host, blk, G, out);
-  return hipGetLastError();
 }
 
 // Stable LSD radix sort of (keys, vals)[off + e], e < n, on bits [0, total_bits); n and
@@ -914,36 +923,36 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
   uint32_t* counters = bins.counters;
   uint32_t* order = w.valA;
   hipError_t err;
-  if (which == 1)
-    hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(E)), dim3(NT), 0, s, order, w.cnt, rect, counters,
-                       bins.mode == CLSP_BINS_DEPTH_SLICED ? 1 : 0, w.tmp, w.rsort);
-  else
-    hipLaunchKernelGGL(recount_kernel, dim3(grid_for(E)), dim3(NT), 0, s, order, rect, w.tab, counters, n, p.TX, p.TY,
-                       w.tmp, w.rsort);
-  // offsets (relative to the slab's first pair) into valB; the capacity check
-  if ((err = scan(w.tmp, w.valB, counters + C_SLAB_N, 0u, E, w.blk, counters + C_SLAB_PAIRS, s, counters,
-                  (uint64_t)p.capacity, which)) != hipSuccess)
-    return err;
-  const int tpasses = passes_for(p.tile_bits);
-  uint32_t* ek = (tpasses % 2 == 0) ? bins.keys : w.pairK;
-  uint32_t* ev = (tpasses % 2 == 0) ? bins.values : w.pairV;
   const int epb = which == 1 ? EMIT_EPB_NEAR : EMIT_EPB;
-  // blocks for the most entries the slab can hold (the first slab of depth-sliced
-  // lists holds at most max(E/16, 16384)); blocks loop beyond the grid
+  // the most entries the slab can hold (the first slab of depth-sliced lists holds at
+  // most max(E/16, 16384)); blocks loop beyond their grids
   const int64_t slab_max = (which == 1 && bins.mode == CLSP_BINS_DEPTH_SLICED)
                                ? std::min<int64_t>(E, std::max<int64_t>(E >> 4, 16384))
                                : E;
+  // counts and per-chunk pair counts, then the chunks' offsets (relative to the slab's
+  // first pair) and the capacity check
+  if (which == 1)
+    hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(slab_max)), dim3(NT), 0, s, order, w.cnt, rect, counters,
+                       bins.mode == CLSP_BINS_DEPTH_SLICED ? 1 : 0, epb, w.tmp, w.rsort, w.blk);
+  else
+    hipLaunchKernelGGL(recount_kernel, dim3(grid_for(slab_max)), dim3(NT), 0, s, order, rect, w.tab, counters,
+                       (uint32_t)n, p.TX, p.TY, epb, w.tmp, w.rsort, w.blk);
+  hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(NT), 0, s, w.blk, 0, counters + C_SLAB_N, (uint32_t)epb,
+                     counters + C_SLAB_PAIRS, counters, (uint64_t)p.capacity, which);
+  const int tpasses = passes_for(p.tile_bits);
+  uint32_t* ek = (tpasses % 2 == 0) ? bins.keys : w.pairK;
+  uint32_t* ev = (tpasses % 2 == 0) ? bins.values : w.pairV;
   // at most four blocks per CU: each block's copy of the mask index serves many groups
   const int eg = (int)std::min<int64_t>(std::max<int64_t>((slab_max + epb - 1) / epb, 1), 1024);
   const int64_t tab_words = (int64_t)V * (p.TY + 1) * (p.TX + 1) + (int64_t)V * p.T;
   if (which == 1 && !use_mask) {
-    hipLaunchKernelGGL((emit_kernel<false, false>), dim3(eg), dim3(NT), 0, s, order, w.valB, w.rsort, w.tab, w.vfirst,
+    hipLaunchKernelGGL((emit_kernel<false, false>), dim3(eg), dim3(NT), 0, s, order, w.tmp, w.blk, w.rsort, w.tab, w.vfirst,
                        mlist, counters, n, p.TX, p.TY, V, epb, ek, ev);
   } else if (tab_words <= EMIT_TAB_WORDS) {
-    hipLaunchKernelGGL((emit_kernel<true, true>), dim3(eg), dim3(NT), (size_t)tab_words * 4, s, order, w.valB, w.rsort,
+    hipLaunchKernelGGL((emit_kernel<true, true>), dim3(eg), dim3(NT), (size_t)tab_words * 4, s, order, w.tmp, w.blk, w.rsort,
                        w.tab, w.vfirst, mlist, counters, n, p.TX, p.TY, V, epb, ek, ev);
   } else {
-    hipLaunchKernelGGL((emit_kernel<true, false>), dim3(eg), dim3(NT), 0, s, order, w.valB, w.rsort, w.tab, w.vfirst,
+    hipLaunchKernelGGL((emit_kernel<true, false>), dim3(eg), dim3(NT), 0, s, order, w.tmp, w.blk, w.rsort, w.tab, w.vfirst,
                        mlist, counters, n, p.TX, p.TY, V, epb, ek, ev);
   }
   if (tpasses > 0) {
@@ -993,7 +1002,9 @@ BinPlan make_bin_plan(int64_t n, int views, int W, int H, int64_t capacity) {
   p.off_valA = take(E * 4);
   p.off_keyB = take(E * 4);
   p.off_valB = take(E * 4);
-  p.off_scanBlk = take((MAX_SCAN_BLOCKS + 1) * 4);
+  // partial sums: the count pass's blocks, or a slab's emission chunks (EMIT_EPB_NEAR
+  // entries or more each)
+  p.off_scanBlk = take((size_t)std::max<int64_t>(MAX_SCAN_BLOCKS, E / EMIT_EPB_NEAR + 1) * 4);
   p.off_hist = take((size_t)256 * MAX_SORT_BLOCKS * 4);
   p.off_digit = take(256 * 4);
   const bool need_pair_buf = passes_for(bits) > 0;
@@ -1055,15 +1066,14 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
   }
   index_mask(p, bins.tile_mask, w, bins.tile_list, counters + C_TILES, s);
   if (E > 0) {
-    // 2. counts
-    hipLaunchKernelGGL(count_kernel, dim3(ceil_div(n, NT), V), dim3(NT), 0, s, rect, proj.flags, w.tab, n, p.TX, p.TY,
-                       use_mask, w.cnt);
-    // 3. compaction of entries with pairs, keyed by depth
+    // 2-3. counts (with the block sums of the has-pairs flags), then the compaction of
+    // entries with pairs, keyed by depth
     {
-      const int G = scan_blocks(E);
-      hipLaunchKernelGGL(scan_reduce_kernel<true>, dim3(G), dim3(NT), 0, s, w.cnt, nullptr, (uint32_t)E, w.blk, G);
-      hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(NT), 0, s, w.blk, G, counters + C_ENTRIES, nullptr,
-                         (uint64_t)0, 0);
+      const int G = count_blocks(E);
+      hipLaunchKernelGGL(count_kernel, dim3(G), dim3(NT), 0, s, rect, proj.flags, w.tab, (uint32_t)n, (uint32_t)E, G,
+                         p.TX, p.TY, use_mask, w.cnt, w.blk);
+      hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(NT), 0, s, w.blk, G, nullptr, 1u, counters + C_ENTRIES,
+                         nullptr, (uint64_t)0, 0);
       hipLaunchKernelGGL(scan_compact_kernel, dim3(G), dim3(NT), 0, s, w.cnt, (uint32_t)E, w.blk, G, proj.depth,
                          w.keyA, w.valA);
     }
