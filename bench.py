@@ -280,12 +280,14 @@ def roofline_of(ms, st, n):
                 "traffic": measured_traffic(dom),
                 "units": {"pixel_records": st["pixel_records"], "flop_per_eval": FLOP_EVAL}}
     # binning: read the projected rectangles, flags and depths of all N entries
-    # (16 B), then per pair 44 B (emit 12 B, one sort read + write 24 B, range scan 8 B)
-    byts = 16 * n + 44 * st["pairs"]
+    # (16 B), then per pair it lists (the first slab's) 44 B (emit 12 B, one sort read +
+    # write 24 B, range scan 8 B)
+    pairs = st["pairs_first_slab"]
+    byts = 16 * n + 44 * pairs
     ach = byts / t / 1e9
     return {"bound": "hbm", "kernel": "bin_and_sort", "achieved": round(ach, 2), "peak": 8000.0, "unit": "GB/s",
             "frac": round(ach / 8000.0, 5), "traffic": measured_traffic(dom),
-            "units": {"entries": n, "pairs": st["pairs"], "algorithmic_bytes": byts}}
+            "units": {"entries": n, "pairs": pairs, "algorithmic_bytes": byts}}
 
 
 def serving_leg(dev, qps, n_requests, log):
