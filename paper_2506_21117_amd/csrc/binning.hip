@@ -82,6 +82,20 @@ __device__ __forceinline__ void block_span(uint32_t n, int G, int b, uint32_t qu
   end = (uint32_t)en;
 }
 
+// Sum of a[lo, hi) across the block (every thread calls it; s4 is 4 words of LDS).
+__device__ __forceinline__ uint32_t block_sum_range(const uint32_t* __restrict__ a, uint32_t lo, uint32_t hi,
+                                                    uint32_t* s4) {
+  uint32_t x = 0;
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += NT) x += a[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  if ((threadIdx.x & 63u) == 0) s4[threadIdx.x >> 6] = x;
+  __syncthreads();
+  x = s4[0] + s4[1] + s4[2] + s4[3];
+  __syncthreads();
+  return x;
+}
+
 // ------------------------------------------------------------------ fills
 // Zero up to CLEAR_SEGS buffers in one launch.
 constexpr int CLEAR_SEGS = 6;
@@ -224,55 +238,22 @@ __device__ void capacity_check(uint32_t* counters, uint64_t capacity, int which)
   }
 }
 
-// ------------------------------------------------------------------ exclusive scan of partial sums
-// One block: exclusive scan in place of the G partial sums blk[0, G), G = ceil(*n_ptr /
-// per) when n_ptr is given (per items per partial sum); the total goes to *total_out.
-// With check_which (1 or 2) the total is a slab's pair count and the capacity check
-// follows.
-constexpr int PSCAN_ITEMS = 16;
-
-__global__ void __launch_bounds__(NT) scan_partials_kernel(uint32_t* __restrict__ blk, int G, const uint32_t* n_ptr,
-                                                           uint32_t per, uint32_t* total_out, uint32_t* counters,
-                                                           uint64_t capacity, int check_which) {
-  __shared__ uint32_t s4[4];
-  const uint32_t g = n_ptr ? (*n_ptr + per - 1) / per : (uint32_t)G;
-  uint32_t carry = 0;
-  for (uint32_t base = 0; base < g; base += NT * PSCAN_ITEMS) {
-    uint32_t v[PSCAN_ITEMS];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < PSCAN_ITEMS; ++k) {
-      const uint32_t idx = base + threadIdx.x * PSCAN_ITEMS + k;
-      v[k] = idx < g ? blk[idx] : 0u;
-      sum += v[k];
-    }
-    uint32_t tot;
-    uint32_t off = carry + block_excl_scan(sum, s4, tot);
-#pragma unroll
-    for (int k = 0; k < PSCAN_ITEMS; ++k) {
-      const uint32_t idx = base + threadIdx.x * PSCAN_ITEMS + k;
-      if (idx < g) blk[idx] = off;
-      off += v[k];
-    }
-    carry += tot;
-  }
-  if (threadIdx.x == 0) {
-    if (total_out) *total_out = carry;
-    if (check_which) capacity_check(counters, capacity, check_which);
-  }
-}
-
-// The final scan step over the entries' has-pairs flags (pair count > 0) as a
-// compaction: entry e with a pair goes to position p (its exclusive prefix) as
-// (depth key, e).
+// The rest of the exclusive scan over the entries' has-pairs flags (pair count > 0), as
+// a compaction: entry e with a pair goes to position p (its exclusive prefix) as
+// (depth key, e).  Block b's base is the sum of the count pass's block sums blk[0, b);
+// block 0 writes the total (the entries with pairs) to *total_out.
 __global__ void __launch_bounds__(NT) scan_compact_kernel(const uint32_t* __restrict__ cnt, uint32_t n,
                                                           const uint32_t* __restrict__ blk, int G,
                                                           const float* __restrict__ depth, uint32_t* __restrict__ keys,
-                                                          uint32_t* __restrict__ vals) {
+                                                          uint32_t* __restrict__ vals, uint32_t* __restrict__ total_out) {
   __shared__ uint32_t s4[4];
+  if (blockIdx.x == 0) {
+    const uint32_t all = block_sum_range(blk, 0, (uint32_t)G, s4);
+    if (threadIdx.x == 0) *total_out = all;
+  }
   uint32_t beg, end;
   block_span(n, G, blockIdx.x, NT, beg, end);
-  uint32_t base = blk[blockIdx.x];
+  uint32_t base = block_sum_range(blk, 0, blockIdx.x, s4);
   for (uint32_t c = beg; c < end; c += SCAN_CHUNK) {
     uint32_t v[SCAN_ITEMS];
     uint32_t sum = 0;
@@ -493,8 +474,8 @@ __device__ __forceinline__ uint32_t group_sum(uint32_t x, int group, uint32_t* s
 }
 
 // The slab's entries are taken in chunks of `epb` (the emission's entries per block):
-// chunk q = slab entries [q*epb, (q+1)*epb), its pair count -> blk[q] (the first step of
-// the exclusive scan that gives the emission offsets; scan_partials_kernel follows).
+// chunk q = slab entries [q*epb, (q+1)*epb), its pair count -> blk[q], from which the
+// emission takes each chunk's pair offset and the slab's pair count.
 // Pairs each slab entry emits: its count from the count pass (first slab) ...
 // Both also copy the slab entries' rectangles into depth order (rsort) for the emission.
 __global__ void __launch_bounds__(NT) gather_counts_kernel(const uint32_t* __restrict__ order,
@@ -564,7 +545,11 @@ constexpr int EMIT_EPB = NT;
 __device__ __forceinline__ uint32_t run_slot(uint32_t p) { return (p / EMIT_RUN) * (EMIT_RUN + 1) + p % EMIT_RUN; }
 
 // Emission of one slab: entry j of the slab (in depth order) writes (global tile,
-// entry) for its tiles at positions [offs[j], offs[j] + count).  Without MASKED every
+// entry) for its counts[j] tiles from position offs[j] on, offs being the exclusive
+// prefix sum of the counts: a chunk's offset is the sum of the earlier chunks' counts
+// qsum[], an entry's the chunk's plus a block scan of the chunk's counts.  The sum of
+// all of qsum is the slab's pair count; block 0 stores it and runs the capacity check,
+// and no block writes a pair of a slab that does not fit.  Without MASKED every
 // tile of the rectangle is a pair (row-major); with MASKED only the tiles set in the
 // mask: those of row ty are the run [rank(ty, x0), rank(ty, x1)) of the mask's sorted
 // tile list `list`, ranks taken from the corner table `tab` plus the view's first list
@@ -573,17 +558,18 @@ __device__ __forceinline__ uint32_t run_slot(uint32_t p) { return (p / EMIT_RUN)
 // owner entry (the last one whose offset is <= the position: an entry without pairs
 // shares its offset with the next one) and the pair's row (binary search over the
 // rectangle's rows on the table's prefix counts), and step through the row's tiles,
-// searching the row again whenever a row or an entry is exhausted.  Runs are staged in LDS and written out with coalesced stores.
+// searching the row again whenever a row or an entry is exhausted.  Runs are staged in
+// LDS and written out with coalesced stores.
 // LDS_TAB: the corner table and the first V*T words of the list are copied into
 // dynamic LDS.
 template <bool MASKED, bool LDS_TAB>
 __global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ order, const uint32_t* __restrict__ counts,
-                                                  const uint32_t* __restrict__ qoff, const uint2* __restrict__ rsort,
+                                                  const uint32_t* __restrict__ qsum, const uint2* __restrict__ rsort,
                                                   const uint32_t* __restrict__ tab,
                                                   const uint32_t* __restrict__ vfirst, const uint32_t* __restrict__ list,
-                                                  const uint32_t* __restrict__ counters, int64_t n, int TX, int TY,
-                                                  int views, int epb, uint32_t* __restrict__ pk,
-                                                  uint32_t* __restrict__ pv) {
+                                                  uint32_t* __restrict__ counters, int64_t n, int TX, int TY,
+                                                  int views, int epb, int which, uint64_t capacity,
+                                                  uint32_t* __restrict__ pk, uint32_t* __restrict__ pv) {
   extern __shared__ uint32_t s_tab[];  // LDS_TAB: the corner table, then the tile list
   __shared__ uint32_t s_off[NT + 1];
   __shared__ uint32_t s_e[NT];
@@ -593,8 +579,27 @@ __global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ o
   __shared__ uint32_t s_k[NT * (EMIT_RUN + 1)];
   __shared__ uint32_t s_v[NT * (EMIT_RUN + 1)];
   __shared__ uint32_t s4[4];
-  if (counters[C_OVERFLOW]) return;
-  const uint32_t m = counters[C_SLAB_N];
+  __shared__ uint32_t s_c[3];
+  // Block 0 writes counters below (the capacity check) that other blocks read here, so
+  // each block reads them once, in one thread: whichever values it sees, an overflowing
+  // slab writes no pair and the others see their own values.
+  if (threadIdx.x == 0) {
+    s_c[0] = counters[C_OVERFLOW];  // set when the first slab overflowed
+    s_c[1] = counters[C_SLAB_N];
+    s_c[2] = which == 1 ? 0u : counters[C_PAIRS1];
+  }
+  __syncthreads();
+  if (s_c[0]) return;
+  const uint32_t m = s_c[1];
+  // the slab's pair count from the chunk sums; block 0 records it and runs the capacity
+  // check, and every block leaves on overflow before writing anything
+  const uint32_t nq = (m + epb - 1) / epb;
+  const uint32_t slab_pairs = block_sum_range(qsum, 0, nq, s4);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    counters[C_SLAB_PAIRS] = slab_pairs;
+    capacity_check(counters, capacity, which);
+  }
+  if ((uint64_t)s_c[2] + slab_pairs > capacity) return;
   if ((uint64_t)blockIdx.x * epb >= m) return;
   const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
   const uint32_t tab_words = (uint32_t)views * TYp * TXp;
@@ -630,14 +635,17 @@ __global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ o
       c = x1 - x0;
     }
   };
+  uint32_t qdone = 0, qb = 0;  // qb: pairs of the chunks [0, qdone)
   for (uint32_t j0 = blockIdx.x * epb; j0 < m; j0 += gridDim.x * epb) {
     const uint32_t cnt = min((uint32_t)epb, m - j0);
     __syncthreads();
-    // the entries' pair offsets: the chunk's offset plus an exclusive scan of its counts
+    // the entries' pair offsets: the chunk's offset (the sum of the earlier chunks'
+    // counts) plus an exclusive scan of its own counts
+    qb += block_sum_range(qsum, qdone, j0 / epb, s4);
+    qdone = j0 / epb;
     const uint32_t ce = threadIdx.x < cnt ? counts[j0 + threadIdx.x] : 0u;
     uint32_t ctot;
     const uint32_t ex = block_excl_scan(ce, s4, ctot);
-    const uint32_t qb = qoff[j0 / epb];
     if (threadIdx.x < cnt) {
       const uint32_t e = order[j0 + threadIdx.x];
       const uint32_t v = (uint32_t)(e / n);
@@ -937,8 +945,6 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
   else
     hipLaunchKernelGGL(recount_kernel, dim3(grid_for(slab_max)), dim3(NT), 0, s, order, rect, w.tab, counters,
                        (uint32_t)n, p.TX, p.TY, epb, w.tmp, w.rsort, w.blk);
-  hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(NT), 0, s, w.blk, 0, counters + C_SLAB_N, (uint32_t)epb,
-                     counters + C_SLAB_PAIRS, counters, (uint64_t)p.capacity, which);
   const int tpasses = passes_for(p.tile_bits);
   uint32_t* ek = (tpasses % 2 == 0) ? bins.keys : w.pairK;
   uint32_t* ev = (tpasses % 2 == 0) ? bins.values : w.pairV;
@@ -947,13 +953,13 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
   const int64_t tab_words = (int64_t)V * (p.TY + 1) * (p.TX + 1) + (int64_t)V * p.T;
   if (which == 1 && !use_mask) {
     hipLaunchKernelGGL((emit_kernel<false, false>), dim3(eg), dim3(NT), 0, s, order, w.tmp, w.blk, w.rsort, w.tab, w.vfirst,
-                       mlist, counters, n, p.TX, p.TY, V, epb, ek, ev);
+                       mlist, counters, n, p.TX, p.TY, V, epb, which, (uint64_t)p.capacity, ek, ev);
   } else if (tab_words <= EMIT_TAB_WORDS) {
     hipLaunchKernelGGL((emit_kernel<true, true>), dim3(eg), dim3(NT), (size_t)tab_words * 4, s, order, w.tmp, w.blk, w.rsort,
-                       w.tab, w.vfirst, mlist, counters, n, p.TX, p.TY, V, epb, ek, ev);
+                       w.tab, w.vfirst, mlist, counters, n, p.TX, p.TY, V, epb, which, (uint64_t)p.capacity, ek, ev);
   } else {
     hipLaunchKernelGGL((emit_kernel<true, false>), dim3(eg), dim3(NT), 0, s, order, w.tmp, w.blk, w.rsort, w.tab, w.vfirst,
-                       mlist, counters, n, p.TX, p.TY, V, epb, ek, ev);
+                       mlist, counters, n, p.TX, p.TY, V, epb, which, (uint64_t)p.capacity, ek, ev);
   }
   if (tpasses > 0) {
     uint32_t *k1 = (ek == bins.keys) ? w.pairK : bins.keys, *v1 = (ev == bins.values) ? w.pairV : bins.values;
@@ -1072,10 +1078,8 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
       const int G = count_blocks(E);
       hipLaunchKernelGGL(count_kernel, dim3(G), dim3(NT), 0, s, rect, proj.flags, w.tab, (uint32_t)n, (uint32_t)E, G,
                          p.TX, p.TY, use_mask, w.cnt, w.blk);
-      hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(NT), 0, s, w.blk, G, nullptr, 1u, counters + C_ENTRIES,
-                         nullptr, (uint64_t)0, 0);
       hipLaunchKernelGGL(scan_compact_kernel, dim3(G), dim3(NT), 0, s, w.cnt, (uint32_t)E, w.blk, G, proj.depth,
-                         w.keyA, w.valA);
+                         w.keyA, w.valA, counters + C_ENTRIES);
     }
     // 4. depth order: 32 key bits, 4 passes, the result back in (keyA, valA)
     radix_sort(w.keyA, w.valA, w.keyB, w.valB, counters + C_ENTRIES, nullptr, E, 32, w.hist, w.dtot, s);
