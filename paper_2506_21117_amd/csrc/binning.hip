@@ -29,8 +29,8 @@ namespace clsp {
 namespace {
 
 constexpr int NT = 256;                     // threads per block
-constexpr int RS_ITEMS = 8;                 // keys per thread per chunk
-constexpr int RS_CHUNK = NT * RS_ITEMS;     // 2048 keys staged in LDS per chunk
+constexpr int RS_ITEMS = 4;                 // keys per thread per chunk
+constexpr int RS_CHUNK = NT * RS_ITEMS;     // 1024 keys staged in LDS per chunk
 constexpr int RS_WAVE_SPAN = 64 * RS_ITEMS; // consecutive keys one wave ranks per chunk
 constexpr int MAX_SORT_BLOCKS = 2048;
 constexpr int SCAN_ITEMS = 8;
@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(NT) rs_scan_kernel(uint32_t* __restrict__ hist
   if (threadIdx.x == 0) tot[blockIdx.x] = total;
 }
 
-// Stable scatter of each block's span.  Each wave ranks 512 consecutive keys with
+// Stable scatter of each block's span.  Each wave ranks RS_WAVE_SPAN consecutive keys with
 // ballot-based digit matching; the block then stages the chunk in LDS ordered by digit
 // and writes every digit's run contiguously.
 __global__ void __launch_bounds__(NT) rs_downsweep_kernel(const uint32_t* __restrict__ kin,
