@@ -271,8 +271,8 @@ clsp_status clsp_bin_and_sort(const clsp_projected *proj, const clsp_camera *cam
  * backward follows.  With depth-sliced bins this call also lists the second slab for
  * the tiles that need it (using the bins' workspace) and finishes those tiles; `proj`
  * must be the projection the bins were built from. */
-#define CLSP_STATE_CHUNK 128
-#define CLSP_STATE_CHUNKS 8
+#define CLSP_STATE_CHUNK 96
+#define CLSP_STATE_CHUNKS 16
 size_t clsp_render_state_bytes(int32_t n_views, int32_t width, int32_t height);
 clsp_status clsp_render_forward(const clsp_projected *proj, const clsp_bins *bins, const clsp_camera *cams,
                                 int32_t n_views, const float *bg, float *image, float *T_final, uint32_t *n_contrib,
