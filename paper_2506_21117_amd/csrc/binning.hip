@@ -18,9 +18,10 @@
 // Every kernel reads its element count from device memory, so nothing is read back.
 //
 // Depth-sliced lists: steps 5-7 first run for the nearest slab of the depth order
-// only; after the forward pass has rendered it, they run again for the remaining
+// only; after the forward pass has rendered it, steps 5-6 run again for the remaining
 // entries, emitting only into the tiles that still have compositing pixels (the
-// "alive" tiles, indexed like the mask), and the forward continues those tiles.
+// "alive" tiles, indexed like the mask), and the forward continues those tiles, each
+// finding its run of the second slab by a search over the sorted tiles (step 7).
 #include <algorithm>
 
 #include "internal.hpp"
@@ -966,8 +967,11 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
     radix_sort(ek, ev, k1, v1, counters + C_SLAB_PAIRS, counters + C_SLAB_BASE, p.capacity, p.tile_bits, w.hist,
                w.dtot, s);
   }
-  hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(p.capacity, 1 << 14)), dim3(NT), 0, s, bins.keys, counters,
-                     reinterpret_cast<uint2*>(ranges));
+  // the second slab's runs are found by the second forward phase itself (only its tiles
+  // read them), which saves a launch
+  if (which == 1)
+    hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(p.capacity, 1 << 14)), dim3(NT), 0, s, bins.keys, counters,
+                       reinterpret_cast<uint2*>(ranges));
   return hipGetLastError();
 }
 

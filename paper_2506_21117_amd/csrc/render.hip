@@ -8,13 +8,15 @@
 // the same LDS record, so the reads are broadcasts.  In the backward each wave sums its
 // 64 pixels' partials with DPP row operations, the four wave sums meet in LDS, and one
 // global float atomic per (record, component) is issued, only for changed Gaussians.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace clsp {
 namespace {
 
 constexpr int NT = TILE_PIX;
-constexpr int C_OVERFLOW = 1, C_TILES = 2, C_ALIVE = 8;
+constexpr int C_OVERFLOW = 1, C_TILES = 2, C_ALIVE = 8, C_SLAB_PAIRS = 11, C_SLAB_BASE = 12;
 constexpr int FW_UNROLL = 4;  // records whose weights the forward computes together
 
 // Opacity of a record at a pixel centre, evaluated with explicitly rounded operations
@@ -78,6 +80,40 @@ __device__ __forceinline__ StateView state_view(void* base, int64_t slots) {
 constexpr int CH = CLSP_STATE_CHUNK;
 constexpr int CHUNKS = CLSP_STATE_CHUNKS;
 
+// First positions i in [0, n) with keys[i] >= x and with keys[i] > x in ascending
+// keys (every thread of the block calls it and gets both): 256-ary searches run
+// together, one probe per thread per round, so n = 16M takes three rounds.
+__device__ __forceinline__ void block_equal_range(const uint32_t* __restrict__ keys, uint32_t n, uint32_t x,
+                                                  uint32_t& first, uint32_t& last) {
+  uint32_t lo_a = 0, hi_a = n, lo_b = 0, hi_b = n;  // each answer lies in [lo, hi]
+  while (hi_a > lo_a || hi_b > lo_b) {
+    const uint32_t span_a = hi_a - lo_a, span_b = hi_b - lo_b;
+    // probes lo + span * t / NT (span >= NT: strictly increasing in t, the first at lo),
+    // or every position lo + t when the span is shorter
+    const uint32_t qa = lo_a + (span_a < NT ? threadIdx.x : (uint32_t)(((uint64_t)span_a * threadIdx.x) / NT));
+    const uint32_t qb = lo_b + (span_b < NT ? threadIdx.x : (uint32_t)(((uint64_t)span_b * threadIdx.x) / NT));
+    const bool below_a = span_a > 0 && (span_a >= NT || threadIdx.x < span_a) && keys[qa] < x;
+    const bool below_b = span_b > 0 && (span_b >= NT || threadIdx.x < span_b) && keys[qb] <= x;
+    const uint32_t ca = (uint32_t)__syncthreads_count(below_a);
+    const uint32_t cb = (uint32_t)__syncthreads_count(below_b);
+    // the answer is past the last probe below x and at or before the first one not below
+    auto narrow = [&](uint32_t& lo, uint32_t& hi, uint32_t span, uint32_t c) {
+      if (span == 0) return;
+      if (span < NT) {  // every position was probed
+        lo = hi = lo + c;
+        return;
+      }
+      const uint32_t l = lo;
+      if (c > 0) lo = l + (uint32_t)(((uint64_t)span * (c - 1)) / NT) + 1;
+      if (c < NT) hi = l + (uint32_t)(((uint64_t)span * c) / NT);
+    };
+    narrow(lo_a, hi_a, span_a, ca);
+    narrow(lo_b, hi_b, span_b, cb);
+  }
+  first = lo_a;
+  last = lo_b;
+}
+
 // Entry of list position k of a tile whose list is [r1.x, r1.y) followed by [r2.x, r2.y).
 __device__ __forceinline__ uint32_t list_entry(const uint32_t* __restrict__ values, uint2 r1, uint2 r2, int k) {
   const int len1 = (int)(r1.y - r1.x);
@@ -92,8 +128,9 @@ __device__ __forceinline__ uint32_t list_entry(const uint32_t* __restrict__ valu
 // so the outputs are identical bit for bit.
 template <int PHASE>
 __global__ void __launch_bounds__(NT) render_forward_kernel(
-    const float* __restrict__ splat, const uint32_t* __restrict__ values, const uint2* __restrict__ ranges,
-    const uint2* __restrict__ ranges2, const uint32_t* __restrict__ tile_list, uint32_t* __restrict__ counters, int T,
+    const float* __restrict__ splat, const uint32_t* __restrict__ values, const uint32_t* __restrict__ pair_keys,
+    const uint2* __restrict__ ranges, uint2* __restrict__ ranges2, const uint32_t* __restrict__ tile_list,
+    uint32_t* __restrict__ counters, int T,
     int TX, int W, int H, float bg0, float bg1, float bg2, float* __restrict__ image, float* __restrict__ T_final,
     uint32_t* __restrict__ n_contrib, void* state, int64_t slots, int sliced, uint32_t* __restrict__ alive,
     uint32_t* __restrict__ alive_mask, int wpv, float* __restrict__ carry) {
@@ -111,7 +148,16 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
   const bool inside = px < W && py < H;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
   const uint2 r1 = ranges[gt];
-  const uint2 r2 = PHASE == 2 ? ranges2[gt] : make_uint2(0u, 0u);
+  uint2 r2 = make_uint2(0u, 0u);
+  if (PHASE == 2) {
+    // this tile's run among the second slab's pairs (sorted by global tile), recorded
+    // in ranges2 for the backward
+    const uint32_t base = counters[C_SLAB_BASE], P2 = counters[C_SLAB_PAIRS];
+    uint32_t first, last;
+    block_equal_range(pair_keys + base, P2, gt, first, last);
+    if (last > first) r2 = make_uint2(base + first, base + last);
+    if (threadIdx.x == 0) ranges2[gt] = r2;
+  }
   const int len1 = (int)(r1.y - r1.x);
   const int k_begin = PHASE == 1 ? 0 : len1;
   const int k_end = PHASE == 1 ? len1 : len1 + (int)(r2.y - r2.x);
@@ -241,26 +287,35 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
   }
 }
 
+// Blocks loop over the rendered tiles (at most L1_BLOCKS of them), so that the loss
+// sum costs one float atomic per block rather than per tile: atomics on one address
+// serialise.
+constexpr int L1_BLOCKS = 512;
+
 __global__ void __launch_bounds__(NT) l1_loss_grad_kernel(const float* __restrict__ image,
                                                           const float* __restrict__ target,
                                                           const uint32_t* __restrict__ tile_list,
                                                           const uint32_t* __restrict__ counters, int T, int TX, int W,
                                                           int H, float* __restrict__ dL, float* __restrict__ loss_sum) {
-  if (blockIdx.x >= counters[C_TILES]) return;
   __shared__ float s_sum[4];
-  const uint32_t gt = tile_list[blockIdx.x];
-  const int v = gt / T, t = gt % T;
-  const int px = (t % TX) * TILE + pixel_x(threadIdx.x);
-  const int py = (t / TX) * TILE + pixel_y(threadIdx.x);
+  const uint32_t tiles = counters[C_TILES];
+  if (blockIdx.x >= tiles) return;
   const float norm = 1.0f / (3.0f * (float)W * (float)H);
+  const size_t hw = (size_t)H * W;
   float acc = 0.0f;
-  if (px < W && py < H) {
-    const size_t hw = (size_t)H * W;
-    for (int c = 0; c < 3; ++c) {
-      const size_t idx = ((size_t)v * 3 + c) * hw + (size_t)py * W + px;
-      const float d = image[idx] - target[idx];
-      dL[idx] = d > 0.0f ? norm : (d < 0.0f ? -norm : 0.0f);
-      acc += fabsf(d);
+  for (uint32_t slot = blockIdx.x; slot < tiles; slot += gridDim.x) {
+    const uint32_t gt = tile_list[slot];
+    const int v = gt / T, t = gt % T;
+    // row-major within the tile: each wave reads four 64-byte row segments
+    const int px = (t % TX) * TILE + (int)(threadIdx.x & 15u);
+    const int py = (t / TX) * TILE + (int)(threadIdx.x >> 4);
+    if (px < W && py < H) {
+      for (int c = 0; c < 3; ++c) {
+        const size_t idx = ((size_t)v * 3 + c) * hw + (size_t)py * W + px;
+        const float d = image[idx] - target[idx];
+        dL[idx] = d > 0.0f ? norm : (d < 0.0f ? -norm : 0.0f);
+        acc += fabsf(d);
+      }
     }
   }
   if (loss_sum) {
@@ -472,15 +527,15 @@ hipError_t launch_render_forward(const clsp_projected& proj, const clsp_bins& bi
   uint32_t* alive = bin_alive_flags(plan, ws);
   float* carry = bin_carry(plan, ws);
   const int wpv = (T + 31) / 32;
-  hipLaunchKernelGGL(render_forward_kernel<1>, dim3(blocks), dim3(NT), 0, s, proj.splat, bins.values,
-                     reinterpret_cast<const uint2*>(bins.ranges), reinterpret_cast<const uint2*>(bins.ranges2),
+  hipLaunchKernelGGL(render_forward_kernel<1>, dim3(blocks), dim3(NT), 0, s, proj.splat, bins.values, bins.keys,
+                     reinterpret_cast<const uint2*>(bins.ranges), reinterpret_cast<uint2*>(bins.ranges2),
                      bins.tile_list, bins.counters, T, TX, W, H, bg[0], bg[1], bg[2], image, T_final, n_contrib, state,
                      (int64_t)blocks, sliced, alive, bins.alive_mask, wpv, carry);
   if (!sliced) return hipGetLastError();
   hipError_t err = launch_list_second_slab(plan, proj, bins, ws, s);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(render_forward_kernel<2>, dim3(blocks), dim3(NT), 0, s, proj.splat, bins.values,
-                     reinterpret_cast<const uint2*>(bins.ranges), reinterpret_cast<const uint2*>(bins.ranges2),
+  hipLaunchKernelGGL(render_forward_kernel<2>, dim3(blocks), dim3(NT), 0, s, proj.splat, bins.values, bins.keys,
+                     reinterpret_cast<const uint2*>(bins.ranges), reinterpret_cast<uint2*>(bins.ranges2),
                      bins.tile_list, bins.counters, T, TX, W, H, bg[0], bg[1], bg[2], image, T_final, n_contrib, state,
                      (int64_t)blocks, sliced, alive, bins.alive_mask, wpv, carry);
   return hipGetLastError();
@@ -489,8 +544,8 @@ hipError_t launch_render_forward(const clsp_projected& proj, const clsp_bins& bi
 hipError_t launch_l1_loss_grad(const float* image, const float* target, const clsp_bins& bins, int views, int W, int H,
                                int TX, int TY, float* dL, float* loss_sum, hipStream_t s) {
   const int T = TX * TY;
-  hipLaunchKernelGGL(l1_loss_grad_kernel, dim3(views * T), dim3(NT), 0, s, image, target, bins.tile_list,
-                     bins.counters, T, TX, W, H, dL, loss_sum);
+  hipLaunchKernelGGL(l1_loss_grad_kernel, dim3(std::min(views * T, L1_BLOCKS)), dim3(NT), 0, s, image, target,
+                     bins.tile_list, bins.counters, T, TX, W, H, dL, loss_sum);
   return hipGetLastError();
 }
 
