@@ -239,6 +239,15 @@ const char *clsp_last_error(void);
 clsp_status clsp_project_preprocess(const clsp_gaussians *g, const clsp_camera *cams, int32_t n_views,
                                     const clsp_projected *out, clsp_stream stream);
 
+/* The same projection for the entries of rows [rows.begin, rows.end) of every view only
+ * (entry v*n + i, i in the range); every other entry of `out` is left as it was.  A
+ * caller that keeps one projection per view re-projects only the rows whose parameters
+ * changed (during local optimisation, the change set O^t; Sec. 3.3 freezes the rest),
+ * and the result is the full projection bit for bit.
+ * Errors: as clsp_project_preprocess, plus rows not within [0, n]. */
+clsp_status clsp_project_preprocess_rows(const clsp_gaussians *g, const clsp_camera *cams, int32_t n_views,
+                                         clsp_range rows, const clsp_projected *out, clsp_stream stream);
+
 /* ---------------------------------------------------------------------------------
  * Render mask and per-tile depth order (Supp. "Local Optimization Kernel", item 1: a
  * boolean ceil(w/16) x ceil(h/16) mask that is true where at least one changed

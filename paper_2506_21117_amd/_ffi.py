@@ -19,7 +19,8 @@ N_COUNTERS = 16
 BINS_COMPLETE, BINS_DEPTH_SLICED = 0, 1
 
 EXPORTED = (
-    "clsp_version", "clsp_last_error", "clsp_project_preprocess", "clsp_bin_and_sort_workspace_bytes",
+    "clsp_version", "clsp_last_error", "clsp_project_preprocess", "clsp_project_preprocess_rows",
+    "clsp_bin_and_sort_workspace_bytes",
     "clsp_bin_and_sort", "clsp_render_state_bytes", "clsp_render_forward", "clsp_l1_loss_grad",
     "clsp_render_backward_workspace_bytes",
     "clsp_render_backward", "clsp_masked_adam_step", "clsp_zero_grads",
@@ -87,6 +88,9 @@ def load(path: Path | None = None):
     L.clsp_last_error.argtypes = []
     L.clsp_project_preprocess.restype = st
     L.clsp_project_preprocess.argtypes = [POINTER(Gaussians), POINTER(Camera), c_int32, POINTER(Projected), c_void_p]
+    L.clsp_project_preprocess_rows.restype = st
+    L.clsp_project_preprocess_rows.argtypes = [POINTER(Gaussians), POINTER(Camera), c_int32, Range, POINTER(Projected),
+                                               c_void_p]
     L.clsp_bin_and_sort_workspace_bytes.restype = c_size_t
     L.clsp_bin_and_sort_workspace_bytes.argtypes = [c_int64, c_int32, c_int32, c_int32, c_int64]
     L.clsp_bin_and_sort.restype = st

@@ -141,6 +141,7 @@ class ProjectedBuffers:
     flags: torch.Tensor   # [V*N] int32
     n: int
     views: int
+    BYTES_PER_ENTRY = 64   # splat 48 + depth 4 + rect 8 + flags 4
 
     @classmethod
     def alloc(cls, n, views, device):
@@ -212,6 +213,18 @@ def project_preprocess(g: GaussianTensors, cams, out: ProjectedBuffers | None = 
     gs = g.as_gaussians(gather)
     ca = camera_array(cams)
     check(lib().clsp_project_preprocess(ctypes.byref(gs), ca, len(cams), ctypes.byref(out.struct()), _stream(stream)))
+    return out
+
+
+def project_preprocess_rows(g: GaussianTensors, cams, rows, out: ProjectedBuffers, stream=None):
+    """Re-project rows [rows[0], rows[1]) of every view into ``out`` (the other entries
+    keep their values)."""
+    if out.n != g.n or out.views != len(cams):
+        raise ValueError("projected buffers sized for another scene")
+    gs = g.as_gaussians()
+    check(lib().clsp_project_preprocess_rows(ctypes.byref(gs), camera_array(cams), len(cams),
+                                             _ffi.Range(int(rows[0]), int(rows[1])), ctypes.byref(out.struct()),
+                                             _stream(stream)))
     return out
 
 

@@ -167,8 +167,27 @@ clsp_status clsp_project_preprocess(const clsp_gaussians* g, const clsp_camera* 
   const clsp::RawParams rp = raw_params(g);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   for (int v = 0; v < n_views; ++v)
-    CHECK(hip_status(clsp::launch_preprocess(rp, dev_cam(cams[v]), v, out->splat, out->depth, out->rect, out->flags, s),
+    CHECK(hip_status(clsp::launch_preprocess(rp, dev_cam(cams[v]), v, 0, g->n, out->splat, out->depth, out->rect,
+                                             out->flags, s),
                      "project_preprocess"));
+  return CLSP_OK;
+}
+
+clsp_status clsp_project_preprocess_rows(const clsp_gaussians* g, const clsp_camera* cams, int32_t n_views,
+                                         clsp_range rows, const clsp_projected* out, clsp_stream stream) {
+  CHECK(check_gaussians(g));
+  CHECK(check_cams(cams, n_views));
+  CHECK(check_projected(out));
+  if ((int64_t)n_views * g->n > MAX_ENTRIES) return fail(CLSP_ERR_INVALID_ARG, "n_views * n >= 2^32");
+  if (rows.begin < 0 || rows.end < rows.begin || rows.end > g->n)
+    return fail(CLSP_ERR_INVALID_ARG, "rows [%lld, %lld) not within [0, %lld]", (long long)rows.begin,
+                (long long)rows.end, (long long)g->n);
+  const clsp::RawParams rp = raw_params(g);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int v = 0; v < n_views; ++v)
+    CHECK(hip_status(clsp::launch_preprocess(rp, dev_cam(cams[v]), v, rows.begin, rows.end, out->splat, out->depth,
+                                             out->rect, out->flags, s),
+                     "project_preprocess_rows"));
   return CLSP_OK;
 }
 

@@ -60,8 +60,9 @@ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // ---------------------------------------------------------------- launchers
 // preprocess.hip
-hipError_t launch_preprocess(const RawParams& g, const DevCam& cam, int view, float* splat, float* depth,
-                             uint32_t* rect, uint32_t* flags, hipStream_t s);
+// Projects entries [r0, r1) of view `view` (all n: r0 = 0, r1 = g.n).
+hipError_t launch_preprocess(const RawParams& g, const DevCam& cam, int view, int64_t r0, int64_t r1, float* splat,
+                             float* depth, uint32_t* rect, uint32_t* flags, hipStream_t s);
 hipError_t launch_preprocess_backward(const RawParams& g, const DevCam& cam, int view, int64_t a0, int64_t a1,
                                       const uint32_t* flags, const float* grad2d, const MutParams& grads,
                                       hipStream_t s);

@@ -184,11 +184,11 @@ __device__ __forceinline__ void view_dir(const Geo& q, const DevCam& cam, float*
   d[2] = dz * inv;
 }
 
-__global__ void __launch_bounds__(256) preprocess_kernel(RawParams g, DevCam cam, int view, float* __restrict__ splat,
-                                                         float* __restrict__ depth, uint2* __restrict__ rect,
-                                                         uint32_t* __restrict__ flags) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.n) return;
+__global__ void __launch_bounds__(256) preprocess_kernel(RawParams g, DevCam cam, int view, int64_t r0, int64_t r1,
+                                                         float* __restrict__ splat, float* __restrict__ depth,
+                                                         uint2* __restrict__ rect, uint32_t* __restrict__ flags) {
+  const int64_t i = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= r1) return;
   const int64_t row = g.gather ? (int64_t)g.gather[i] : i;
   const int64_t e = (int64_t)view * g.n + i;
   Geo q;
@@ -379,11 +379,11 @@ __global__ void __launch_bounds__(128) preprocess_backward_kernel(RawParams g, D
 
 }  // namespace
 
-hipError_t launch_preprocess(const RawParams& g, const DevCam& cam, int view, float* splat, float* depth,
-                             uint32_t* rect, uint32_t* flags, hipStream_t s) {
-  if (g.n == 0) return hipSuccess;
-  const int blocks = ceil_div(g.n, 256);
-  hipLaunchKernelGGL(preprocess_kernel, dim3(blocks), dim3(256), 0, s, g, cam, view, splat, depth,
+hipError_t launch_preprocess(const RawParams& g, const DevCam& cam, int view, int64_t r0, int64_t r1, float* splat,
+                             float* depth, uint32_t* rect, uint32_t* flags, hipStream_t s) {
+  if (r1 <= r0) return hipSuccess;
+  const int blocks = ceil_div(r1 - r0, 256);
+  hipLaunchKernelGGL(preprocess_kernel, dim3(blocks), dim3(256), 0, s, g, cam, view, r0, r1, splat, depth,
                      reinterpret_cast<uint2*>(rect), flags);
   return hipGetLastError();
 }

@@ -20,10 +20,16 @@ from ._ffi import C_STICKY, check
 
 class SplatOptimizer:
     def __init__(self, params: api.GaussianTensors, cams, targets, active=None, local=True, bg=(0.0, 0.0, 0.0),
-                 capacity=None, lr=api.DEFAULT_LR):
+                 capacity=None, lr=api.DEFAULT_LR, projection_cache_bytes=32 << 30):
         """params: device parameters (updated in place); cams: list of cameras of one
         size; targets: [V, 3, H, W] float32 device tensor; active: (a0, a1) change set
-        (default: all rows); local: restrict rendering to the change set's tile mask."""
+        (default: all rows); local: restrict rendering to the change set's tile mask.
+
+        Local steps keep each view's projection of all Gaussians (64 B per Gaussian per
+        view, when that fits in ``projection_cache_bytes``) and re-project only the
+        change set's rows: the other rows are frozen, so their projection for a view is
+        the same every time the view comes back.  Call ``invalidate_projections()`` after
+        changing rows outside the change set."""
         self.params = params
         self.cams = list(cams)
         self.targets = targets
@@ -38,6 +44,9 @@ class SplatOptimizer:
         self.m = params.zeros_like()
         self.v = params.zeros_like()
         self.proj = api.ProjectedBuffers.alloc(self.n, 1, dev)
+        cache = self.local and self.n * len(self.cams) * api.ProjectedBuffers.BYTES_PER_ENTRY <= projection_cache_bytes
+        self.proj_views = [api.ProjectedBuffers.alloc(self.n, 1, dev) for _ in self.cams] if cache else None
+        self._projected = [False] * len(self.cams)
         self.image = torch.zeros(1, 3, H, W, dtype=torch.float32, device=dev)
         self.T = torch.zeros(1, H, W, dtype=torch.float32, device=dev)
         self.nc = torch.zeros(1, H, W, dtype=torch.int32, device=dev)
@@ -88,6 +97,7 @@ class SplatOptimizer:
         self._m = self.m.as_params()
         self._v = self.v.as_params()
         self._proj = self.proj.struct()
+        self._proj_views = None if self.proj_views is None else [pv.struct() for pv in self.proj_views]
         self._bins = self.bins.struct()
         self._range = _ffi.Range(a0, a1)
         self._bg = (ctypes.c_float * 3)(*self.bg)
@@ -102,6 +112,11 @@ class SplatOptimizer:
                       "loss": p(self.loss_sum), "ws": p(self.bins.ws), "bws": p(self.bwd_ws), "state": p(self.state),
                       "targets": [p(self.targets[v:v + 1]) for v in range(len(self.cams))]}
         self._sizes = (self.bins.ws.numel(), self.bwd_ws.numel(), self.state.numel())
+
+    def invalidate_projections(self):
+        """The next step on each view projects every row again (needed after rows outside
+        the change set were modified)."""
+        self._projected = [False] * len(self.cams)
 
     def overflowed(self) -> bool:
         """True if any step since the last check ran out of pair capacity (sticky
@@ -163,19 +178,28 @@ class SplatOptimizer:
         P = self._ptrs
         by = ctypes.byref
         use_mask = 1 if self.local else 0
-        check(L.clsp_project_preprocess(by(self._g), cam, 1, by(self._proj), st))
+        if self._proj_views is None:
+            proj = self._proj
+            check(L.clsp_project_preprocess(by(self._g), cam, 1, by(proj), st))
+        else:
+            proj = self._proj_views[view]
+            if self._projected[view]:
+                check(L.clsp_project_preprocess_rows(by(self._g), cam, 1, self._range, by(proj), st))
+            else:
+                check(L.clsp_project_preprocess(by(self._g), cam, 1, by(proj), st))
+                self._projected[view] = True
         ev = events or {}
         mark = lambda name, i: ev[name][i].record(stream) if name in ev else None
         mark("bin_and_sort", 0)
-        check(L.clsp_bin_and_sort(by(self._proj), cam, 1, self._range, use_mask, by(self._bins), st))
+        check(L.clsp_bin_and_sort(by(proj), cam, 1, self._range, use_mask, by(self._bins), st))
         mark("bin_and_sort", 1)
         mark("render_forward", 0)
-        check(L.clsp_render_forward(by(self._proj), by(self._bins), cam, 1, self._bg, P["image"], P["T"], P["nc"],
+        check(L.clsp_render_forward(by(proj), by(self._bins), cam, 1, self._bg, P["image"], P["T"], P["nc"],
                                     P["state"], self._sizes[2], st))
         mark("render_forward", 1)
         check(L.clsp_l1_loss_grad(P["image"], P["targets"][view], by(self._bins), cam, 1, P["dL"], P["loss"], st))
         mark("render_backward", 0)
-        check(L.clsp_render_backward(by(self._g), by(self._proj), by(self._bins), cam, 1, self._bg, self._range, P["T"],
+        check(L.clsp_render_backward(by(self._g), by(proj), by(self._bins), cam, 1, self._bg, self._range, P["T"],
                                      P["nc"], P["state"], self._sizes[2], P["dL"], by(self._gr), P["bws"],
                                      self._sizes[1], st))
         mark("render_backward", 1)

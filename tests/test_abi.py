@@ -92,6 +92,11 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
     assert L.clsp_project_preprocess(ctypes.byref(g), bad, 1, ctypes.byref(proj), None) == _ffi.CLSP_ERR_INVALID_ARG
     big = _cam(16384, 16384)   # more than 65536 tiles per view
     assert L.clsp_project_preprocess(ctypes.byref(g), big, 1, ctypes.byref(proj), None) == _ffi.CLSP_ERR_INVALID_ARG
+    # row ranges outside [0, n] or reversed
+    for r0, r1 in ((-1, 3), (4, 11), (6, 5)):
+        assert L.clsp_project_preprocess_rows(ctypes.byref(g), cam, 1, _ffi.Range(r0, r1), ctypes.byref(proj),
+                                              None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert b"rows" in L.clsp_last_error()
 
     ws_need = L.clsp_bin_and_sort_workspace_bytes(10, 1, 64, 48, 100)
     bins = _ffi.Bins(fake, fake, fake, fake, fake, fake, fake, fake, fake, ws_need, 100, 10, 1, 0)

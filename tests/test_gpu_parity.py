@@ -102,6 +102,56 @@ def test_preprocess_parity(dev, case):
             np.testing.assert_array_equal(a[vis_g].astype(np.int64), b[vis_g])
 
 
+def _same_projection(a, b):
+    for k in ("splat", "depth", "rect", "flags"):
+        np.testing.assert_array_equal(to_np(getattr(a, k)).view(np.uint32), to_np(getattr(b, k)).view(np.uint32))
+
+
+@pytest.mark.parametrize("case", ["sh3", "ring2"])
+def test_projecting_changed_rows_equals_full_projection(dev, case):
+    """Re-projecting rows [a0, a1) after their parameters changed gives the full
+    projection of the new parameters, bit for bit, and leaves the other rows alone."""
+    sc, cams = workload(case)
+    g = api.GaussianTensors.from_scene(sc, dev)
+    proj = gpu_preprocess(g, cams)
+    a0, a1 = sc.n // 3, 2 * sc.n // 3
+    rng = np.random.default_rng(11)
+    for k in api.GaussianTensors.NAMES:
+        x = getattr(g, k)
+        x[..., a0:a1] += torch.as_tensor(rng.normal(size=x[..., a0:a1].shape).astype(np.float32) * 0.05, device=dev)
+    api.project_preprocess_rows(g, cams, (a0, a1), proj)
+    _same_projection(proj, gpu_preprocess(g, cams))
+    api.project_preprocess_rows(g, cams, (a1, a1), proj)   # an empty range writes nothing
+    _same_projection(proj, gpu_preprocess(g, cams))
+
+
+def test_local_steps_keep_each_views_projection_of_frozen_rows(dev):
+    """The optimiser's local steps re-project only the change set of the step's view;
+    afterwards every view's kept projection, its change set re-projected, equals a full
+    projection of the current parameters (the frozen rows never changed).  The change
+    ball sits on the cube face z = +1, so it is visible and the steps move it."""
+    from paper_2506_21117_amd.optim import SplatOptimizer
+
+    w = scenes.local_change(n=40_000, n_views=3, width=320, height=180, fx=320.0, radius=0.4, center=(0.0, 0.0, 1.0))
+    a = (w.active_begin, w.scene.n)
+    g = api.GaussianTensors.from_scene(w.scene, dev)
+    frozen = {k: getattr(g, k)[..., :a[0]].clone() for k in api.GaussianTensors.NAMES}
+    targets = torch.rand(3, 3, 180, 320, generator=torch.Generator(device=dev).manual_seed(2), device=dev)
+    opt = SplatOptimizer(g, w.cameras, targets, active=a, local=True)
+    assert opt.proj_views is not None
+    for i in range(7):
+        opt.step(i % 3)
+    torch.cuda.synchronize()
+    assert not opt.overflowed()
+    for k in api.GaussianTensors.NAMES:
+        np.testing.assert_array_equal(to_np(getattr(g, k)[..., :a[0]]), to_np(frozen[k]))
+        moved = getattr(g, k)[..., a[0]:] != getattr(api.GaussianTensors.from_scene(w.scene, dev), k)[..., a[0]:]
+        assert bool(moved.any()), k
+    for v, cam in enumerate(w.cameras):
+        api.project_preprocess_rows(g, [cam], a, opt.proj_views[v])
+        _same_projection(opt.proj_views[v], gpu_preprocess(g, [cam]))
+
+
 # ------------------------------------------------------------------ a2, a3 binning
 def _check_bins(bins, proj, cams, active, use_mask):
     c = bins.read_counters()
