@@ -222,8 +222,8 @@ def main():
 # They describe the kernels whose sources hash to `source_sha256` and are reported only
 # while the sources still do (profiles/traffic_local_step_1M_1280x720.txt).
 MEASURED_TRAFFIC = {
-    "source_sha256": "e839be756c94dc89d8600e1cc39ed9e18a07eaa07bed84bb79eff0cb932666ed",
-    "bytes": {"bin_and_sort": 183.066e6, "render_forward": 13.531e6, "render_backward": 15.233e6},
+    "source_sha256": "82d51947c0da2a0c51ca3ed8ca3f633e54953a473cb50aec1013780c76ebf6b8",
+    "bytes": {"bin_and_sort": 210.012e6, "render_forward": 14.438e6, "render_backward": 16.510e6},
 }
 
 
