@@ -201,21 +201,35 @@ __global__ void __launch_bounds__(NT) count_kernel(const uint2* __restrict__ rec
   uint32_t beg, end;
   block_span(E, G, blockIdx.x, NT, beg, end);
   uint32_t has = 0;
-  for (uint32_t e = beg + threadIdx.x; e < end; e += NT) {
-    uint32_t c = 0;
-    if (flags[e] & CLSP_FLAG_VISIBLE) {
-      const uint2 r = rect[e];
-      const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
-      if (x1 > x0 && y1 > y0) {
-        if (!use_mask) {
-          c = (x1 - x0) * (y1 - y0);
-        } else {
-          c = tab_rect(tab, (e / n) * (uint32_t)(TY + 1), (uint32_t)(TX + 1), x0, x1, y0, y1);
-        }
-      }
+  constexpr int U = 4;  // entries per thread per round, their loads issued together
+  const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
+  for (uint32_t e0 = beg + threadIdx.x; e0 < end; e0 += U * NT) {
+    uint32_t fl[U];
+    uint2 r[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const uint32_t e = e0 + k * NT;
+      fl[k] = e < end ? flags[e] : 0u;
+      r[k] = e < end ? rect[e] : make_uint2(0u, 0u);
     }
-    cnt[e] = c;
-    has += c != 0u ? 1u : 0u;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const uint32_t e = e0 + k * NT;
+      // a rectangle within the tile grid (preprocess writes no other), or none
+      const uint32_t x0 = min(r[k].x & 0xffffu, (uint32_t)TX), x1 = min(r[k].x >> 16, (uint32_t)TX);
+      const uint32_t y0 = min(r[k].y & 0xffffu, (uint32_t)TY), y1 = min(r[k].y >> 16, (uint32_t)TY);
+      const bool ok = (fl[k] & CLSP_FLAG_VISIBLE) && x1 > x0 && y1 > y0;
+      uint32_t c = 0;
+      if (!use_mask) {
+        c = (x1 - x0) * (y1 - y0);
+      } else {
+        const uint32_t v = e < end ? e / n : 0u;
+        c = tab_rect(tab, v * TYp, TXp, ok ? x0 : 0u, ok ? x1 : 0u, ok ? y0 : 0u, ok ? y1 : 0u);
+      }
+      c = ok ? c : 0u;
+      if (e < end) cnt[e] = c;
+      has += c != 0u ? 1u : 0u;
+    }
   }
   uint32_t tot;
   block_excl_scan(has, s4, tot);
@@ -256,12 +270,14 @@ __global__ void __launch_bounds__(NT) scan_compact_kernel(const uint32_t* __rest
   block_span(n, G, blockIdx.x, NT, beg, end);
   uint32_t base = block_sum_range(blk, 0, blockIdx.x, s4);
   for (uint32_t c = beg; c < end; c += SCAN_CHUNK) {
-    uint32_t v[SCAN_ITEMS];
+    uint32_t v[SCAN_ITEMS], dk[SCAN_ITEMS];
     uint32_t sum = 0;
     const uint32_t t0 = c + threadIdx.x * SCAN_ITEMS;
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
-      v[k] = (t0 + k < end && cnt[t0 + k] != 0u) ? 1u : 0u;
+      const bool in = t0 + k < end;
+      v[k] = (in && cnt[t0 + k] != 0u) ? 1u : 0u;
+      dk[k] = in ? __float_as_uint(depth[t0 + k]) : 0u;  // depth > 0.2: the bit pattern orders like the value
       sum += v[k];
     }
     uint32_t tot;
@@ -269,7 +285,7 @@ __global__ void __launch_bounds__(NT) scan_compact_kernel(const uint32_t* __rest
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
       if (v[k]) {
-        keys[off] = __float_as_uint(depth[t0 + k]);  // depth > 0.2: the bit pattern orders like the value
+        keys[off] = dk[k];
         vals[off] = t0 + k;
       }
       off += v[k];
