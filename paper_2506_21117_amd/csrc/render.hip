@@ -360,7 +360,6 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
   if (k0 >= maxlast) return;
   const int last_chunk = min(CHUNKS - 1, (maxlast - 1) / CH);
   const int k1 = (chunk == last_chunk) ? maxlast : (chunk + 1) * CH;
-
   __shared__ float4 s_a[NT];
   __shared__ float4 s_b[NT];
   __shared__ float s_c[NT];
@@ -369,12 +368,30 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
   __shared__ float s_g[NT][9];
 
   const uint32_t gt = tile_list[slot];
+  const uint2 r1 = ranges[gt], r2 = ranges2[gt];
+  if (a0 > 0 || a1 < n) {
+    // A chunk without a record of the active range adds nothing to any gradient: its
+    // frozen records only un-blend, and no other chunk starts from where it ends.  (The
+    // block-wide OR goes through s_act, which is rewritten before its first use below.)
+    const int64_t vb = (int64_t)(gt / T) * n;
+    bool any = false;
+    for (int k = k0 + (int)threadIdx.x; k < k1; k += NT) {
+      const int64_t gid = (int64_t)list_entry(values, r1, r2, k) - vb;
+      any = any || (gid >= a0 && gid < a1);
+    }
+    const bool wave_any = __ballot(any) != 0ull;
+    if ((threadIdx.x & 63u) == 0) s_act[threadIdx.x >> 6] = wave_any ? 1u : 0u;
+    __syncthreads();
+    const bool block_any = (s_act[0] | s_act[1] | s_act[2] | s_act[3]) != 0u;
+    __syncthreads();
+    if (!block_any) return;
+  }
+
   const int v = gt / T, t = gt % T;
   const int px = (t % TX) * TILE + pixel_x(threadIdx.x);
   const int py = (t / TX) * TILE + pixel_y(threadIdx.x);
   const bool inside = px < W && py < H;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  const uint2 r1 = ranges[gt], r2 = ranges2[gt];
   const size_t hw = (size_t)H * W;
   const size_t pix = (size_t)py * W + px;
 
