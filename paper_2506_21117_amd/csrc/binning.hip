@@ -621,8 +621,9 @@ __global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ o
   const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
   const uint32_t tab_words = (uint32_t)views * TYp * TXp;
   if (MASKED && LDS_TAB) {
-    // eight loads in flight per thread
-    const uint32_t words = tab_words + (uint32_t)views * (uint32_t)(TX * TY);
+    // the table and the list's valid part (the rendered tiles; the second slab's list
+    // of alive tiles is shorter still); eight loads in flight per thread
+    const uint32_t words = tab_words + min((uint32_t)views * (uint32_t)(TX * TY), counters[C_TILES]);
     for (uint32_t w0 = threadIdx.x; w0 < words; w0 += 8 * NT) {
       uint32_t t[8];
 #pragma unroll
@@ -776,8 +777,10 @@ __global__ void __launch_bounds__(MI_NT) mask_index_kernel(const uint32_t* __res
                                                            int TX, int TY, uint32_t* __restrict__ wpre,
                                                            uint32_t* __restrict__ list, uint32_t* __restrict__ vfirst,
                                                            uint32_t* __restrict__ tab, uint32_t* __restrict__ count_out,
-                                                           int lds_tab) {
+                                                           int lds_tab, const uint32_t* __restrict__ skip_if_zero) {
   extern __shared__ uint32_t s_tab[];  // lds_tab: the corner table under construction
+  // an index nobody will read (no tile is alive: the second slab is empty)
+  if (skip_if_zero && *skip_if_zero == 0u) return;
   const int T = TX * TY;
   __shared__ uint32_t s_w[MI_NT / 64];
   __shared__ uint32_t s_carry;
@@ -928,12 +931,12 @@ WsPtrs carve(const BinPlan& p, char* ws) {
 // Index of `mask`: sorted tile list into `list`, view first positions and corner table
 // into w.vfirst and w.tab.
 void index_mask(const BinPlan& p, const uint32_t* mask, const WsPtrs& w, uint32_t* list, uint32_t* count_out,
-                hipStream_t s) {
+                hipStream_t s, const uint32_t* skip_if_zero = nullptr) {
   const int wpv = (p.T + 31) / 32;
   const int64_t words = (int64_t)p.views * (p.TY + 1) * (p.TX + 1);
   const int lds = words <= MI_TAB_WORDS;
   hipLaunchKernelGGL(mask_index_kernel, dim3(1), dim3(MI_NT), lds ? (size_t)words * 4 : 0, s, mask, p.views, wpv, p.TX,
-                     p.TY, w.wpre, list, w.vfirst, w.tab, count_out, lds);
+                     p.TY, w.wpre, list, w.vfirst, w.tab, count_out, lds, skip_if_zero);
 }
 
 // Lists one slab of the depth order (order = valA after the 32-bit depth sort):
@@ -1114,7 +1117,7 @@ hipError_t launch_list_second_slab(const BinPlan& p, const clsp_projected& proj,
                                    hipStream_t s) {
   if (p.entries == 0) return hipSuccess;
   const WsPtrs w = carve(p, ws);
-  index_mask(p, bins.alive_mask, w, w.tlist, nullptr, s);
+  index_mask(p, bins.alive_mask, w, w.tlist, nullptr, s, bins.counters + C_ALIVE);
   return list_slab(p, proj, bins, w, 2, 1, bins.alive_mask, w.tlist, bins.ranges2, s);
 }
 
