@@ -17,7 +17,7 @@ namespace {
 
 constexpr int NT = TILE_PIX;
 constexpr int C_OVERFLOW = 1, C_TILES = 2, C_ALIVE = 8, C_SLAB_PAIRS = 11, C_SLAB_BASE = 12;
-constexpr int FW_UNROLL = 4;  // records whose weights the forward computes together
+constexpr int FW_UNROLL = 8;  // records whose weights the forward computes together
 
 // Opacity of a record at a pixel centre, evaluated with explicitly rounded operations
 // so the forward and the backward take the same decisions bit for bit.
