@@ -287,6 +287,18 @@ clsp_status clsp_render_forward(const clsp_projected *proj, const clsp_bins *bin
                                 int32_t n_views, const float *bg, float *image, float *T_final, uint32_t *n_contrib,
                                 void *state, size_t state_bytes, clsp_stream stream);
 
+/* clsp_render_forward followed by clsp_l1_loss_grad (below) in one pass: the forward
+ * also writes dL_dimage for the pixels it renders, from the colour it stores, and adds
+ * their loss to loss_sum (device float[1], accumulated +=; may be NULL).  image,
+ * T_final, n_contrib, state and dL_dimage get the same values as from the two calls
+ * (loss_sum up to float summation order); it saves the second call's launch and its
+ * read of the image.  target: planar [n_views][3][H][W] like image.
+ * Errors: as clsp_render_forward, plus target or dL_dimage NULL. */
+clsp_status clsp_render_forward_l1(const clsp_projected *proj, const clsp_bins *bins, const clsp_camera *cams,
+                                   int32_t n_views, const float *bg, const float *target, float *image,
+                                   float *T_final, uint32_t *n_contrib, void *state, size_t state_bytes,
+                                   float *dL_dimage, float *loss_sum, clsp_stream stream);
+
 /* ---------------------------------------------------------------------------------
  * L1 photometric loss gradient on the rendered tiles: dL_dimage = sign(image - target)
  * / (3 H W) (sign(0) = 0, full-image normalisation in every mode), zero elsewhere is NOT

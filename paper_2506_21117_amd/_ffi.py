@@ -21,7 +21,8 @@ BINS_COMPLETE, BINS_DEPTH_SLICED = 0, 1
 EXPORTED = (
     "clsp_version", "clsp_last_error", "clsp_project_preprocess", "clsp_project_preprocess_rows",
     "clsp_bin_and_sort_workspace_bytes",
-    "clsp_bin_and_sort", "clsp_render_state_bytes", "clsp_render_forward", "clsp_l1_loss_grad",
+    "clsp_bin_and_sort", "clsp_render_state_bytes", "clsp_render_forward", "clsp_render_forward_l1",
+    "clsp_l1_loss_grad",
     "clsp_render_backward_workspace_bytes",
     "clsp_render_backward", "clsp_masked_adam_step", "clsp_zero_grads",
 )
@@ -101,6 +102,10 @@ def load(path: Path | None = None):
     L.clsp_render_forward.restype = st
     L.clsp_render_forward.argtypes = [POINTER(Projected), POINTER(Bins), POINTER(Camera), c_int32, POINTER(c_float),
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    L.clsp_render_forward_l1.restype = st
+    L.clsp_render_forward_l1.argtypes = [POINTER(Projected), POINTER(Bins), POINTER(Camera), c_int32, POINTER(c_float),
+                                         c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p,
+                                         c_void_p]
     L.clsp_l1_loss_grad.restype = st
     L.clsp_l1_loss_grad.argtypes = [c_void_p, c_void_p, POINTER(Bins), POINTER(Camera), c_int32, c_void_p, c_void_p,
                                     c_void_p]

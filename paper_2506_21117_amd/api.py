@@ -273,6 +273,28 @@ def render_forward(proj, bins, cams, bg=(0.0, 0.0, 0.0), image=None, T_final=Non
     return image, T_final, n_contrib
 
 
+def render_forward_l1(proj, bins, cams, target, bg=(0.0, 0.0, 0.0), image=None, T_final=None, n_contrib=None,
+                      state=None, dL=None, loss_sum=None, stream=None):
+    """``render_forward`` and ``l1_loss_grad`` in one pass.  Returns (image, T_final,
+    n_contrib, dL)."""
+    V, H, W = len(cams), cams[0].height, cams[0].width
+    dev = proj.splat.device
+    image = torch.zeros(V, 3, H, W, dtype=torch.float32, device=dev) if image is None else image
+    T_final = torch.zeros(V, H, W, dtype=torch.float32, device=dev) if T_final is None else T_final
+    n_contrib = torch.zeros(V, H, W, dtype=torch.int32, device=dev) if n_contrib is None else n_contrib
+    dL = torch.zeros(V, 3, H, W, dtype=torch.float32, device=dev) if dL is None else dL
+    for t, shape in ((image, (V, 3, H, W)), (T_final, (V, H, W)), (n_contrib, (V, H, W)), (target, (V, 3, H, W)),
+                     (dL, (V, 3, H, W))):
+        if tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"tensor of shape {tuple(t.shape)}, expected contiguous {shape}")
+    bgc = (ctypes.c_float * 3)(*[float(x) for x in bg])
+    check(lib().clsp_render_forward_l1(ctypes.byref(proj.struct()), ctypes.byref(bins.struct()), camera_array(cams), V,
+                                       bgc, _ptr(target), _ptr(image), _ptr(T_final), _ptr(n_contrib), _ptr(state),
+                                       0 if state is None else state.numel(), _ptr(dL), _ptr(loss_sum),
+                                       _stream(stream)))
+    return image, T_final, n_contrib, dL
+
+
 def l1_loss_grad(image, target, bins, cams, dL=None, loss_sum=None, stream=None):
     if dL is None:
         dL = torch.zeros_like(image)

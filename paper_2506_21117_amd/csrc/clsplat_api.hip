@@ -236,6 +236,27 @@ clsp_status clsp_render_forward(const clsp_projected* proj, const clsp_bins* bin
                     "render_forward");
 }
 
+clsp_status clsp_render_forward_l1(const clsp_projected* proj, const clsp_bins* bins, const clsp_camera* cams,
+                                   int32_t n_views, const float* bg, const float* target, float* image, float* T_final,
+                                   uint32_t* n_contrib, void* state, size_t state_bytes, float* dL_dimage,
+                                   float* loss_sum, clsp_stream stream) {
+  CHECK(check_projected(proj));
+  CHECK(check_bins(bins));
+  CHECK(check_cams(cams, n_views));
+  if (!bg || !image || !T_final || !n_contrib || !target || !dL_dimage)
+    return fail(CLSP_ERR_INVALID_ARG, "render_forward_l1 input, output or bg is NULL");
+  const int W = cams[0].width, H = cams[0].height;
+  if (state && state_bytes < clsp_render_state_bytes(n_views, W, H))
+    return fail(CLSP_ERR_INVALID_ARG, "state of %zu bytes is smaller than the %zu needed", state_bytes,
+                clsp_render_state_bytes(n_views, W, H));
+  CHECK(check_bins_ws(bins, clsp::make_bin_plan(bins->n, n_views, W, H, bins->capacity)));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return hip_status(clsp::launch_render_forward(*proj, *bins, n_views, W, H, (W + CLSP_TILE - 1) / CLSP_TILE,
+                                                (H + CLSP_TILE - 1) / CLSP_TILE, bg, image, T_final, n_contrib,
+                                                state, s, target, dL_dimage, loss_sum),
+                    "render_forward_l1");
+}
+
 clsp_status clsp_l1_loss_grad(const float* image, const float* target, const clsp_bins* bins, const clsp_camera* cams,
                               int32_t n_views, float* dL_dimage, float* loss_sum, clsp_stream stream) {
   CHECK(check_bins(bins));

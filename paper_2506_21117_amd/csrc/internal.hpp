@@ -92,9 +92,12 @@ float* bin_carry(const BinPlan& p, char* ws);
 
 // render.hip
 size_t render_state_bytes(int views, int TX, int TY);
+// With dL given (target too) it also writes the L1 gradient of the rendered pixels and
+// adds their loss to *loss_sum (if given), as launch_l1_loss_grad would.
 hipError_t launch_render_forward(const clsp_projected& proj, const clsp_bins& bins, int views, int W, int H,
                                  int TX, int TY, const float bg[3], float* image, float* T_final,
-                                 uint32_t* n_contrib, void* state, hipStream_t s);
+                                 uint32_t* n_contrib, void* state, hipStream_t s, const float* target = nullptr,
+                                 float* dL = nullptr, float* loss_sum = nullptr);
 hipError_t launch_l1_loss_grad(const float* image, const float* target, const clsp_bins& bins, int views, int W,
                                int H, int TX, int TY, float* dL, float* loss_sum, hipStream_t s);
 hipError_t launch_render_backward(const clsp_projected& proj, const clsp_bins& bins, int views, int64_t n, int W,

@@ -120,6 +120,13 @@ __device__ __forceinline__ uint32_t list_entry(const uint32_t* __restrict__ valu
   return k < len1 ? values[r1.x + k] : values[r2.x + (k - len1)];
 }
 
+// Optional L1 loss gradient computed by the forward itself (dL NULL: none).
+struct L1Out {
+  const float* target;
+  float* dL;
+  float* loss_sum;
+};
+
 // PHASE 1 composites each rendered tile's first list (the whole list for complete
 // bins).  With `sliced`, tiles in which a pixel is still compositing at the end are
 // marked alive and their per-pixel state is saved in `carry`; PHASE 2 continues the
@@ -133,7 +140,7 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
     uint32_t* __restrict__ counters, int T,
     int TX, int W, int H, float bg0, float bg1, float bg2, float* __restrict__ image, float* __restrict__ T_final,
     uint32_t* __restrict__ n_contrib, void* state, int64_t slots, int sliced, uint32_t* __restrict__ alive,
-    uint32_t* __restrict__ alive_mask, int wpv, float* __restrict__ carry) {
+    uint32_t* __restrict__ alive_mask, int wpv, float* __restrict__ carry, L1Out l1) {
   const uint32_t slot = blockIdx.x;
   if (slot >= counters[C_TILES]) return;
   if (PHASE == 2 && (counters[C_OVERFLOW] || !alive[slot])) return;
@@ -243,8 +250,9 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
       j = jhi;
     }
   }
+  bool more = false;  // the second phase continues this tile
   if (PHASE == 1 && sliced) {
-    const bool more = __syncthreads_count(done) < NT;
+    more = __syncthreads_count(done) < NT;
     if (more) {
       // save the state; the second list continues this tile
       my_carry[0 * NT] = Tr;
@@ -276,14 +284,34 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
     __syncthreads();
     if (threadIdx.x == 0) sv.maxlast[slot] = s_max;
   }
+  const size_t hw = (size_t)H * W;
+  const size_t pix = (size_t)py * W + px;
+  const float col[3] = {fmaf(Tr, bg0, cr), fmaf(Tr, bg1, cg), fmaf(Tr, bg2, cb)};
   if (inside) {
-    const size_t hw = (size_t)H * W;
-    const size_t pix = (size_t)py * W + px;
-    image[((size_t)v * 3 + 0) * hw + pix] = fmaf(Tr, bg0, cr);
-    image[((size_t)v * 3 + 1) * hw + pix] = fmaf(Tr, bg1, cg);
-    image[((size_t)v * 3 + 2) * hw + pix] = fmaf(Tr, bg2, cb);
+    for (int c = 0; c < 3; ++c) image[((size_t)v * 3 + c) * hw + pix] = col[c];
     T_final[(size_t)v * hw + pix] = Tr;
     n_contrib[(size_t)v * hw + pix] = last;
+  }
+  // L1 gradient of the finished pixels (the same arithmetic as l1_loss_grad_kernel on
+  // the stored image); a tile the second phase continues is finished there
+  if (l1.dL && !more) {
+    const float norm = 1.0f / (3.0f * (float)W * (float)H);
+    float acc = 0.0f;
+    if (inside) {
+      for (int c = 0; c < 3; ++c) {
+        const size_t idx = ((size_t)v * 3 + c) * hw + pix;
+        const float d = col[c] - l1.target[idx];
+        l1.dL[idx] = d > 0.0f ? norm : (d < 0.0f ? -norm : 0.0f);
+        acc += fabsf(d);
+      }
+    }
+    if (l1.loss_sum) {
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      __syncthreads();  // s_c is free: the blending is over
+      if ((threadIdx.x & 63) == 0) s_c[threadIdx.x >> 6] = acc;
+      __syncthreads();
+      if (threadIdx.x == 0) atomicAdd(l1.loss_sum, (s_c[0] + s_c[1] + s_c[2] + s_c[3]) * norm);
+    }
   }
 }
 
@@ -535,7 +563,8 @@ size_t render_state_bytes(int views, int TX, int TY) {
 
 hipError_t launch_render_forward(const clsp_projected& proj, const clsp_bins& bins, int views, int W, int H, int TX,
                                  int TY, const float bg[3], float* image, float* T_final, uint32_t* n_contrib,
-                                 void* state, hipStream_t s) {
+                                 void* state, hipStream_t s, const float* target, float* dL, float* loss_sum) {
+  const L1Out l1{target, dL, loss_sum};
   const int T = TX * TY;
   const int blocks = views * T;
   const int sliced = bins.mode == CLSP_BINS_DEPTH_SLICED;
@@ -547,14 +576,14 @@ hipError_t launch_render_forward(const clsp_projected& proj, const clsp_bins& bi
   hipLaunchKernelGGL(render_forward_kernel<1>, dim3(blocks), dim3(NT), 0, s, proj.splat, bins.values, bins.keys,
                      reinterpret_cast<const uint2*>(bins.ranges), reinterpret_cast<uint2*>(bins.ranges2),
                      bins.tile_list, bins.counters, T, TX, W, H, bg[0], bg[1], bg[2], image, T_final, n_contrib, state,
-                     (int64_t)blocks, sliced, alive, bins.alive_mask, wpv, carry);
+                     (int64_t)blocks, sliced, alive, bins.alive_mask, wpv, carry, l1);
   if (!sliced) return hipGetLastError();
   hipError_t err = launch_list_second_slab(plan, proj, bins, ws, s);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(render_forward_kernel<2>, dim3(blocks), dim3(NT), 0, s, proj.splat, bins.values, bins.keys,
                      reinterpret_cast<const uint2*>(bins.ranges), reinterpret_cast<uint2*>(bins.ranges2),
                      bins.tile_list, bins.counters, T, TX, W, H, bg[0], bg[1], bg[2], image, T_final, n_contrib, state,
-                     (int64_t)blocks, sliced, alive, bins.alive_mask, wpv, carry);
+                     (int64_t)blocks, sliced, alive, bins.alive_mask, wpv, carry, l1);
   return hipGetLastError();
 }
 

@@ -2,7 +2,7 @@
 
 One step (one view, the 3D Gaussian Splatting convention) runs, all on one stream:
 project all Gaussians -> render mask and per-tile depth order (masked tiles only in
-local mode) -> forward render -> L1 loss gradient -> backward render and preprocess
+local mode) -> forward render with the L1 loss gradient -> backward render and preprocess
 backward for the change set -> masked Adam on the change set, which also clears the
 change set's gradient rows for the next step.  This is the local optimisation of CL-Splats (Sec. 3.3 "Local Optimization
 Kernel"; Supp. "3DGS Optimization in Changed Regions"); the full-scene step is the same
@@ -194,10 +194,10 @@ class SplatOptimizer:
         check(L.clsp_bin_and_sort(by(proj), cam, 1, self._range, use_mask, by(self._bins), st))
         mark("bin_and_sort", 1)
         mark("render_forward", 0)
-        check(L.clsp_render_forward(by(proj), by(self._bins), cam, 1, self._bg, P["image"], P["T"], P["nc"],
-                                    P["state"], self._sizes[2], st))
+        # the forward also writes the L1 loss gradient of the pixels it renders
+        check(L.clsp_render_forward_l1(by(proj), by(self._bins), cam, 1, self._bg, P["targets"][view], P["image"],
+                                       P["T"], P["nc"], P["state"], self._sizes[2], P["dL"], P["loss"], st))
         mark("render_forward", 1)
-        check(L.clsp_l1_loss_grad(P["image"], P["targets"][view], by(self._bins), cam, 1, P["dL"], P["loss"], st))
         mark("render_backward", 0)
         check(L.clsp_render_backward(by(self._g), by(proj), by(self._bins), cam, 1, self._bg, self._range, P["T"],
                                      P["nc"], P["state"], self._sizes[2], P["dL"], by(self._gr), P["bws"],

@@ -311,6 +311,41 @@ def test_l1_loss_grad_exact(dev):
     assert abs(float(loss) - ref_loss) <= 1e-5 * ref_loss
 
 
+@pytest.mark.parametrize("mode", [COMPLETE, api._ffi.BINS_DEPTH_SLICED])
+@pytest.mark.parametrize("case,local", [("cloud", False), ("cloud", True), ("local", True)])
+def test_forward_with_l1_equals_forward_then_l1(dev, mode, case, local):
+    """The forward's own L1 gradient (finished in the second phase for tiles that need
+    the second slab) equals the separate L1 call on the stored image, bit for bit."""
+    sc, cams, a = _sliced_case(case)
+    act = a if local else None
+    g = api.GaussianTensors.from_scene(sc, dev)
+    proj = gpu_preprocess(g, cams)
+    bg = (0.1, 0.2, 0.3)
+    V, H, W = len(cams), cams[0].height, cams[0].width
+    tgt = torch.rand(V, 3, H, W, generator=torch.Generator(device=dev).manual_seed(8), device=dev)
+    outs = []
+    for fused in (False, True):
+        bins = api.bin_and_sort(proj, cams, act, local, capacity=8_000_000, mode=mode)
+        state = api.render_state(cams, dev).zero_()   # chunks past a tile's end are not written
+        loss = torch.zeros(1, device=dev)
+        if fused:
+            img, T, nc, dL = api.render_forward_l1(proj, bins, cams, tgt, bg, state=state, loss_sum=loss)
+        else:
+            img, T, nc = api.render_forward(proj, bins, cams, bg, state=state)
+            dL = api.l1_loss_grad(img, tgt, bins, cams, loss_sum=loss)
+        torch.cuda.synchronize()
+        c = bins.read_counters()
+        assert not c["overflow"]
+        outs.append((to_np(img), to_np(T), to_np(nc), to_np(dL), float(loss), to_np(state), c))
+    (i0, T0, n0, d0, l0, s0, c0), (i1, T1, n1, d1, l1, s1, c1) = outs
+    for x, y in ((i0, i1), (T0, T1), (n0, n1), (d0, d1), (s0, s1)):
+        np.testing.assert_array_equal(x, y)
+    assert abs(l0 - l1) <= 1e-5 * abs(l0) and l0 > 0
+    assert np.count_nonzero(d1) > 0
+    if mode != COMPLETE and case == "cloud" and not local:
+        assert c1["alive"] > 0   # some pixels were finished by the second phase
+
+
 # ------------------------------------------------------------------ a6, a7 backward
 @pytest.mark.parametrize("case", CASES)
 @pytest.mark.parametrize("local", [False, True])
