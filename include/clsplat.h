@@ -21,6 +21,9 @@
  *   clsp_masked_adam_step    Adam on the rows of O^t only; other rows and their moments
  *                            are not touched
  *   clsp_zero_grads          clear the gradient rows of O^t
+ *   clsp_render_forward_l1, clsp_render_backward_adam, clsp_project_preprocess_rows
+ *                            fused or partial forms of the calls above, for the
+ *                            optimisation step
  *
  * Conventions shared by every call
  * --------------------------------
@@ -342,6 +345,23 @@ clsp_status clsp_masked_adam_step(const clsp_params *params, const clsp_params *
 
 /* Set the gradient rows in `active` to zero. */
 clsp_status clsp_zero_grads(const clsp_params *grads, clsp_range active, clsp_stream stream);
+
+/* One optimisation step's backward and Adam update for a single view in one call:
+ * clsp_zero_grads + clsp_render_backward (n_views = 1) + clsp_masked_adam_step
+ * (row_mask NULL) on the same rows, with no gradient buffer: the preprocess backward
+ * applies each row's Adam update from the gradients it has just computed, and rows
+ * and components without a gradient get Adam's update for a zero gradient.  params
+ * must describe the same arrays as g (which is read, then written); exp_avg and
+ * exp_avg_sq as for clsp_masked_adam_step (hp->zero_grads is ignored).  The results
+ * equal the three calls' bit for bit; it saves the Adam launch and the gradient
+ * buffer's writes and reads.
+ * Errors: as clsp_render_backward and clsp_masked_adam_step, plus n_views != 1. */
+clsp_status clsp_render_backward_adam(const clsp_gaussians *g, const clsp_projected *proj, const clsp_bins *bins,
+                                      const clsp_camera *cams, int32_t n_views, const float *bg, clsp_range active,
+                                      const float *T_final, const uint32_t *n_contrib, const void *state,
+                                      size_t state_bytes, const float *dL_dimage, const clsp_params *params,
+                                      const clsp_params *exp_avg, const clsp_params *exp_avg_sq,
+                                      const clsp_adam_hparams *hp, void *ws, size_t ws_bytes, clsp_stream stream);
 
 #ifdef __cplusplus
 }

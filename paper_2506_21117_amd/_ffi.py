@@ -24,7 +24,7 @@ EXPORTED = (
     "clsp_bin_and_sort", "clsp_render_state_bytes", "clsp_render_forward", "clsp_render_forward_l1",
     "clsp_l1_loss_grad",
     "clsp_render_backward_workspace_bytes",
-    "clsp_render_backward", "clsp_masked_adam_step", "clsp_zero_grads",
+    "clsp_render_backward", "clsp_masked_adam_step", "clsp_zero_grads", "clsp_render_backward_adam",
 )
 
 
@@ -120,6 +120,11 @@ def load(path: Path | None = None):
                                         c_void_p, POINTER(AdamHParams), c_void_p]
     L.clsp_zero_grads.restype = st
     L.clsp_zero_grads.argtypes = [POINTER(Params), Range, c_void_p]
+    L.clsp_render_backward_adam.restype = st
+    L.clsp_render_backward_adam.argtypes = [POINTER(Gaussians), POINTER(Projected), POINTER(Bins), POINTER(Camera),
+                                            c_int32, POINTER(c_float), Range, c_void_p, c_void_p, c_void_p, c_size_t,
+                                            c_void_p, POINTER(Params), POINTER(Params), POINTER(Params),
+                                            POINTER(AdamHParams), c_void_p, c_size_t, c_void_p]
     if path is None:
         _lib = L
     return L

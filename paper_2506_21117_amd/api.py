@@ -355,3 +355,25 @@ def masked_adam_step(params: GaussianTensors, grads, exp_avg, exp_avg_sq, active
     check(lib().clsp_masked_adam_step(ctypes.byref(params.as_params()), ctypes.byref(grads.as_params()),
                                       ctypes.byref(exp_avg.as_params()), ctypes.byref(exp_avg_sq.as_params()),
                                       _ffi.Range(a0, a1), _ptr(row_mask), ctypes.byref(hp), _stream(stream)))
+
+
+def render_backward_adam(g: GaussianTensors, proj, bins, cam, bg, active, T_final, n_contrib, state, dL, exp_avg,
+                         exp_avg_sq, step, lr=DEFAULT_LR, beta1=0.9, beta2=0.999, eps=1e-15, ws=None, stream=None):
+    """One view's backward and one Adam step of the rows in ``active`` (``g`` is updated
+    in place): zero_grads + render_backward + masked_adam_step in one call, without a
+    gradient buffer."""
+    a0, a1 = (0, g.n) if active is None else (int(active[0]), int(active[1]))
+    if ws is None:
+        ws = render_backward_workspace(a1 - a0, 1, g.means.device)
+    bgc = (ctypes.c_float * 3)(*[float(x) for x in bg])
+    hp = _ffi.AdamHParams()
+    hp.lr = (ctypes.c_float * 6)(*[float(x) for x in lr])
+    hp.beta1, hp.beta2, hp.eps, hp.step = float(beta1), float(beta2), float(eps), int(step)
+    check(lib().clsp_render_backward_adam(ctypes.byref(g.as_gaussians()), ctypes.byref(proj.struct()),
+                                          ctypes.byref(bins.struct()), camera_array([cam]), 1, bgc,
+                                          _ffi.Range(a0, a1), _ptr(T_final), _ptr(n_contrib), _ptr(state),
+                                          0 if state is None else state.numel(), _ptr(dL),
+                                          ctypes.byref(g.as_params()), ctypes.byref(exp_avg.as_params()),
+                                          ctypes.byref(exp_avg_sq.as_params()), ctypes.byref(hp), _ptr(ws), ws.numel(),
+                                          _stream(stream)))
+    return g

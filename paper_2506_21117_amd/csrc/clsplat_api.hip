@@ -336,6 +336,63 @@ clsp_status clsp_masked_adam_step(const clsp_params* params, const clsp_params* 
                     "masked_adam_step");
 }
 
+clsp_status clsp_render_backward_adam(const clsp_gaussians* g, const clsp_projected* proj, const clsp_bins* bins,
+                                      const clsp_camera* cams, int32_t n_views, const float* bg, clsp_range active,
+                                      const float* T_final, const uint32_t* n_contrib, const void* state,
+                                      size_t state_bytes, const float* dL_dimage, const clsp_params* params,
+                                      const clsp_params* exp_avg, const clsp_params* exp_avg_sq,
+                                      const clsp_adam_hparams* hp, void* ws, size_t ws_bytes, clsp_stream stream) {
+  CHECK(check_gaussians(g));
+  if (g->gather) return fail(CLSP_ERR_INVALID_ARG, "render_backward_adam needs un-gathered parameters");
+  CHECK(check_projected(proj));
+  CHECK(check_bins(bins));
+  CHECK(check_cams(cams, n_views));
+  if (n_views != 1) return fail(CLSP_ERR_INVALID_ARG, "render_backward_adam takes one view (n_views=%d)", n_views);
+  CHECK(check_params(params, "params"));
+  CHECK(check_params(exp_avg, "exp_avg"));
+  CHECK(check_params(exp_avg_sq, "exp_avg_sq"));
+  CHECK(check_range(active, g->n));
+  if (params->n != g->n || params->sh_degree != g->sh_degree || exp_avg->n != g->n || exp_avg_sq->n != g->n ||
+      exp_avg->sh_degree != g->sh_degree || exp_avg_sq->sh_degree != g->sh_degree)
+    return fail(CLSP_ERR_INVALID_ARG, "params and moments differ in layout from the parameters");
+  if (!hp) return fail(CLSP_ERR_INVALID_ARG, "hparams is NULL");
+  if (!hp->step_device && hp->step < 1) return fail(CLSP_ERR_INVALID_ARG, "step must be >= 1");
+  if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f && hp->beta2 >= 0.f && hp->beta2 < 1.f && hp->eps >= 0.f))
+    return fail(CLSP_ERR_INVALID_ARG, "invalid Adam betas or eps");
+  if (!bg || !T_final || !n_contrib || !dL_dimage)
+    return fail(CLSP_ERR_INVALID_ARG, "render_backward_adam input is NULL");
+  if (!state || state_bytes < clsp_render_state_bytes(n_views, cams[0].width, cams[0].height))
+    return fail(CLSP_ERR_INVALID_ARG, "render_backward_adam needs the forward's state (%zu bytes)",
+                clsp_render_state_bytes(n_views, cams[0].width, cams[0].height));
+  const int64_t na = active.end - active.begin;
+  const size_t need = clsp_render_backward_workspace_bytes(na, n_views);
+  if (na > 0 && (!ws || ws_bytes < need))
+    return fail(CLSP_ERR_INVALID_ARG, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+  if (na == 0) return CLSP_OK;
+  const int W = cams[0].width, H = cams[0].height;
+  const int TX = (W + CLSP_TILE - 1) / CLSP_TILE, TY = (H + CLSP_TILE - 1) / CLSP_TILE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  float* g2d = static_cast<float*>(ws);
+  CHECK(hip_status(clsp::launch_render_backward(*proj, *bins, n_views, g->n, W, H, TX, TY, bg, active.begin,
+                                                active.end, T_final, n_contrib, const_cast<void*>(state), dL_dimage,
+                                                g2d, s),
+                   "render_backward_adam"));
+  clsp::FusedAdam A;
+  A.P = mut_params(params);
+  A.M = mut_params(exp_avg);
+  A.V = mut_params(exp_avg_sq);
+  for (int k = 0; k < 6; ++k) A.lr[k] = hp->lr[k];
+  A.b1 = hp->beta1;
+  A.b2 = hp->beta2;
+  A.eps = hp->eps;
+  A.bc1 = (float)(1.0 - pow((double)hp->beta1, (double)hp->step));
+  A.bc2 = (float)(1.0 - pow((double)hp->beta2, (double)hp->step));
+  A.step_dev = hp->step_device;
+  return hip_status(clsp::launch_preprocess_backward_adam(raw_params(g), dev_cam(cams[0]), active.begin, active.end,
+                                                          proj->flags, g2d, A, s),
+                    "render_backward_adam");
+}
+
 clsp_status clsp_zero_grads(const clsp_params* grads, clsp_range active, clsp_stream stream) {
   CHECK(check_params(grads, "grads"));
   CHECK(check_range(active, grads->n));

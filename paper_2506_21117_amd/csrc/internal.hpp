@@ -66,6 +66,17 @@ hipError_t launch_preprocess(const RawParams& g, const DevCam& cam, int view, in
 hipError_t launch_preprocess_backward(const RawParams& g, const DevCam& cam, int view, int64_t a0, int64_t a1,
                                       const uint32_t* flags, const float* grad2d, const MutParams& grads,
                                       hipStream_t s);
+// One view's preprocess backward followed by one Adam step of rows [a0, a1).
+struct FusedAdam {
+  MutParams P, M, V;
+  float lr[6];
+  float b1, b2, eps;
+  float bc1, bc2;            // 1 - beta^step (host step count)
+  const int32_t* step_dev;   // device step count, or null
+};
+hipError_t launch_preprocess_backward_adam(const RawParams& g, const DevCam& cam, int64_t a0, int64_t a1,
+                                           const uint32_t* flags, const float* grad2d, const FusedAdam& A,
+                                           hipStream_t s);
 
 // binning.hip
 struct BinPlan {

@@ -245,12 +245,15 @@ __global__ void __launch_bounds__(256) preprocess_kernel(RawParams g, DevCam cam
   flags[e] = fl;
 }
 
-// Chain rule for the changed Gaussians [a0, a1) of one view; adds into grads.
-__global__ void __launch_bounds__(128) preprocess_backward_kernel(RawParams g, DevCam cam, int view, int64_t a0,
-                                                                  int64_t a1, const uint32_t* __restrict__ flags,
-                                                                  const float* __restrict__ grad2d, MutParams out) {
-  const int64_t i = a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a1) return;
+// Chain rule for changed Gaussian i (in [a0, a1)) of one view: hands each parameter
+// component's gradient to put(c, value) once, c over the flat list means[3],
+// log_scales[3], quats[4], opacity, sh[3K] (sh coefficient k of channel ch is
+// 11 + 3k + ch); components without a gradient (invisible, clamped channel, no
+// screen-space gradient) are not handed over.
+template <class Put>
+__device__ __forceinline__ void backward_row(const RawParams& g, const DevCam& cam, int view, int64_t i, int64_t a0,
+                                             int64_t a1, const uint32_t* __restrict__ flags,
+                                             const float* __restrict__ grad2d, Put put) {
   const int64_t e = (int64_t)view * g.n + i;
   const uint32_t fl = flags[e];
   if (!(fl & CLSP_FLAG_VISIBLE)) return;
@@ -266,7 +269,6 @@ __global__ void __launch_bounds__(128) preprocess_backward_kernel(RawParams g, D
   Geo q;
   load_geo(g, row, cam, q);
   const int64_t nr = g.n_rows;
-  const int64_t no = out.n;
   const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
 
   float dmu[3] = {0.f, 0.f, 0.f};
@@ -284,7 +286,7 @@ __global__ void __launch_bounds__(128) preprocess_backward_kernel(RawParams g, D
       float coef[16];
       for (int k = 0; k < K; ++k) {
         coef[k] = g.sh[((int64_t)k * 3 + ch) * nr + row];
-        out.sh[((int64_t)k * 3 + ch) * no + i] += gpre * Yb[k];
+        put(11 + k * 3 + ch, gpre * Yb[k]);
       }
       float gx, gy, gz;
       sh_eval_grad(d[0], d[1], d[2], K, coef, gx, gy, gz);
@@ -298,7 +300,7 @@ __global__ void __launch_bounds__(128) preprocess_backward_kernel(RawParams g, D
   }
 
   // opacity
-  out.opac[i] += go * q.o * (1.0f - q.o);
+  put(10, go * q.o * (1.0f - q.o));
 
   // conic -> screen covariance: G2 = -K GK K with GK = [[gA, gB/2], [gB/2, gC]]
   const float h = 0.5f * gB;
@@ -327,7 +329,7 @@ __global__ void __launch_bounds__(128) preprocess_backward_kernel(RawParams g, D
   float gR[9];
   for (int k = 0; k < 3; ++k) {
     const float acc = gW[k] * q.Rq[k] + gW[3 + k] * q.Rq[3 + k] + gW[6 + k] * q.Rq[6 + k];
-    out.log_scales[k * no + i] += acc * q.s[k];
+    put(3 + k, acc * q.s[k]);
     gR[k] = gW[k] * q.s[k];
     gR[3 + k] = gW[3 + k] * q.s[k];
     gR[6 + k] = gW[6 + k] * q.s[k];
@@ -340,10 +342,10 @@ __global__ void __launch_bounds__(128) preprocess_backward_kernel(RawParams g, D
     const float gy = 2.0f * (x * (gR[1] + gR[3]) + w * (gR[2] - gR[6]) + z * (gR[5] + gR[7])) - 4.0f * y * (gR[0] + gR[8]);
     const float gz = 2.0f * (w * (gR[3] - gR[1]) + x * (gR[2] + gR[6]) + y * (gR[5] + gR[7])) - 4.0f * z * (gR[0] + gR[4]);
     const float dot = w * gw + x * gx + y * gy + z * gz;
-    out.quats[i] += (gw - w * dot) * q.qinv;
-    out.quats[no + i] += (gx - x * dot) * q.qinv;
-    out.quats[2 * no + i] += (gy - y * dot) * q.qinv;
-    out.quats[3 * no + i] += (gz - z * dot) * q.qinv;
+    put(6, (gw - w * dot) * q.qinv);
+    put(7, (gx - x * dot) * q.qinv);
+    put(8, (gy - y * dot) * q.qinv);
+    put(9, (gz - z * dot) * q.qinv);
   }
   // M = J Rcam: dJ = dM Rcam^T (only the four non-zero entries of J matter)
   const float gJ00 = gM[0] * cam.R[0] + gM[1] * cam.R[1] + gM[2] * cam.R[2];
@@ -372,9 +374,63 @@ __global__ void __launch_bounds__(128) preprocess_backward_kernel(RawParams g, D
   gZ -= (gu * cam.fx * q.X + gv * cam.fy * q.Y) * iz2;
   // p = Rcam mu + t
   for (int k = 0; k < 3; ++k) dmu[k] += cam.R[k] * gX + cam.R[3 + k] * gY + cam.R[6 + k] * gZ;
-  out.means[i] += dmu[0];
-  out.means[no + i] += dmu[1];
-  out.means[2 * no + i] += dmu[2];
+  put(0, dmu[0]);
+  put(1, dmu[1]);
+  put(2, dmu[2]);
+}
+
+// Component c of row i of a parameter set (the flat order of backward_row).
+__device__ __forceinline__ float* param_comp(const MutParams& X, int c, int64_t i) {
+  const int64_t n = X.n;
+  if (c < 3) return X.means + c * n + i;
+  if (c < 6) return X.log_scales + (c - 3) * n + i;
+  if (c < 10) return X.quats + (c - 6) * n + i;
+  if (c == 10) return X.opac + i;
+  return X.sh + (int64_t)(c - 11) * n + i;
+}
+
+// Chain rule for the changed Gaussians [a0, a1) of one view; adds into grads.
+__global__ void __launch_bounds__(128) preprocess_backward_kernel(RawParams g, DevCam cam, int view, int64_t a0,
+                                                                  int64_t a1, const uint32_t* __restrict__ flags,
+                                                                  const float* __restrict__ grad2d, MutParams out) {
+  const int64_t i = a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a1) return;
+  backward_row(g, cam, view, i, a0, a1, flags, grad2d, [&](int c, float v) { *param_comp(out, c, i) += v; });
+}
+
+// The same for a single view, followed by one Adam step of the row with those
+// gradients (the rest zero), exactly as zeroed gradients + the kernel above + the Adam
+// kernel would do it.
+__global__ void __launch_bounds__(128) preprocess_backward_adam_kernel(RawParams g, DevCam cam, int64_t a0,
+                                                                       int64_t a1, const uint32_t* __restrict__ flags,
+                                                                       const float* __restrict__ grad2d, FusedAdam A) {
+  const int64_t i = a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a1) return;
+  float bc1 = A.bc1, bc2 = A.bc2;
+  if (A.step_dev) {
+    const float t = (float)max(*A.step_dev, 1);
+    bc1 = 1.0f - powf(A.b1, t);
+    bc2 = 1.0f - powf(A.b2, t);
+  }
+  auto step = [&](int c, float gg) {
+    const int grp = c < 3 ? 0 : c < 6 ? 1 : c < 10 ? 2 : c == 10 ? 3 : c < 14 ? 4 : 5;
+    float* m = param_comp(A.M, c, i);
+    float* v = param_comp(A.V, c, i);
+    float* p = param_comp(A.P, c, i);
+    const float mm = A.b1 * (*m) + (1.0f - A.b1) * gg;
+    const float vv = A.b2 * (*v) + (1.0f - A.b2) * gg * gg;
+    *m = mm;
+    *v = vv;
+    *p -= A.lr[grp] * (mm / bc1) / (sqrtf(vv / bc2) + A.eps);
+  };
+  uint64_t got = 0;  // components updated with their gradient
+  backward_row(g, cam, 0, i, a0, a1, flags, grad2d, [&](int c, float v) {
+    step(c, 0.0f + v);  // the gradient as the separate calls see it: 0 + v
+    got |= 1ull << c;
+  });
+  const int C = 11 + 3 * (A.P.sh_degree + 1) * (A.P.sh_degree + 1);
+  for (int c = 0; c < C; ++c)
+    if (!((got >> c) & 1ull)) step(c, 0.0f);
 }
 
 }  // namespace
@@ -385,6 +441,15 @@ hipError_t launch_preprocess(const RawParams& g, const DevCam& cam, int view, in
   const int blocks = ceil_div(r1 - r0, 256);
   hipLaunchKernelGGL(preprocess_kernel, dim3(blocks), dim3(256), 0, s, g, cam, view, r0, r1, splat, depth,
                      reinterpret_cast<uint2*>(rect), flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_backward_adam(const RawParams& g, const DevCam& cam, int64_t a0, int64_t a1,
+                                           const uint32_t* flags, const float* grad2d, const FusedAdam& A,
+                                           hipStream_t s) {
+  if (a1 <= a0) return hipSuccess;
+  hipLaunchKernelGGL(preprocess_backward_adam_kernel, dim3(ceil_div(a1 - a0, 128)), dim3(128), 0, s, g, cam, a0, a1,
+                     flags, grad2d, A);
   return hipGetLastError();
 }
 

@@ -2,9 +2,10 @@
 
 One step (one view, the 3D Gaussian Splatting convention) runs, all on one stream:
 project all Gaussians -> render mask and per-tile depth order (masked tiles only in
-local mode) -> forward render with the L1 loss gradient -> backward render and preprocess
-backward for the change set -> masked Adam on the change set, which also clears the
-change set's gradient rows for the next step.  This is the local optimisation of CL-Splats (Sec. 3.3 "Local Optimization
+local mode) -> forward render with the L1 loss gradient -> backward render, then the
+preprocess backward for the change set, which in local steps applies each changed
+row's Adam update from the gradients it has just computed (full steps: a separate
+masked Adam call, which also clears the gradient rows for the next step).  This is the local optimisation of CL-Splats (Sec. 3.3 "Local Optimization
 Kernel"; Supp. "3DGS Optimization in Changed Regions"); the full-scene step is the same
 with no mask and every row active.
 """
@@ -40,7 +41,8 @@ class SplatOptimizer:
         self.lr = lr
         dev = params.means.device
         W, H = self.cams[0].width, self.cams[0].height
-        self.grads = params.zeros_like()
+        # full steps keep a gradient buffer for the separate Adam call (see step())
+        self.grads = None if self.local else params.zeros_like()
         self.m = params.zeros_like()
         self.v = params.zeros_like()
         self.proj = api.ProjectedBuffers.alloc(self.n, 1, dev)
@@ -93,7 +95,6 @@ class SplatOptimizer:
         self._cams = [api.camera_array([c]) for c in self.cams]
         self._g = self.params.as_gaussians()
         self._pp = self.params.as_params()
-        self._gr = self.grads.as_params()
         self._m = self.m.as_params()
         self._v = self.v.as_params()
         self._proj = self.proj.struct()
@@ -104,9 +105,9 @@ class SplatOptimizer:
         self._hp = _ffi.AdamHParams()
         self._hp.lr = (ctypes.c_float * 6)(*[float(x) for x in self.lr])
         self._hp.beta1, self._hp.beta2, self._hp.eps = 0.9, 0.999, 1e-15
-        # Adam clears the gradient rows it used, so every step starts from zero gradients
-        # (they start at zero) without a separate clearing launch
+        # the separate Adam call clears the gradient rows it used (full steps)
         self._hp.zero_grads = 1
+        self._gr = None if self.grads is None else self.grads.as_params()
         p = lambda t: ctypes.c_void_p(t.data_ptr())
         self._ptrs = {"image": p(self.image), "T": p(self.T), "nc": p(self.nc), "dL": p(self.dL),
                       "loss": p(self.loss_sum), "ws": p(self.bins.ws), "bws": p(self.bwd_ws), "state": p(self.state),
@@ -198,12 +199,21 @@ class SplatOptimizer:
         check(L.clsp_render_forward_l1(by(proj), by(self._bins), cam, 1, self._bg, P["targets"][view], P["image"],
                                        P["T"], P["nc"], P["state"], self._sizes[2], P["dL"], P["loss"], st))
         mark("render_forward", 1)
-        mark("render_backward", 0)
-        check(L.clsp_render_backward(by(self._g), by(proj), by(self._bins), cam, 1, self._bg, self._range, P["T"],
-                                     P["nc"], P["state"], self._sizes[2], P["dL"], by(self._gr), P["bws"],
-                                     self._sizes[1], st))
-        mark("render_backward", 1)
         self.step_count += 1
         self._hp.step = self.step_count
-        check(L.clsp_masked_adam_step(by(self._pp), by(self._gr), by(self._m), by(self._v), self._range, None,
-                                      by(self._hp), st))
+        mark("render_backward", 0)
+        if self.local:
+            # the preprocess backward applies each changed row's Adam update from the
+            # gradients it has just computed (no gradient buffer, no Adam launch)
+            check(L.clsp_render_backward_adam(by(self._g), by(proj), by(self._bins), cam, 1, self._bg, self._range,
+                                              P["T"], P["nc"], P["state"], self._sizes[2], P["dL"], by(self._pp),
+                                              by(self._m), by(self._v), by(self._hp), P["bws"], self._sizes[1], st))
+            mark("render_backward", 1)
+        else:
+            # every row: Adam's own kernel streams the rows faster than the fused update
+            check(L.clsp_render_backward(by(self._g), by(proj), by(self._bins), cam, 1, self._bg, self._range,
+                                         P["T"], P["nc"], P["state"], self._sizes[2], P["dL"], by(self._gr), P["bws"],
+                                         self._sizes[1], st))
+            mark("render_backward", 1)
+            check(L.clsp_masked_adam_step(by(self._pp), by(self._gr), by(self._m), by(self._v), self._range, None,
+                                          by(self._hp), st))

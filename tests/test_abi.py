@@ -97,6 +97,17 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
         assert L.clsp_project_preprocess_rows(ctypes.byref(g), cam, 1, _ffi.Range(r0, r1), ctypes.byref(proj),
                                               None) == _ffi.CLSP_ERR_INVALID_ARG
     assert b"rows" in L.clsp_last_error()
+    # the fused backward + Adam call takes one view
+    prm = _ffi.Params(fake, fake, fake, fake, fake, 10, 0)
+    hp = _ffi.AdamHParams()
+    hp.step, hp.beta1, hp.beta2 = 1, 0.9, 0.999
+    bins1 = _ffi.Bins(fake, fake, fake, fake, fake, fake, fake, fake, fake, 1 << 20, 100, 10, 1, 0)
+    same = (_ffi.Camera * 2)(cam[0], cam[0])
+    assert L.clsp_render_backward_adam(ctypes.byref(g), ctypes.byref(proj), ctypes.byref(bins1), same, 2, None,
+                                       _ffi.Range(0, 10), fake, fake, fake, 1 << 30, fake, ctypes.byref(prm),
+                                       ctypes.byref(prm), ctypes.byref(prm), ctypes.byref(hp), fake, 1 << 30,
+                                       None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert b"one view" in L.clsp_last_error()
 
     ws_need = L.clsp_bin_and_sort_workspace_bytes(10, 1, 64, 48, 100)
     bins = _ffi.Bins(fake, fake, fake, fake, fake, fake, fake, fake, fake, ws_need, 100, 10, 1, 0)

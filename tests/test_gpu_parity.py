@@ -428,6 +428,54 @@ def test_local_step_equals_full_step_on_gpu(dev):
         np.testing.assert_allclose(gl, gf, rtol=1e-4, atol=1e-6 * scale)
 
 
+@pytest.mark.parametrize("case,local", [("sh3", True), ("sh3", False), ("tiny", True)])
+def test_backward_adam_equals_backward_then_adam(dev, case, local):
+    """clsp_render_backward_adam equals zero_grads + render_backward + masked_adam_step
+    over three steps (so the moments are not trivial) up to the float summation order
+    of the raster backward's atomics, which differs between any two runs: nearly every
+    element is equal within 1e-5 relative, none is off by more than a few learning
+    rates (a wrong component, learning-rate group or missed zero-gradient update would
+    move many elements by a learning rate or more)."""
+    sc, cams = workload(case)
+    cam = cams[0]
+    n = sc.n
+    a = (n // 2, n) if local else (0, n)
+    bg = (0.1, 0.2, 0.3)
+    tgt = torch.rand(1, 3, cam.height, cam.width, generator=torch.Generator(device=dev).manual_seed(6), device=dev)
+    runs = []
+    for fused in (False, True):
+        g = api.GaussianTensors.from_scene(sc, dev)
+        m, v, grads = g.zeros_like(), g.zeros_like(), g.zeros_like()
+        for step in (1, 2, 3):
+            proj = gpu_preprocess(g, [cam])
+            bins = api.bin_and_sort(proj, [cam], a if local else None, use_mask=local, capacity=400_000)
+            state = api.render_state([cam], dev)
+            img, T, nc, dL = api.render_forward_l1(proj, bins, [cam], tgt, bg, state=state)
+            if fused:
+                api.render_backward_adam(g, proj, bins, cam, bg, a, T, nc, state, dL, m, v, step)
+            else:
+                api.zero_grads(grads, a)
+                api.render_backward(g, proj, bins, [cam], bg, a, T, nc, state, dL, grads)
+                api.masked_adam_step(g, grads, m, v, a, step)
+        torch.cuda.synchronize()
+        runs.append((g, m, v))
+    (g0, m0, v0), (g1, m1, v1) = runs
+    moved = 0
+    for k in api.GaussianTensors.NAMES:
+        for name, x, y, bound in (("params", g0, g1, 6 * max(api.DEFAULT_LR)), ("m", m0, m1, None),
+                                  ("v", v0, v1, None)):
+            a_, b_ = to_np(getattr(x, k)).astype(np.float64), to_np(getattr(y, k)).astype(np.float64)
+            d = np.abs(a_ - b_)
+            close = d <= 1e-5 * np.abs(a_) + 1e-6 * (np.abs(a_).max() + 1e-30)
+            assert close.mean() >= 0.995, (name, k, float(close.mean()))
+            if bound is not None:
+                assert d.max() <= bound, (name, k, float(d.max()))
+            else:
+                assert d.max() <= 0.05 * (np.abs(a_).max() + 1e-30), (name, k, float(d.max()))
+        moved += int((to_np(getattr(m1, k)) != 0).sum())
+    assert moved > 0
+
+
 # ------------------------------------------------------------------ a8 masked Adam
 @pytest.mark.parametrize("sh_degree", [0, 3])
 @pytest.mark.parametrize("with_mask", [False, True])
