@@ -222,8 +222,8 @@ def main():
 # They describe the kernels whose sources hash to `source_sha256` and are reported only
 # while the sources still do (profiles/traffic_local_step_1M_1280x720.txt).
 MEASURED_TRAFFIC = {
-    "source_sha256": "82d51947c0da2a0c51ca3ed8ca3f633e54953a473cb50aec1013780c76ebf6b8",
-    "bytes": {"bin_and_sort": 210.012e6, "render_forward": 14.438e6, "render_backward": 16.510e6},
+    "source_sha256": "443556d416143781caf3b63fc799e4fe0661c49cff71ca5d5551699b6373dd43",
+    "bytes": {"bin_and_sort": 209.797e6, "render_forward": 17.211e6, "render_backward": 17.183e6},
 }
 
 
@@ -381,11 +381,14 @@ def cpu_baseline(sc, cams, a, scene_gt, order, budget_s, log):
 
 
 # ---- summaries of rocprofv3 output (host only) ----------------------------------------
-# A step of this script's timed loop starts at preprocess_kernel and ends at adam_kernel.
-# Within it the C-ABI calls are: bin_and_sort = the kernels after preprocess_kernel up to
-# the first render_forward_kernel<1>; render_forward = that one up to the last
-# render_forward_kernel (the second depth slab's listing runs between the two phases);
-# render_backward = the kernels after l1_loss_grad_kernel up to preprocess_backward_kernel.
+# A step of this script's timed loop starts at preprocess_kernel and ends with the Adam
+# update: adam_kernel (full steps), or preprocess_backward_adam_kernel, which holds it
+# (local steps).  Within it the C-ABI calls are: bin_and_sort = the kernels after
+# preprocess_kernel up to the first render_forward_kernel<1>; render_forward = that one
+# up to the last render_forward_kernel (the second depth slab's listing runs between the
+# two phases; local steps compute the L1 gradient inside the forward); render_backward =
+# the kernels after l1_loss_grad_kernel (or after the forward) up to the preprocess
+# backward.
 CALLS = ("bin_and_sort", "render_forward", "render_backward")
 
 
@@ -403,15 +406,16 @@ def split_steps(seq, k):
         s1 = starts[j + 1] if j + 1 < len(starts) else len(seq)
         st = seq[s0:s1]
         names = [x[0] for x in st]
-        if "adam_kernel" not in names:
+        ends = [i for i, nm in enumerate(names) if nm in ("adam_kernel", "preprocess_backward_adam_kernel")]
+        if not ends:
             continue
-        st = st[:names.index("adam_kernel") + 1]
+        st = st[:ends[0] + 1]
         names = names[:len(st)]
         try:
             i_f1 = names.index("render_forward_kernel<1>")
             i_f2 = max(i for i, nm in enumerate(names) if nm.startswith("render_forward_kernel"))
-            i_l1 = names.index("l1_loss_grad_kernel")
-            i_pb = names.index("preprocess_backward_kernel")
+            i_l1 = names.index("l1_loss_grad_kernel") if "l1_loss_grad_kernel" in names else i_f2
+            i_pb = max(i for i, nm in enumerate(names) if nm.startswith("preprocess_backward"))
         except ValueError:
             continue
         out.append((st, {"bin_and_sort": st[1:i_f1], "render_forward": st[i_f1:i_f2 + 1],

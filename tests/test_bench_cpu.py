@@ -137,3 +137,19 @@ def test_traffic_summary_scales_by_the_copy_calibration(tmp_path):
     assert rows["render_backward"][0] == round(31 * 1024 * 2 / 1e6, 3)
     step_fetch = (100 + 1 + 10 + 1 + 1 + 20 + 1 + 30 + 1 + 5) * 1024 * 2 / 1e6
     assert rows["step"][0] == round(step_fetch, 3)
+
+
+def test_step_split_of_a_fused_local_step():
+    """Local steps compute the L1 gradient in the forward and Adam in the preprocess
+    backward: the step ends there and the backward call starts after the forward."""
+    names = ["preprocess_kernel", "count_kernel", "emit_kernel<true, true>", "render_forward_kernel<1>",
+             "recount_kernel", "render_forward_kernel<2>", "fill_u32_kernel", "render_backward_kernel",
+             "preprocess_backward_adam_kernel"]
+    seq = [(n, 1000 * i, 1000 * i + 500, 500) for i, n in enumerate(names * 2)]
+    steps = bench.split_steps(seq, 10)
+    assert len(steps) == 2
+    disp, calls = steps[0]
+    assert [x[0] for x in disp] == names
+    assert [x[0] for x in calls["bin_and_sort"]] == ["count_kernel", "emit_kernel<true, true>"]
+    assert [x[0] for x in calls["render_forward"]] == names[3:6]
+    assert [x[0] for x in calls["render_backward"]] == names[6:]
