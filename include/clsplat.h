@@ -353,8 +353,12 @@ clsp_status clsp_zero_grads(const clsp_params *grads, clsp_range active, clsp_st
  * and components without a gradient get Adam's update for a zero gradient.  params
  * must describe the same arrays as g (which is read, then written); exp_avg and
  * exp_avg_sq as for clsp_masked_adam_step (hp->zero_grads is ignored).  The results
- * equal the three calls' bit for bit; it saves the Adam launch and the gradient
- * buffer's writes and reads.
+ * equal the three calls' up to the summation order of the raster backward's float
+ * atomics; it saves the Adam launch and the gradient buffer's writes and reads.
+ * ws (clsp_render_backward_workspace_bytes(active.end - active.begin, 1) bytes) must be
+ * all zero on entry, e.g. zero-filled once when allocated: the call leaves it all zero,
+ * so it needs no clearing launch of its own (a workspace last used by
+ * clsp_render_backward must be cleared first).
  * Errors: as clsp_render_backward and clsp_masked_adam_step, plus n_views != 1. */
 clsp_status clsp_render_backward_adam(const clsp_gaussians *g, const clsp_projected *proj, const clsp_bins *bins,
                                       const clsp_camera *cams, int32_t n_views, const float *bg, clsp_range active,

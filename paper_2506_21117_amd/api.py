@@ -306,8 +306,9 @@ def l1_loss_grad(image, target, bins, cams, dL=None, loss_sum=None, stream=None)
 
 
 def render_backward_workspace(n_active, views, device):
+    """Zero-filled (render_backward_adam needs a zero workspace and leaves it zero)."""
     b = lib().clsp_render_backward_workspace_bytes(int(n_active), int(views))
-    return torch.empty(max(1, b), dtype=torch.uint8, device=device)
+    return torch.zeros(max(1, b), dtype=torch.uint8, device=device)
 
 
 def render_backward(g: GaussianTensors, proj, bins, cams, bg, active, T_final, n_contrib, state, dL,
@@ -361,7 +362,8 @@ def render_backward_adam(g: GaussianTensors, proj, bins, cam, bg, active, T_fina
                          exp_avg_sq, step, lr=DEFAULT_LR, beta1=0.9, beta2=0.999, eps=1e-15, ws=None, stream=None):
     """One view's backward and one Adam step of the rows in ``active`` (``g`` is updated
     in place): zero_grads + render_backward + masked_adam_step in one call, without a
-    gradient buffer."""
+    gradient buffer.  ``ws`` must be zero (as ``render_backward_workspace`` returns it);
+    the call leaves it zero, so one workspace serves every step."""
     a0, a1 = (0, g.n) if active is None else (int(active[0]), int(active[1]))
     if ws is None:
         ws = render_backward_workspace(a1 - a0, 1, g.means.device)

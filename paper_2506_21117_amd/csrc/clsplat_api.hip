@@ -373,9 +373,10 @@ clsp_status clsp_render_backward_adam(const clsp_gaussians* g, const clsp_projec
   const int TX = (W + CLSP_TILE - 1) / CLSP_TILE, TY = (H + CLSP_TILE - 1) / CLSP_TILE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   float* g2d = static_cast<float*>(ws);
+  // the workspace is zero on entry (and left zero below): no clearing launch
   CHECK(hip_status(clsp::launch_render_backward(*proj, *bins, n_views, g->n, W, H, TX, TY, bg, active.begin,
                                                 active.end, T_final, n_contrib, const_cast<void*>(state), dL_dimage,
-                                                g2d, s),
+                                                g2d, s, false),
                    "render_backward_adam"));
   clsp::FusedAdam A;
   A.P = mut_params(params);

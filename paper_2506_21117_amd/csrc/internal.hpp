@@ -114,7 +114,7 @@ hipError_t launch_l1_loss_grad(const float* image, const float* target, const cl
 hipError_t launch_render_backward(const clsp_projected& proj, const clsp_bins& bins, int views, int64_t n, int W,
                                   int H, int TX, int TY, const float bg[3], int64_t a0, int64_t a1,
                                   const float* T_final, const uint32_t* n_contrib, void* state, const float* dL,
-                                  float* grad2d, hipStream_t s);
+                                  float* grad2d, hipStream_t s, bool clear = true);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 
 // adam.hip

@@ -431,6 +431,13 @@ __global__ void __launch_bounds__(128) preprocess_backward_adam_kernel(RawParams
   const int C = 11 + 3 * (A.P.sh_degree + 1) * (A.P.sh_degree + 1);
   for (int c = 0; c < C; ++c)
     if (!((got >> c) & 1ull)) step(c, 0.0f);
+  // leave the row's screen-space gradient zero for the next call, which then needs no
+  // clearing launch (rows never reached here were never written)
+  float4* gp = reinterpret_cast<float4*>(const_cast<float*>(grad2d) + (i - a0) * G2D_STRIDE);
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  gp[0] = z;
+  gp[1] = z;
+  gp[2] = z;
 }
 
 }  // namespace

@@ -598,10 +598,12 @@ hipError_t launch_l1_loss_grad(const float* image, const float* target, const cl
 hipError_t launch_render_backward(const clsp_projected& proj, const clsp_bins& bins, int views, int64_t n, int W,
                                   int H, int TX, int TY, const float bg[3], int64_t a0, int64_t a1,
                                   const float* T_final, const uint32_t* n_contrib, void* state, const float* dL,
-                                  float* grad2d, hipStream_t s) {
+                                  float* grad2d, hipStream_t s, bool clear) {
   const int T = TX * TY;
-  hipError_t err = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, (a1 - a0) * views * G2D_STRIDE, s);
-  if (err != hipSuccess) return err;
+  if (clear) {
+    const hipError_t err = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, (a1 - a0) * views * G2D_STRIDE, s);
+    if (err != hipSuccess) return err;
+  }
   hipLaunchKernelGGL(render_backward_kernel, dim3(views * T, CHUNKS), dim3(NT), 0, s, proj.splat, bins.values,
                      reinterpret_cast<const uint2*>(bins.ranges), reinterpret_cast<const uint2*>(bins.ranges2),
                      bins.tile_list, bins.counters, T, TX, W, H, n,

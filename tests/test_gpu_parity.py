@@ -446,13 +446,16 @@ def test_backward_adam_equals_backward_then_adam(dev, case, local):
     for fused in (False, True):
         g = api.GaussianTensors.from_scene(sc, dev)
         m, v, grads = g.zeros_like(), g.zeros_like(), g.zeros_like()
+        ws = api.render_backward_workspace(a[1] - a[0], 1, dev)   # one workspace for every step
         for step in (1, 2, 3):
             proj = gpu_preprocess(g, [cam])
             bins = api.bin_and_sort(proj, [cam], a if local else None, use_mask=local, capacity=400_000)
             state = api.render_state([cam], dev)
             img, T, nc, dL = api.render_forward_l1(proj, bins, [cam], tgt, bg, state=state)
             if fused:
-                api.render_backward_adam(g, proj, bins, cam, bg, a, T, nc, state, dL, m, v, step)
+                api.render_backward_adam(g, proj, bins, cam, bg, a, T, nc, state, dL, m, v, step, ws=ws)
+                torch.cuda.synchronize()
+                assert not bool(ws.any()), "the fused call leaves its workspace zero"
             else:
                 api.zero_grads(grads, a)
                 api.render_backward(g, proj, bins, [cam], bg, a, T, nc, state, dL, grads)
