@@ -222,8 +222,8 @@ def main():
 # They describe the kernels whose sources hash to `source_sha256` and are reported only
 # while the sources still do (profiles/traffic_local_step_1M_1280x720.txt).
 MEASURED_TRAFFIC = {
-    "source_sha256": "443556d416143781caf3b63fc799e4fe0661c49cff71ca5d5551699b6373dd43",
-    "bytes": {"bin_and_sort": 209.797e6, "render_forward": 17.211e6, "render_backward": 17.183e6},
+    "source_sha256": "249caf1e218c27bbdd7bdb9dae9fef7a74fc86c97267b71825bd3d7174b31b89",
+    "bytes": {"bin_and_sort": 209.797e6, "render_forward": 17.211e6, "render_backward": 17.165e6},
 }
 
 
