@@ -108,6 +108,12 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
                                        ctypes.byref(prm), ctypes.byref(prm), ctypes.byref(hp), fake, 1 << 30,
                                        None) == _ffi.CLSP_ERR_INVALID_ARG
     assert b"one view" in L.clsp_last_error()
+    # the forward with the L1 gradient needs a target and a gradient output
+    bgc = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
+    for tgt, dl in ((None, fake), (fake, None)):
+        assert L.clsp_render_forward_l1(ctypes.byref(proj), ctypes.byref(bins1), cam, 1, bgc, tgt, fake, fake, fake,
+                                        None, 0, dl, None, None) == _ffi.CLSP_ERR_INVALID_ARG
+        assert b"NULL" in L.clsp_last_error()
 
     ws_need = L.clsp_bin_and_sort_workspace_bytes(10, 1, 64, 48, 100)
     bins = _ffi.Bins(fake, fake, fake, fake, fake, fake, fake, fake, fake, ws_need, 100, 10, 1, 0)
