@@ -222,8 +222,8 @@ def main():
 # They describe the kernels whose sources hash to `source_sha256` and are reported only
 # while the sources still do (profiles/traffic_local_step_1M_1280x720.txt).
 MEASURED_TRAFFIC = {
-    "source_sha256": "249caf1e218c27bbdd7bdb9dae9fef7a74fc86c97267b71825bd3d7174b31b89",
-    "bytes": {"bin_and_sort": 209.797e6, "render_forward": 17.211e6, "render_backward": 17.165e6},
+    "source_sha256": "b4d4f4a3fa75e0dcf9aed556eb071d18d4b15e58122a5feba16186e2301e431e",
+    "bytes": {"bin_and_sort": 209.797e6, "render_forward": 17.194e6, "render_backward": 17.393e6},
 }
 
 

@@ -428,9 +428,35 @@ __global__ void __launch_bounds__(128) preprocess_backward_adam_kernel(RawParams
     step(c, 0.0f + v);  // the gradient as the separate calls see it: 0 + v
     got |= 1ull << c;
   });
+  // the components without a gradient, eight at a time: their moments and parameters
+  // are all read before any is written (the arrays may alias as far as the compiler
+  // knows, so a write in between would order every later read after it)
   const int C = 11 + 3 * (A.P.sh_degree + 1) * (A.P.sh_degree + 1);
-  for (int c = 0; c < C; ++c)
-    if (!((got >> c) & 1ull)) step(c, 0.0f);
+  for (int c0 = 0; c0 < C; c0 += 8) {
+    float mv[8], vv[8], pv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = c0 + u;
+      if (c < C && !((got >> c) & 1ull)) {
+        mv[u] = *param_comp(A.M, c, i);
+        vv[u] = *param_comp(A.V, c, i);
+        pv[u] = *param_comp(A.P, c, i);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = c0 + u;
+      if (c < C && !((got >> c) & 1ull)) {
+        const int grp = c < 3 ? 0 : c < 6 ? 1 : c < 10 ? 2 : c == 10 ? 3 : c < 14 ? 4 : 5;
+        const float gg = 0.0f;
+        const float mm = A.b1 * mv[u] + (1.0f - A.b1) * gg;
+        const float v2 = A.b2 * vv[u] + (1.0f - A.b2) * gg * gg;
+        *param_comp(A.M, c, i) = mm;
+        *param_comp(A.V, c, i) = v2;
+        *param_comp(A.P, c, i) = pv[u] - A.lr[grp] * (mm / bc1) / (sqrtf(v2 / bc2) + A.eps);
+      }
+    }
+  }
   // leave the row's screen-space gradient zero for the next call, which then needs no
   // clearing launch (rows never reached here were never written)
   float4* gp = reinterpret_cast<float4*>(const_cast<float*>(grad2d) + (i - a0) * G2D_STRIDE);

@@ -319,6 +319,8 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
 // sum costs one float atomic per block rather than per tile: atomics on one address
 // serialise.
 constexpr int L1_BLOCKS = 512;
+// Workgroups of the backward, which loop over the (tile, chunk) items.
+constexpr int64_t BWD_BLOCKS = 16384;
 
 __global__ void __launch_bounds__(NT) l1_loss_grad_kernel(const float* __restrict__ image,
                                                           const float* __restrict__ target,
@@ -379,178 +381,186 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
     int T, int TX, int W, int H, int64_t n, float bg0, float bg1, float bg2, int64_t a0, int64_t a1,
     const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib, void* state, int64_t slots,
     const float* __restrict__ dL, float* __restrict__ grad2d) {
-  const uint32_t slot = blockIdx.x;
-  if (slot >= counters[C_TILES]) return;
-  const StateView sv = state_view(state, slots);
-  const int maxlast = (int)sv.maxlast[slot];
-  const int chunk = blockIdx.y;
-  const int k0 = chunk * CH;
-  if (k0 >= maxlast) return;
-  const int last_chunk = min(CHUNKS - 1, (maxlast - 1) / CH);
-  const int k1 = (chunk == last_chunk) ? maxlast : (chunk + 1) * CH;
   __shared__ float4 s_a[NT];
   __shared__ float4 s_b[NT];
   __shared__ float s_c[NT];
   __shared__ uint32_t s_e[NT];
   __shared__ uint32_t s_act[NT];  // the record's Gaussian is in the active range
   __shared__ float s_g[NT][9];
+  // One (rendered tile, chunk) work item per iteration: the grid is capped and loops
+  // over the items, chunk-major, so that no workgroup is launched for the slots past
+  // the rendered tiles.
+  auto item = [&](uint32_t slot, int chunk) {
+    const StateView sv = state_view(state, slots);
+    const int maxlast = (int)sv.maxlast[slot];
+    const int k0 = chunk * CH;
+    if (k0 >= maxlast) return;
+    const int last_chunk = min(CHUNKS - 1, (maxlast - 1) / CH);
+    const int k1 = (chunk == last_chunk) ? maxlast : (chunk + 1) * CH;
 
-  const uint32_t gt = tile_list[slot];
-  const uint2 r1 = ranges[gt], r2 = ranges2[gt];
-  if (a0 > 0 || a1 < n) {
-    // A chunk without a record of the active range adds nothing to any gradient: its
-    // frozen records only un-blend, and no other chunk starts from where it ends.  (The
-    // block-wide OR goes through s_act, which is rewritten before its first use below.)
-    const int64_t vb = (int64_t)(gt / T) * n;
-    bool any = false;
-    for (int k = k0 + (int)threadIdx.x; k < k1; k += NT) {
-      const int64_t gid = (int64_t)list_entry(values, r1, r2, k) - vb;
-      any = any || (gid >= a0 && gid < a1);
-    }
-    const bool wave_any = __ballot(any) != 0ull;
-    if ((threadIdx.x & 63u) == 0) s_act[threadIdx.x >> 6] = wave_any ? 1u : 0u;
-    __syncthreads();
-    const bool block_any = (s_act[0] | s_act[1] | s_act[2] | s_act[3]) != 0u;
-    __syncthreads();
-    if (!block_any) return;
-  }
-
-  const int v = gt / T, t = gt % T;
-  const int px = (t % TX) * TILE + pixel_x(threadIdx.x);
-  const int py = (t / TX) * TILE + pixel_y(threadIdx.x);
-  const bool inside = px < W && py < H;
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  const size_t hw = (size_t)H * W;
-  const size_t pix = (size_t)py * W + px;
-
-  float Tr = 1.0f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-  uint32_t last = 0;
-  float Tfin = 1.0f;
-  if (inside) {
-    Tfin = T_final[(size_t)v * hw + pix];
-    last = n_contrib[(size_t)v * hw + pix];
-    g0 = dL[((size_t)v * 3 + 0) * hw + pix];
-    g1 = dL[((size_t)v * 3 + 1) * hw + pix];
-    g2 = dL[((size_t)v * 3 + 2) * hw + pix];
-  }
-  // state at the end of this chunk: transmittance, and the colour of everything behind
-  // it (later chunks plus the background)
-  const float4* my_chunks = sv.chunks + (size_t)slot * CHUNKS * NT + threadIdx.x;
-  float S0 = Tfin * bg0, S1 = Tfin * bg1, S2 = Tfin * bg2;
-  for (int c = last_chunk; c > chunk; --c) {
-    const float4 st = my_chunks[(size_t)c * NT];
-    S0 += st.y;
-    S1 += st.z;
-    S2 += st.w;
-  }
-  Tr = (chunk == last_chunk) ? Tfin : my_chunks[(size_t)chunk * NT].x;
-
-  const int64_t na = a1 - a0;
-  const int64_t vbase = (int64_t)v * n;
-  const uint32_t lane = threadIdx.x & 63;
-
-  for (int end = k1; end > k0; end -= NT) {
-    const int beg = max(k0, end - NT);
-    const int cnt = end - beg;
-    __syncthreads();
-    if ((int)threadIdx.x < cnt) {
-      const uint32_t e = list_entry(values, r1, r2, beg + (int)threadIdx.x);
-      stage_record(splat, e, s_a[threadIdx.x], s_b[threadIdx.x], s_c[threadIdx.x]);
-      s_e[threadIdx.x] = e;
-      const int64_t gid = (int64_t)e - vbase;
-      s_act[threadIdx.x] = (gid >= a0 && gid < a1) ? 1u : 0u;
-    }
-#pragma unroll
-    for (int c = 0; c < 9; ++c) s_g[threadIdx.x][c] = 0.0f;
-    __syncthreads();
-    // a frozen Gaussian's record: only the transmittance and the colour behind move on
-    auto unblend = [&](bool ok, float alpha, float4 b, float c) {
-      if (!ok) return;
-      // 1 - alpha is in [0.01, 1]: the hardware reciprocal (about 1 ulp) in place of a
-      // division
-      const float Tj = Tr * __builtin_amdgcn_rcpf(1.0f - alpha);
-      const float w = alpha * Tj;
-      S0 = fmaf(w, b.z, S0);
-      S1 = fmaf(w, b.w, S1);
-      S2 = fmaf(w, c, S2);
-      Tr = Tj;
-    };
-    for (int j = cnt - 1; j >= 0; --j) {
-      const int k = beg + j;
-      if (!s_act[j]) {
-        if (j >= 1 && !s_act[j - 1]) {
-          // two frozen records: weights together, then undone in reverse order
-          const float4 a0 = s_a[j], b0 = s_b[j], a1 = s_a[j - 1], b1 = s_b[j - 1];
-          const float c0 = s_c[j], c1 = s_c[j - 1];
-          float dx0, dy0, G0, al0, dx1, dy1, G1, al1;
-          bool cl0, cl1;
-          const bool ok0 = splat_alpha(a0, b0, fx, fy, dx0, dy0, G0, al0, cl0) && k < (int)last;
-          const bool ok1 = splat_alpha(a1, b1, fx, fy, dx1, dy1, G1, al1, cl1) && k - 1 < (int)last;
-          unblend(ok0, al0, b0, c0);
-          unblend(ok1, al1, b1, c1);
-          --j;
-        } else {
-          const float4 a = s_a[j], b = s_b[j];
-          float dx, dy, G, alpha;
-          bool clamped;
-          const bool ok = splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped) && k < (int)last;
-          unblend(ok, alpha, b, s_c[j]);
-        }
-        continue;
+    const uint32_t gt = tile_list[slot];
+    const uint2 r1 = ranges[gt], r2 = ranges2[gt];
+    if (a0 > 0 || a1 < n) {
+      // A chunk without a record of the active range adds nothing to any gradient: its
+      // frozen records only un-blend, and no other chunk starts from where it ends.  (The
+      // block-wide OR goes through s_act, which is rewritten before its first use below.)
+      const int64_t vb = (int64_t)(gt / T) * n;
+      bool any = false;
+      for (int k = k0 + (int)threadIdx.x; k < k1; k += NT) {
+        const int64_t gid = (int64_t)list_entry(values, r1, r2, k) - vb;
+        any = any || (gid >= a0 && gid < a1);
       }
-      // Every lane evaluates the record's weight; if some lane of the wave is touched,
-      // the gradient terms are computed branch-free, masked by 0/1 factors (exact: the
-      // unmasked terms are multiplied by 1, the masked ones add zeros), and reduced.
-      const float4 a = s_a[j], b = s_b[j];
-      const float cb = s_c[j];
-      float dx, dy, G, alpha;
-      bool clamped;
-      const bool contrib = splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped) && k < (int)last;
-      if (__ballot(contrib)) {
-        const float om = 1.0f - alpha;
-        const float io = __builtin_amdgcn_rcpf(om);  // om in [0.01, 1]
-        const float Tj = Tr * io;
+      const bool wave_any = __ballot(any) != 0ull;
+      if ((threadIdx.x & 63u) == 0) s_act[threadIdx.x >> 6] = wave_any ? 1u : 0u;
+      __syncthreads();
+      const bool block_any = (s_act[0] | s_act[1] | s_act[2] | s_act[3]) != 0u;
+      __syncthreads();
+      if (!block_any) return;
+    }
+
+    const int v = gt / T, t = gt % T;
+    const int px = (t % TX) * TILE + pixel_x(threadIdx.x);
+    const int py = (t / TX) * TILE + pixel_y(threadIdx.x);
+    const bool inside = px < W && py < H;
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const size_t hw = (size_t)H * W;
+    const size_t pix = (size_t)py * W + px;
+
+    float Tr = 1.0f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    uint32_t last = 0;
+    float Tfin = 1.0f;
+    if (inside) {
+      Tfin = T_final[(size_t)v * hw + pix];
+      last = n_contrib[(size_t)v * hw + pix];
+      g0 = dL[((size_t)v * 3 + 0) * hw + pix];
+      g1 = dL[((size_t)v * 3 + 1) * hw + pix];
+      g2 = dL[((size_t)v * 3 + 2) * hw + pix];
+    }
+    // state at the end of this chunk: transmittance, and the colour of everything behind
+    // it (later chunks plus the background)
+    const float4* my_chunks = sv.chunks + (size_t)slot * CHUNKS * NT + threadIdx.x;
+    float S0 = Tfin * bg0, S1 = Tfin * bg1, S2 = Tfin * bg2;
+    for (int c = last_chunk; c > chunk; --c) {
+      const float4 st = my_chunks[(size_t)c * NT];
+      S0 += st.y;
+      S1 += st.z;
+      S2 += st.w;
+    }
+    Tr = (chunk == last_chunk) ? Tfin : my_chunks[(size_t)chunk * NT].x;
+
+    const int64_t na = a1 - a0;
+    const int64_t vbase = (int64_t)v * n;
+    const uint32_t lane = threadIdx.x & 63;
+
+    for (int end = k1; end > k0; end -= NT) {
+      const int beg = max(k0, end - NT);
+      const int cnt = end - beg;
+      __syncthreads();
+      if ((int)threadIdx.x < cnt) {
+        const uint32_t e = list_entry(values, r1, r2, beg + (int)threadIdx.x);
+        stage_record(splat, e, s_a[threadIdx.x], s_b[threadIdx.x], s_c[threadIdx.x]);
+        s_e[threadIdx.x] = e;
+        const int64_t gid = (int64_t)e - vbase;
+        s_act[threadIdx.x] = (gid >= a0 && gid < a1) ? 1u : 0u;
+      }
+#pragma unroll
+      for (int c = 0; c < 9; ++c) s_g[threadIdx.x][c] = 0.0f;
+      __syncthreads();
+      // a frozen Gaussian's record: only the transmittance and the colour behind move on
+      auto unblend = [&](bool ok, float alpha, float4 b, float c) {
+        if (!ok) return;
+        // 1 - alpha is in [0.01, 1]: the hardware reciprocal (about 1 ulp) in place of a
+        // division
+        const float Tj = Tr * __builtin_amdgcn_rcpf(1.0f - alpha);
         const float w = alpha * Tj;
-        const float dLda = g0 * (Tj * b.z - S0 * io) + g1 * (Tj * b.w - S1 * io) + g2 * (Tj * cb - S2 * io);
-        S0 = contrib ? fmaf(w, b.z, S0) : S0;
-        S1 = contrib ? fmaf(w, b.w, S1) : S1;
-        S2 = contrib ? fmaf(w, cb, S2) : S2;
-        Tr = contrib ? Tj : Tr;
-        const float cf = contrib ? 1.0f : 0.0f;
-        const float gf = (contrib && !clamped) ? 1.0f : 0.0f;  // the 0.99 clamp has zero derivative
-        const float gp = alpha * dLda * gf;                     // dL/dpower
-        // dL/du = gp (A dx + B dy), dL/dv = gp (B dx + C dy); in staged units A = A2 / K_AC,
-        // B = B2 / K_B = B2 / (2 K_AC), C = C2 / K_AC
-        const float gk = gp * (1.0f / K_AC);
-        float p[9];
-        p[0] = gk * (a.z * dx + 0.5f * a.w * dy);
-        p[1] = gk * (0.5f * a.w * dx + b.x * dy);
-        p[2] = -0.5f * gp * dx * dx;
-        p[3] = -gp * dx * dy;
-        p[4] = -0.5f * gp * dy * dy;
-        p[5] = G * dLda * gf;  // dL/dopacity
-        p[6] = w * g0 * cf;
-        p[7] = w * g1 * cf;
-        p[8] = w * g2 * cf;
+        S0 = fmaf(w, b.z, S0);
+        S1 = fmaf(w, b.w, S1);
+        S2 = fmaf(w, c, S2);
+        Tr = Tj;
+      };
+      for (int j = cnt - 1; j >= 0; --j) {
+        const int k = beg + j;
+        if (!s_act[j]) {
+          if (j >= 1 && !s_act[j - 1]) {
+            // two frozen records: weights together, then undone in reverse order
+            const float4 a0 = s_a[j], b0 = s_b[j], a1 = s_a[j - 1], b1 = s_b[j - 1];
+            const float c0 = s_c[j], c1 = s_c[j - 1];
+            float dx0, dy0, G0, al0, dx1, dy1, G1, al1;
+            bool cl0, cl1;
+            const bool ok0 = splat_alpha(a0, b0, fx, fy, dx0, dy0, G0, al0, cl0) && k < (int)last;
+            const bool ok1 = splat_alpha(a1, b1, fx, fy, dx1, dy1, G1, al1, cl1) && k - 1 < (int)last;
+            unblend(ok0, al0, b0, c0);
+            unblend(ok1, al1, b1, c1);
+            --j;
+          } else {
+            const float4 a = s_a[j], b = s_b[j];
+            float dx, dy, G, alpha;
+            bool clamped;
+            const bool ok = splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped) && k < (int)last;
+            unblend(ok, alpha, b, s_c[j]);
+          }
+          continue;
+        }
+        // Every lane evaluates the record's weight; if some lane of the wave is touched,
+        // the gradient terms are computed branch-free, masked by 0/1 factors (exact: the
+        // unmasked terms are multiplied by 1, the masked ones add zeros), and reduced.
+        const float4 a = s_a[j], b = s_b[j];
+        const float cb = s_c[j];
+        float dx, dy, G, alpha;
+        bool clamped;
+        const bool contrib = splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped) && k < (int)last;
+        if (__ballot(contrib)) {
+          const float om = 1.0f - alpha;
+          const float io = __builtin_amdgcn_rcpf(om);  // om in [0.01, 1]
+          const float Tj = Tr * io;
+          const float w = alpha * Tj;
+          const float dLda = g0 * (Tj * b.z - S0 * io) + g1 * (Tj * b.w - S1 * io) + g2 * (Tj * cb - S2 * io);
+          S0 = contrib ? fmaf(w, b.z, S0) : S0;
+          S1 = contrib ? fmaf(w, b.w, S1) : S1;
+          S2 = contrib ? fmaf(w, cb, S2) : S2;
+          Tr = contrib ? Tj : Tr;
+          const float cf = contrib ? 1.0f : 0.0f;
+          const float gf = (contrib && !clamped) ? 1.0f : 0.0f;  // the 0.99 clamp has zero derivative
+          const float gp = alpha * dLda * gf;                     // dL/dpower
+          // dL/du = gp (A dx + B dy), dL/dv = gp (B dx + C dy); in staged units A = A2 / K_AC,
+          // B = B2 / K_B = B2 / (2 K_AC), C = C2 / K_AC
+          const float gk = gp * (1.0f / K_AC);
+          float p[9];
+          p[0] = gk * (a.z * dx + 0.5f * a.w * dy);
+          p[1] = gk * (0.5f * a.w * dx + b.x * dy);
+          p[2] = -0.5f * gp * dx * dx;
+          p[3] = -gp * dx * dy;
+          p[4] = -0.5f * gp * dy * dy;
+          p[5] = G * dLda * gf;  // dL/dopacity
+          p[6] = w * g0 * cf;
+          p[7] = w * g1 * cf;
+          p[8] = w * g2 * cf;
 #pragma unroll
-        for (int c = 0; c < 9; ++c) {
-          const float sum = wave_sum_lane63(p[c]);
-          if (lane == 63 && sum != 0.0f) atomicAdd(&s_g[j][c], sum);
+          for (int c = 0; c < 9; ++c) {
+            const float sum = wave_sum_lane63(p[c]);
+            if (lane == 63 && sum != 0.0f) atomicAdd(&s_g[j][c], sum);
+          }
+        }
+      }
+      __syncthreads();
+      if ((int)threadIdx.x < cnt) {
+        const int64_t gid = (int64_t)s_e[threadIdx.x] - vbase;
+        if (s_act[threadIdx.x]) {
+          float* dst = grad2d + ((int64_t)v * na + (gid - a0)) * G2D_STRIDE;
+#pragma unroll
+          for (int c = 0; c < 9; ++c) {
+            const float val = s_g[threadIdx.x][c];
+            if (val != 0.0f) atomicAdd(dst + c, val);
+          }
         }
       }
     }
-    __syncthreads();
-    if ((int)threadIdx.x < cnt) {
-      const int64_t gid = (int64_t)s_e[threadIdx.x] - vbase;
-      if (s_act[threadIdx.x]) {
-        float* dst = grad2d + ((int64_t)v * na + (gid - a0)) * G2D_STRIDE;
-#pragma unroll
-        for (int c = 0; c < 9; ++c) {
-          const float val = s_g[threadIdx.x][c];
-          if (val != 0.0f) atomicAdd(dst + c, val);
-        }
-      }
-    }
+  };
+  const uint32_t tiles = counters[C_TILES];
+  const uint32_t items = tiles * (uint32_t)CHUNKS;
+  for (uint32_t w = blockIdx.x; w < items; w += gridDim.x) {
+    __syncthreads();  // the previous item's LDS is free
+    item(w % tiles, (int)(w / tiles));
   }
 }
 
@@ -604,7 +614,8 @@ hipError_t launch_render_backward(const clsp_projected& proj, const clsp_bins& b
     const hipError_t err = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, (a1 - a0) * views * G2D_STRIDE, s);
     if (err != hipSuccess) return err;
   }
-  hipLaunchKernelGGL(render_backward_kernel, dim3(views * T, CHUNKS), dim3(NT), 0, s, proj.splat, bins.values,
+  const int grid = (int)std::min<int64_t>((int64_t)views * T * CHUNKS, BWD_BLOCKS);
+  hipLaunchKernelGGL(render_backward_kernel, dim3(grid), dim3(NT), 0, s, proj.splat, bins.values,
                      reinterpret_cast<const uint2*>(bins.ranges), reinterpret_cast<const uint2*>(bins.ranges2),
                      bins.tile_list, bins.counters, T, TX, W, H, n,
                      bg[0], bg[1], bg[2], a0, a1, T_final, n_contrib, state, (int64_t)views * T, dL, grad2d);
