@@ -321,7 +321,14 @@ __global__ void __launch_bounds__(NT) rs_upsweep_kernel(const uint32_t* __restri
   uint32_t beg, end;
   block_span(n, Ge, blockIdx.x, RS_CHUNK, beg, end);
   const int w = threadIdx.x >> 6;
-  for (uint32_t e = beg + threadIdx.x; e < end; e += NT) atomicAdd(&h[w][(keys[e] >> shift) & msk], 1u);
+  for (uint32_t e0 = beg + threadIdx.x; e0 < end; e0 += RS_ITEMS * NT) {
+    uint32_t k[RS_ITEMS];
+#pragma unroll
+    for (int u = 0; u < RS_ITEMS; ++u) k[u] = e0 + u * NT < end ? keys[e0 + u * NT] : 0u;
+#pragma unroll
+    for (int u = 0; u < RS_ITEMS; ++u)
+      if (e0 + u * NT < end) atomicAdd(&h[w][(k[u] >> shift) & msk], 1u);
+  }
   __syncthreads();
   for (int d = threadIdx.x; d < radix; d += NT) hist[(int64_t)d * Ge + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
@@ -394,20 +401,26 @@ __global__ void __launch_bounds__(NT) rs_downsweep_kernel(const uint32_t* __rest
 
   for (uint32_t c = beg; c < end; c += RS_CHUNK) {
     const uint32_t clen = min((uint32_t)RS_CHUNK, end - c);
-    for (int d = tid; d < 4 * 256; d += NT) (&s_wcnt[0][0])[d] = 0;
-    __syncthreads();
-
+    // the chunk's keys and values: all loads in flight while the counts are cleared
     uint32_t key[RS_ITEMS], val[RS_ITEMS], rnk[RS_ITEMS];
     const uint32_t wbase = c + w * RS_WAVE_SPAN;
 #pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {
       const uint32_t e = wbase + it * 64 + lane;
+      key[it] = e < end ? kin[e] : 0u;
+      val[it] = e < end ? vin[e] : 0u;
+    }
+    for (int d = tid; d < 4 * 256; d += NT) (&s_wcnt[0][0])[d] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+      const uint32_t e = wbase + it * 64 + lane;
       const bool valid = e < end;
-      key[it] = valid ? kin[e] : 0u;
-      val[it] = valid ? vin[e] : 0u;
       const uint32_t d = (key[it] >> shift) & msk;
       uint64_t peers = __ballot(valid);
-      for (int b = 0; b < bits; ++b) {
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        if (b >= bits) break;
         const uint64_t bal = __ballot((d >> b) & 1u);
         peers &= ((d >> b) & 1u) ? bal : ~bal;
       }
