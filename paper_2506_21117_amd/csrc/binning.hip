@@ -316,18 +316,23 @@ __global__ void __launch_bounds__(NT) rs_upsweep_kernel(const uint32_t* __restri
   keys += load_off(off_ptr);
   const int radix = 1 << bits;
   const uint32_t msk = (uint32_t)radix - 1u;
-  for (int d = threadIdx.x; d < 4 * 256; d += NT) (&h[0][0])[d] = 0;
-  __syncthreads();
   uint32_t beg, end;
   block_span(n, Ge, blockIdx.x, RS_CHUNK, beg, end);
   const int w = threadIdx.x >> 6;
-  for (uint32_t e0 = beg + threadIdx.x; e0 < end; e0 += RS_ITEMS * NT) {
-    uint32_t k[RS_ITEMS];
+  // the first keys are in flight while the histograms are cleared
+  uint32_t e0 = beg + threadIdx.x;
+  uint32_t k[RS_ITEMS];
 #pragma unroll
-    for (int u = 0; u < RS_ITEMS; ++u) k[u] = e0 + u * NT < end ? keys[e0 + u * NT] : 0u;
+  for (int u = 0; u < RS_ITEMS; ++u) k[u] = e0 + u * NT < end ? keys[e0 + u * NT] : 0u;
+  for (int d = threadIdx.x; d < 4 * 256; d += NT) (&h[0][0])[d] = 0;
+  __syncthreads();
+  while (e0 < end) {
 #pragma unroll
     for (int u = 0; u < RS_ITEMS; ++u)
       if (e0 + u * NT < end) atomicAdd(&h[w][(k[u] >> shift) & msk], 1u);
+    e0 += RS_ITEMS * NT;
+#pragma unroll
+    for (int u = 0; u < RS_ITEMS; ++u) k[u] = e0 + u * NT < end ? keys[e0 + u * NT] : 0u;
   }
   __syncthreads();
   for (int d = threadIdx.x; d < radix; d += NT) hist[(int64_t)d * Ge + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
@@ -391,13 +396,6 @@ __global__ void __launch_bounds__(NT) rs_downsweep_kernel(const uint32_t* __rest
   const uint32_t lane = lane_id();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-  // global base of each digit for this block
-  {
-    const uint32_t t = tid < radix ? tot[tid] : 0u;
-    uint32_t all;
-    const uint32_t ex = block_excl_scan(t, s4, all);
-    if (tid < radix) s_base[tid] = ex + hist[(int64_t)tid * G + blockIdx.x];
-  }
 
   for (uint32_t c = beg; c < end; c += RS_CHUNK) {
     const uint32_t clen = min((uint32_t)RS_CHUNK, end - c);
@@ -409,6 +407,13 @@ __global__ void __launch_bounds__(NT) rs_downsweep_kernel(const uint32_t* __rest
       const uint32_t e = wbase + it * 64 + lane;
       key[it] = e < end ? kin[e] : 0u;
       val[it] = e < end ? vin[e] : 0u;
+    }
+    if (c == beg) {
+      // the global base of each digit for this block, while the first loads are in flight
+      const uint32_t t = tid < radix ? tot[tid] : 0u;
+      uint32_t all;
+      const uint32_t ex = block_excl_scan(t, s4, all);
+      if (tid < radix) s_base[tid] = ex + hist[(int64_t)tid * G + blockIdx.x];
     }
     for (int d = tid; d < 4 * 256; d += NT) (&s_wcnt[0][0])[d] = 0;
     __syncthreads();
