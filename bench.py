@@ -222,8 +222,8 @@ def main():
 # They describe the kernels whose sources hash to `source_sha256` and are reported only
 # while the sources still do (profiles/traffic_local_step_1M_1280x720.txt).
 MEASURED_TRAFFIC = {
-    "source_sha256": "b4d4f4a3fa75e0dcf9aed556eb071d18d4b15e58122a5feba16186e2301e431e",
-    "bytes": {"bin_and_sort": 209.797e6, "render_forward": 17.194e6, "render_backward": 17.393e6},
+    "source_sha256": "488e29e2f832eaefa264e7e8a45ca885d11a4c5a4f22bd6b7045222030df4d55",
+    "bytes": {"bin_and_sort": 210.172e6, "render_forward": 17.277e6, "render_backward": 17.393e6},
 }
 
 
