@@ -428,14 +428,14 @@ __global__ void __launch_bounds__(128) preprocess_backward_adam_kernel(RawParams
     step(c, 0.0f + v);  // the gradient as the separate calls see it: 0 + v
     got |= 1ull << c;
   });
-  // the components without a gradient, eight at a time: their moments and parameters
+  // the components without a gradient, sixteen at a time: their moments and parameters
   // are all read before any is written (the arrays may alias as far as the compiler
   // knows, so a write in between would order every later read after it)
   const int C = 11 + 3 * (A.P.sh_degree + 1) * (A.P.sh_degree + 1);
-  for (int c0 = 0; c0 < C; c0 += 8) {
-    float mv[8], vv[8], pv[8];
+  for (int c0 = 0; c0 < C; c0 += 16) {
+    float mv[16], vv[16], pv[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       const int c = c0 + u;
       if (c < C && !((got >> c) & 1ull)) {
         mv[u] = *param_comp(A.M, c, i);
@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(128) preprocess_backward_adam_kernel(RawParams
       }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       const int c = c0 + u;
       if (c < C && !((got >> c) & 1ull)) {
         const int grp = c < 3 ? 0 : c < 6 ? 1 : c < 10 ? 2 : c == 10 ? 3 : c < 14 ? 4 : 5;
