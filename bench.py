@@ -222,8 +222,8 @@ def main():
 # They describe the kernels whose sources hash to `source_sha256` and are reported only
 # while the sources still do (profiles/traffic_local_step_1M_1280x720.txt).
 MEASURED_TRAFFIC = {
-    "source_sha256": "488e29e2f832eaefa264e7e8a45ca885d11a4c5a4f22bd6b7045222030df4d55",
-    "bytes": {"bin_and_sort": 210.172e6, "render_forward": 17.277e6, "render_backward": 17.393e6},
+    "source_sha256": "e74fa3b85a338f40c824be184db430f78bcd060dc1b47a114c3f5bbac6c1eeae",
+    "bytes": {"bin_and_sort": 210.173e6, "render_forward": 17.277e6, "render_backward": 17.494e6},
 }
 
 
