@@ -55,10 +55,12 @@ def lib():
         L.orc_preprocess.argtypes = [i64, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, fp, ip]
         L.orc_preprocess.restype = ctypes.c_int
         L.orc_render.argtypes = [i64, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, i64, ip, dp, dp, ip, ip,
-                                 dp, dp, dp, ip]
+                                 dp, dp, dp, ip, dp, dp]
         L.orc_render.restype = ctypes.c_int
         L.orc_preprocess_backward.argtypes = [i64, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_preprocess_backward.restype = ctypes.c_int
+        L.orc_error_bounds.argtypes = [i64, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_error_bounds.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -129,18 +131,33 @@ def preprocess(scene, cam, params=None) -> dict:
     return res
 
 
+def error_bounds(scene, cam, params=None) -> dict:
+    """Per-Gaussian bounds on the error of a float32 evaluation of the projected
+    quantities (see err_bounds in oracle.c): ``u``, ``v`` (pixels), ``K`` (each conic
+    entry) and ``rgb`` [N, 3]; zero for culled Gaussians."""
+    n = scene.n
+    args = _scene_args(scene, params)
+    out = np.zeros((n, 6))
+    rc = lib().orc_error_bounds(n, scene.sh_degree, *[_p(a) for a in args], _p(cam_vec(cam)), _p(out))
+    assert rc == 0, rc
+    return {"u": out[:, 0], "v": out[:, 1], "K": out[:, 2], "rgb": out[:, 3:6]}
+
+
 def all_pixels(width, height) -> np.ndarray:
     ys, xs = np.mgrid[0:height, 0:width]
     return np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.int32)
 
 
-def render(scene, cam, bg=(0.0, 0.0, 0.0), pixels=None, dL_dC=None, params=None) -> dict:
+def render(scene, cam, bg=(0.0, 0.0, 0.0), pixels=None, dL_dC=None, params=None, pert=None) -> dict:
     """Brute-force render of ``pixels`` ([M, 2] int (px, py); default: the whole image).
 
     Returns ``rgb`` [M, 3], ``T`` [M], ``ncontrib`` [M], ``flag`` [M] and, for a full
     image, ``image`` [3, H, W].  With ``dL_dC`` ([M, 3], or [3, H, W] for a full image)
     it also returns the screen-space gradient ``grad2d`` [N, 9] (u, v, A, B, C, opacity,
-    r, g, b), the absolute-term sums ``s2d`` [N, 9] and ``gflag`` [N]."""
+    r, g, b), the absolute-term sums ``s2d`` [N, 9], the bound ``e2d`` [N, 9] on the
+    float32 rounding of the compositing chains (see orc_render) and ``gflag`` [N].
+    ``pert`` ([N, 9] in [-1, 1]) shifts each Gaussian's projected quantities by that
+    fraction of their float32 error bounds before rendering."""
     n = scene.n
     full = pixels is None
     if full:
@@ -152,7 +169,7 @@ def render(scene, cam, bg=(0.0, 0.0, 0.0), pixels=None, dL_dC=None, params=None)
     T = np.zeros(m)
     nc = np.zeros(m, dtype=np.int32)
     flag = np.zeros(m, dtype=np.int32)
-    grad2d = s2d = gflag = None
+    grad2d = s2d = gflag = e2d = None
     dl = None
     if dL_dC is not None:
         dl = _f64(dL_dC)
@@ -161,11 +178,13 @@ def render(scene, cam, bg=(0.0, 0.0, 0.0), pixels=None, dL_dC=None, params=None)
         assert dl.shape == (m, 3)
         grad2d = np.zeros((n, 9))
         s2d = np.zeros((n, 9))
+        e2d = np.zeros((n, 9))
     gflag = np.zeros(n, dtype=np.int32)
     bgv = _f64(bg)
     rc = lib().orc_render(n, scene.sh_degree, *[_p(a) for a in args], _p(cam_vec(cam)), _p(bgv), m,
                           _p(pixels, ctypes.c_int32), _p(rgb), _p(T), _p(nc, ctypes.c_int32),
-                          _p(flag, ctypes.c_int32), _p(dl), _p(grad2d), _p(s2d), _p(gflag, ctypes.c_int32))
+                          _p(flag, ctypes.c_int32), _p(dl), _p(grad2d), _p(s2d), _p(gflag, ctypes.c_int32),
+                          _p(e2d), _p(None if pert is None else _f64(pert)))
     assert rc == 0, rc
     res = {"rgb": rgb, "T": T, "ncontrib": nc, "flag": flag, "gflag": gflag}
     if full:
@@ -174,6 +193,7 @@ def render(scene, cam, bg=(0.0, 0.0, 0.0), pixels=None, dL_dC=None, params=None)
     if grad2d is not None:
         res["grad2d"] = grad2d
         res["s2d"] = s2d
+        res["e2d"] = e2d
     return res
 
 
@@ -194,10 +214,11 @@ def split_raw(g: np.ndarray, sh_degree: int) -> dict:
     }
 
 
-def preprocess_backward(scene, cam, grad2d, s2d=None, params=None) -> dict:
+def preprocess_backward(scene, cam, grad2d, s2d=None, params=None, e2d=None) -> dict:
     """Raw-parameter gradients (SoA dict) from a screen-space gradient [N, 9]; with
     ``s2d`` also the absolute-term bound ``s`` of each entry (same layout, key
-    ``"s"``)."""
+    ``"s"``); with ``e2d`` (a screen-space error bound) that bound carried to the raw
+    parameters through the absolute value of the chain rule (key ``"e"``)."""
     n = scene.n
     P = n_raw(scene.sh_degree)
     args = _scene_args(scene, params)
@@ -209,28 +230,71 @@ def preprocess_backward(scene, cam, grad2d, s2d=None, params=None) -> dict:
     res = split_raw(g, scene.sh_degree)
     if sr is not None:
         res["s"] = split_raw(sr, scene.sh_degree)
+    if e2d is not None:
+        er = np.zeros((n, P))
+        scratch = np.zeros((n, P))
+        rc = lib().orc_preprocess_backward(n, scene.sh_degree, *[_p(a) for a in args], _p(cam_vec(cam)),
+                                           _p(_f64(grad2d)), _p(_f64(e2d)), _p(scratch), _p(er))
+        assert rc == 0, rc
+        res["e"] = split_raw(er, scene.sh_degree)
     return res
 
 
-def gradients(scene, cams, dL_dC_views, bg=(0.0, 0.0, 0.0), pixels=None, params=None) -> dict:
+# The float32 error term of the gradient comparison (see ``gradients``): renders with
+# PERTURB_PATTERNS random sign patterns, and PERTURB_FACTOR times the largest deviation.
+PERTURB_PATTERNS = 4
+PERTURB_FACTOR = 2.0
+
+
+def gradients(scene, cams, dL_dC_views, bg=(0.0, 0.0, 0.0), pixels=None, params=None,
+              perturb=PERTURB_PATTERNS, seed=0) -> dict:
     """Raw-parameter gradients summed over views (``dL_dC_views[v]`` as for
-    ``render``).  Returns the SoA gradient dict with ``s`` bounds and ``gflag``."""
+    ``render``).  Returns the SoA gradient dict with the ``s`` sums, ``gflag`` and the
+    float32 error term ``e`` of each entry:
+
+    * the rounding of the compositing chains (``e2d`` of ``render``) carried to the raw
+      parameters through the absolute value of the chain rule, plus
+    * PERTURB_FACTOR times the largest change of the gradient when every Gaussian's
+      projected quantities are moved by plus or minus their float32 error bounds, with
+      ``perturb`` random sign patterns (seeded by ``seed``): a first-order estimate of
+      how far a float32 evaluation of the same definition lands, with each pixel's
+      contribution entering with its sign, as in the sum itself.
+
+    ``perturb=0`` skips the perturbed renders (``e`` then holds the chain term only)."""
     total = None
-    stot = None
+    stot = etot = None
     gflag = np.zeros(scene.n, dtype=np.int32)
     for v, cam in enumerate(cams):
         pix = None if pixels is None else pixels[v]
         r = render(scene, cam, bg, pix, dL_dC_views[v], params)
-        g = preprocess_backward(scene, cam, r["grad2d"], r["s2d"], params)
+        g = preprocess_backward(scene, cam, r["grad2d"], r["s2d"], params, e2d=r["e2d"])
         s = g.pop("s")
+        e = g.pop("e")
         if total is None:
-            total, stot = g, s
+            total, stot, etot = g, s, e
         else:
             for k in total:
                 total[k] = total[k] + g[k]
                 stot[k] = stot[k] + s[k]
+                etot[k] = etot[k] + e[k]
         gflag |= r["gflag"]
     total["s"] = stot
+    if perturb:
+        rng = np.random.default_rng(seed)
+        dev = None
+        for _ in range(perturb):
+            gp = None
+            for v, cam in enumerate(cams):
+                pix = None if pixels is None else pixels[v]
+                pert = rng.choice(np.array([-1.0, 1.0]), size=(scene.n, 9))
+                r = render(scene, cam, bg, pix, dL_dC_views[v], params, pert=pert)
+                g = preprocess_backward(scene, cam, r["grad2d"], None, params)
+                gp = g if gp is None else {k: gp[k] + g[k] for k in gp}
+            d = {k: np.abs(gp[k] - total[k]) for k in gp}
+            dev = d if dev is None else {k: np.maximum(dev[k], d[k]) for k in d}
+        for k in etot:
+            etot[k] = etot[k] + PERTURB_FACTOR * dev[k]
+    total["e"] = etot
     total["gflag"] = gflag
     return total
 

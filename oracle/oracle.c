@@ -176,6 +176,11 @@ typedef struct {
   /* saved for the backward */
   double s[3], qn[4], qnorm, Rq[9], Sigma[9], J[6], M[6], dir[3], dist, Xt, Yt;
   double limx, limy;
+  /* first-order bounds on the error of a float32 evaluation of the quantities above
+   * (not part of the method: they size the comparison bar, see err_bounds()) */
+  double e_u, e_v;       /* absolute error of u, v (pixels) */
+  double e_K;            /* absolute error of each conic entry */
+  double e_rgb[3];       /* absolute error of each colour channel */
 } gstate_t;
 
 #define ORC_F_VISIBLE 1
@@ -214,6 +219,8 @@ static void quat_to_rot_grad(const double q[4], double dR[4][9]) {
 }
 
 static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+static void err_bounds(const scene_t *sc, int64_t i, const cam_t *cam, const double mu[3], gstate_t *g);
 
 /* Forward geometry and colour of Gaussian i for one camera. */
 static void project_one(const scene_t *sc, int64_t i, const cam_t *cam, gstate_t *g) {
@@ -333,8 +340,77 @@ static void project_one(const scene_t *sc, int64_t i, const cam_t *cam, gstate_t
   const double kappa = 2.0 * log(255.0 * g->o);
   g->rx = sqrt(kappa * g->cov2[0]) * (1.0 + 1.0 / 4096.0);
   g->ry = sqrt(kappa * g->cov2[2]) * (1.0 + 1.0 / 4096.0);
+  err_bounds(sc, i, cam, mu, g);
   g->visible = 1;
   g->flags |= ORC_F_VISIBLE;
+}
+
+/* ------------------------------------------------------------------ float32 error model
+ * Not part of the method: it sizes the comparison bar for a float32 evaluation of the
+ * same definition.  Per Gaussian and view, first-order bounds on the error of each
+ * projected quantity when evaluated in float32 (unit roundoff U32 = 2^-24), each
+ * operation of a chain counted once with its operands' magnitudes:
+ *   - camera-space centre: a coordinate is a 3-term fused dot product plus a
+ *     translation, error <= 3 U32 times the sum of the absolute values of its terms
+ *     (mX, mY, mZ);
+ *   - u = fx X/Z + cx: the errors of X and Z carried through the quotient (3 U32 each),
+ *     the rounding of the reciprocal and product (3 U32 |u - cx|), the final sum
+ *     (2 U32 |u|);
+ *   - screen covariance M Sigma M^T + 0.3 I with Sigma = Rq diag(s^2) Rq^T, M = J Rcam:
+ *     the roundings of the normalised quaternion, the rotation entries, the scales'
+ *     exponentials and the Jacobian's reciprocal depth move Sigma by ~8 U32 s_max^2 and
+ *     M by a few U32 of its rows, so every entry is wrong by at most
+ *     E_cov = 8 U32 s_max^2 (|M_0| + |M_1|)^2 plus 2 U32 (a + c) for its own sums; the
+ *     conic K = cov^-1 then by 2 E_cov / lambda_min^2 (the derivative of an inverse is
+ *     -K dS K, of norm ||K||^2 ||dS||) plus 4 U32 of its largest entry;
+ *   - opacity: the logistic function in float32, 4 U32 relative;
+ *   - colour: the spherical-harmonic sum is rounded relative to the sum of the
+ *     magnitudes of its terms (each basis polynomial by the magnitude of its monomials,
+ *     8 U32), and the unit view direction carries an error of ~8 U32 (|c| + |mu|)/dist,
+ *     which moves each basis value by at most its gradient's size times that. */
+#define U32 (1.0 / 16777216.0)
+static void err_bounds(const scene_t *sc, int64_t i, const cam_t *cam, const double mu[3], gstate_t *g) {
+  const int64_t n = sc->n;
+  double m[3];
+  for (int a = 0; a < 3; ++a)
+    m[a] = fabs(cam->R[3 * a] * mu[0]) + fabs(cam->R[3 * a + 1] * mu[1]) + fabs(cam->R[3 * a + 2] * mu[2]) +
+           fabs(cam->t[a]);
+  const double X = g->p[0], Y = g->p[1], Z = g->p[2];
+  g->e_u = U32 * (3.0 * cam->fx / Z * (m[0] + fabs(X) * m[2] / Z) + 3.0 * fabs(g->u - cam->cx) + 2.0 * fabs(g->u));
+  g->e_v = U32 * (3.0 * cam->fy / Z * (m[1] + fabs(Y) * m[2] / Z) + 3.0 * fabs(g->v - cam->cy) + 2.0 * fabs(g->v));
+  /* rows of M = J Rcam and the largest scale */
+  double nM[2];
+  for (int r = 0; r < 2; ++r)
+    nM[r] = sqrt(g->M[3 * r] * g->M[3 * r] + g->M[3 * r + 1] * g->M[3 * r + 1] + g->M[3 * r + 2] * g->M[3 * r + 2]);
+  double smax = g->s[0];
+  if (g->s[1] > smax) smax = g->s[1];
+  if (g->s[2] > smax) smax = g->s[2];
+  const double a = g->cov2[0], b = g->cov2[1], c = g->cov2[2];
+  const double Ecov = 8.0 * U32 * smax * smax * (nM[0] + nM[1]) * (nM[0] + nM[1]) + 2.0 * U32 * (a + c);
+  const double lmin = 0.5 * (a + c) - sqrt(0.25 * (a - c) * (a - c) + b * b);
+  double Kmax = fabs(g->conic[0]);
+  if (fabs(g->conic[1]) > Kmax) Kmax = fabs(g->conic[1]);
+  if (fabs(g->conic[2]) > Kmax) Kmax = fabs(g->conic[2]);
+  g->e_K = 4.0 * U32 * Kmax + 2.0 * Ecov / (lmin * lmin);
+  /* colour */
+  double cp[3];
+  for (int a2 = 0; a2 < 3; ++a2)
+    cp[a2] = -(cam->R[a2] * cam->t[0] + cam->R[3 + a2] * cam->t[1] + cam->R[6 + a2] * cam->t[2]);
+  const double rdir = 8.0 * U32 * (sqrt(cp[0] * cp[0] + cp[1] * cp[1] + cp[2] * cp[2]) +
+                                   sqrt(mu[0] * mu[0] + mu[1] * mu[1] + mu[2] * mu[2])) / g->dist;
+  double Mb[16], dY[16][3];
+  sh_basis_mag(g->dir, Mb);
+  sh_basis_grad(g->dir, dY);
+  const int K = (sc->sh_degree + 1) * (sc->sh_degree + 1);
+  for (int ch = 0; ch < 3; ++ch) {
+    double mag = 0.5, dmag = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const double f = fabs(sc->sh[((int64_t)k * 3 + ch) * n + i]);
+      mag += f * Mb[k];
+      dmag += f * (fabs(dY[k][0]) + fabs(dY[k][1]) + fabs(dY[k][2]));
+    }
+    g->e_rgb[ch] = 8.0 * U32 * mag + rdir * dmag;
+  }
 }
 
 static void make_scene(scene_t *sc, int64_t n, int sh_degree, const double *means, const double *log_scales,
@@ -364,6 +440,24 @@ int orc_preprocess(int64_t n, int sh_degree, const double *means, const double *
   return ORC_OK;
 }
 
+/* The float32 error bounds of err_bounds() per Gaussian (stride 6): e_u, e_v, e_K,
+ * e_rgb[3]; zero for culled Gaussians. */
+int orc_error_bounds(int64_t n, int sh_degree, const double *means, const double *log_scales, const double *quats,
+                     const double *opac, const double *sh, const double *camv, double *out) {
+  if (n < 0 || sh_degree < 0 || sh_degree > 3) return ORC_EINVAL;
+  scene_t sc; make_scene(&sc, n, sh_degree, means, log_scales, quats, opac, sh);
+  cam_t cam; load_cam(camv, &cam);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    gstate_t g;
+    project_one(&sc, i, &cam, &g);
+    double *o = out + 6 * i;
+    if (!g.visible) { for (int k = 0; k < 6; ++k) o[k] = 0.0; continue; }
+    o[0] = g.e_u; o[1] = g.e_v; o[2] = g.e_K; o[3] = g.e_rgb[0]; o[4] = g.e_rgb[1]; o[5] = g.e_rgb[2];
+  }
+  return ORC_OK;
+}
+
 /* ------------------------------------------------------------------ depth order */
 typedef struct { float z; int64_t id; } zkey_t;
 static int cmp_zkey(const void *a, const void *b) {
@@ -380,6 +474,7 @@ typedef struct {
   int flags;
   int visible;
   float z32;
+  double e_u, e_v, e_K, e_rgb[3];   /* float32 error bounds (err_bounds) */
 } rstate_t;
 
 typedef struct {
@@ -398,11 +493,25 @@ typedef struct {
  * each Gaussian's screen-space quantities into grad2d ([n][9]: u, v, A, B, C, opacity,
  * r, g, b) and the sum of absolute per-pixel terms into s2d ([n][9]).  gflag[n] is set
  * for Gaussians blended at (or decided near a threshold at) a flagged pixel.
+ *
+ * pert ([n][9], optional, entries in [-1, 1]) perturbs each Gaussian's projected
+ * quantities u, v, A, B, C, opacity, r, g, b by that fraction of their float32 error
+ * bounds (err_bounds; the opacity by 4 U32 relative) before rendering: rendering with a
+ * few random sign patterns shows how far a float32 evaluation's gradient can move,
+ * with the pixels' contributions combined with their signs, as they are in the sum.
+ *
+ * e2d ([n][9], optional) receives the part of the float32 error that such
+ * perturbations do not model: the rounding of the compositing chains themselves (the
+ * transmittance as a running product, or rebuilt backwards by division, and the colour
+ * sums), 4 U32 per blended Gaussian of the pixel plus 16 U32, relative to each
+ * partial's magnitude with dL/dalpha taken as sum |g| (T c + S/(1 - alpha)), before its
+ * two parts cancel.
  */
 int orc_render(int64_t n, int sh_degree, const double *means, const double *log_scales, const double *quats,
                const double *opac, const double *sh, const double *camv, const double *bg, int64_t npix,
                const int32_t *pix, double *out_rgb, double *out_T, int32_t *out_ncontrib, int32_t *out_flag,
-               const double *dL_dC, double *grad2d, double *s2d, int32_t *gflag) {
+               const double *dL_dC, double *grad2d, double *s2d, int32_t *gflag, double *e2d,
+               const double *pert) {
   if (n < 0 || npix < 0 || sh_degree < 0 || sh_degree > 3) return ORC_EINVAL;
   scene_t sc; make_scene(&sc, n, sh_degree, means, log_scales, quats, opac, sh);
   cam_t cam; load_cam(camv, &cam);
@@ -418,6 +527,17 @@ int orc_render(int64_t n, int sh_degree, const double *means, const double *log_
     r->u = g.u; r->v = g.v;
     for (int k = 0; k < 3; ++k) { r->conic[k] = g.conic[k]; r->rgb[k] = g.rgb[k]; }
     r->o = g.o; r->flags = g.flags; r->visible = g.visible; r->z32 = g.z32;
+    r->e_u = g.e_u; r->e_v = g.e_v; r->e_K = g.e_K;
+    for (int k = 0; k < 3; ++k) r->e_rgb[k] = g.e_rgb[k];
+    if (pert && r->visible) {
+      const double *x = pert + 9 * i;
+      r->u += x[0] * g.e_u;
+      r->v += x[1] * g.e_v;
+      for (int k = 0; k < 3; ++k) r->conic[k] += x[2 + k] * g.e_K;
+      r->o *= 1.0 + x[5] * 4.0 * U32;
+      for (int k = 0; k < 3; ++k)
+        if (r->rgb[k] > 0.0) r->rgb[k] = fmax(0.0, r->rgb[k] + x[6 + k] * g.e_rgb[k]);
+    }
   }
   int64_t nv = 0;
   for (int64_t i = 0; i < n; ++i)
@@ -525,9 +645,33 @@ int orc_render(int64_t n, int sh_degree, const double *means, const double *log_
         const double gC[3] = {dL_dC[3 * p], dL_dC[3 * p + 1], dL_dC[3 * p + 2]};
         /* suffix colour S_j = sum_{k>j} alpha_k T_k c_k + T_final bg, built back to front */
         double S[3] = {T * bg[0], T * bg[1], T * bg[2]};
+        /* chain rounding (see the function comment) */
+        const double rho = 4.0 * U32 * (double)nc + 16.0 * U32;
         for (size_t jj = nc; jj-- > 0;) {
           const contrib_t *c = &list[jj];
           const rstate_t *g = &gs[c->id];
+          if (e2d) {
+            const double om = 1.0 - c->alpha;
+            double ma = 0.0;
+            for (int ch = 0; ch < 3; ++ch) ma += fabs(gC[ch]) * (c->T * g->rgb[ch] + S[ch] / om);
+            double e[9];
+            for (int k = 0; k < 9; ++k) e[k] = 0.0;
+            if (!c->clamped) {
+              const double A = g->conic[0], B = g->conic[1], Cc = g->conic[2];
+              const double mdp = rho * c->alpha * ma;
+              e[0] = mdp * fabs(A * c->dx + B * c->dy);
+              e[1] = mdp * fabs(B * c->dx + Cc * c->dy);
+              e[2] = mdp * 0.5 * c->dx * c->dx;
+              e[3] = mdp * fabs(c->dx * c->dy);
+              e[4] = mdp * 0.5 * c->dy * c->dy;
+              e[5] = rho * c->G * ma;
+            }
+            for (int ch = 0; ch < 3; ++ch) e[6 + ch] = rho * fabs(gC[ch]) * c->alpha * c->T;
+            for (int k = 0; k < 9; ++k) {
+#pragma omp atomic
+              e2d[9 * c->id + k] += e[k];
+            }
+          }
           double d2[9];
           double dL_dalpha = 0.0;
           for (int ch = 0; ch < 3; ++ch) {

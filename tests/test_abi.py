@@ -70,6 +70,16 @@ def _cam(w=64, h=48):
     return c
 
 
+def _gpu_visible():
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_gpu_visible(), reason="passes the stand-in device address 0x1000 to entry points; run only "
+                                           "where no GPU could ever receive a launch on it")
 def test_invalid_arguments_are_rejected_on_the_host(L):
     from paper_2506_21117_amd import _ffi
     fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first

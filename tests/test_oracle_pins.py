@@ -173,6 +173,39 @@ def test_covariance_against_numeric_jacobian_and_scipy_rotation(orc):
     assert checked > 20
 
 
+def test_clamped_jacobian_covariance_closed_form(orc):
+    """Past the lateral limit the Jacobian uses the clamped ratio: X~/Z = sign(X) 1.3 (W/2)/fx
+    (and Y~/Z likewise with H and fy), while the projected centre keeps the true ratio.
+    For an isotropic Gaussian under an identity camera rotation, Sigma2 = s^2 J J^T + 0.3 I
+    with J = [[fx/Z, 0, -fx X~/Z^2], [0, fy/Z, -fy Y~/Z^2]], written out here by hand."""
+    W, H, fx, fy = 64, 40, 50.0, 45.0
+    cam = Camera(np.eye(3), (0, 0, 4), fx, fy, W / 2, H / 2, W, H)
+    lx, ly = 1.3 * (W / 2) / fx, 1.3 * (H / 2) / fy      # 0.832 and 0.5777...
+    # centres (camera space: Z = 4 + z): clamped in x (both signs), in y (both signs),
+    # in both, and one inside both limits
+    mus = [(4.2, 0.3, 0.5), (-4.0, -0.2, 0.0), (0.4, 3.1, 0.2), (-0.3, -3.6, 1.0), (5.0, 3.8, 0.3), (0.5, 0.4, 0.0)]
+    s = 0.3
+    q = (1.0, 0.0, 0.0, 0.0)
+    sc = make_scene(mus, [[math.log(s)] * 3] * len(mus), [q] * len(mus), [0.7] * len(mus),
+                    [dc_for_rgb((0.5,) * 3)] * len(mus))
+    pp = orc.preprocess(sc, cam)
+    want_flags = [(1, 0), (1, 0), (0, 1), (0, 1), (1, 1), (0, 0)]
+    for i, (cx_, cy_) in enumerate(want_flags):
+        assert bool(pp["flags"][i] & orc.F_CLAMPX) == bool(cx_), i
+        assert bool(pp["flags"][i] & orc.F_CLAMPY) == bool(cy_), i
+        mu = sc.means[:, i].astype(np.float64)
+        s32 = float(np.exp(np.float64(sc.log_scales[0, i])))
+        X, Y, Z = mu[0], mu[1], mu[2] + 4.0
+        rx = X / Z if not cx_ else math.copysign(lx, X)
+        ry = Y / Z if not cy_ else math.copysign(ly, Y)
+        a = s32 ** 2 * (fx / Z) ** 2 * (1 + rx * rx) + 0.3
+        b = s32 ** 2 * (fx / Z) * (fy / Z) * rx * ry
+        c = s32 ** 2 * (fy / Z) ** 2 * (1 + ry * ry) + 0.3
+        np.testing.assert_allclose([pp["cov_a"][i], pp["cov_b"][i], pp["cov_c"][i]], [a, b, c], rtol=1e-12,
+                                   atol=1e-14)
+        np.testing.assert_allclose([pp["u"][i], pp["v"][i]], [fx * X / Z + W / 2, fy * Y / Z + H / 2], rtol=1e-13)
+
+
 # ------------------------------------------------------------------ B, C: compositing
 def test_two_gaussians_composite(orc):
     cam = Camera(np.eye(3), (0, 0, 4), 64, 64, 32, 32, 64, 64)
@@ -425,6 +458,45 @@ def test_fd_gradients_jacobian_clamp_and_sh_clamp(orc):
     assert (clampx & contrib).sum() >= 2 and (shc & contrib).sum() >= 2
     pick = np.nonzero(contrib & (clampx | shc))[0]
     _fd_check(orc, sc, [cam], (0.0, 0.0, 0.0), dl, rng, pick=pick)
+
+
+def test_fd_gradients_y_clamped(orc):
+    """Gaussians far above and below the view (vertical ratio clamped, so Y~ = Z Y~/Z
+    depends on the depth only) that still reach the image; every means component of
+    each such Gaussian is checked against central differences."""
+    rng = np.random.default_rng(17)
+    cam = Camera(np.eye(3), (0, 0, 4), 40, 40, 16, 12, 32, 24)
+    n = 40
+    means = np.stack([rng.uniform(-0.6, 0.6, n), rng.choice([-1.0, 1.0], n) * rng.uniform(2.2, 4.0, n),
+                      rng.uniform(-1, 1, n)], 1)
+    ls = rng.normal(-0.6, 0.25, (n, 3))
+    sc = make_scene(means, ls, rng.normal(size=(n, 4)), rng.uniform(0.4, 0.95, n), rng.uniform(-1, 1, (n, 3)))
+    pp = orc.preprocess(sc, cam)
+    clampy = (pp["flags"] & orc.F_CLAMPY) != 0
+    dl = rng.normal(size=(3, 24, 32))
+    r = orc.render(sc, cam, dL_dC=dl)
+    contrib = np.abs(r["grad2d"]).sum(1) > 0
+    pick = np.nonzero(contrib & clampy)[0]
+    assert len(pick) >= 4, len(pick)
+    g = orc.gradients(sc, [cam], [dl])
+    base = [np.asarray(a, np.float64).copy() for a in sc.param_arrays()]
+    checked = 0
+    for i in pick:
+        for c in range(3):
+            val = base[0][c, i]
+            h = 5e-6 * max(1.0, abs(val))
+            pp_, pm_ = [a.copy() for a in base], [a.copy() for a in base]
+            pp_[0][c, i] += h
+            pm_[0][c, i] -= h
+            rp = orc.render(sc, cam, params=tuple(pp_))
+            rm = orc.render(sc, cam, params=tuple(pm_))
+            if not (np.array_equal(rp["ncontrib"], rm["ncontrib"]) and np.array_equal(rp["flag"], rm["flag"])):
+                continue
+            fd = float(((rp["image"] - rm["image"]) * dl).sum()) / (2 * h)
+            an = g["means"][c, i]
+            assert abs(an - fd) <= 1e-6 * max(abs(fd), abs(an)) + 1e-10, (c, i, an, fd)
+            checked += 1
+    assert checked >= 3 * len(pick) - 2, checked
 
 
 # ------------------------------------------------------------------ K: the local-kernel claim
