@@ -217,7 +217,11 @@ typedef struct clsp_bins {
  * ignored), so a captured graph can replay the call while the caller advances the
  * counter on the device.  With zero_grads != 0 the call also sets the gradient rows of
  * `active` to zero after using them (all of them, row_mask or not), which replaces a
- * separate clsp_zero_grads before the next step's backward. */
+ * separate clsp_zero_grads before the next step's backward.  skip_flag (device
+ * uint32[1], nullable): when it holds a nonzero value at the time the update runs, the
+ * call leaves params, gradients and moments unchanged; pass &bins->counters[1] (the
+ * pair-capacity overflow of the step's lists) so that a step whose lists did not fit
+ * updates nothing (clsp_render_backward_adam checks its bins' flag by itself). */
 typedef struct clsp_adam_hparams {
   float lr[6];
   float beta1, beta2, eps;
@@ -225,6 +229,7 @@ typedef struct clsp_adam_hparams {
   const int32_t *step_device;
   int32_t zero_grads;
   int32_t reserved;
+  const uint32_t *skip_flag;
 } clsp_adam_hparams;
 
 /* Library version string and the last error message of the calling host thread. */
@@ -276,10 +281,13 @@ clsp_status clsp_bin_and_sort(const clsp_projected *proj, const clsp_camera *cam
  * are left as they were.
  * state (nullable, device, clsp_render_state_bytes(n_views, width, height) bytes)
  * receives the compositing state the backward needs: for each rendered tile (in
- * tile_list order) the largest n_contrib of its pixels and, per pixel, the
- * transmittance and the colour added by each chunk of CLSP_STATE_CHUNK consecutive
- * list entries (at most CLSP_STATE_CHUNKS chunks; the last takes the remainder).  It
- * lets the backward process the chunks of a tile in parallel.  Pass NULL when no
+ * tile_list order) the largest n_contrib of its pixels, the tile's chunk length and,
+ * per pixel, the transmittance and the colour added by each chunk of consecutive list
+ * entries.  Chunks start CLSP_STATE_CHUNK entries long; when a tile's list fills
+ * CLSP_STATE_CHUNKS of them, neighbouring chunks are merged pairwise and the length
+ * doubles, so a list of L entries has chunks of at most max(CLSP_STATE_CHUNK,
+ * 2 L / CLSP_STATE_CHUNKS) entries.  It lets the backward process the chunks of a tile
+ * in parallel, each from its own stored transmittance.  Pass NULL when no
  * backward follows.  With depth-sliced bins this call also lists the second slab for
  * the tiles that need it (using the bins' workspace) and finishes those tiles; `proj`
  * must be the projection the bins were built from. */
@@ -322,7 +330,9 @@ clsp_status clsp_l1_loss_grad(const float *image, const float *target, const cls
  * clsp_render_forward call on the same bins.  Each tile's list is split into the
  * chunks of the forward's state and every (tile, chunk) is processed by its own
  * workgroup, back to front from that chunk's stored transmittance and the colour of
- * the chunks behind it.
+ * the chunks behind it.  If counters[1] of the bins is set (the lists ran out of pair
+ * capacity, so the forward did not render every tile completely) the call writes no
+ * gradient at all.
  * ws: device workspace of clsp_render_backward_workspace_bytes(active.end -
  * active.begin, n_views) bytes. */
 size_t clsp_render_backward_workspace_bytes(int64_t n_active, int32_t n_views);
@@ -358,7 +368,9 @@ clsp_status clsp_zero_grads(const clsp_params *grads, clsp_range active, clsp_st
  * ws (clsp_render_backward_workspace_bytes(active.end - active.begin, 1) bytes) must be
  * all zero on entry, e.g. zero-filled once when allocated: the call leaves it all zero,
  * so it needs no clearing launch of its own (a workspace last used by
- * clsp_render_backward must be cleared first).
+ * clsp_render_backward must be cleared first).  If counters[1] of the bins is set
+ * (pair-capacity overflow) the call changes nothing: params, exp_avg and exp_avg_sq
+ * keep their values bit for bit.
  * Errors: as clsp_render_backward and clsp_masked_adam_step, plus n_views != 1. */
 clsp_status clsp_render_backward_adam(const clsp_gaussians *g, const clsp_projected *proj, const clsp_bins *bins,
                                       const clsp_camera *cams, int32_t n_views, const float *bg, clsp_range active,

@@ -61,7 +61,8 @@ class Bins(ctypes.Structure):
 
 class AdamHParams(ctypes.Structure):
     _fields_ = [("lr", c_float * 6), ("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("step", c_int32),
-                ("step_device", c_void_p), ("zero_grads", c_int32), ("reserved", c_int32)]
+                ("step_device", c_void_p), ("zero_grads", c_int32), ("reserved", c_int32),
+                ("skip_flag", c_void_p)]
 
 
 _lib = None

@@ -338,10 +338,13 @@ DEFAULT_LR = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3, 2.5e-3 / 20.0)
 
 
 def masked_adam_step(params: GaussianTensors, grads, exp_avg, exp_avg_sq, active, step, lr=DEFAULT_LR, beta1=0.9,
-                     beta2=0.999, eps=1e-15, row_mask=None, stream=None, step_device=None, zero_grads=False):
+                     beta2=0.999, eps=1e-15, row_mask=None, stream=None, step_device=None, zero_grads=False,
+                     skip_flag=None):
     """``step`` (host int) or ``step_device`` (int32 device tensor [1]) gives the 1-based
     step count of the bias corrections.  With ``zero_grads`` the gradient rows of
-    ``active`` are set to zero after use."""
+    ``active`` are set to zero after use.  ``skip_flag`` (a one-element 32-bit device
+    tensor, e.g. ``bins.counters[1:2]``, the pair-capacity overflow): when it is nonzero
+    on the device, nothing is updated."""
     a0, a1 = (0, params.n) if active is None else (int(active[0]), int(active[1]))
     hp = _ffi.AdamHParams()
     hp.lr = (ctypes.c_float * 6)(*[float(x) for x in lr])
@@ -351,6 +354,10 @@ def masked_adam_step(params: GaussianTensors, grads, exp_avg, exp_avg_sq, active
         if step_device.dtype != torch.int32 or step_device.numel() != 1 or not step_device.is_cuda:
             raise ValueError("step_device must be an int32 CUDA tensor of one element")
         hp.step_device = step_device.data_ptr()
+    if skip_flag is not None:
+        if skip_flag.element_size() != 4 or skip_flag.numel() != 1 or not skip_flag.is_cuda:
+            raise ValueError("skip_flag must be a 32-bit CUDA tensor of one element")
+        hp.skip_flag = skip_flag.data_ptr()
     if row_mask is not None and (row_mask.dtype != torch.uint8 or row_mask.numel() != params.n):
         raise ValueError("row_mask must be uint8 [N]")
     check(lib().clsp_masked_adam_step(ctypes.byref(params.as_params()), ctypes.byref(grads.as_params()),

@@ -15,6 +15,7 @@ struct AdamConst {
   float bc1, bc2;             // 1 - beta^step (host step count)
   const int32_t* step_dev;    // device step count, or null
   int zero_grads;             // clear the gradient rows after use
+  const uint32_t* skip;       // device flag: nonzero leaves every buffer unchanged, or null
 };
 
 __device__ __forceinline__ void adam_one(float* p, float* g, float* m, float* v, float lr, const AdamConst& h) {
@@ -30,7 +31,7 @@ __device__ __forceinline__ void adam_one(float* p, float* g, float* m, float* v,
 __global__ void __launch_bounds__(256) adam_kernel(MutParams P, MutParams Gr, MutParams M, MutParams V, int64_t a0,
                                                    int64_t a1, const uint8_t* __restrict__ row_mask, AdamConst h) {
   const int64_t i = a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a1) return;
+  if (i >= a1 || (h.skip && *h.skip)) return;
   if (row_mask && !row_mask[i]) {
     if (h.zero_grads) {
       const int64_t n = Gr.n;
@@ -88,6 +89,7 @@ hipError_t launch_adam(const MutParams& p, const MutParams& g, const MutParams& 
   h.bc2 = (float)(1.0 - pow((double)hp.beta2, (double)hp.step));
   h.step_dev = hp.step_device;
   h.zero_grads = hp.zero_grads;
+  h.skip = hp.skip_flag;
   hipLaunchKernelGGL(adam_kernel, dim3(ceil_div(a1 - a0, 256)), dim3(256), 0, s, p, g, m, v, a0, a1, row_mask, h);
   return hipGetLastError();
 }

@@ -309,7 +309,7 @@ clsp_status clsp_render_backward(const clsp_gaussians* g, const clsp_projected* 
   const clsp::MutParams gm = mut_params(grads);
   for (int v = 0; v < n_views; ++v)
     CHECK(hip_status(clsp::launch_preprocess_backward(rp, dev_cam(cams[v]), v, active.begin, active.end, proj->flags,
-                                                      g2d, gm, s),
+                                                      g2d, gm, bins->counters + 1, s),
                      "preprocess_backward"));
   return CLSP_OK;
 }
@@ -389,6 +389,7 @@ clsp_status clsp_render_backward_adam(const clsp_gaussians* g, const clsp_projec
   A.bc1 = (float)(1.0 - pow((double)hp->beta1, (double)hp->step));
   A.bc2 = (float)(1.0 - pow((double)hp->beta2, (double)hp->step));
   A.step_dev = hp->step_device;
+  A.skip = bins->counters + 1;   // pair-capacity overflow of the step's lists
   return hip_status(clsp::launch_preprocess_backward_adam(raw_params(g), dev_cam(cams[0]), active.begin, active.end,
                                                           proj->flags, g2d, A, s),
                     "render_backward_adam");

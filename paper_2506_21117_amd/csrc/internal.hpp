@@ -63,9 +63,10 @@ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // Projects entries [r0, r1) of view `view` (all n: r0 = 0, r1 = g.n).
 hipError_t launch_preprocess(const RawParams& g, const DevCam& cam, int view, int64_t r0, int64_t r1, float* splat,
                              float* depth, uint32_t* rect, uint32_t* flags, hipStream_t s);
+// skip (device, nullable): nonzero leaves everything unchanged.
 hipError_t launch_preprocess_backward(const RawParams& g, const DevCam& cam, int view, int64_t a0, int64_t a1,
                                       const uint32_t* flags, const float* grad2d, const MutParams& grads,
-                                      hipStream_t s);
+                                      const uint32_t* skip, hipStream_t s);
 // One view's preprocess backward followed by one Adam step of rows [a0, a1).
 struct FusedAdam {
   MutParams P, M, V;
@@ -73,6 +74,7 @@ struct FusedAdam {
   float b1, b2, eps;
   float bc1, bc2;            // 1 - beta^step (host step count)
   const int32_t* step_dev;   // device step count, or null
+  const uint32_t* skip;      // device flag: nonzero leaves everything unchanged, or null
 };
 hipError_t launch_preprocess_backward_adam(const RawParams& g, const DevCam& cam, int64_t a0, int64_t a1,
                                            const uint32_t* flags, const float* grad2d, const FusedAdam& A,

@@ -392,9 +392,10 @@ __device__ __forceinline__ float* param_comp(const MutParams& X, int c, int64_t 
 // Chain rule for the changed Gaussians [a0, a1) of one view; adds into grads.
 __global__ void __launch_bounds__(128) preprocess_backward_kernel(RawParams g, DevCam cam, int view, int64_t a0,
                                                                   int64_t a1, const uint32_t* __restrict__ flags,
-                                                                  const float* __restrict__ grad2d, MutParams out) {
+                                                                  const float* __restrict__ grad2d, MutParams out,
+                                                                  const uint32_t* __restrict__ skip) {
   const int64_t i = a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a1) return;
+  if (i >= a1 || (skip && *skip)) return;
   backward_row(g, cam, view, i, a0, a1, flags, grad2d, [&](int c, float v) { *param_comp(out, c, i) += v; });
 }
 
@@ -405,7 +406,9 @@ __global__ void __launch_bounds__(128) preprocess_backward_adam_kernel(RawParams
                                                                        int64_t a1, const uint32_t* __restrict__ flags,
                                                                        const float* __restrict__ grad2d, FusedAdam A) {
   const int64_t i = a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a1) return;
+  // a step whose lists ran out of pair capacity updates nothing (the raster backward
+  // wrote no gradient either, so the workspace is still zero)
+  if (i >= a1 || (A.skip && *A.skip)) return;
   float bc1 = A.bc1, bc2 = A.bc2;
   if (A.step_dev) {
     const float t = (float)max(*A.step_dev, 1);
@@ -488,11 +491,11 @@ hipError_t launch_preprocess_backward_adam(const RawParams& g, const DevCam& cam
 
 hipError_t launch_preprocess_backward(const RawParams& g, const DevCam& cam, int view, int64_t a0, int64_t a1,
                                       const uint32_t* flags, const float* grad2d, const MutParams& grads,
-                                      hipStream_t s) {
+                                      const uint32_t* skip, hipStream_t s) {
   if (a1 <= a0) return hipSuccess;
   const int blocks = ceil_div(a1 - a0, 128);
   hipLaunchKernelGGL(preprocess_backward_kernel, dim3(blocks), dim3(128), 0, s, g, cam, view, a0, a1, flags, grad2d,
-                     grads);
+                     grads, skip);
   return hipGetLastError();
 }
 

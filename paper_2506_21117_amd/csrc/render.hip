@@ -61,24 +61,37 @@ __device__ __forceinline__ bool splat_alpha(const float4 a, const float4 b, floa
   return !(p2 > 0.0f) && alpha >= ALPHA_MIN;
 }
 
-// Compositing state per rendered tile slot: the largest contributor count of its pixels,
-// then per (chunk, pixel) the transmittance after the chunk and the chunk's colour.
+// Compositing state per rendered tile slot: the largest contributor count of its pixels
+// and the tile's chunk length, then per (chunk, pixel) the transmittance after the chunk
+// and the chunk's colour.
 struct StateView {
   uint32_t* maxlast;   // [slots]
+  uint32_t* chunk_len; // [slots]
   float4* chunks;      // [slots][CHUNKS][256]
 };
 
-__host__ __device__ inline size_t state_header_bytes(int64_t slots) { return ((size_t)slots * 4 + 255) & ~(size_t)255; }
+__host__ __device__ inline size_t state_header_bytes(int64_t slots) { return ((size_t)slots * 8 + 255) & ~(size_t)255; }
 
 __device__ __forceinline__ StateView state_view(void* base, int64_t slots) {
   StateView v;
   v.maxlast = reinterpret_cast<uint32_t*>(base);
+  v.chunk_len = v.maxlast + slots;
   v.chunks = reinterpret_cast<float4*>(reinterpret_cast<char*>(base) + state_header_bytes(slots));
   return v;
 }
 
+// A tile's list is cut into chunks of CH entries; when a list reaches CHUNKS of them,
+// neighbouring chunks are merged pairwise and the chunk length doubles, so every chunk
+// holds at most max(CH, 2L/CHUNKS) entries of a list of L and no chunk is unbounded.
 constexpr int CH = CLSP_STATE_CHUNK;
 constexpr int CHUNKS = CLSP_STATE_CHUNKS;
+
+// The chunk length of a tile after compositing the first `len` entries of its list.
+__device__ __forceinline__ int chunk_len_after(int len) {
+  int c = CH;
+  while (len >= CHUNKS * c) c *= 2;
+  return c;
+}
 
 // First positions i in [0, n) with keys[i] >= x and with keys[i] > x in ascending
 // keys (every thread of the block calls it and gets both): 256-ary searches run
@@ -179,6 +192,7 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
   uint32_t last = 0;
   bool done = !inside;
   int chunk = 0;
+  int chl = CH;  // the tile's current chunk length (uniform over the workgroup)
   if (PHASE == 2) {
     Tr = my_carry[0 * NT];
     cr = my_carry[1 * NT];
@@ -189,7 +203,9 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
     db = my_carry[6 * NT];
     last = __float_as_uint(my_carry[7 * NT]);
     done = my_carry[8 * NT] != 0.0f;
-    chunk = min(len1 / CH, CHUNKS - 1);
+    // the first phase composited the whole first list (the tile was still alive)
+    chl = chunk_len_after(len1);
+    chunk = len1 / chl;
   }
   for (int kb = k_begin; kb < k_end; kb += NT) {
     if (__syncthreads_count(done) == NT) break;
@@ -202,7 +218,7 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
     const int cnt = min(NT, k_end - kb);
     // segments of the batch between chunk boundaries of the list
     for (int j = 0; j < cnt;) {
-      const int next_b = ((kb + j) / CH + 1) * CH;
+      const int next_b = ((kb + j) / chl + 1) * chl;
       const int jhi = min(cnt, next_b - kb);
       // Branch-free blending, FW_UNROLL records per iteration: their weights are
       // computed first, then applied in order with selects; a lane that has stopped
@@ -239,13 +255,24 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
         for (int u = 0; u < FW_UNROLL; ++u) blend(okq[u] && !done, al[u], bq[u], cq[u], (uint32_t)(kb + jj + u + 1));
       }
       // a chunk boundary of the tile's list: record this pixel's state
-      if (kb + jhi == next_b && chunk < CHUNKS - 1) {
+      if (kb + jhi == next_b) {
         if (keep) my_chunks[(size_t)chunk * NT] = make_float4(Tr, dr, dg, db);
         cr += dr;
         cg += dg;
         cb += db;
         dr = dg = db = 0.0f;
-        ++chunk;
+        if (++chunk == CHUNKS) {
+          // every chunk is full: merge neighbours pairwise (the transmittance after the
+          // second, the sum of the colours) and double the chunk length
+          if (keep) {
+            for (int c = 0; c < CHUNKS / 2; ++c) {
+              const float4 x = my_chunks[(size_t)(2 * c) * NT], y = my_chunks[(size_t)(2 * c + 1) * NT];
+              my_chunks[(size_t)c * NT] = make_float4(y.x, x.y + y.y, x.z + y.z, x.w + y.w);
+            }
+          }
+          chunk = CHUNKS / 2;
+          chl *= 2;
+        }
       }
       j = jhi;
     }
@@ -282,7 +309,10 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
     __syncthreads();
     atomicMax(&s_max, last);
     __syncthreads();
-    if (threadIdx.x == 0) sv.maxlast[slot] = s_max;
+    if (threadIdx.x == 0) {
+      sv.maxlast[slot] = s_max;
+      sv.chunk_len[slot] = (uint32_t)chl;
+    }
   }
   const size_t hw = (size_t)H * W;
   const size_t pix = (size_t)py * W + px;
@@ -393,10 +423,12 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
   auto item = [&](uint32_t slot, int chunk) {
     const StateView sv = state_view(state, slots);
     const int maxlast = (int)sv.maxlast[slot];
-    const int k0 = chunk * CH;
+    if (maxlast == 0) return;
+    const int chl = (int)sv.chunk_len[slot];
+    const int k0 = chunk * chl;
     if (k0 >= maxlast) return;
-    const int last_chunk = min(CHUNKS - 1, (maxlast - 1) / CH);
-    const int k1 = (chunk == last_chunk) ? maxlast : (chunk + 1) * CH;
+    const int last_chunk = (maxlast - 1) / chl;   // < CHUNKS: the forward keeps it so
+    const int k1 = (chunk == last_chunk) ? maxlast : (chunk + 1) * chl;
 
     const uint32_t gt = tile_list[slot];
     const uint2 r1 = ranges[gt], r2 = ranges2[gt];
@@ -556,6 +588,8 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
       }
     }
   };
+  // lists that ran out of pair capacity were not rendered completely: no gradient
+  if (counters[C_OVERFLOW]) return;
   const uint32_t tiles = counters[C_TILES];
   const uint32_t items = tiles * (uint32_t)CHUNKS;
   for (uint32_t w = blockIdx.x; w < items; w += gridDim.x) {

@@ -105,8 +105,10 @@ class SplatOptimizer:
         self._hp = _ffi.AdamHParams()
         self._hp.lr = (ctypes.c_float * 6)(*[float(x) for x in self.lr])
         self._hp.beta1, self._hp.beta2, self._hp.eps = 0.9, 0.999, 1e-15
-        # the separate Adam call clears the gradient rows it used (full steps)
+        # the separate Adam call clears the gradient rows it used (full steps), and skips
+        # the update of a step whose lists overflowed the pair capacity
         self._hp.zero_grads = 1
+        self._hp.skip_flag = ctypes.c_void_p(self.bins.counters.data_ptr() + 4 * _ffi.C_OVERFLOW)
         self._gr = None if self.grads is None else self.grads.as_params()
         p = lambda t: ctypes.c_void_p(t.data_ptr())
         self._ptrs = {"image": p(self.image), "T": p(self.T), "nc": p(self.nc), "dL": p(self.dL),

@@ -47,7 +47,7 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(_ffi.Gaussians) == 6 * 8 + 8 + 8 + 4 + 4
     assert ctypes.sizeof(_ffi.Params) == 5 * 8 + 8 + 4 + 4
     assert ctypes.sizeof(_ffi.Bins) == 9 * 8 + 8 + 8 + 8 + 4 + 4
-    assert ctypes.sizeof(_ffi.AdamHParams) == 4 * 10 + 8 + 8
+    assert ctypes.sizeof(_ffi.AdamHParams) == 4 * 10 + 8 + 8 + 8
 
 
 def test_workspace_queries(L):

@@ -72,7 +72,8 @@ def test_autograd_against_fp64_finite_differences(dev):
                 fd = float(((rp["image"] - rm["image"]) * dl).sum()) / (2 * h)
                 g = gpu[gi].reshape(ncomp, sc.n)[c, i]
                 s = ref["s"][name].reshape(ncomp, sc.n)[c, i]
-                tol = 1e-3 * abs(fd) + 1e-5 * s + 1e-8
+                e = ref["e"][name].reshape(ncomp, sc.n)[c, i]   # float32 term of the GPU side
+                tol = 1e-3 * abs(fd) + 1e-5 * s + e + 1e-8
                 if ref["gflag"][i]:
                     continue
                 assert abs(g - fd) <= tol, (name, c, i, g, fd, s)
@@ -111,17 +112,43 @@ def test_autograd_recompute_and_stored_at_1080p(dev):
     image_bytes = img_r.numel() * 4
     assert held_r <= image_bytes + (64 << 20), (held_r, image_bytes)   # output (+ allocator slack) only
     assert held_s > held_r + image_bytes // 2
-    # the two backward passes add their float atomics in different orders: compare
-    # norm-wise, and element-wise with a floor at 1 % of the tensor's RMS for cancelling
-    # sums (their order noise scales with the sum of |terms|, not with the result; the
-    # per-element bound with that scale is checked against the reference elsewhere)
+    # the two backward passes add their float atomics in different orders; the
+    # per-element bound of that order noise (2 (10 + tiles) U32 times the sum of |terms|)
+    # needs the reference's sums and is checked on a smaller scene
+    # (test_autograd_modes_differ_by_summation_order_only); here the norm-wise difference
+    # only guards against a mode using wrong buffers, which moves gradients by O(1)
     for name, a, b in zip(api.GaussianTensors.NAMES, g_r, g_s):
         a, b = a.double(), b.double()
         rel = float((a - b).norm() / b.norm())
-        rms = float(b.pow(2).mean().sqrt())
-        worst = float(((a - b).abs() / (1e-3 * b.abs() + 1e-2 * rms)).max())
-        print(f"{name}: norm-wise rel diff {rel:.2e}, worst element / tolerance {worst:.3f}")
-        # float32 order noise of sums of thousands of terms that cancel (quaternion
-        # gradients most): up to ~1e-5 of the norm was seen, 1e-4 leaves margin while
-        # staying 10x inside the 1e-3 gradient bar
-        assert rel < 1e-4 and worst <= 1.0, (name, rel, worst)
+        print(f"{name}: norm-wise rel diff {rel:.2e}")
+        assert rel < 1e-3, (name, rel)
+
+
+def test_autograd_modes_differ_by_summation_order_only(dev):
+    """Recompute and stored modes on the 500-Gaussian SH-3 scene: equal images, and
+    gradients within the summation-order bound: each per-pixel term passes through at
+    most 6 DPP additions in its wave, 4 LDS atomics and one global atomic per tile, so
+    two orders differ by at most 2 (10 + tiles) U32 times the sum of the absolute terms
+    (the reference's s through the chain rule), plus the chain rule's own float32
+    rounding (1e-5 s) on each side."""
+    w = scenes.fd_scene()
+    sc, cams = w.scene, w.cameras
+    ps = _leaf(sc, dev)
+    wts = torch.as_tensor(np.random.default_rng(3).normal(size=(1, 3, cams[0].height, cams[0].width))
+                          .astype(np.float32), device=dev)
+    res = {}
+    for mode in ("recompute", "stored"):
+        for p in ps:
+            p.grad = None
+        img = render(*ps, cams, mode=mode)
+        (img * wts).sum().backward()
+        torch.cuda.synchronize()
+        res[mode] = (img.detach().clone(), [to_np(p.grad).astype(np.float64) for p in ps])
+    assert torch.equal(res["recompute"][0], res["stored"][0])
+    ref = oracle.gradients(sc, cams, [to_np(wts[0]).astype(np.float64)], perturb=0)
+    tiles = api.tile_grid(cams[0].width, cams[0].height)
+    u32 = 2.0 ** -24
+    for name, a, b in zip(api.GaussianTensors.NAMES, res["recompute"][1], res["stored"][1]):
+        s = ref["s"][name]
+        tol = 2 * (10 + tiles[0] * tiles[1]) * u32 * s + 2e-5 * s + 1e-12
+        assert np.all(np.abs(a - b) <= tol), (name, float((np.abs(a - b) / tol).max()))

@@ -378,9 +378,6 @@ def test_render_backward_parity(dev, case, local):
     print(f"{case} local={local}: worst gradient error / tolerance {worst:.3f}")
 
 
-@pytest.mark.skip(reason="one row of 60 000 exceeds the gradient bar 1.7x on a cancelling mean component "
-                         "(error 5e-5 of the sum of |terms|): the bar's float32 term does not yet model the "
-                         "transmittance rebuilt by division over chunks of deep lists")
 def test_render_backward_with_more_items_than_workgroups(dev):
     """A dense scene in one 640x480 view: 1 200 rendered tiles x CLSP_STATE_CHUNKS
     (tile, chunk) items exceed the backward's workgroup count, so workgroups take
@@ -420,8 +417,111 @@ def test_render_backward_with_more_items_than_workgroups(dev):
     print(f"more items than workgroups: worst gradient error / tolerance {worst:.3f}")
 
 
+def _deep_scene():
+    """Faint, large Gaussians filling a cube seen from 4 units away: every pixel blends
+    hundreds of them before its transmittance falls to 1e-4, and tiles list thousands,
+    so the compositing state's chunks fill up and merge (twice) and the backward's last
+    chunks run deep."""
+    rng = np.random.default_rng(21)
+    sc = scenes.uniform_cube_scene(rng, 60_000, log_scale_mean=-2.5, log_scale_sd=0.2)
+    sc.opacity_logit[:] = np.float32(-3.5)          # opacity 0.029
+    cam = scenes.look_at((0.0, 0.0, -4.0), width=128, height=128, fx=128.0, fy=128.0)
+    return sc, [cam]
+
+
+@pytest.mark.parametrize("mode", [COMPLETE, api._ffi.BINS_DEPTH_SLICED])
+def test_render_backward_deep_lists(dev, mode):
+    """Lists far past CLSP_STATE_CHUNKS x CLSP_STATE_CHUNK entries: the forward merges the
+    chunks of the compositing state and doubles their length, and the backward starts
+    every chunk of every tile from its stored state; pixels and gradients at eight
+    seeded pixels per tile against the reference."""
+    sc, cams = _deep_scene()
+    cam = cams[0]
+    n = sc.n
+    bg = (0.1, 0.3, 0.2)
+    g = api.GaussianTensors.from_scene(sc, dev)
+    proj = gpu_preprocess(g, cams)
+    bins = api.bin_and_sort(proj, cams, None, use_mask=False, capacity=2_000_000, mode=mode)
+    state = api.render_state(cams, dev)
+    img, T, nc = api.render_forward(proj, bins, cams, bg, state=state)
+    torch.cuda.synchronize()
+    assert not bins.read_counters()["overflow"]
+    hdr = (Path(__file__).resolve().parents[1] / "include" / "clsplat.h").read_text()
+    chunk, chunks = (int(re.search(rf"#define {k} (\d+)", hdr).group(1)) for k in ("CLSP_STATE_CHUNK", "CLSP_STATE_CHUNKS"))
+    TX, TY = api.tile_grid(cam.width, cam.height)
+    ncn = to_np(nc[0]).astype(np.int64)
+    per_tile = ncn.reshape(TY, 16, TX, 16).max(axis=(1, 3))
+    assert per_tile.max() > 2 * chunks * chunk, per_tile.max()     # two merges of the chunks
+    assert (per_tile > chunks * chunk).mean() > 0.25
+    rng = np.random.default_rng(9)
+    pix = []
+    for ty in range(TY):
+        for tx in range(TX):
+            for o in rng.permutation(256)[:8]:
+                pix.append((tx * 16 + o % 16, ty * 16 + o // 16))
+    pixels = np.asarray(pix, dtype=np.int32)
+    vals = rng.normal(size=(len(pixels), 3)).astype(np.float32)
+    dl_np = np.zeros(tuple(img.shape), dtype=np.float32)
+    dl_np[0, :, pixels[:, 1], pixels[:, 0]] = vals
+    grads = g.zeros_like()
+    api.render_backward(g, proj, bins, cams, bg, (0, n), T, nc, state, torch.as_tensor(dl_np, device=dev), grads)
+    torch.cuda.synchronize()
+    ref = oracle.gradients(sc, cams, [vals.astype(np.float64)], bg, pixels=[pixels])
+    got = to_np(img[0])[:, pixels[:, 1], pixels[:, 0]].T
+    # each pixel takes thousands of alpha-threshold decisions here (faint Gaussians whose
+    # footprints end at alpha = 1/255), so more pixels than usual have one within 1e-5
+    # of its threshold; they are excused as everywhere, and counted
+    check_pixels(got, oracle.render(sc, cam, bg, pixels=pixels), "deep lists", max_flagged=0.03)
+    worst = check_grads(grads, ref, slice(0, n), "deep lists")
+    print(f"deep lists (max contributor position {per_tile.max()}): worst gradient error / tolerance {worst:.3f}")
+
+
+def test_capacity_overflow_updates_nothing(dev):
+    """A step whose lists ran out of pair capacity writes no gradient, and neither the
+    fused backward + Adam nor the Adam call with the overflow flag as its skip flag
+    changes parameters or moments."""
+    sc, cams = workload("tiny")
+    cam = cams[0]
+    n = sc.n
+    a = (n // 2, n)
+    g = api.GaussianTensors.from_scene(sc, dev)
+    rng = np.random.default_rng(4)
+    m, v = g.zeros_like(), g.zeros_like()
+    for t in (m, v):
+        for k in api.GaussianTensors.NAMES:
+            getattr(t, k).copy_(torch.as_tensor(np.abs(rng.normal(size=tuple(getattr(t, k).shape))).astype(np.float32)
+                                                * 1e-3, device=dev))
+    g0, m0, v0 = g.clone(), m.clone(), v.clone()
+    tgt = torch.rand(1, 3, cam.height, cam.width, generator=torch.Generator(device=dev).manual_seed(1), device=dev)
+    proj = gpu_preprocess(g, cams)
+    bins = api.bin_and_sort(proj, cams, a, use_mask=True, capacity=64)
+    state = api.render_state(cams, dev)
+    img, T, nc, dL = api.render_forward_l1(proj, bins, cams, tgt, state=state)
+    grads = g.zeros_like()
+    api.render_backward(g, proj, bins, cams, (0, 0, 0), a, T, nc, state, dL, grads)
+    ws = api.render_backward_workspace(a[1] - a[0], 1, dev)
+    api.render_backward_adam(g, proj, bins, cam, (0, 0, 0), a, T, nc, state, dL, m, v, 1, ws=ws)
+    api.masked_adam_step(g, grads, m, v, a, 1, skip_flag=bins.counters[1:2])
+    torch.cuda.synchronize()
+    assert bins.read_counters()["overflow"]
+    for k in api.GaussianTensors.NAMES:
+        assert not bool(getattr(grads, k).any()), k
+        for x, y in ((g, g0), (m, m0), (v, v0)):
+            np.testing.assert_array_equal(to_np(getattr(x, k)), to_np(getattr(y, k)))
+    assert not bool(ws.any())
+    # the same Adam call without the flag does move the moments (zero gradient: decay)
+    api.masked_adam_step(g, grads, m, v, a, 1)
+    torch.cuda.synchronize()
+    assert not np.array_equal(to_np(m.means), to_np(m0.means))
+
+
 def test_gradients_accumulate(dev):
-    """render_backward adds to the gradient buffers."""
+    """render_backward adds to the gradient buffers.  Two runs sum the same per-pixel
+    terms in different orders (float atomics): each term passes through at most 6 DPP
+    additions in its wave, 4 LDS atomics of its workgroup and one global atomic per
+    tile, so two sums differ by at most 2 (10 + tiles) U32 times the sum of the absolute
+    terms (the reference's s, carried through the chain rule), and the accumulation
+    itself rounds once more."""
     sc, cams = workload("tiny")
     g = api.GaussianTensors.from_scene(sc, dev)
     proj = gpu_preprocess(g, cams)
@@ -434,10 +534,14 @@ def test_gradients_accumulate(dev):
     g2 = g1.clone()
     api.render_backward(g, proj, bins, cams, (0, 0, 0), None, T, nc, state, dl, g2)
     torch.cuda.synchronize()
+    ref = oracle.gradients(sc, cams, [to_np(dl[0]).astype(np.float64)], perturb=0)
+    u32 = 2.0 ** -24
+    tiles = bins.read_counters()["tiles"]
     for k in api.GaussianTensors.NAMES:
-        a, b = to_np(getattr(g1, k)), to_np(getattr(g2, k))
-        # the two runs sum their float atomics in different orders
-        np.testing.assert_allclose(b, 2 * a, rtol=1e-4, atol=1e-6 * np.abs(a).max())
+        a, b = to_np(getattr(g1, k)).astype(np.float64), to_np(getattr(g2, k)).astype(np.float64)
+        # float32 rounding of the chain rule on the GPU: relative to its magnitude (s)
+        tol = 2 * (10 + tiles) * u32 * ref["s"][k] + 1e-5 * ref["s"][k] + 2 * u32 * np.abs(b) + 1e-12
+        assert np.all(np.abs(b - 2 * a) <= tol), (k, float((np.abs(b - 2 * a) / tol).max()))
     api.zero_grads(g2, (100, 200))
     torch.cuda.synchronize()
     assert np.all(to_np(g2.means)[:, 100:200] == 0) and np.any(to_np(g2.means)[:, 200:] != 0)
