@@ -30,7 +30,8 @@
  * - Every data pointer is a DEVICE pointer owned by the caller, except `cams`, `bg`
  *   and `hp`, which are HOST pointers read before the call returns.  The library never
  *   allocates device memory; scratch space is a caller-provided workspace whose size
- *   the *_workspace_bytes() queries return.
+ *   the *_workspace_bytes() queries return (clsp_render_backward_noalloc instead uses a
+ *   fixed static device array of the library).
  * - Every call enqueues work on `stream` (a hipStream_t; NULL is the default stream)
  *   and returns without synchronising.  Inputs must stay valid until that work is done.
  * - Arguments are validated on the host before anything is enqueued.  On error nothing
@@ -341,6 +342,29 @@ clsp_status clsp_render_backward(const clsp_gaussians *g, const clsp_projected *
                                  const float *T_final, const uint32_t *n_contrib, const void *state,
                                  size_t state_bytes, const float *dL_dimage, const clsp_params *grads, void *ws,
                                  size_t ws_bytes, clsp_stream stream);
+
+/* ---------------------------------------------------------------------------------
+ * clsp_render_backward without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving or training loops, hosts
+ * that forbid allocation).  Same arguments, results and errors as clsp_render_backward
+ * minus ws/ws_bytes: the screen-space gradients live in a static device array of
+ * CLSP_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on until the
+ * process ends, so the call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine).  The array's address on the current device is looked up on the
+ * first call made with that device current.  The call clears the part it uses before
+ * use (by a kernel on `stream`), so nothing carries over from an earlier call.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams, or from different host threads, without ordering between them)
+ * race and give wrong gradients.
+ * Errors: as clsp_render_backward, plus (active.end - active.begin) * n_views *
+ * clsp_render_backward_workspace_bytes(1, 1) > CLSP_NOALLOC_SCRATCH_BYTES, and a non-NULL
+ * stream that belongs to another device than the current one (CLSP_ERR_INVALID_ARG). */
+#define CLSP_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+clsp_status clsp_render_backward_noalloc(const clsp_gaussians *g, const clsp_projected *proj, const clsp_bins *bins,
+                                         const clsp_camera *cams, int32_t n_views, const float *bg, clsp_range active,
+                                         const float *T_final, const uint32_t *n_contrib, const void *state,
+                                         size_t state_bytes, const float *dL_dimage, const clsp_params *grads,
+                                         clsp_stream stream);
 
 /* ---------------------------------------------------------------------------------
  * Masked Adam (Supp. "3DGS Optimization in Changed Regions": gradients and optimiser

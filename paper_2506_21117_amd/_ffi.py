@@ -25,6 +25,7 @@ EXPORTED = (
     "clsp_l1_loss_grad",
     "clsp_render_backward_workspace_bytes",
     "clsp_render_backward", "clsp_masked_adam_step", "clsp_zero_grads", "clsp_render_backward_adam",
+    "clsp_render_backward_noalloc",
 )
 
 
@@ -116,6 +117,10 @@ def load(path: Path | None = None):
     L.clsp_render_backward.argtypes = [POINTER(Gaussians), POINTER(Projected), POINTER(Bins), POINTER(Camera), c_int32,
                                        POINTER(c_float), Range, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p,
                                        POINTER(Params), c_void_p, c_size_t, c_void_p]
+    L.clsp_render_backward_noalloc.restype = st
+    L.clsp_render_backward_noalloc.argtypes = [POINTER(Gaussians), POINTER(Projected), POINTER(Bins), POINTER(Camera),
+                                               c_int32, POINTER(c_float), Range, c_void_p, c_void_p, c_void_p,
+                                               c_size_t, c_void_p, POINTER(Params), c_void_p]
     L.clsp_masked_adam_step.restype = st
     L.clsp_masked_adam_step.argtypes = [POINTER(Params), POINTER(Params), POINTER(Params), POINTER(Params), Range,
                                         c_void_p, POINTER(AdamHParams), c_void_p]

@@ -327,6 +327,20 @@ def render_backward(g: GaussianTensors, proj, bins, cams, bg, active, T_final, n
     return grads
 
 
+def render_backward_noalloc(g: GaussianTensors, proj, bins, cams, bg, active, T_final, n_contrib, state, dL,
+                            grads: GaussianTensors, stream=None):
+    """``render_backward`` with the library's static scratch instead of a workspace (the
+    call allocates no device memory); calls that overlap on one GPU race."""
+    a0, a1 = (0, g.n) if active is None else (int(active[0]), int(active[1]))
+    bgc = (ctypes.c_float * 3)(*[float(x) for x in bg])
+    check(lib().clsp_render_backward_noalloc(ctypes.byref(g.as_gaussians()), ctypes.byref(proj.struct()),
+                                             ctypes.byref(bins.struct()), camera_array(cams), len(cams), bgc,
+                                             _ffi.Range(a0, a1), _ptr(T_final), _ptr(n_contrib), _ptr(state),
+                                             0 if state is None else state.numel(), _ptr(dL),
+                                             ctypes.byref(grads.as_params()), _stream(stream)))
+    return grads
+
+
 def zero_grads(grads: GaussianTensors, active=None, stream=None):
     a0, a1 = (0, grads.n) if active is None else (int(active[0]), int(active[1]))
     check(lib().clsp_zero_grads(ctypes.byref(grads.as_params()), _ffi.Range(a0, a1), _stream(stream)))

@@ -4,7 +4,14 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <mutex>
+
 #include "internal.hpp"
+
+// Screen-space gradient scratch of clsp_render_backward_noalloc, one copy per GPU.  In
+// host code this name stands for the variable, not for its device address: host code
+// passes only the address hipGetSymbolAddress returned for the current device.
+static __device__ __align__(256) float scratch[CLSP_NOALLOC_SCRATCH_BYTES / sizeof(float)];
 
 namespace {
 
@@ -150,6 +157,75 @@ clsp_status check_bins_ws(const clsp_bins* b, const clsp::BinPlan& plan) {
     if (_s != CLSP_OK) return _s;       \
   } while (0)
 
+// Device address of `scratch` on each GPU, looked up on the first call made with that
+// GPU current.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[MAX_DEVICES] = {};
+
+clsp_status scratch_for_stream(hipStream_t s, float** out) {
+  int dev = -1;
+  CHECK(hip_status(hipGetDevice(&dev), "hipGetDevice"));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(CLSP_ERR_UNSUPPORTED, "device %d beyond the %d supported", dev, MAX_DEVICES);
+  if (s) {
+    hipDevice_t sdev = -1;
+    CHECK(hip_status(hipStreamGetDevice(s, &sdev), "hipStreamGetDevice"));
+    if (sdev != dev)
+      return fail(CLSP_ERR_INVALID_ARG, "stream belongs to device %d but device %d is current", (int)sdev, dev);
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    CHECK(hip_status(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"));
+    if (!p) return fail(CLSP_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return CLSP_OK;
+}
+
+// Validation shared by clsp_render_backward and clsp_render_backward_noalloc.
+clsp_status check_render_backward(const clsp_gaussians* g, const clsp_projected* proj, const clsp_bins* bins,
+                                  const clsp_camera* cams, int32_t n_views, const float* bg, clsp_range active,
+                                  const float* T_final, const uint32_t* n_contrib, const void* state,
+                                  size_t state_bytes, const float* dL_dimage, const clsp_params* grads) {
+  CHECK(check_gaussians(g));
+  if (g->gather) return fail(CLSP_ERR_INVALID_ARG, "render_backward needs un-gathered parameters");
+  CHECK(check_projected(proj));
+  CHECK(check_bins(bins));
+  CHECK(check_cams(cams, n_views));
+  CHECK(check_params(grads, "grads"));
+  CHECK(check_range(active, g->n));
+  if (grads->n != g->n || grads->sh_degree != g->sh_degree)
+    return fail(CLSP_ERR_INVALID_ARG, "grads layout differs from the parameters");
+  if (!bg || !T_final || !n_contrib || !dL_dimage) return fail(CLSP_ERR_INVALID_ARG, "render_backward input is NULL");
+  if (!state || state_bytes < clsp_render_state_bytes(n_views, cams[0].width, cams[0].height))
+    return fail(CLSP_ERR_INVALID_ARG, "render_backward needs the forward's state (%zu bytes)",
+                clsp_render_state_bytes(n_views, cams[0].width, cams[0].height));
+  return CLSP_OK;
+}
+
+// The raster backward into g2d (cleared first), then the preprocess backward per view.
+clsp_status run_render_backward(const clsp_gaussians* g, const clsp_projected* proj, const clsp_bins* bins,
+                                const clsp_camera* cams, int32_t n_views, const float* bg, clsp_range active,
+                                const float* T_final, const uint32_t* n_contrib, const void* state,
+                                const float* dL_dimage, const clsp_params* grads, float* g2d, hipStream_t s,
+                                const char* what) {
+  const int W = cams[0].width, H = cams[0].height;
+  const int TX = (W + CLSP_TILE - 1) / CLSP_TILE, TY = (H + CLSP_TILE - 1) / CLSP_TILE;
+  CHECK(hip_status(clsp::launch_render_backward(*proj, *bins, n_views, g->n, W, H, TX, TY, bg, active.begin,
+                                                active.end, T_final, n_contrib, const_cast<void*>(state), dL_dimage,
+                                                g2d, s),
+                   what));
+  const clsp::RawParams rp = raw_params(g);
+  const clsp::MutParams gm = mut_params(grads);
+  for (int v = 0; v < n_views; ++v)
+    CHECK(hip_status(clsp::launch_preprocess_backward(rp, dev_cam(cams[v]), v, active.begin, active.end, proj->flags,
+                                                      g2d, gm, bins->counters + 1, s),
+                     what));
+  return CLSP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -279,39 +355,38 @@ clsp_status clsp_render_backward(const clsp_gaussians* g, const clsp_projected* 
                                  const float* T_final, const uint32_t* n_contrib, const void* state,
                                  size_t state_bytes, const float* dL_dimage, const clsp_params* grads, void* ws,
                                  size_t ws_bytes, clsp_stream stream) {
-  CHECK(check_gaussians(g));
-  if (g->gather) return fail(CLSP_ERR_INVALID_ARG, "render_backward needs un-gathered parameters");
-  CHECK(check_projected(proj));
-  CHECK(check_bins(bins));
-  CHECK(check_cams(cams, n_views));
-  CHECK(check_params(grads, "grads"));
-  CHECK(check_range(active, g->n));
-  if (grads->n != g->n || grads->sh_degree != g->sh_degree)
-    return fail(CLSP_ERR_INVALID_ARG, "grads layout differs from the parameters");
-  if (!bg || !T_final || !n_contrib || !dL_dimage) return fail(CLSP_ERR_INVALID_ARG, "render_backward input is NULL");
-  if (!state || state_bytes < clsp_render_state_bytes(n_views, cams[0].width, cams[0].height))
-    return fail(CLSP_ERR_INVALID_ARG, "render_backward needs the forward's state (%zu bytes)",
-                clsp_render_state_bytes(n_views, cams[0].width, cams[0].height));
+  CHECK(check_render_backward(g, proj, bins, cams, n_views, bg, active, T_final, n_contrib, state, state_bytes,
+                              dL_dimage, grads));
   const int64_t na = active.end - active.begin;
   const size_t need = clsp_render_backward_workspace_bytes(na, n_views);
   if (na > 0 && (!ws || ws_bytes < need))
     return fail(CLSP_ERR_INVALID_ARG, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
   if (na == 0) return CLSP_OK;
-  const int W = cams[0].width, H = cams[0].height;
-  const int TX = (W + CLSP_TILE - 1) / CLSP_TILE, TY = (H + CLSP_TILE - 1) / CLSP_TILE;
+  return run_render_backward(g, proj, bins, cams, n_views, bg, active, T_final, n_contrib, state, dL_dimage, grads,
+                             static_cast<float*>(ws), reinterpret_cast<hipStream_t>(stream), "render_backward");
+}
+
+clsp_status clsp_render_backward_noalloc(const clsp_gaussians* g, const clsp_projected* proj, const clsp_bins* bins,
+                                         const clsp_camera* cams, int32_t n_views, const float* bg, clsp_range active,
+                                         const float* T_final, const uint32_t* n_contrib, const void* state,
+                                         size_t state_bytes, const float* dL_dimage, const clsp_params* grads,
+                                         clsp_stream stream) {
+  CHECK(check_render_backward(g, proj, bins, cams, n_views, bg, active, T_final, n_contrib, state, state_bytes,
+                              dL_dimage, grads));
+  const int64_t na = active.end - active.begin;
+  const size_t need = clsp_render_backward_workspace_bytes(na, n_views);
+  if (need > CLSP_NOALLOC_SCRATCH_BYTES)
+    return fail(CLSP_ERR_INVALID_ARG,
+                "render_backward_noalloc: %lld active Gaussians x %d views need %zu bytes of scratch, more than its "
+                "%zu (at most %lld active Gaussian-views)",
+                (long long)na, n_views, need, (size_t)CLSP_NOALLOC_SCRATCH_BYTES,
+                (long long)(CLSP_NOALLOC_SCRATCH_BYTES / clsp_render_backward_workspace_bytes(1, 1)));
+  if (na == 0) return CLSP_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  float* g2d = static_cast<float*>(ws);
-  CHECK(hip_status(clsp::launch_render_backward(*proj, *bins, n_views, g->n, W, H, TX, TY, bg, active.begin,
-                                                active.end, T_final, n_contrib, const_cast<void*>(state), dL_dimage,
-                                                g2d, s),
-                   "render_backward"));
-  const clsp::RawParams rp = raw_params(g);
-  const clsp::MutParams gm = mut_params(grads);
-  for (int v = 0; v < n_views; ++v)
-    CHECK(hip_status(clsp::launch_preprocess_backward(rp, dev_cam(cams[v]), v, active.begin, active.end, proj->flags,
-                                                      g2d, gm, bins->counters + 1, s),
-                     "preprocess_backward"));
-  return CLSP_OK;
+  float* g2d = nullptr;
+  CHECK(scratch_for_stream(s, &g2d));
+  return run_render_backward(g, proj, bins, cams, n_views, bg, active, T_final, n_contrib, state, dL_dimage, grads,
+                             g2d, s, "render_backward_noalloc");
 }
 
 clsp_status clsp_masked_adam_step(const clsp_params* params, const clsp_params* grads, const clsp_params* exp_avg,

@@ -171,6 +171,20 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
                                   ctypes.byref(p), fake, 1 << 20, None) == _ffi.CLSP_ERR_INVALID_ARG
     assert b"state" in L.clsp_last_error()
     assert L.clsp_render_state_bytes(1, 64, 48) >= 12 * 8 * 256 * 16
+    # the allocation-free backward refuses change sets whose screen-space gradients
+    # exceed its static scratch (32 MiB / 48 B per active Gaussian and view = 699 050)
+    big_n = 700_000
+    gb = _ffi.Gaussians(fake, fake, fake, fake, fake, None, big_n, big_n, 0, 0)
+    pb = _ffi.Params(fake, fake, fake, fake, fake, big_n, 0, 0)
+    bb = _ffi.Bins(fake, fake, fake, fake, fake, fake, fake, fake, fake, 1 << 40, 100, big_n, 1, 0)
+    assert L.clsp_render_backward_noalloc(ctypes.byref(gb), ctypes.byref(proj), ctypes.byref(bb), cam, 1,
+                                          (ctypes.c_float * 3)(0, 0, 0), _ffi.Range(0, big_n), fake, fake, fake,
+                                          1 << 30, fake, ctypes.byref(pb), None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert b"scratch" in L.clsp_last_error()
+    assert L.clsp_render_backward_noalloc(ctypes.byref(g), ctypes.byref(proj), ctypes.byref(bins), cam, 1,
+                                          (ctypes.c_float * 3)(0, 0, 0), _ffi.Range(0, 10), fake, fake, None, 0, fake,
+                                          ctypes.byref(p), None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert b"state" in L.clsp_last_error()
 
 
 def test_missing_library_fails_loudly(tmp_path):
