@@ -57,7 +57,8 @@ def lib():
         L.orc_render.argtypes = [i64, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, i64, ip, dp, dp, ip, ip,
                                  dp, dp, dp, ip, dp, dp]
         L.orc_render.restype = ctypes.c_int
-        L.orc_preprocess_backward.argtypes = [i64, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_preprocess_backward.argtypes = [i64, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
+                                              ctypes.c_int]
         L.orc_preprocess_backward.restype = ctypes.c_int
         L.orc_error_bounds.argtypes = [i64, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp]
         L.orc_error_bounds.restype = ctypes.c_int
@@ -134,13 +135,14 @@ def preprocess(scene, cam, params=None) -> dict:
 def error_bounds(scene, cam, params=None) -> dict:
     """Per-Gaussian bounds on the error of a float32 evaluation of the projected
     quantities (see err_bounds in oracle.c): ``u``, ``v`` (pixels), ``K`` (each conic
-    entry) and ``rgb`` [N, 3]; zero for culled Gaussians."""
+    entry), ``rgb`` [N, 3], ``cov`` (each screen-covariance entry) and ``det`` (relative
+    error of the conic from the rounding of its inversion); zero for culled Gaussians."""
     n = scene.n
     args = _scene_args(scene, params)
-    out = np.zeros((n, 6))
+    out = np.zeros((n, 8))
     rc = lib().orc_error_bounds(n, scene.sh_degree, *[_p(a) for a in args], _p(cam_vec(cam)), _p(out))
     assert rc == 0, rc
-    return {"u": out[:, 0], "v": out[:, 1], "K": out[:, 2], "rgb": out[:, 3:6]}
+    return {"u": out[:, 0], "v": out[:, 1], "K": out[:, 2], "rgb": out[:, 3:6], "cov": out[:, 6], "det": out[:, 7]}
 
 
 def all_pixels(width, height) -> np.ndarray:
@@ -217,15 +219,17 @@ def split_raw(g: np.ndarray, sh_degree: int) -> dict:
 def preprocess_backward(scene, cam, grad2d, s2d=None, params=None, e2d=None) -> dict:
     """Raw-parameter gradients (SoA dict) from a screen-space gradient [N, 9]; with
     ``s2d`` also the absolute-term bound ``s`` of each entry (same layout, key
-    ``"s"``); with ``e2d`` (a screen-space error bound) that bound carried to the raw
-    parameters through the absolute value of the chain rule (key ``"e"``)."""
+    ``"s"``: ``s2d`` carried through the chain rule evaluated on absolute values, the
+    size of the terms a float32 evaluation rounds before they cancel); with ``e2d`` (a
+    screen-space error bound) that bound carried to the raw parameters through the
+    absolute values of the exact Jacobian (key ``"e"``)."""
     n = scene.n
     P = n_raw(scene.sh_degree)
     args = _scene_args(scene, params)
     g = np.zeros((n, P))
     sr = np.zeros((n, P)) if s2d is not None else None
     rc = lib().orc_preprocess_backward(n, scene.sh_degree, *[_p(a) for a in args], _p(cam_vec(cam)),
-                                       _p(_f64(grad2d)), _p(None if s2d is None else _f64(s2d)), _p(g), _p(sr))
+                                       _p(_f64(grad2d)), _p(None if s2d is None else _f64(s2d)), _p(g), _p(sr), 1)
     assert rc == 0, rc
     res = split_raw(g, scene.sh_degree)
     if sr is not None:
@@ -234,7 +238,7 @@ def preprocess_backward(scene, cam, grad2d, s2d=None, params=None, e2d=None) -> 
         er = np.zeros((n, P))
         scratch = np.zeros((n, P))
         rc = lib().orc_preprocess_backward(n, scene.sh_degree, *[_p(a) for a in args], _p(cam_vec(cam)),
-                                           _p(_f64(grad2d)), _p(_f64(e2d)), _p(scratch), _p(er))
+                                           _p(_f64(grad2d)), _p(_f64(e2d)), _p(scratch), _p(er), 0)
         assert rc == 0, rc
         res["e"] = split_raw(er, scene.sh_degree)
     return res

@@ -180,6 +180,8 @@ typedef struct {
    * (not part of the method: they size the comparison bar, see err_bounds()) */
   double e_u, e_v;       /* absolute error of u, v (pixels) */
   double e_K;            /* absolute error of each conic entry */
+  double e_cov;          /* absolute error of each screen-covariance entry */
+  double e_det;          /* relative error of the conic from its inversion's rounding */
   double e_rgb[3];       /* absolute error of each colour channel */
 } gstate_t;
 
@@ -192,6 +194,11 @@ typedef struct {
 #define ORC_F_NEAR 64          /* some Gaussian-level decision is near its threshold */
 
 static int near_rel(double x, double thr) { return fabs(x - thr) <= NEAR_REL * fabs(thr); }
+/* x (> 0) within a factor exp(max(NEAR_REL, rel)) of thr (> 0): rel bounds the error of
+ * ln x in a float32 evaluation of x, so the decision x vs thr may go either way there */
+static int near_band(double x, double thr, double rel) {
+  return fabs(log(x / thr)) <= fmax(NEAR_REL, rel);
+}
 
 /* Rotation matrix of a unit quaternion (w, x, y, z). */
 static void quat_to_rot(const double q[4], double R[9]) {
@@ -392,6 +399,11 @@ static void err_bounds(const scene_t *sc, int64_t i, const cam_t *cam, const dou
   if (fabs(g->conic[1]) > Kmax) Kmax = fabs(g->conic[1]);
   if (fabs(g->conic[2]) > Kmax) Kmax = fabs(g->conic[2]);
   g->e_K = 4.0 * U32 * Kmax + 2.0 * Ecov / (lmin * lmin);
+  /* the inversion K = (c, -b, a) / (ac - b^2) rounds the determinant relative to
+   * (|ac| + b^2) / |ac - b^2| (cancellation for elongated footprints), then the
+   * reciprocal and the products */
+  g->e_cov = Ecov;
+  g->e_det = 2.0 * U32 * (fabs(a * c) + b * b) / fabs(a * c - b * b) + 3.0 * U32;
   /* colour */
   double cp[3];
   for (int a2 = 0; a2 < 3; ++a2)
@@ -440,8 +452,8 @@ int orc_preprocess(int64_t n, int sh_degree, const double *means, const double *
   return ORC_OK;
 }
 
-/* The float32 error bounds of err_bounds() per Gaussian (stride 6): e_u, e_v, e_K,
- * e_rgb[3]; zero for culled Gaussians. */
+/* The float32 error bounds of err_bounds() per Gaussian (stride 8): e_u, e_v, e_K,
+ * e_rgb[3], e_cov, e_det; zero for culled Gaussians. */
 int orc_error_bounds(int64_t n, int sh_degree, const double *means, const double *log_scales, const double *quats,
                      const double *opac, const double *sh, const double *camv, double *out) {
   if (n < 0 || sh_degree < 0 || sh_degree > 3) return ORC_EINVAL;
@@ -451,9 +463,10 @@ int orc_error_bounds(int64_t n, int sh_degree, const double *means, const double
   for (int64_t i = 0; i < n; ++i) {
     gstate_t g;
     project_one(&sc, i, &cam, &g);
-    double *o = out + 6 * i;
-    if (!g.visible) { for (int k = 0; k < 6; ++k) o[k] = 0.0; continue; }
+    double *o = out + 8 * i;
+    if (!g.visible) { for (int k = 0; k < 8; ++k) o[k] = 0.0; continue; }
     o[0] = g.e_u; o[1] = g.e_v; o[2] = g.e_K; o[3] = g.e_rgb[0]; o[4] = g.e_rgb[1]; o[5] = g.e_rgb[2];
+    o[6] = g.e_cov; o[7] = g.e_det;
   }
   return ORC_OK;
 }
@@ -475,6 +488,7 @@ typedef struct {
   int visible;
   float z32;
   double e_u, e_v, e_K, e_rgb[3];   /* float32 error bounds (err_bounds) */
+  double e_cov, e_det;
 } rstate_t;
 
 typedef struct {
@@ -527,7 +541,7 @@ int orc_render(int64_t n, int sh_degree, const double *means, const double *log_
     r->u = g.u; r->v = g.v;
     for (int k = 0; k < 3; ++k) { r->conic[k] = g.conic[k]; r->rgb[k] = g.rgb[k]; }
     r->o = g.o; r->flags = g.flags; r->visible = g.visible; r->z32 = g.z32;
-    r->e_u = g.e_u; r->e_v = g.e_v; r->e_K = g.e_K;
+    r->e_u = g.e_u; r->e_v = g.e_v; r->e_K = g.e_K; r->e_cov = g.e_cov; r->e_det = g.e_det;
     for (int k = 0; k < 3; ++k) r->e_rgb[k] = g.e_rgb[k];
     if (pert && r->visible) {
       const double *x = pert + 9 * i;
@@ -562,6 +576,7 @@ int orc_render(int64_t n, int sh_degree, const double *means, const double *log_
       if (err) continue;
       const double px = pix[2 * p] + 0.5, py = pix[2 * p + 1] + 0.5;
       double T = 1.0, C[3] = {0.0, 0.0, 0.0};
+      double relT = 0.0;   /* bound on the relative float32 error of T */
       size_t nc = 0, nn = 0;
       int flag = 0;
       for (int64_t r = 0; r < nv && !err; ++r) {
@@ -574,23 +589,35 @@ int orc_render(int64_t n, int sh_degree, const double *means, const double *log_
         int near = (qf < NEAR_REL * qabs);
         const double power = -0.5 * qf;
         int action; /* 0 skip, 1 blend, 2 stop */
-        double G = 0.0, alpha = 0.0, Tn = T;
+        double G = 0.0, alpha = 0.0, Tn = T, relTn = relT;
         int clamped = 0;
         if (power > 0.0) {
           action = 0;
         } else {
           G = exp(power);
           const double oG = g->o * G;
-          /* decision 2: alpha clamp; decision 3: alpha skip; decision 4: stop */
-          if (near_rel(oG, a_max)) near = 1;
+          /* float32 error of ln(o G) = ln o + power: the centre's error bounds times
+           * |d power/d (u, v)| = |K d|; the covariance's, through the inverse (d power =
+           * (K d)^T dS (K d) / 2, |dS| <= 2 e_cov), |K d|^2 e_cov; the inversion's
+           * rounding, |power| e_det; the evaluation of the quadratic form (4 U32 of the
+           * sum of its absolute terms); the opacity and the exponential (4 U32 each) */
+          const double Ku = A * dx + B * dy, Kv = B * dx + Cc * dy;
+          const double rel_a = fabs(Ku) * g->e_u + fabs(Kv) * g->e_v + (Ku * Ku + Kv * Kv) * g->e_cov +
+                               0.5 * qf * g->e_det + 4.0 * U32 * qabs + 8.0 * U32;
+          /* decision 2: alpha clamp; decision 3: alpha skip; decision 4: stop; each
+           * flagged when its value lies within its float32 error of the threshold */
+          if (near_band(oG, a_max, rel_a)) near = 1;
           clamped = !(oG < a_max);
           alpha = clamped ? a_max : oG;
-          if (near_rel(alpha, a_min)) near = 1;
+          if (near_band(alpha, a_min, rel_a)) near = 1;
           if (alpha < a_min) {
             action = 0;
           } else {
             Tn = T * (1.0 - alpha);
-            if (near_rel(Tn, t_stop)) near = 1;
+            /* T' = T (1 - alpha): the relative error of 1 - alpha is alpha/(1 - alpha)
+             * times alpha's (to first order), plus the product's rounding */
+            relTn = relT + (clamped ? 0.0 : alpha / (1.0 - alpha) * rel_a) + 2.0 * U32;
+            if (near_band(Tn, t_stop, relTn)) near = 1;
             action = (Tn < t_stop) ? 2 : 1;
           }
         }
@@ -617,6 +644,7 @@ int orc_render(int64_t n, int sh_degree, const double *means, const double *log_
         ++nc;
         for (int ch = 0; ch < 3; ++ch) C[ch] += alpha * T * g->rgb[ch];
         T = Tn;
+        relT = relTn;
       }
       for (int ch = 0; ch < 3; ++ch) out_rgb[3 * p + ch] = C[ch] + T * bg[ch];
       out_T[p] = T;
@@ -713,12 +741,21 @@ int orc_render(int64_t n, int sh_degree, const double *means, const double *log_
 /* ------------------------------------------------------------------ preprocess backward */
 /* Chain rule from the screen-space gradient d2[9] (u, v, A, B, C, o, r, g, b) of
  * Gaussian i to its raw parameters: means(3), log_scales(3), quats(4), opacity
- * logit(1), sh[k][ch] (3K), written to out[]. */
+ * logit(1), sh[k][ch] (3K), written to out[].
+ *
+ * With magnitude != 0 the same chain is evaluated on absolute values: every factor of
+ * every product and every term of every sum is replaced by its absolute value (each SH
+ * basis value by the magnitude of its monomials).  That is the size of the terms a
+ * float32 evaluation of the chain rounds, in any order, before they cancel: for an
+ * isotropic Gaussian, for instance, the quaternion gradient is exactly zero, yet a
+ * float32 evaluation leaves a residue of a few U32 of these terms. */
+#define AB(x) (magnitude ? fabs(x) : (x))
 static void backward_one(const scene_t *sc, int64_t i, const cam_t *cam, const gstate_t *g, const double d2[9],
                          double *out, int magnitude) {
   const int64_t n = sc->n;
   const int K = (sc->sh_degree + 1) * (sc->sh_degree + 1);
   const int P = 11 + 3 * K;
+  const double sg = magnitude ? 1.0 : -1.0;   /* the sign of a subtracted term */
   for (int k = 0; k < P; ++k) out[k] = 0.0;
   if (!g->visible) return;
   double dmu[3] = {0, 0, 0};
@@ -730,29 +767,30 @@ static void backward_one(const scene_t *sc, int64_t i, const cam_t *cam, const g
     sh_basis_grad(g->dir, dY);
     double ddir[3] = {0, 0, 0};
     for (int ch = 0; ch < 3; ++ch) {
-      const double gp = (g->pre[ch] < 0.0) ? 0.0 : d2[6 + ch];
+      const double gp = (g->pre[ch] < 0.0) ? 0.0 : AB(d2[6 + ch]);
       for (int k = 0; k < K; ++k) {
         out[11 + 3 * k + ch] = gp * Yb[k];
-        const double f = sc->sh[((int64_t)k * 3 + ch) * n + i];
-        for (int a = 0; a < 3; ++a) ddir[a] += gp * f * dY[k][a];
+        const double f = AB(sc->sh[((int64_t)k * 3 + ch) * n + i]);
+        for (int a = 0; a < 3; ++a) ddir[a] += gp * f * AB(dY[k][a]);
       }
     }
-    const double dd = g->dir[0] * ddir[0] + g->dir[1] * ddir[1] + g->dir[2] * ddir[2];
-    for (int a = 0; a < 3; ++a) dmu[a] += (ddir[a] - g->dir[a] * dd) / g->dist;
+    double dd = 0.0;
+    for (int a = 0; a < 3; ++a) dd += AB(g->dir[a]) * ddir[a];
+    for (int a = 0; a < 3; ++a) dmu[a] += (ddir[a] + sg * AB(g->dir[a]) * dd) / g->dist;
   }
 
   /* opacity */
-  out[10] = d2[5] * g->o * (1.0 - g->o);
+  out[10] = AB(d2[5]) * g->o * (1.0 - g->o);
 
   /* conic -> screen covariance: dL/dcov2 = -K GK K, with GK symmetric and the
    * off-diagonal conic entry B appearing twice */
-  const double Kc[4] = {g->conic[0], g->conic[1], g->conic[1], g->conic[2]};
-  const double GK[4] = {d2[2], 0.5 * d2[3], 0.5 * d2[3], d2[4]};
+  const double Kc[4] = {AB(g->conic[0]), AB(g->conic[1]), AB(g->conic[1]), AB(g->conic[2])};
+  const double GK[4] = {AB(d2[2]), 0.5 * AB(d2[3]), 0.5 * AB(d2[3]), AB(d2[4])};
   double KG[4], GC2[4];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) KG[2 * a + b] = Kc[2 * a] * GK[b] + Kc[2 * a + 1] * GK[2 + b];
   for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) GC2[2 * a + b] = -(KG[2 * a] * Kc[b] + KG[2 * a + 1] * Kc[2 + b]);
+    for (int b = 0; b < 2; ++b) GC2[2 * a + b] = sg * (KG[2 * a] * Kc[b] + KG[2 * a + 1] * Kc[2 + b]);
 
   /* cov2 = M Sigma M^T + 0.3 I:  dSigma = M^T GC2 M,  dM = 2 GC2 M Sigma */
   double GSig[9];
@@ -760,7 +798,7 @@ static void backward_one(const scene_t *sc, int64_t i, const cam_t *cam, const g
     for (int b = 0; b < 3; ++b) {
       double acc = 0.0;
       for (int r = 0; r < 2; ++r)
-        for (int c = 0; c < 2; ++c) acc += g->M[3 * r + a] * GC2[2 * r + c] * g->M[3 * c + b];
+        for (int c = 0; c < 2; ++c) acc += AB(g->M[3 * r + a]) * GC2[2 * r + c] * AB(g->M[3 * c + b]);
       GSig[3 * a + b] = acc;
     }
   double GM[6];
@@ -768,7 +806,7 @@ static void backward_one(const scene_t *sc, int64_t i, const cam_t *cam, const g
     for (int b = 0; b < 3; ++b) {
       double acc = 0.0;
       for (int c = 0; c < 2; ++c)
-        for (int k = 0; k < 3; ++k) acc += 2.0 * GC2[2 * r + c] * g->M[3 * c + k] * g->Sigma[3 * k + b];
+        for (int k = 0; k < 3; ++k) acc += 2.0 * GC2[2 * r + c] * AB(g->M[3 * c + k]) * AB(g->Sigma[3 * k + b]);
       GM[3 * r + b] = acc;
     }
   /* M = J Rcam:  dJ = dM Rcam^T */
@@ -776,37 +814,37 @@ static void backward_one(const scene_t *sc, int64_t i, const cam_t *cam, const g
   for (int r = 0; r < 2; ++r)
     for (int k = 0; k < 3; ++k) {
       double acc = 0.0;
-      for (int b = 0; b < 3; ++b) acc += GM[3 * r + b] * cam->R[3 * k + b];
+      for (int b = 0; b < 3; ++b) acc += GM[3 * r + b] * AB(cam->R[3 * k + b]);
       GJ[3 * r + k] = acc;
     }
   /* J -> camera-space centre */
   const double X = g->p[0], Y = g->p[1], Z = g->p[2];
   const double fx = cam->fx, fy = cam->fy;
   double dX = 0, dY_ = 0, dZ = 0, dXt = 0, dYt = 0;
-  dZ += GJ[0] * (-fx / (Z * Z));
-  dXt += GJ[2] * (-fx / (Z * Z));
-  dZ += GJ[2] * (2.0 * fx * g->Xt / (Z * Z * Z));
-  dZ += GJ[4] * (-fy / (Z * Z));
-  dYt += GJ[5] * (-fy / (Z * Z));
-  dZ += GJ[5] * (2.0 * fy * g->Yt / (Z * Z * Z));
-  if (g->flags & ORC_F_CLAMPX) dZ += dXt * (g->Xt / Z); else dX += dXt;
-  if (g->flags & ORC_F_CLAMPY) dZ += dYt * (g->Yt / Z); else dY_ += dYt;
+  dZ += GJ[0] * AB(-fx / (Z * Z));
+  dXt += GJ[2] * AB(-fx / (Z * Z));
+  dZ += GJ[2] * AB(2.0 * fx * g->Xt / (Z * Z * Z));
+  dZ += GJ[4] * AB(-fy / (Z * Z));
+  dYt += GJ[5] * AB(-fy / (Z * Z));
+  dZ += GJ[5] * AB(2.0 * fy * g->Yt / (Z * Z * Z));
+  if (g->flags & ORC_F_CLAMPX) dZ += dXt * AB(g->Xt / Z); else dX += dXt;
+  if (g->flags & ORC_F_CLAMPY) dZ += dYt * AB(g->Yt / Z); else dY_ += dYt;
   /* projected centre */
-  dX += d2[0] * fx / Z;
-  dZ += d2[0] * (-fx * X / (Z * Z));
-  dY_ += d2[1] * fy / Z;
-  dZ += d2[1] * (-fy * Y / (Z * Z));
+  dX += AB(d2[0]) * fx / Z;
+  dZ += AB(d2[0]) * AB(-fx * X / (Z * Z));
+  dY_ += AB(d2[1]) * fy / Z;
+  dZ += AB(d2[1]) * AB(-fy * Y / (Z * Z));
   /* p = Rcam mu + t */
   const double dp[3] = {dX, dY_, dZ};
   for (int a = 0; a < 3; ++a)
-    dmu[a] += cam->R[a] * dp[0] + cam->R[3 + a] * dp[1] + cam->R[6 + a] * dp[2];
+    dmu[a] += AB(cam->R[a]) * dp[0] + AB(cam->R[3 + a]) * dp[1] + AB(cam->R[6 + a]) * dp[2];
   for (int a = 0; a < 3; ++a) out[a] = dmu[a];
 
   /* Sigma = Rq diag(s^2) Rq^T */
   for (int k = 0; k < 3; ++k) {
     double quad = 0.0;
     for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) quad += g->Rq[3 * a + k] * GSig[3 * a + b] * g->Rq[3 * b + k];
+      for (int b = 0; b < 3; ++b) quad += AB(g->Rq[3 * a + k]) * GSig[3 * a + b] * AB(g->Rq[3 * b + k]);
     const double ds = 2.0 * g->s[k] * quad;
     out[3 + k] = ds * g->s[k]; /* d/dlog_scale */
   }
@@ -814,30 +852,35 @@ static void backward_one(const scene_t *sc, int64_t i, const cam_t *cam, const g
   for (int a = 0; a < 3; ++a)
     for (int k = 0; k < 3; ++k) {
       double acc = 0.0;
-      for (int b = 0; b < 3; ++b) acc += 2.0 * GSig[3 * a + b] * g->Rq[3 * b + k] * g->s[k] * g->s[k];
+      for (int b = 0; b < 3; ++b) acc += 2.0 * GSig[3 * a + b] * AB(g->Rq[3 * b + k]) * g->s[k] * g->s[k];
       GR[3 * a + k] = acc;
     }
   double dR[4][9], dqn[4];
   quat_to_rot_grad(g->qn, dR);
   for (int m = 0; m < 4; ++m) {
     double acc = 0.0;
-    for (int e = 0; e < 9; ++e) acc += GR[e] * dR[m][e];
+    for (int e = 0; e < 9; ++e) acc += GR[e] * AB(dR[m][e]);
     dqn[m] = acc;
   }
   double dot = 0.0;
-  for (int m = 0; m < 4; ++m) dot += g->qn[m] * dqn[m];
-  for (int m = 0; m < 4; ++m) out[6 + m] = (dqn[m] - g->qn[m] * dot) / g->qnorm;
+  for (int m = 0; m < 4; ++m) dot += AB(g->qn[m]) * dqn[m];
+  for (int m = 0; m < 4; ++m) out[6 + m] = (dqn[m] + sg * AB(g->qn[m]) * dot) / g->qnorm;
 }
+#undef AB
 
 /*
  * grads[n][P] = chain rule of grad2d[n][9] (P = 11 + 3K raw parameters per Gaussian).
- * If s2d and s_raw are given, s_raw[n][P] = |Jac| s2d, an upper bound on the sum of
- * absolute per-pixel terms of each raw-parameter gradient (with each SH basis value
- * replaced by its monomial magnitude, which bounds its float32 evaluation error).
+ * If s2d and s_raw are given, s_raw[n][P] carries s2d[n][9] to the raw parameters
+ * column by column: with abs_chain != 0 through the chain rule evaluated on absolute
+ * values (backward_one with magnitude != 0), an upper bound on the sum of the absolute
+ * values of the terms each raw-parameter gradient is summed and chained from, which
+ * scales its float32 rounding; with abs_chain == 0 through the absolute values of the
+ * exact Jacobian, which carries a bound on the error of the screen-space gradient
+ * (first order) to the raw parameters.
  */
 int orc_preprocess_backward(int64_t n, int sh_degree, const double *means, const double *log_scales,
                             const double *quats, const double *opac, const double *sh, const double *camv,
-                            const double *grad2d, const double *s2d, double *grads, double *s_raw) {
+                            const double *grad2d, const double *s2d, double *grads, double *s_raw, int abs_chain) {
   if (n < 0 || sh_degree < 0 || sh_degree > 3) return ORC_EINVAL;
   scene_t sc; make_scene(&sc, n, sh_degree, means, log_scales, quats, opac, sh);
   cam_t cam; load_cam(camv, &cam);
@@ -855,7 +898,7 @@ int orc_preprocess_backward(int64_t n, int sh_degree, const double *means, const
       for (int c = 0; c < 9; ++c) {
         double e[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         e[c] = 1.0;
-        backward_one(&sc, i, &cam, &g, e, col, 1);
+        backward_one(&sc, i, &cam, &g, e, col, abs_chain ? 1 : 0);
         for (int k = 0; k < P; ++k) sr[k] += fabs(col[k]) * s2d[9 * i + c];
       }
     }

@@ -224,15 +224,21 @@ __global__ void __launch_bounds__(256) preprocess_kernel(RawParams g, DevCam cam
     rgb[ch] = acc;
   }
 
-  // extent of the ellipse alpha >= 1/255, and its tile rectangle
-  const float kappa = 2.0f * (__logf(q.o) + 5.541263545158426f);  // 2 ln(255 o)
-  const float kap = fmaxf(kappa, 0.0f);
-  const float rx = sqrtf(kap * q.a) * EXTENT_MARGIN;
-  const float ry = sqrtf(kap * q.c) * EXTENT_MARGIN;
-  const float fx0 = floorf(__fmul_rn(__fsub_rn(__fsub_rn(u, rx), 0.5f), 0.0625f));
-  const float fx1 = floorf(__fmul_rn(__fsub_rn(__fadd_rn(u, rx), 0.5f), 0.0625f)) + 1.0f;
-  const float fy0 = floorf(__fmul_rn(__fsub_rn(__fsub_rn(v, ry), 0.5f), 0.0625f));
-  const float fy1 = floorf(__fmul_rn(__fsub_rn(__fadd_rn(v, ry), 0.5f), 0.0625f)) + 1.0f;
+  // extent of the ellipse alpha >= 1/255, and its tile rectangle, evaluated from the
+  // rounded extents that are stored: no contraction here, or u + rx would be fused
+  // with rx's last product into an fma and round differently from the stored values
+  float rx, ry, fx0, fx1, fy0, fy1;
+  {
+#pragma clang fp contract(off)
+    const float kappa = 2.0f * (__logf(q.o) + 5.541263545158426f);  // 2 ln(255 o)
+    const float kap = fmaxf(kappa, 0.0f);
+    rx = sqrtf(kap * q.a) * EXTENT_MARGIN;
+    ry = sqrtf(kap * q.c) * EXTENT_MARGIN;
+    fx0 = floorf(((u - rx) - 0.5f) * 0.0625f);
+    fx1 = floorf(((u + rx) - 0.5f) * 0.0625f) + 1.0f;
+    fy0 = floorf(((v - ry) - 0.5f) * 0.0625f);
+    fy1 = floorf(((v + ry) - 0.5f) * 0.0625f) + 1.0f;
+  }
   const uint32_t x0 = (uint32_t)fminf(fmaxf(fx0, 0.0f), (float)cam.TX);
   const uint32_t x1 = (uint32_t)fminf(fmaxf(fx1, 0.0f), (float)cam.TX);
   const uint32_t y0 = (uint32_t)fminf(fmaxf(fy0, 0.0f), (float)cam.TY);

@@ -58,17 +58,23 @@ def masked_pixels(bins, cam, view=0):
     return np.concatenate(out).astype(np.int32) if out else np.zeros((0, 2), np.int32), tiles
 
 
-def check_pixels(got_rgb, ref, what="", max_flagged=1e-3):
-    """got_rgb [M, 3] vs the oracle render dict of the same pixels; flagged pixels are
-    excused (and must be rare: at most a fraction ``max_flagged``, or 3)."""
-    ok = ref["flag"] == 0
+def check_pixels(got_rgb, ref, what="", max_excused=1e-3):
+    """got_rgb [M, 3] vs the oracle render dict of the same pixels.  A pixel outside the
+    tolerance is excused only when the oracle flags it (one of its decisions lies within
+    that decision's float32 error of its threshold, so a float32 evaluation may take it
+    either way); excused pixels must be rare: at most a fraction ``max_excused``, or 3."""
+    flagged = ref["flag"] != 0
     err = np.abs(got_rgb - ref["rgb"])
     tol = PIX_REL * np.abs(ref["rgb"]) + PIX_ABS
-    bad = (err > tol) & ok[:, None]
-    assert not bad.any(), (f"{what}: {bad.any(1).sum()} pixels outside tolerance; worst err "
-                           f"{err[bad].max():.3e} at ref {ref['rgb'][bad][np.argmax(err[bad])]:.4f}")
-    assert (~ok).mean() < max_flagged or (~ok).sum() <= 3, f"{what}: {(~ok).sum()} near-threshold pixels"
-    return float(err[np.broadcast_to(ok[:, None], err.shape)].max()) if ok.any() else 0.0
+    fail = (err > tol).any(1)
+    bad = fail & ~flagged
+    assert not bad.any(), (f"{what}: {bad.sum()} pixels outside tolerance; worst err "
+                           f"{err[bad].max():.3e} at ref {ref['rgb'][bad][np.argmax(err[bad].max(1))]}")
+    excused = fail & flagged
+    assert excused.mean() < max_excused or excused.sum() <= 3, (
+        f"{what}: {excused.sum()} excused pixels of {len(excused)} ({flagged.sum()} flagged)")
+    keep = ~excused
+    return float(err[keep].max()) if keep.any() else 0.0
 
 
 def check_grads(gpu: api.GaussianTensors, ref: dict, rows, what=""):

@@ -103,8 +103,12 @@ def test_float32_projection_stays_within_the_error_bounds(orc, name):
 
 @pytest.mark.parametrize("name", ["tiny", "sh3"])
 def test_gradient_bar_detects_two_percent_errors(orc, name):
-    """With the float32 term included, a 2% error of a gradient entry exceeds the bar
-    for at least 90% of the entries."""
+    """With the float32 terms included, a 2% error of a gradient entry exceeds the bar
+    for at least 90% of the entries, and at least 80% of the quaternion entries: the
+    quaternion gradient of a nearly isotropic Gaussian (these scenes draw each axis'
+    log-scale from N(-3, 0.5)) is a small difference of large terms, so the rounding
+    allowance s, the size of the terms a float32 evaluation cancels, is large against
+    its value (median s/|g| ~ 240 here against ~8 for the means)."""
     w = WORKLOADS[name]()
     cam = w.cameras[0]
     dl = np.random.default_rng(1).normal(size=(3, cam.height, cam.width))
@@ -113,4 +117,62 @@ def test_gradient_bar_detects_two_percent_errors(orc, name):
         o, s, e = ref[k], ref["s"][k], ref["e"][k]
         nz = s > 0
         tol = 1e-3 * np.abs(o) + 1e-5 * s + e
-        assert (tol[nz] < 0.02 * np.abs(o[nz])).mean() >= 0.9, k
+        assert (tol[nz] < 0.02 * np.abs(o[nz])).mean() >= (0.8 if k == "quats" else 0.9), k
+
+
+def test_rounding_allowance_covers_cancelled_quaternion_terms(orc):
+    """A Gaussian with three equal scales has an exactly zero quaternion gradient, but
+    its float32 evaluation cancels terms of the size of the other gradients: the
+    rounding allowance s is positive there and of that size, not zero."""
+    w = scenes.tiny(n=300)
+    sc = w.scene
+    sc.log_scales[:] = sc.log_scales[:1]          # equal scales per Gaussian
+    cam = w.cameras[0]
+    dl = np.random.default_rng(2).normal(size=(3, cam.height, cam.width))
+    ref = orc.gradients(sc, [cam], [dl], perturb=0)
+    hit = ref["s"]["means"].sum(0) > 0
+    assert hit.sum() > 50
+    assert np.all(np.abs(ref["quats"][:, hit]) <= 1e-12 * ref["s"]["quats"][:, hit] + 1e-300)
+    assert np.all(ref["s"]["quats"][1:, hit].max(0) > 1e-3 * np.abs(ref["means"][:, hit]).max(0))
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_float32_exponent_stays_within_its_bound(orc, name):
+    """The band in which the oracle flags a pixel's alpha decisions as near a threshold
+    (a float32 evaluation may take them either way) is its bound on the float32 error
+    of the exponent -d^T K d / 2: the centre's bounds times |K d|, the covariance's
+    times |K d|^2, the inversion's rounding times |exponent|, and the quadratic form's
+    own rounding.  An independent float32 evaluation of the exponent at pixel centres
+    on the alpha = 1/255 ellipse, in eight directions, stays inside it."""
+    w = WORKLOADS[name]()
+    cam = w.cameras[0]
+    ref = orc.preprocess(w.scene, cam)
+    eb = orc.error_bounds(w.scene, cam)
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        u32, v32, K32, _ = f32_projection(w.scene, cam)
+    vis = ref["visible"] & ((ref["flags"] & (orc.F_CLAMPX | orc.F_CLAMPY | orc.F_NEAR)) == 0)
+    idx = np.nonzero(vis)[0]
+    idx = np.random.default_rng(7).choice(idx, size=min(4000, len(idx)), replace=False)
+    A, B, C = ref["A"][idx], ref["B"][idx], ref["C"][idx]
+    kap = 2.0 * np.log(255.0 * ref["opacity"][idx])
+    u32 = u32.astype(np.float64)[idx].astype(F)
+    v32 = v32.astype(np.float64)[idx].astype(F)
+    K32 = K32[:, idx]
+    ratios = []
+    for th in np.arange(8) * np.pi / 8:
+        ex, ey = np.cos(th), np.sin(th)
+        r = np.sqrt(kap / (A * ex * ex + 2 * B * ex * ey + C * ey * ey))
+        px = np.floor(ref["u"][idx] + r * ex) + 0.5
+        py = np.floor(ref["v"][idx] + r * ey) + 0.5
+        dx, dy = px - ref["u"][idx], py - ref["v"][idx]
+        q = A * dx * dx + 2 * B * dx * dy + C * dy * dy
+        qabs = np.abs(A * dx * dx) + 2 * np.abs(B * dx * dy) + np.abs(C * dy * dy)
+        dx32, dy32 = px.astype(F) - u32, py.astype(F) - v32
+        q32 = K32[0] * dx32 * dx32 + F(2) * K32[1] * dx32 * dy32 + K32[2] * dy32 * dy32
+        Ku, Kv = A * dx + B * dy, B * dx + C * dy
+        bound = (np.abs(Ku) * eb["u"][idx] + np.abs(Kv) * eb["v"][idx] + (Ku * Ku + Kv * Kv) * eb["cov"][idx]
+                 + 0.5 * q * eb["det"][idx] + 4 * 2.0 ** -24 * qabs)
+        ratios.append(np.abs(0.5 * q32.astype(np.float64) - 0.5 * q) / bound)
+    r = np.concatenate(ratios)
+    assert r.max() < 0.7, float(r.max())
+    assert np.median(r) > 1e-3, float(np.median(r))

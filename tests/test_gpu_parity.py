@@ -469,9 +469,9 @@ def test_render_backward_deep_lists(dev, mode):
     ref = oracle.gradients(sc, cams, [vals.astype(np.float64)], bg, pixels=[pixels])
     got = to_np(img[0])[:, pixels[:, 1], pixels[:, 0]].T
     # each pixel takes thousands of alpha-threshold decisions here (faint Gaussians whose
-    # footprints end at alpha = 1/255), so more pixels than usual have one within 1e-5
-    # of its threshold; they are excused as everywhere, and counted
-    check_pixels(got, oracle.render(sc, cam, bg, pixels=pixels), "deep lists", max_flagged=0.03)
+    # footprints end at alpha = 1/255), so more pixels than usual have one within its
+    # float32 error of its threshold; they are excused as everywhere, and counted
+    check_pixels(got, oracle.render(sc, cam, bg, pixels=pixels), "deep lists", max_excused=0.03)
     worst = check_grads(grads, ref, slice(0, n), "deep lists")
     print(f"deep lists (max contributor position {per_tile.max()}): worst gradient error / tolerance {worst:.3f}")
 
