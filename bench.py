@@ -36,8 +36,14 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving latency leg")
     ap.add_argument("--no-visible", action="store_true",
                     help="skip the local leg whose change ball sits on the cube face z = +1 (visible)")
-    ap.add_argument("--qps", type=float, default=100.0, help="arrival rate of the serving leg")
-    ap.add_argument("--requests", type=int, default=400, help="requests of the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests per arrival rate of the serving sweep (closed loop, then Poisson at 0.25, 0.5 "
+                         "and 0.8 of the closed-loop rate)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the one-off timing of the full-scene (200k, SH3, 8 x 800x800) and differentiation "
+                         "(3M, SH3, 4 x 1920x1080) workloads")
+    ap.add_argument("--cpu-single", action="store_true",
+                    help="also time one complete oracle local step on one thread")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 10 times (the reference kernel of known size for "
                          "the HBM byte counters) and exit")
@@ -137,8 +143,14 @@ def main():
         if opt.overflowed():
             raise RuntimeError("pair capacity overflow during the timed steps")
         call_ms[dom] = float(np.mean([e[dom][0].elapsed_time(e[dom][1]) for e in ev]))
-        # algorithmic units of the timed calls, from the last step's state
-        stats = opt.render_stats()
+        # algorithmic units of a step: the timed steps cycle over the views, so a step's
+        # work is averaged over one more (untimed) step on every view
+        per_view = []
+        for vi in range(len(cams)):
+            opt.step(vi, stream)
+            torch.cuda.synchronize()
+            per_view.append(opt.render_stats())
+        stats = {k: float(np.mean([st[k] for st in per_view])) for k in per_view[0]}
         return dt, call_ms, stats, opt
 
     if args.only_full:
@@ -167,20 +179,27 @@ def main():
         t_v, ms_v, st_v, opt_v = run(True, sc=wv.scene, targets=tv, a=av, steps=max(args.steps // 2, 1))
         it_v = max(args.steps // 2, 1) / t_v
         log(f"visible change set {wv.name}: {it_v:.1f} it/s, calls {ms_v}, {st_v}")
+        over_v = None if res_full is None else it_v / res_full[0]
         visible = {"workload": wv.name, "active_gaussians": av[1] - av[0], "it_s": round(it_v, 3),
-                   "over_full": None if res_full is None else round(it_v / res_full[0], 3),
-                   "call_ms": {k: round(v, 4) for k, v in ms_v.items()}, "stats": st_v}
+                   "over_full": None if over_v is None else round(over_v, 3),
+                   "target_over_full": TARGET_LOCAL_OVER_FULL,
+                   "gap_to_target": None if over_v is None else round(TARGET_LOCAL_OVER_FULL / over_v, 3),
+                   "call_ms": {k: round(v, 4) for k, v in ms_v.items()}, "work_per_step": st_v,
+                   "roofline": roofline_of(ms_v, st_v, wv.scene.n)}
         del opt_v, tv
         torch.cuda.empty_cache()
 
     roofline = roofline_of(ms_local, st_local, sc.n)
     serving = None
     if not args.no_serve:
-        serving = serving_leg(dev, args.qps, args.requests, log)
+        serving = serving_leg(dev, args.serve_requests, log)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(sc, cams, a, w.scene_gt, order, args.cpu_seconds, log)
+        if args.cpu_single:
+            cpu["single_thread"] = cpu_single_thread(sc, cams, a, w.scene_gt, order, log)
 
+    others = None if args.no_configs else other_configs(dev, log)
     mpix = st_local["pixels"] * it_local / 1e6
     out = {
         "metric": "fwd+bwd it/s local vs full at 1M Gaussians 720p; render p50/p99 ms",
@@ -198,13 +217,20 @@ def main():
         "config": {"workload": w.name, "n_gaussians": sc.n, "width": cams[0].width, "height": cams[0].height,
                    "views": len(cams), "active_gaussians": a[1] - a[0], "mode": "local",
                    "masked_tile_frac": round(st_local["tiles"] / st_local["tiles_total"], 4),
-                   "pairs_local": st_local["pairs"]},
+                   "pairs_local": round(st_local["pairs"])},
         "local_mpix_s": round(mpix, 2),
         "full_it_s": None if res_full is None else round(res_full[0], 3),
         "local_over_full": None if res_full is None else round(it_local / res_full[0], 3),
-        "full_pairs": None if res_full is None else res_full[2]["pairs"],
-        "local_stats": st_local,
+        # the stated change set is hidden from every view (no record of it is ever
+        # composited, pixel_records_active = 0), so its local step computes no gradient;
+        # the visible-change leg below is the one whose local step does gradient work
+        "local_over_full_note": "stated change set occluded in all views (no gradient work); see "
+                                "visible_change_variant for the leg with gradient work and its gap to the 5x target",
+        "full_pairs": None if res_full is None else round(res_full[2]["pairs"]),
+        "local_work_per_step": st_local,
+        "full_work_per_step": None if res_full is None else res_full[2],
         "visible_change_variant": visible,
+        "other_configs": others,
         # the dominant call over the timed steps, the others over the second half of warm-up
         "call_ms_local": {k: round(v, 4) for k, v in ms_local.items()},
         "call_ms_full": None if res_full is None else {k: round(v, 4) for k, v in res_full[1].items()},
@@ -245,6 +271,9 @@ def measured_traffic(call):
         return None
     return MEASURED_TRAFFIC["bytes"].get(call)
 
+
+# The target ratio of the local step's rate to the full-scene step's on the same views.
+TARGET_LOCAL_OVER_FULL = 5.0
 
 # FP32 operations per (pixel, record) evaluation, counted from the model's formulas:
 # the Gaussian weight (offset 2, quadratic form 9, exp 1, opacity product and clamp 2),
@@ -290,14 +319,16 @@ def roofline_of(ms, st, n):
             "units": {"entries": n, "pairs": pairs, "algorithmic_bytes": byts}}
 
 
-def serving_leg(dev, qps, n_requests, log):
-    """Render latency of stored scene states under Poisson arrivals (the 2M-Gaussian
-    base with 7 change steps; resolutions 640x480, 1280x720, 1920x1080)."""
+def serving_leg(dev, n_requests, log):
+    """Render latency of stored scene states (the 2M-Gaussian base with 7 change steps;
+    resolutions 640x480, 1280x720, 1920x1080): the closed-loop rate X (every request
+    waiting at the start), then Poisson arrivals at 0.25 X, 0.5 X and 0.8 X, each with
+    ``n_requests`` requests; the headline is p50/p99 at 0.5 X."""
     import numpy as np
     import torch
 
     import scenes
-    from paper_2506_21117_amd.serve import Engine, GpuBackend, StateStore, poisson_requests
+    from paper_2506_21117_amd.serve import Engine, GpuBackend, Request, StateStore, poisson_requests
 
     t0 = time.time()
     states, history = scenes.serving_history(seed=5)
@@ -308,25 +339,107 @@ def serving_leg(dev, qps, n_requests, log):
     camfn = lambda r, W, H: scenes.sphere_camera(r, 4.0, width=W, height=H, fx=H / (2 * np.tan(np.radians(20))))
     be = GpuBackend(store, dev, max_slots=4)
     eng = Engine(be, hbm_budget_bytes=64 << 30, max_slots=4, max_batch=4)
-    # warm-up: one request per (timestep, resolution) learns the pair capacities
+    # warm-up: one request per (timestep, resolution)
     rng = np.random.default_rng(50)
-    warm = [poisson_requests(rng, 1, 0.0, 1, [res], camfn)[0] for res in scenes.RESOLUTIONS]
-    warm = [type(r)(i, k, r.camera, 0.0) for i, (k, r) in enumerate((k, r) for k in range(store.timesteps)
-                                                                      for r in warm)]
+    warm = [Request(i, k, camfn(rng, W, H), 0.0)
+            for i, (k, (W, H)) in enumerate((k, res) for k in range(store.timesteps) for res in scenes.RESOLUTIONS)]
     eng.run(warm)
     torch.cuda.synchronize()
-    reqs = poisson_requests(np.random.default_rng(51), n_requests, qps, store.timesteps, scenes.RESOLUTIONS, camfn)
-    _, st = eng.run(reqs)
+
+    def leg(qps, seed):
+        reqs = poisson_requests(np.random.default_rng(seed), n_requests, qps, store.timesteps, scenes.RESOLUTIONS,
+                                camfn)
+        _, st = eng.run(reqs)
+        torch.cuda.synchronize()
+        sm = st.summary()
+        return {"qps": None if qps == 0 else round(qps, 1), "requests": n_requests, "p50_ms": round(sm["p50_ms"], 3),
+                "p99_ms": round(sm["p99_ms"], 3), "mean_ms": round(sm["mean_ms"], 3),
+                "frames_per_s": round(sm["frames_per_s"], 1), "groups": sm["groups"], "retries": sm["retries"],
+                "mean_group": round(sm["completed"] / max(sm["groups"], 1), 2), "peak_inflight": sm["peak_inflight"]}
+
+    closed = leg(0.0, 51)          # all arrivals at t = 0: the saturation rate
+    X = closed["frames_per_s"]
+    log(f"serving closed loop: {closed}")
+    sweep = []
+    for i, f in enumerate((0.25, 0.5, 0.8)):
+        r = leg(f * X, 52 + i)
+        r["fraction_of_saturation"] = f
+        log(f"serving at {f} X = {r['qps']} QPS: {r}")
+        sweep.append(r)
+    head = sweep[1]
+    return {"saturation_frames_per_s": X, "closed_loop": closed, "poisson": sweep,
+            "headline": {"qps": head["qps"], "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
+                         "frames_per_s": head["frames_per_s"]},
+            "workload": "2M-Gaussian base + 7 change steps, SH3, resolutions 640x480/1280x720/1920x1080 uniform, "
+                        "random timestep, camera uniform on the radius-4 sphere, max 4 views per call, 4 slots"}
+
+
+def other_configs(dev, log):
+    """One-off timing of the other two workloads: full-scene optimisation (200k
+    Gaussians, SH degree 3, 8 ring views of 800x800; every row active, Adam over all
+    rows) and differentiation at scale (3M Gaussians, SH degree 3, a batch of 4
+    1920x1080 views through the autograd wrapper in recompute mode, L1 loss)."""
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2506_21117_amd import api
+    from paper_2506_21117_amd.autograd import render
+    from paper_2506_21117_amd.optim import SplatOptimizer
+
+    out = {}
+    w = scenes.full_scene()
+    params = api.GaussianTensors.from_scene(w.scene, dev)
+    tg = torch.as_tensor(w.targets, device=dev)
+    opt = SplatOptimizer(params, w.cameras, tg, local=False)
+    for i in range(8):
+        opt.step(i % len(w.cameras))
     torch.cuda.synchronize()
-    s = st.summary()
-    log(f"serving at {qps} QPS: {s}")
-    return {"qps": qps, "requests": n_requests, "p50_ms": round(s["p50_ms"], 3), "p99_ms": round(s["p99_ms"], 3),
-            "mean_ms": round(s["mean_ms"], 3), "frames_per_s": round(s["frames_per_s"], 1), "groups": s["groups"],
-            "retries": s["retries"], "workload": "2M-Gaussian base + 7 change steps, SH3, resolutions "
-                                                 "640x480/1280x720/1920x1080, Poisson arrivals, max 4 views per call"}
+    steps = 64
+    t = time.perf_counter()
+    for i in range(steps):
+        opt.step(i % len(w.cameras))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    if opt.overflowed():
+        raise RuntimeError("pair capacity overflow in the full-scene leg")
+    out["full_scene_200k_sh3_800x800_8v"] = {"it_s": round(steps / dt, 2), "ms_per_step": round(1000 * dt / steps, 3),
+                                            "steps": steps, "mode": "full (every row active), one view per step"}
+    log(f"config full-scene: {out['full_scene_200k_sh3_800x800_8v']}")
+    del opt, params, tg, w
+    torch.cuda.empty_cache()
+
+    w = scenes.differentiation()
+    g = api.GaussianTensors.from_scene(w.scene, dev)
+    leaves = [t.clone().requires_grad_(True) for t in g.tensors()]
+    tg = torch.as_tensor(w.targets, device=dev)
+
+    def it():
+        img = render(*leaves, w.cameras, mode="recompute")
+        loss = (img - tg).abs().mean()
+        loss.backward()
+        for x in leaves:
+            x.grad = None
+
+    for _ in range(2):
+        it()
+    torch.cuda.synchronize()
+    steps = 6
+    t = time.perf_counter()
+    for _ in range(steps):
+        it()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    out["differentiation_3m_sh3_1920x1080_4v"] = {
+        "it_s": round(steps / dt, 3), "ms_per_iteration": round(1000 * dt / steps, 2), "steps": steps,
+        "mode": "autograd recompute: forward of 4 views, L1 loss, backward (re-runs preprocess, binning, forward)"}
+    log(f"config differentiation: {out['differentiation_3m_sh3_1920x1080_4v']}")
+    del leaves, g, tg, w
+    torch.cuda.empty_cache()
+    return out
 
 
-def cpu_baseline(sc, cams, a, scene_gt, order, budget_s, log):
+def cpu_baseline(sc, cams, a, scene_gt, order, budget_s, log, threads=None):
     """The CPU oracle (float64, brute force per pixel) running complete local steps of
     the same workload until ``budget_s`` seconds have passed: project every Gaussian,
     build the render mask from the change set, render every masked pixel, L1 gradient
@@ -341,7 +454,8 @@ def cpu_baseline(sc, cams, a, scene_gt, order, budget_s, log):
     params = {k: np.asarray(x, dtype=np.float64) for k, x in zip(names, sc.param_arrays())}
     m = {k: np.zeros_like(x) for k, x in params.items()}
     v = {k: np.zeros_like(x) for k, x in params.items()}
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    if threads is None:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rows = slice(a[0], a[1])
     steps = 0
     t_start = time.perf_counter()
@@ -378,6 +492,23 @@ def cpu_baseline(sc, cams, a, scene_gt, order, budget_s, log):
                       f"forward of every masked pixel, L1 gradient, brute-force forward+backward, preprocess "
                       f"backward, Adam on the change set; {dt:.1f}s measured, no extrapolation (the render of "
                       f"the targets at the masked pixels is excluded)"}
+
+
+def cpu_single_thread(sc, cams, a, scene_gt, order, log):
+    """One complete oracle local step (as in ``cpu_baseline``) on one OpenMP thread."""
+    import ctypes
+
+    import oracle
+    gomp = ctypes.CDLL("libgomp.so.1")
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.lib()
+    gomp.omp_set_num_threads(1)
+    try:
+        r = cpu_baseline(sc, cams, a, scene_gt, order, 0.0, log, threads=1)
+    finally:
+        gomp.omp_set_num_threads(threads)
+    r["sample"] = "one complete local step on one thread; " + r["sample"].split("; ", 1)[0]
+    return r
 
 
 # ---- summaries of rocprofv3 output (host only) ----------------------------------------

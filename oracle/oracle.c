@@ -197,7 +197,9 @@ static int near_rel(double x, double thr) { return fabs(x - thr) <= NEAR_REL * f
 /* x (> 0) within a factor exp(max(NEAR_REL, rel)) of thr (> 0): rel bounds the error of
  * ln x in a float32 evaluation of x, so the decision x vs thr may go either way there */
 static int near_band(double x, double thr, double rel) {
-  return fabs(log(x / thr)) <= fmax(NEAR_REL, rel);
+  const double r = fmax(NEAR_REL, rel), q = x / thr;
+  if (r < 0.5 && (q < 0.5 || q > 2.0)) return 0;   /* |ln q| > ln 2 > r: no logarithm needed */
+  return fabs(log(q)) <= r;
 }
 
 /* Rotation matrix of a unit quaternion (w, x, y, z). */

@@ -227,6 +227,9 @@ class GpuBackend:
         self.pairs_per_view = {}      # (timestep, W, H) -> largest pair count seen for one view
 
     def _capacity(self, reqs):
+        """Pair capacity for the admission estimate: the largest per-view count seen for
+        this (timestep, resolution), or 4 per Gaussian before any was seen.  The lists
+        themselves are sized exactly (see ``launch``)."""
         key = reqs[0].key
         n = len(self.store.gathers[key[0]])
         per = self.pairs_per_view.get(key, 4 * n)
@@ -245,30 +248,55 @@ class GpuBackend:
         return int(proj + bins + ws + images)
 
     def launch(self, reqs, slot):
+        """Stage 1 on the slot's stream: project the state's Gaussians and count the
+        pairs of the complete lists (a binning call with no pair capacity, which reports
+        the count and emits nothing).  Stage 2 (``done`` starts it once stage 1 has
+        finished): lists with exactly that capacity, which bounds the depth-sliced
+        lists' pairs, and the forward.  No request is rendered twice."""
         torch, api = self.torch, self.api
         s = self.streams[slot]
         ts = reqs[0].timestep
         cams = [r.camera for r in reqs]
         gather = self.store.device_gathers[ts]
         n = int(gather.numel())
+        W, H = cams[0].width, cams[0].height
         with torch.cuda.stream(s):
             proj = api.ProjectedBuffers.alloc(n, len(cams), self.device)
-            W, H = cams[0].width, cams[0].height
-            bins = api.BinBuffers.alloc(n, len(cams), W, H, self._capacity(reqs), self.device)
+            probe = api.BinBuffers.alloc(n, len(cams), W, H, 1, self.device, api._ffi.BINS_COMPLETE)
             api.project_preprocess(self.store.device_pool, cams, proj, gather=gather, stream=s)
+            api.bin_and_sort(proj, cams, None, False, probe, stream=s)
+            count = torch.empty(1, dtype=torch.int32, pin_memory=True)
+            count.copy_(probe.counters[0:1], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return {"reqs": reqs, "ev": ev, "stage": 1, "proj": proj, "probe": probe, "count": count, "stream": s,
+                "cams": cams}
+
+    def _stage2(self, h):
+        torch, api = self.torch, self.api
+        s, cams, proj = h["stream"], h["cams"], h["proj"]
+        pairs = int(h["count"].numpy().view(np.uint32)[0])
+        W, H = cams[0].width, cams[0].height
+        with torch.cuda.stream(s):
+            bins = api.BinBuffers.alloc(proj.n, len(cams), W, H, max(pairs, 1), self.device)
             api.bin_and_sort(proj, cams, None, False, bins, stream=s)
             img, T, nc = api.render_forward(proj, bins, cams, self.bg, stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
-        return {"reqs": reqs, "ev": ev, "img": img, "bins": bins, "keep": (proj, T, nc), "stream": s}
+        h.update(stage=2, ev=ev, img=img, bins=bins, keep=(T, nc), probe=None, pairs=pairs)
 
     def done(self, h):
-        return h["ev"].query()
+        if not h["ev"].query():
+            return False
+        if h["stage"] == 1:
+            self._stage2(h)
+            return False
+        return True
 
     def finish(self, h):
         c = h["bins"].read_counters()
         key = h["reqs"][0].key
-        per = -(-c["pairs"] // len(h["reqs"]))
+        per = -(-h["pairs"] // len(h["reqs"]))
         self.pairs_per_view[key] = max(self.pairs_per_view.get(key, 0), per)
         if c["overflow"]:
             return None
