@@ -428,3 +428,68 @@ def tile_list_reference(u, v, rx, ry, z32, visible, width, height, tile):
     sel = np.nonzero(np.asarray(visible, bool) & (x0 <= tx) & (tx < x1) & (y0 <= ty) & (ty < y1))[0]
     zbits = np.asarray(z32, dtype=np.float32).view(np.uint32)[sel].astype(np.int64)
     return sel[np.lexsort((sel, zbits))]
+
+
+# ------------------------------------------------------------------ change region: spheres
+# Supp. "Identifying Changed 3D Regions via Majority Voting": one sphere per cluster of
+# changed Gaussians, centred on the cluster's mean, radius 1.1 times the 98th percentile
+# of the distances to it; Supp. "3DGS Optimization in Changed Regions": every 15
+# iterations, changed Gaussians whose centre lies outside every sphere are removed.
+SPHERE_QUANTILE = 0.98
+SPHERE_SCALE = 1.1
+
+
+def fit_spheres(means, labels, n_spheres):
+    """Centres [S, 3] and radii [S] (float64) of the clusters of ``means`` ([3, M]) given
+    by ``labels`` ([M] int; -1: in no cluster).  The percentile interpolates linearly
+    between the order statistics at positions floor(q) and floor(q) + 1 of the sorted
+    distances, q = 0.98 (c - 1) for a cluster of c points.  An empty cluster gets centre
+    0 and radius -1 (it contains nothing)."""
+    means = _f64(means)
+    labels = np.asarray(labels)
+    centers = np.zeros((n_spheres, 3))
+    radii = np.full(n_spheres, -1.0)
+    for s in range(n_spheres):
+        pts = means[:, labels == s]
+        c = pts.shape[1]
+        if c == 0:
+            continue
+        m = pts.sum(axis=1) / c
+        d = np.sort(np.sqrt(((pts - m[:, None]) ** 2).sum(axis=0)))
+        q = SPHERE_QUANTILE * (c - 1)
+        lo = int(np.floor(q))
+        hi = min(lo + 1, c - 1)
+        centers[s] = m
+        radii[s] = SPHERE_SCALE * (d[lo] + (q - lo) * (d[hi] - d[lo]))
+    return centers, radii
+
+
+def sphere_keep(means, centers, radii):
+    """Whether each centre ([3, M]) lies in the union of the spheres: |mu - m| <= r for
+    some sphere (the boundary counts as inside).  The decision is taken in float32, in
+    this order, with every operation rounded: d = mu - m per axis, d2 = (dx dx + dy dy) +
+    dz dz, inside iff d2 <= r r, so that a float32 implementation takes the same
+    decisions; spheres with a negative radius contain nothing."""
+    f = np.float32
+    mu = np.asarray(means, dtype=f)
+    keep = np.zeros(mu.shape[1], dtype=bool)
+    for m, r in zip(np.asarray(centers, dtype=f), np.asarray(radii, dtype=f)):
+        if r < 0:
+            continue
+        dx, dy, dz = mu[0] - m[0], mu[1] - m[1], mu[2] - m[2]
+        d2 = (dx * dx + dy * dy) + dz * dz
+        keep |= d2 <= r * r
+    return keep
+
+
+def compact_rows(arrays, keep, begin):
+    """The parameter arrays (last axis = Gaussian) with the rows [begin, N) whose
+    ``keep`` ([N - begin] bool) is false removed: rows before ``begin`` stay where they
+    are and the kept rows follow in their order, so the changed Gaussians stay the
+    contiguous suffix (Supp. "History Recovery")."""
+    keep = np.asarray(keep, dtype=bool)
+    out = []
+    for a in arrays:
+        a = np.asarray(a)
+        out.append(np.concatenate([a[..., :begin], a[..., begin:][..., keep]], axis=-1))
+    return out
