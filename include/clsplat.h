@@ -403,6 +403,54 @@ clsp_status clsp_render_backward_adam(const clsp_gaussians *g, const clsp_projec
                                       const clsp_params *exp_avg, const clsp_params *exp_avg_sq,
                                       const clsp_adam_hparams *hp, void *ws, size_t ws_bytes, clsp_stream stream);
 
+/* ---------------------------------------------------------------------------------
+ * Change-region spheres (Supp. "Identifying Changed 3D Regions via Majority Voting";
+ * Sec. 3.3 "Sphere Pruning"; Supp. "3DGS Optimization in Changed Regions").  The change
+ * set O^t is clustered outside this library; each cluster gets one sphere, and during
+ * local optimisation the changed Gaussians whose centre has left every sphere are
+ * removed (the paper checks every 15 iterations), keeping O^t the contiguous suffix.
+ *
+ * clsp_fit_spheres: means (device float[3][n_rows], component-major) of rows
+ * [rows.begin, rows.end); labels (device int32[rows.end - rows.begin]) give each row's
+ * cluster in 0..n_spheres-1, or -1 for none.  Writes centers (device float[n_spheres][3])
+ * = the cluster's mean (summed in double, rounded to float) and radii (device
+ * float[n_spheres]) = CLSP_SPHERE_SCALE x the CLSP_SPHERE_QUANTILE percentile of the
+ * float32 distances to that centre, interpolated linearly between the order statistics
+ * floor(q) and floor(q) + 1, q = CLSP_SPHERE_QUANTILE (c - 1) for c points (computed in
+ * double, rounded to float).  An empty cluster gets centre 0 and radius -1.
+ * Errors: NULL pointers, n_spheres not in 1..CLSP_MAX_SPHERES, rows not within
+ * [0, n_rows]. */
+#define CLSP_SPHERE_QUANTILE 0.98
+#define CLSP_SPHERE_SCALE 1.1
+#define CLSP_MAX_SPHERES 4096
+clsp_status clsp_fit_spheres(const float *means, int64_t n_rows, clsp_range rows, const int32_t *labels,
+                             int32_t n_spheres, float *centers, float *radii, clsp_stream stream);
+
+/* clsp_sphere_keep: keep[i - rows.begin] = 1 when the centre of row i lies in some
+ * sphere (|mu - m| <= r, the boundary inside; spheres with a negative radius contain
+ * nothing), else 0; kept (device uint32[1], overwritten) = the number of 1s.  The
+ * decision is taken in float32 in this order, every operation rounded: d = mu - m per
+ * axis, d2 = (dx dx + dy dy) + dz dz, inside iff d2 <= r r.
+ * Errors: NULL pointers, n_spheres not in 1..CLSP_MAX_SPHERES, rows not within
+ * [0, n_rows]. */
+clsp_status clsp_sphere_keep(const float *means, int64_t n_rows, clsp_range rows, const float *centers,
+                             const float *radii, int32_t n_spheres, uint8_t *keep, uint32_t *kept,
+                             clsp_stream stream);
+
+/* clsp_compact_rows: copies src (and, when both are given, the Adam moments src_m, src_v)
+ * to dst (dst_m, dst_v) without the rows of [rows.begin, src->n) whose keep (as written
+ * by clsp_sphere_keep) is 0: rows before rows.begin stay where they are, the kept rows
+ * follow in their order.  rows.end must equal src->n (the change set is the suffix).
+ * dst->n should be rows.begin + kept; no row at or past dst->n is written.  Source and
+ * destination must not overlap; every set uses its own n as its row stride.
+ * ws: device workspace of clsp_compact_rows_workspace_bytes(rows.end - rows.begin).
+ * Errors: NULL or mismatched parameter sets (sh degree), rows.end != src->n,
+ * dst->n < rows.begin or > src->n, workspace too small. */
+size_t clsp_compact_rows_workspace_bytes(int64_t n_changed);
+clsp_status clsp_compact_rows(const clsp_params *src, const clsp_params *src_m, const clsp_params *src_v,
+                              clsp_range rows, const uint8_t *keep, const clsp_params *dst, const clsp_params *dst_m,
+                              const clsp_params *dst_v, void *ws, size_t ws_bytes, clsp_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

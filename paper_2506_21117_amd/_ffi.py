@@ -25,7 +25,8 @@ EXPORTED = (
     "clsp_l1_loss_grad",
     "clsp_render_backward_workspace_bytes",
     "clsp_render_backward", "clsp_masked_adam_step", "clsp_zero_grads", "clsp_render_backward_adam",
-    "clsp_render_backward_noalloc",
+    "clsp_render_backward_noalloc", "clsp_fit_spheres", "clsp_sphere_keep", "clsp_compact_rows_workspace_bytes",
+    "clsp_compact_rows",
 )
 
 
@@ -131,6 +132,16 @@ def load(path: Path | None = None):
                                             c_int32, POINTER(c_float), Range, c_void_p, c_void_p, c_void_p, c_size_t,
                                             c_void_p, POINTER(Params), POINTER(Params), POINTER(Params),
                                             POINTER(AdamHParams), c_void_p, c_size_t, c_void_p]
+    L.clsp_fit_spheres.restype = st
+    L.clsp_fit_spheres.argtypes = [c_void_p, c_int64, Range, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
+    L.clsp_sphere_keep.restype = st
+    L.clsp_sphere_keep.argtypes = [c_void_p, c_int64, Range, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
+                                   c_void_p]
+    L.clsp_compact_rows_workspace_bytes.restype = c_size_t
+    L.clsp_compact_rows_workspace_bytes.argtypes = [c_int64]
+    L.clsp_compact_rows.restype = st
+    L.clsp_compact_rows.argtypes = [POINTER(Params), POINTER(Params), POINTER(Params), Range, c_void_p, POINTER(Params),
+                                    POINTER(Params), POINTER(Params), c_void_p, c_size_t, c_void_p]
     if path is None:
         _lib = L
     return L

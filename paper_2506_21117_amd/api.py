@@ -400,3 +400,57 @@ def render_backward_adam(g: GaussianTensors, proj, bins, cam, bg, active, T_fina
                                           ctypes.byref(exp_avg_sq.as_params()), ctypes.byref(hp), _ptr(ws), ws.numel(),
                                           _stream(stream)))
     return g
+
+
+# ------------------------------------------------------------------ change-region spheres
+def _means_ptr(means):
+    if means.dtype != torch.float32 or means.dim() != 2 or means.shape[0] != 3 or not means.is_contiguous():
+        raise ValueError("means must be a contiguous float32 tensor [3, N]")
+    return _ptr(means), int(means.shape[1])
+
+
+def fit_spheres(means, rows, labels, n_spheres, stream=None):
+    """Centres [S, 3] and radii [S] of the clusters ``labels`` (int32 [rows[1] -
+    rows[0]], -1: none) of the rows ``rows`` of ``means`` [3, N]."""
+    mp, nr = _means_ptr(means)
+    r0, r1 = int(rows[0]), int(rows[1])
+    if labels.dtype != torch.int32 or labels.numel() != r1 - r0 or not labels.is_contiguous():
+        raise ValueError("labels must be a contiguous int32 tensor of one entry per row")
+    centers = torch.empty(int(n_spheres), 3, dtype=torch.float32, device=means.device)
+    radii = torch.empty(int(n_spheres), dtype=torch.float32, device=means.device)
+    check(lib().clsp_fit_spheres(mp, nr, _ffi.Range(r0, r1), _ptr(labels), int(n_spheres), _ptr(centers), _ptr(radii),
+                                 _stream(stream)))
+    return centers, radii
+
+
+def sphere_keep(means, rows, centers, radii, keep=None, kept=None, stream=None):
+    """(keep uint8 [rows[1] - rows[0]], kept int32 [1]): which rows' centres lie in the
+    union of the spheres, and how many."""
+    mp, nr = _means_ptr(means)
+    r0, r1 = int(rows[0]), int(rows[1])
+    centers = centers.contiguous()
+    radii = radii.contiguous()
+    if keep is None:
+        keep = torch.empty(max(r1 - r0, 1), dtype=torch.uint8, device=means.device)
+    if kept is None:
+        kept = torch.empty(1, dtype=torch.int32, device=means.device)
+    check(lib().clsp_sphere_keep(mp, nr, _ffi.Range(r0, r1), _ptr(centers), _ptr(radii), int(radii.numel()),
+                                 _ptr(keep), _ptr(kept), _stream(stream)))
+    return keep, kept
+
+
+def compact_workspace(n_changed, device):
+    b = lib().clsp_compact_rows_workspace_bytes(int(n_changed))
+    return torch.empty(max(1, b), dtype=torch.uint8, device=device)
+
+
+def compact_rows(src: GaussianTensors, rows, keep, dst: GaussianTensors, moments=None, ws=None, stream=None):
+    """Copy ``src`` to ``dst`` without the rows of [rows[0], N) whose ``keep`` is 0; with
+    ``moments`` = (src_m, src_v, dst_m, dst_v) the Adam moments too."""
+    r0, r1 = int(rows[0]), int(rows[1])
+    if ws is None:
+        ws = compact_workspace(r1 - r0, src.means.device)
+    mo = [None] * 4 if moments is None else [ctypes.byref(m.as_params()) for m in moments]
+    check(lib().clsp_compact_rows(ctypes.byref(src.as_params()), mo[0], mo[1], _ffi.Range(r0, r1), _ptr(keep),
+                                  ctypes.byref(dst.as_params()), mo[2], mo[3], _ptr(ws), ws.numel(), _stream(stream)))
+    return dst

@@ -470,6 +470,71 @@ clsp_status clsp_render_backward_adam(const clsp_gaussians* g, const clsp_projec
                     "render_backward_adam");
 }
 
+clsp_status clsp_fit_spheres(const float* means, int64_t n_rows, clsp_range rows, const int32_t* labels,
+                             int32_t n_spheres, float* centers, float* radii, clsp_stream stream) {
+  if (!means || !labels || !centers || !radii) return fail(CLSP_ERR_INVALID_ARG, "fit_spheres pointer is NULL");
+  if (n_spheres < 1 || n_spheres > CLSP_MAX_SPHERES)
+    return fail(CLSP_ERR_INVALID_ARG, "n_spheres=%d not in 1..%d", n_spheres, CLSP_MAX_SPHERES);
+  CHECK(check_range(rows, n_rows));
+  return hip_status(clsp::launch_fit_spheres(means, n_rows, rows.begin, rows.end, labels, n_spheres, centers, radii,
+                                             reinterpret_cast<hipStream_t>(stream)),
+                    "fit_spheres");
+}
+
+clsp_status clsp_sphere_keep(const float* means, int64_t n_rows, clsp_range rows, const float* centers,
+                             const float* radii, int32_t n_spheres, uint8_t* keep, uint32_t* kept,
+                             clsp_stream stream) {
+  if (!means || !centers || !radii || !keep || !kept) return fail(CLSP_ERR_INVALID_ARG, "sphere_keep pointer is NULL");
+  if (n_spheres < 1 || n_spheres > CLSP_MAX_SPHERES)
+    return fail(CLSP_ERR_INVALID_ARG, "n_spheres=%d not in 1..%d", n_spheres, CLSP_MAX_SPHERES);
+  CHECK(check_range(rows, n_rows));
+  return hip_status(clsp::launch_sphere_keep(means, n_rows, rows.begin, rows.end, centers, radii, n_spheres, keep,
+                                             kept, reinterpret_cast<hipStream_t>(stream)),
+                    "sphere_keep");
+}
+
+size_t clsp_compact_rows_workspace_bytes(int64_t n_changed) {
+  if (n_changed < 0) return 0;
+  return clsp::compact_workspace_bytes(n_changed);
+}
+
+clsp_status clsp_compact_rows(const clsp_params* src, const clsp_params* src_m, const clsp_params* src_v,
+                              clsp_range rows, const uint8_t* keep, const clsp_params* dst, const clsp_params* dst_m,
+                              const clsp_params* dst_v, void* ws, size_t ws_bytes, clsp_stream stream) {
+  CHECK(check_params(src, "src"));
+  CHECK(check_params(dst, "dst"));
+  const bool moments = src_m || src_v || dst_m || dst_v;
+  if (moments) {
+    if (!src_m || !src_v || !dst_m || !dst_v)
+      return fail(CLSP_ERR_INVALID_ARG, "compact_rows: give all four moment sets or none");
+    CHECK(check_params(src_m, "src_m"));
+    CHECK(check_params(src_v, "src_v"));
+    CHECK(check_params(dst_m, "dst_m"));
+    CHECK(check_params(dst_v, "dst_v"));
+    if (src_m->n != src->n || src_v->n != src->n || dst_m->n != dst->n || dst_v->n != dst->n)
+      return fail(CLSP_ERR_INVALID_ARG, "compact_rows: moments sized differently from their parameters");
+  }
+  const clsp_params* all[6] = {src, src_m, src_v, dst, dst_m, dst_v};
+  for (const clsp_params* q : all)
+    if (q && q->sh_degree != src->sh_degree) return fail(CLSP_ERR_INVALID_ARG, "compact_rows: sh degrees differ");
+  CHECK(check_range(rows, src->n));
+  if (rows.end != src->n) return fail(CLSP_ERR_INVALID_ARG, "compact_rows: rows.end must equal src->n");
+  if (dst->n < rows.begin || dst->n > src->n)
+    return fail(CLSP_ERR_INVALID_ARG, "compact_rows: dst->n=%lld not in [%lld, %lld]", (long long)dst->n,
+                (long long)rows.begin, (long long)src->n);
+  if (rows.end > rows.begin && !keep) return fail(CLSP_ERR_INVALID_ARG, "compact_rows: keep is NULL");
+  const size_t need = clsp_compact_rows_workspace_bytes(rows.end - rows.begin);
+  if (!ws || ws_bytes < need)
+    return fail(CLSP_ERR_INVALID_ARG, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+  clsp::MutParams s3[3] = {mut_params(src), moments ? mut_params(src_m) : mut_params(src),
+                           moments ? mut_params(src_v) : mut_params(src)};
+  clsp::MutParams d3[3] = {mut_params(dst), moments ? mut_params(dst_m) : mut_params(dst),
+                           moments ? mut_params(dst_v) : mut_params(dst)};
+  return hip_status(clsp::launch_compact_rows(s3, d3, moments ? 3 : 1, rows.begin, rows.end, keep, ws,
+                                              reinterpret_cast<hipStream_t>(stream)),
+                    "compact_rows");
+}
+
 clsp_status clsp_zero_grads(const clsp_params* grads, clsp_range active, clsp_stream stream) {
   CHECK(check_params(grads, "grads"));
   CHECK(check_range(active, grads->n));

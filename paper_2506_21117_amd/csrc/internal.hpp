@@ -119,6 +119,16 @@ hipError_t launch_render_backward(const clsp_projected& proj, const clsp_bins& b
                                   float* grad2d, hipStream_t s, bool clear = true);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 
+// spheres.hip
+hipError_t launch_fit_spheres(const float* means, int64_t nr, int64_t a0, int64_t a1, const int32_t* labels, int ns,
+                              float* centers, float* radii, hipStream_t s);
+hipError_t launch_sphere_keep(const float* means, int64_t nr, int64_t a0, int64_t a1, const float* centers,
+                              const float* radii, int ns, uint8_t* keep, uint32_t* kept, hipStream_t s);
+size_t compact_workspace_bytes(int64_t na);
+// src/dst[0] parameters, [1], [2] the Adam moments (used when sets == 3)
+hipError_t launch_compact_rows(const MutParams src[3], const MutParams dst[3], int sets, int64_t a0, int64_t a1,
+                               const uint8_t* keep, void* ws, hipStream_t s);
+
 // adam.hip
 hipError_t launch_adam(const MutParams& p, const MutParams& g, const MutParams& m, const MutParams& v, int64_t a0,
                        int64_t a1, const uint8_t* row_mask, const clsp_adam_hparams& hp, hipStream_t s);

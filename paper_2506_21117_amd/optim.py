@@ -116,6 +116,44 @@ class SplatOptimizer:
                       "targets": [p(self.targets[v:v + 1]) for v in range(len(self.cams))]}
         self._sizes = (self.bins.ws.numel(), self.bwd_ws.numel(), self.state.numel())
 
+    def prune(self, centers, radii):
+        """Remove the changed Gaussians whose centre has left every sphere (Sec. 3.3
+        "Sphere Pruning"; the paper checks every 15 iterations): the membership test and
+        the compaction of parameters and Adam moments run in the library
+        (clsp_sphere_keep, clsp_compact_rows); the change set stays the contiguous suffix
+        after the unchanged rows.  ``centers`` [S, 3], ``radii`` [S] (device float32, e.g.
+        from ``api.fit_spheres``).  Reads the kept count back (synchronises) and returns
+        how many rows were removed.  The parameter tensors of ``params`` (and the
+        moments) are replaced by the shorter ones; frozen rows keep their cached
+        projections, and the pair buffers keep their capacity (removing Gaussians only
+        removes pairs)."""
+        if not self.local:
+            raise ValueError("pruning applies to the change set of local optimisation")
+        a0, a1 = self.active
+        keep, kept = api.sphere_keep(self.params.means, (a0, a1), centers, radii)
+        k = int(kept.item())
+        if k == a1 - a0:
+            return 0
+        n_new = a0 + k
+        dev = self.params.means.device
+        deg = self.params.sh_degree
+        newp, newm, newv = (api.GaussianTensors.zeros(n_new, deg, dev) for _ in range(3))
+        api.compact_rows(self.params, (a0, a1), keep, newp, moments=(self.m, self.v, newm, newv))
+        for old, new in ((self.params, newp), (self.m, newm), (self.v, newv)):
+            for name in api.GaussianTensors.NAMES:
+                setattr(old, name, getattr(new, name))
+        self.n = n_new
+        self.active = (a0, n_new)
+        cut = lambda pb: api.ProjectedBuffers(pb.splat[:n_new], pb.depth[:n_new], pb.rect[:n_new], pb.flags[:n_new],
+                                              n_new, 1)
+        self.proj = cut(self.proj)
+        if self.proj_views is not None:
+            self.proj_views = [cut(pv) for pv in self.proj_views]
+        self.bins.n = n_new
+        self.bwd_ws = api.render_backward_workspace(k, 1, dev)
+        self._prepare_calls()
+        return (a1 - a0) - k
+
     def invalidate_projections(self):
         """The next step on each view projects every row again (needed after rows outside
         the change set were modified)."""

@@ -191,3 +191,29 @@ def test_missing_library_fails_loudly(tmp_path):
     from paper_2506_21117_amd import _ffi
     with pytest.raises(_ffi.LibraryMissing):
         _ffi.load(tmp_path / "nope.so")
+
+
+@pytest.mark.skipif(_gpu_visible(), reason="passes the stand-in device address 0x1000 to entry points; run only "
+                                           "where no GPU could ever receive a launch on it")
+def test_sphere_calls_reject_invalid_arguments_on_the_host(L):
+    from paper_2506_21117_amd import _ffi
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert L.clsp_fit_spheres(fake, 10, _ffi.Range(0, 10), fake, 0, fake, fake, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_fit_spheres(fake, 10, _ffi.Range(0, 10), fake, 5000, fake, fake, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_fit_spheres(fake, 10, _ffi.Range(4, 11), fake, 2, fake, fake, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_sphere_keep(fake, 10, _ffi.Range(0, 10), fake, fake, 2, None, fake, None) == _ffi.CLSP_ERR_INVALID_ARG
+    src = _ffi.Params(fake, fake, fake, fake, fake, 10, 0, 0)
+    dst = _ffi.Params(fake, fake, fake, fake, fake, 8, 0, 0)
+    big = _ffi.Params(fake, fake, fake, fake, fake, 11, 0, 0)
+    ws = L.clsp_compact_rows_workspace_bytes(6)
+    ok = lambda s_, r, d, w=ws: L.clsp_compact_rows(ctypes.byref(s_), None, None, r, fake, ctypes.byref(d), None, None,
+                                                    fake, w, None)
+    assert ok(src, _ffi.Range(4, 9), dst) == _ffi.CLSP_ERR_INVALID_ARG       # the change set must be the suffix
+    assert ok(src, _ffi.Range(4, 10), big) == _ffi.CLSP_ERR_INVALID_ARG      # more rows than the source
+    assert ok(src, _ffi.Range(9, 10), dst) == _ffi.CLSP_ERR_INVALID_ARG      # fewer rows than the prefix
+    assert ok(src, _ffi.Range(4, 10), dst, 0) == _ffi.CLSP_ERR_INVALID_ARG   # no workspace
+    assert b"workspace" in L.clsp_last_error()
+    deg3 = _ffi.Params(fake, fake, fake, fake, fake, 8, 3, 0)
+    assert ok(src, _ffi.Range(4, 10), deg3) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_compact_rows(ctypes.byref(src), ctypes.byref(src), None, _ffi.Range(4, 10), fake, ctypes.byref(dst),
+                               None, None, fake, ws, None) == _ffi.CLSP_ERR_INVALID_ARG   # half the moments
