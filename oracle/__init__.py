@@ -493,3 +493,73 @@ def compact_rows(arrays, keep, begin):
         a = np.asarray(a)
         out.append(np.concatenate([a[..., :begin], a[..., begin:][..., keep]], axis=-1))
     return out
+
+
+# ------------------------------------------------------------------ change lifting
+# Supp. "Detecting Changes in 2D": the binary change masks are dilated by 2% of the image
+# width, by a convolution with a kernel of ones and a threshold at 0.  Supp.
+# "Identifying Changed 3D Regions via Majority Voting": each Gaussian's centre is
+# projected into every view; c_i counts the views whose mask holds it, o_i those whose
+# image it falls outside; g_i is changed iff 4/3 o_i < |I| < 2 c_i.
+DILATE_FRACTION = 0.02
+
+
+def dilation_radius(width):
+    """Half-width of the square dilation kernel: 2% of the image width, rounded to the
+    nearest pixel (halves up)."""
+    return int(np.floor(DILATE_FRACTION * width + 0.5))
+
+
+def dilate_masks(masks, radius):
+    """masks [V, H, W] (0/1) -> [V, H, W] uint8: 1 where the sum of the mask over the
+    (2 radius + 1)^2 square around the pixel (pixels outside the image count 0) is > 0.
+    The sums are exact integer box sums of the mask's integral image."""
+    m = (np.asarray(masks) != 0).astype(np.int64)
+    V, H, W = m.shape
+    S = np.zeros((V, H + 1, W + 1), dtype=np.int64)
+    S[:, 1:, 1:] = m.cumsum(1).cumsum(2)
+    y0 = np.clip(np.arange(H) - radius, 0, H)
+    y1 = np.clip(np.arange(H) + radius + 1, 0, H)
+    x0 = np.clip(np.arange(W) - radius, 0, W)
+    x1 = np.clip(np.arange(W) + radius + 1, 0, W)
+    box = (S[:, y1][:, :, x1] - S[:, y0][:, :, x1] - S[:, y1][:, :, x0] + S[:, y0][:, :, x0])
+    return (box > 0).astype(np.uint8)
+
+
+def project_centres_f32(means, cam):
+    """Pixel coordinates (u, v) and depth Z of the centres ([3, N]) in float32, every
+    operation rounded, in this order: X = ((R00 x + R01 y) + R02 z) + t0 (Y, Z alike),
+    u = (fx X) / Z + cx, v = (fy Y) / Z + cy."""
+    f = np.float32
+    x, y, z = (np.asarray(means[k], dtype=f) for k in range(3))
+    R = np.asarray(cam.R, dtype=f).reshape(3, 3)
+    t = np.asarray(cam.t, dtype=f)
+    P = [((R[a, 0] * x + R[a, 1] * y) + R[a, 2] * z) + t[a] for a in range(3)]
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        u = (f(cam.fx) * P[0]) / P[2] + f(cam.cx)
+        v = (f(cam.fy) * P[1]) / P[2] + f(cam.cy)
+    return u, v, P[2]
+
+
+def majority_vote(means, cams, masks):
+    """(changed [N] bool, c [N], o [N]) for centres ``means`` [3, N], cameras ``cams``
+    and masks [V, H, W]: a centre is outside view v when its depth is at most the near
+    plane 0.2 or its pixel coordinates leave [0, W) x [0, H); otherwise it falls in
+    pixel (floor(u), floor(v)) and counts for c when the mask is 1 there.  The
+    projection is taken in float32 as ``project_centres_f32`` states (the precision of
+    the GPU kernel, so both take the same decisions)."""
+    masks = np.asarray(masks)
+    n = np.asarray(means).shape[1]
+    c = np.zeros(n, dtype=np.int64)
+    o = np.zeros(n, dtype=np.int64)
+    for v_, cam in enumerate(cams):
+        u, v, Z = project_centres_f32(means, cam)
+        inside = (Z > np.float32(0.2)) & (u >= 0) & (u < np.float32(cam.width)) & (v >= 0) & \
+                 (v < np.float32(cam.height))
+        o += ~inside
+        px = np.where(inside, np.floor(np.where(inside, u, 0)), 0).astype(np.int64)
+        py = np.where(inside, np.floor(np.where(inside, v, 0)), 0).astype(np.int64)
+        c += inside & (masks[v_, py, px] != 0)
+    V = len(cams)
+    changed = (4 * o < 3 * V) & (V < 2 * c)
+    return changed, c, o
