@@ -404,6 +404,40 @@ clsp_status clsp_render_backward_adam(const clsp_gaussians *g, const clsp_projec
                                       const clsp_adam_hparams *hp, void *ws, size_t ws_bytes, clsp_stream stream);
 
 /* ---------------------------------------------------------------------------------
+ * Lifting 2D change masks to the change set (the steps before local optimisation).
+ *
+ * clsp_dilate_masks (Supp. "Detecting Changes in 2D": the binary change masks are
+ * dilated by 2% of the image width, by a convolution with a kernel of ones and a
+ * threshold at 0): out[v][y][x] = 1 when masks[v] (uint8, nonzero = changed,
+ * [n_views][height][width]) holds a nonzero pixel in the (2 radius + 1)^2 square around
+ * (x, y), pixels outside the image counting as 0; else 0.  The paper's radius is
+ * round(CLSP_DILATE_FRACTION width), halves up.  out must not overlap masks.
+ * ws: device workspace of clsp_dilate_masks_workspace_bytes(n_views, width, height).
+ * Errors: NULL pointers, n_views not in 1..64, sizes not in 1..16384, radius < 0,
+ * workspace too small. */
+#define CLSP_DILATE_FRACTION 0.02
+size_t clsp_dilate_masks_workspace_bytes(int32_t n_views, int32_t width, int32_t height);
+clsp_status clsp_dilate_masks(const uint8_t *masks, int32_t n_views, int32_t width, int32_t height, int32_t radius,
+                              uint8_t *out, void *ws, size_t ws_bytes, clsp_stream stream);
+
+/* clsp_majority_vote (Supp. "Identifying Changed 3D Regions via Majority Voting"): the
+ * centre of Gaussian i < n (means: device float[3][n_rows], component-major) is
+ * projected into every view of cams (host, equal sizes) in float32, every operation
+ * rounded, in this order: X = ((R0 x + R1 y) + R2 z) + t0 (Y, Z alike), u = (fx X) / Z +
+ * cx, v = (fy Y) / Z + cy.  It is outside view k when Z <= 0.2 or (u, v) is not in
+ * [0, W) x [0, H); otherwise it falls in pixel (floor(u), floor(v)).  in_count[i] (device
+ * uint8[n]) = views whose mask (masks: device uint8 [n_views][H][W], nonzero = changed)
+ * holds it there, out_count[i] (uint8[n]) = views it is outside, changed[i] (uint8[n]) =
+ * 1 iff 4 out_count < 3 n_views and n_views < 2 in_count (the paper's
+ * 4/3 o_i < |I| < 2 c_i), n_changed (device uint32[1], overwritten) = the number of 1s.
+ * The changed Gaussians become O^t once the rows are reordered static-first.
+ * Errors: NULL pointers, n < 0 or n > n_rows, invalid cameras (as for
+ * clsp_project_preprocess). */
+clsp_status clsp_majority_vote(const float *means, int64_t n_rows, int64_t n, const clsp_camera *cams,
+                               int32_t n_views, const uint8_t *masks, uint8_t *in_count, uint8_t *out_count,
+                               uint8_t *changed, uint32_t *n_changed, clsp_stream stream);
+
+/* ---------------------------------------------------------------------------------
  * Change-region spheres (Supp. "Identifying Changed 3D Regions via Majority Voting";
  * Sec. 3.3 "Sphere Pruning"; Supp. "3DGS Optimization in Changed Regions").  The change
  * set O^t is clustered outside this library; each cluster gets one sphere, and during

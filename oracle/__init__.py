@@ -523,7 +523,7 @@ def dilate_masks(masks, radius):
     x0 = np.clip(np.arange(W) - radius, 0, W)
     x1 = np.clip(np.arange(W) + radius + 1, 0, W)
     box = (S[:, y1][:, :, x1] - S[:, y0][:, :, x1] - S[:, y1][:, :, x0] + S[:, y0][:, :, x0])
-    return (box > 0).astype(np.uint8)
+    return np.ascontiguousarray(box > 0).astype(np.uint8)
 
 
 def project_centres_f32(means, cam):

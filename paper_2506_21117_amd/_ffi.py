@@ -26,7 +26,7 @@ EXPORTED = (
     "clsp_render_backward_workspace_bytes",
     "clsp_render_backward", "clsp_masked_adam_step", "clsp_zero_grads", "clsp_render_backward_adam",
     "clsp_render_backward_noalloc", "clsp_fit_spheres", "clsp_sphere_keep", "clsp_compact_rows_workspace_bytes",
-    "clsp_compact_rows",
+    "clsp_compact_rows", "clsp_dilate_masks_workspace_bytes", "clsp_dilate_masks", "clsp_majority_vote",
 )
 
 
@@ -142,6 +142,14 @@ def load(path: Path | None = None):
     L.clsp_compact_rows.restype = st
     L.clsp_compact_rows.argtypes = [POINTER(Params), POINTER(Params), POINTER(Params), Range, c_void_p, POINTER(Params),
                                     POINTER(Params), POINTER(Params), c_void_p, c_size_t, c_void_p]
+    L.clsp_dilate_masks_workspace_bytes.restype = c_size_t
+    L.clsp_dilate_masks_workspace_bytes.argtypes = [c_int32, c_int32, c_int32]
+    L.clsp_dilate_masks.restype = st
+    L.clsp_dilate_masks.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_size_t,
+                                    c_void_p]
+    L.clsp_majority_vote.restype = st
+    L.clsp_majority_vote.argtypes = [c_void_p, c_int64, c_int64, POINTER(Camera), c_int32, c_void_p, c_void_p,
+                                     c_void_p, c_void_p, c_void_p, c_void_p]
     if path is None:
         _lib = L
     return L

@@ -454,3 +454,45 @@ def compact_rows(src: GaussianTensors, rows, keep, dst: GaussianTensors, moments
     check(lib().clsp_compact_rows(ctypes.byref(src.as_params()), mo[0], mo[1], _ffi.Range(r0, r1), _ptr(keep),
                                   ctypes.byref(dst.as_params()), mo[2], mo[3], _ptr(ws), ws.numel(), _stream(stream)))
     return dst
+
+
+# ------------------------------------------------------------------ change lifting
+DILATE_FRACTION = 0.02
+
+
+def dilation_radius(width):
+    """The paper's dilation half-width: 2% of the image width, rounded (halves up)."""
+    return int(DILATE_FRACTION * width + 0.5)
+
+
+def dilate_masks(masks, radius, out=None, stream=None):
+    """masks: uint8 [V, H, W] (nonzero = changed) -> uint8 [V, H, W] dilated by a square
+    of half-width ``radius``."""
+    if masks.dtype != torch.uint8 or masks.dim() != 3 or not masks.is_contiguous():
+        raise ValueError("masks must be a contiguous uint8 tensor [V, H, W]")
+    V, H, W = (int(x) for x in masks.shape)
+    if out is None:
+        out = torch.empty_like(masks)
+    b = lib().clsp_dilate_masks_workspace_bytes(V, W, H)
+    ws = torch.empty(max(1, b), dtype=torch.uint8, device=masks.device)
+    check(lib().clsp_dilate_masks(_ptr(masks), V, W, H, int(radius), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def majority_vote(means, cams, masks, n=None, stream=None):
+    """(changed uint8 [n], in_count uint8 [n], out_count uint8 [n], n_changed int32 [1])
+    for the centres ``means`` [3, N] (the first ``n`` rows) against the masks [V, H, W]."""
+    mp, nr = _means_ptr(means)
+    n = nr if n is None else int(n)
+    if masks.dtype != torch.uint8 or masks.dim() != 3 or not masks.is_contiguous() or masks.shape[0] != len(cams):
+        raise ValueError("masks must be a contiguous uint8 tensor [V, H, W], one per camera")
+    if (int(masks.shape[1]), int(masks.shape[2])) != (cams[0].height, cams[0].width):
+        raise ValueError("masks must have the cameras' size")
+    dev = means.device
+    changed = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+    cin = torch.empty_like(changed)
+    cout = torch.empty_like(changed)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    check(lib().clsp_majority_vote(mp, nr, n, camera_array(cams), len(cams), _ptr(masks), _ptr(cin), _ptr(cout),
+                                   _ptr(changed), _ptr(cnt), _stream(stream)))
+    return changed[:n], cin[:n], cout[:n], cnt

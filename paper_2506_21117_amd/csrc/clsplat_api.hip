@@ -470,6 +470,40 @@ clsp_status clsp_render_backward_adam(const clsp_gaussians* g, const clsp_projec
                     "render_backward_adam");
 }
 
+size_t clsp_dilate_masks_workspace_bytes(int32_t n_views, int32_t width, int32_t height) {
+  if (n_views < 1 || width < 1 || height < 1) return 0;
+  return clsp::dilate_workspace_bytes(n_views, width, height);
+}
+
+clsp_status clsp_dilate_masks(const uint8_t* masks, int32_t n_views, int32_t width, int32_t height, int32_t radius,
+                              uint8_t* out, void* ws, size_t ws_bytes, clsp_stream stream) {
+  if (!masks || !out) return fail(CLSP_ERR_INVALID_ARG, "dilate_masks pointer is NULL");
+  if (n_views < 1 || n_views > CLSP_MAX_VIEWS) return fail(CLSP_ERR_INVALID_ARG, "n_views=%d not in 1..%d", n_views, CLSP_MAX_VIEWS);
+  if (width < 1 || height < 1 || width > CLSP_MAX_SIDE || height > CLSP_MAX_SIDE)
+    return fail(CLSP_ERR_INVALID_ARG, "image size %dx%d not in 1..%d", width, height, CLSP_MAX_SIDE);
+  if (radius < 0) return fail(CLSP_ERR_INVALID_ARG, "radius < 0");
+  const size_t need = clsp_dilate_masks_workspace_bytes(n_views, width, height);
+  if (!ws || ws_bytes < need)
+    return fail(CLSP_ERR_INVALID_ARG, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+  return hip_status(clsp::launch_dilate_masks(masks, n_views, width, height, radius, out, ws,
+                                              reinterpret_cast<hipStream_t>(stream)),
+                    "dilate_masks");
+}
+
+clsp_status clsp_majority_vote(const float* means, int64_t n_rows, int64_t n, const clsp_camera* cams,
+                               int32_t n_views, const uint8_t* masks, uint8_t* in_count, uint8_t* out_count,
+                               uint8_t* changed, uint32_t* n_changed, clsp_stream stream) {
+  if (!means || !masks || !in_count || !out_count || !changed || !n_changed)
+    return fail(CLSP_ERR_INVALID_ARG, "majority_vote pointer is NULL");
+  if (n < 0 || n > n_rows) return fail(CLSP_ERR_INVALID_ARG, "n=%lld not in 0..n_rows", (long long)n);
+  CHECK(check_cams(cams, n_views));
+  clsp::DevCam dc[CLSP_MAX_VIEWS];
+  for (int v = 0; v < n_views; ++v) dc[v] = dev_cam(cams[v]);
+  return hip_status(clsp::launch_majority_vote(means, n_rows, n, dc, n_views, masks, in_count, out_count, changed,
+                                               n_changed, reinterpret_cast<hipStream_t>(stream)),
+                    "majority_vote");
+}
+
 clsp_status clsp_fit_spheres(const float* means, int64_t n_rows, clsp_range rows, const int32_t* labels,
                              int32_t n_spheres, float* centers, float* radii, clsp_stream stream) {
   if (!means || !labels || !centers || !radii) return fail(CLSP_ERR_INVALID_ARG, "fit_spheres pointer is NULL");

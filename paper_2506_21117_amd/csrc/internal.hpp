@@ -129,6 +129,14 @@ size_t compact_workspace_bytes(int64_t na);
 hipError_t launch_compact_rows(const MutParams src[3], const MutParams dst[3], int sets, int64_t a0, int64_t a1,
                                const uint8_t* keep, void* ws, hipStream_t s);
 
+// lifting.hip
+size_t dilate_workspace_bytes(int views, int W, int H);
+hipError_t launch_dilate_masks(const uint8_t* masks, int views, int W, int H, int r, uint8_t* out, void* ws,
+                               hipStream_t s);
+hipError_t launch_majority_vote(const float* means, int64_t nr, int64_t n, const DevCam* cams, int views,
+                                const uint8_t* masks, uint8_t* c_in, uint8_t* c_out, uint8_t* changed,
+                                uint32_t* n_changed, hipStream_t s);
+
 // adam.hip
 hipError_t launch_adam(const MutParams& p, const MutParams& g, const MutParams& m, const MutParams& v, int64_t a0,
                        int64_t a1, const uint8_t* row_mask, const clsp_adam_hparams& hp, hipStream_t s);

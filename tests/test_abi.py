@@ -217,3 +217,20 @@ def test_sphere_calls_reject_invalid_arguments_on_the_host(L):
     assert ok(src, _ffi.Range(4, 10), deg3) == _ffi.CLSP_ERR_INVALID_ARG
     assert L.clsp_compact_rows(ctypes.byref(src), ctypes.byref(src), None, _ffi.Range(4, 10), fake, ctypes.byref(dst),
                                None, None, fake, ws, None) == _ffi.CLSP_ERR_INVALID_ARG   # half the moments
+
+
+@pytest.mark.skipif(_gpu_visible(), reason="passes the stand-in device address 0x1000 to entry points; run only "
+                                           "where no GPU could ever receive a launch on it")
+def test_lifting_calls_reject_invalid_arguments_on_the_host(L):
+    from paper_2506_21117_amd import _ffi
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    ws = L.clsp_dilate_masks_workspace_bytes(2, 64, 48)
+    assert ws == 2 * 64 * 48
+    assert L.clsp_dilate_masks(fake, 2, 64, 48, -1, fake, fake, ws, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_dilate_masks(fake, 0, 64, 48, 3, fake, fake, ws, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_dilate_masks(fake, 2, 64, 48, 3, fake, fake, ws - 1, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert b"workspace" in L.clsp_last_error()
+    cam = _cam()
+    assert L.clsp_majority_vote(fake, 10, 11, cam, 1, fake, fake, fake, fake, fake, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_majority_vote(fake, 10, 10, cam, 0, fake, fake, fake, fake, fake, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_majority_vote(fake, 10, 10, cam, 1, None, fake, fake, fake, fake, None) == _ffi.CLSP_ERR_INVALID_ARG
