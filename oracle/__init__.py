@@ -563,3 +563,41 @@ def majority_vote(means, cams, masks):
     V = len(cams)
     changed = (4 * o < 3 * V) & (V < 2 * c)
     return changed, c, o
+
+
+# ------------------------------------------------------------------ history and merges
+# Supp. "History Recovery": before optimising step t the Gaussians are reordered so the
+# unchanged ones (I^t = 0) come first, and O^t (the changed Gaussians' values) and I^t
+# are stored; G^{t-1} is rebuilt from G^t by putting the first #static Gaussians of G^t
+# where I^t = 0 and O^t where I^t = 1 (alg:example).  Supp. "Batched Updates": two
+# concurrent updates merge as the unchanged Gaussians of G^{t-1} followed by O_1 and O_2.
+def reorder_static_first(arrays, indicator):
+    """The rows (last axis) with indicator 0 in their order, then those with 1 in their
+    order; returns (arrays, #static)."""
+    ind = np.asarray(indicator, dtype=bool)
+    order = np.concatenate([np.nonzero(~ind)[0], np.nonzero(ind)[0]])
+    return [np.asarray(a)[..., order] for a in arrays], int((~ind).sum())
+
+
+def recover_previous(latest, indicator, changed_before):
+    """G^{k-1} from G^k (``latest``), I^k (``indicator``, over G^{k-1}) and O^k
+    (``changed_before``): an array of the target size, O^k at the positions where I^k is
+    1 and the first #static Gaussians of G^k, in order, where it is 0."""
+    ind = np.asarray(indicator, dtype=bool)
+    n_static = int((~ind).sum())
+    out = []
+    for g, o in zip(latest, changed_before):
+        g, o = np.asarray(g), np.asarray(o)
+        n = np.empty(g.shape[:-1] + (len(ind),), dtype=g.dtype)
+        n[..., ind] = o
+        n[..., ~ind] = g[..., :n_static]
+        out.append(n)
+    return out
+
+
+def merge_updates(prev, ind1, ind2, o1, o2):
+    """G^t = G^{t-1}[not I_1 and not I_2] followed by O_1 and O_2 (the unchanged
+    Gaussians in their order, then both updates)."""
+    keep = ~(np.asarray(ind1, dtype=bool) | np.asarray(ind2, dtype=bool))
+    return [np.concatenate([np.asarray(p)[..., keep], np.asarray(a), np.asarray(b)], axis=-1)
+            for p, a, b in zip(prev, o1, o2)]
