@@ -485,6 +485,40 @@ clsp_status clsp_compact_rows(const clsp_params *src, const clsp_params *src_m, 
                               clsp_range rows, const uint8_t *keep, const clsp_params *dst, const clsp_params *dst_m,
                               const clsp_params *dst_v, void *ws, size_t ws_bytes, clsp_stream stream);
 
+/* ---------------------------------------------------------------------------------
+ * History of the reconstruction (Supp. "History Recovery", Alg. alg:example; Supp.
+ * "Batched Updates").  Row copies of whole Gaussians (every parameter component; each
+ * set uses its own n as its row stride); source and destination must not overlap.
+ * ws: device workspace of clsp_history_workspace_bytes() bytes.
+ *
+ * clsp_reorder_static_first: before step t is optimised, dst = the rows of src whose
+ * changed (uint8[src->n], e.g. from clsp_majority_vote: I^t) is 0, in order, then those
+ * whose changed is 1, in order, so that O^t is the suffix and dst[:#static] is the
+ * static part of G^{t-1}; n_static (device uint32[1]) = #static.  dst->n must equal
+ * src->n.  The caller keeps I^t and O^t (dst's suffix at this moment) for recovery.
+ *
+ * clsp_recover_previous: G^{k-1} from G^k (latest), I^k (indicator, uint8[dst->n], over
+ * G^{k-1}) and O^k (changed_before, the changed Gaussians' values before step k):
+ * dst[i] = O^k[j] where indicator[i] is the j-th 1, latest[j] where it is the j-th 0.
+ * Sizes must agree (latest->n >= zeros of I^k, changed_before->n = ones of I^k); a row
+ * whose source is missing is not written.  Repeating it recovers any earlier state.
+ *
+ * clsp_merge_updates: two concurrent updates of G^{t-1} (prev): dst = the rows of prev
+ * that neither ind1 nor ind2 (uint8[prev->n]) marks, in order, then o1's rows, then
+ * o2's (the paper's merge, read so that every unchanged Gaussian is kept).  dst->n should
+ * be that total; no row at or past dst->n is written.
+ * Errors: NULL or mismatched parameter sets (sh degree), size mismatches stated above
+ * that the host can check, workspace too small. */
+size_t clsp_history_workspace_bytes(void);
+clsp_status clsp_reorder_static_first(const clsp_params *src, const uint8_t *changed, const clsp_params *dst,
+                                      uint32_t *n_static, void *ws, size_t ws_bytes, clsp_stream stream);
+clsp_status clsp_recover_previous(const clsp_params *latest, const uint8_t *indicator,
+                                  const clsp_params *changed_before, const clsp_params *dst, void *ws,
+                                  size_t ws_bytes, clsp_stream stream);
+clsp_status clsp_merge_updates(const clsp_params *prev, const uint8_t *ind1, const uint8_t *ind2,
+                               const clsp_params *o1, const clsp_params *o2, const clsp_params *dst, void *ws,
+                               size_t ws_bytes, clsp_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,6 +27,7 @@ EXPORTED = (
     "clsp_render_backward", "clsp_masked_adam_step", "clsp_zero_grads", "clsp_render_backward_adam",
     "clsp_render_backward_noalloc", "clsp_fit_spheres", "clsp_sphere_keep", "clsp_compact_rows_workspace_bytes",
     "clsp_compact_rows", "clsp_dilate_masks_workspace_bytes", "clsp_dilate_masks", "clsp_majority_vote",
+    "clsp_history_workspace_bytes", "clsp_reorder_static_first", "clsp_recover_previous", "clsp_merge_updates",
 )
 
 
@@ -150,6 +151,17 @@ def load(path: Path | None = None):
     L.clsp_majority_vote.restype = st
     L.clsp_majority_vote.argtypes = [c_void_p, c_int64, c_int64, POINTER(Camera), c_int32, c_void_p, c_void_p,
                                      c_void_p, c_void_p, c_void_p, c_void_p]
+    L.clsp_history_workspace_bytes.restype = c_size_t
+    L.clsp_history_workspace_bytes.argtypes = []
+    L.clsp_reorder_static_first.restype = st
+    L.clsp_reorder_static_first.argtypes = [POINTER(Params), c_void_p, POINTER(Params), c_void_p, c_void_p, c_size_t,
+                                            c_void_p]
+    L.clsp_recover_previous.restype = st
+    L.clsp_recover_previous.argtypes = [POINTER(Params), c_void_p, POINTER(Params), POINTER(Params), c_void_p,
+                                        c_size_t, c_void_p]
+    L.clsp_merge_updates.restype = st
+    L.clsp_merge_updates.argtypes = [POINTER(Params), c_void_p, c_void_p, POINTER(Params), POINTER(Params),
+                                     POINTER(Params), c_void_p, c_size_t, c_void_p]
     if path is None:
         _lib = L
     return L

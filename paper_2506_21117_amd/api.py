@@ -496,3 +496,49 @@ def majority_vote(means, cams, masks, n=None, stream=None):
     check(lib().clsp_majority_vote(mp, nr, n, camera_array(cams), len(cams), _ptr(masks), _ptr(cin), _ptr(cout),
                                    _ptr(changed), _ptr(cnt), _stream(stream)))
     return changed[:n], cin[:n], cout[:n], cnt
+
+
+# ------------------------------------------------------------------ history
+def _history_ws(device):
+    return torch.empty(max(1, lib().clsp_history_workspace_bytes()), dtype=torch.uint8, device=device)
+
+
+def _u8(t, n, what):
+    if t.dtype != torch.uint8 or t.numel() != n or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous uint8 tensor of {n} entries")
+    return _ptr(t)
+
+
+def reorder_static_first(src: GaussianTensors, changed, stream=None):
+    """(dst, n_static int32 [1]): src's rows with changed = 0 first, then those with 1."""
+    dev = src.means.device
+    dst = GaussianTensors.zeros(src.n, src.sh_degree, dev)
+    ns = torch.empty(1, dtype=torch.int32, device=dev)
+    ws = _history_ws(dev)
+    check(lib().clsp_reorder_static_first(ctypes.byref(src.as_params()), _u8(changed, src.n, "changed"),
+                                          ctypes.byref(dst.as_params()), _ptr(ns), _ptr(ws), ws.numel(),
+                                          _stream(stream)))
+    return dst, ns
+
+
+def recover_previous(latest: GaussianTensors, indicator, changed_before: GaussianTensors, stream=None):
+    """G^{k-1} from G^k, I^k and O^k."""
+    dev = latest.means.device
+    n = int(indicator.numel())
+    dst = GaussianTensors.zeros(n, latest.sh_degree, dev)
+    ws = _history_ws(dev)
+    check(lib().clsp_recover_previous(ctypes.byref(latest.as_params()), _u8(indicator, n, "indicator"),
+                                      ctypes.byref(changed_before.as_params()), ctypes.byref(dst.as_params()),
+                                      _ptr(ws), ws.numel(), _stream(stream)))
+    return dst
+
+
+def merge_updates(prev: GaussianTensors, ind1, ind2, o1: GaussianTensors, o2: GaussianTensors, n_out, stream=None):
+    """The rows of ``prev`` neither update marks, then o1's, then o2's (``n_out`` rows)."""
+    dev = prev.means.device
+    dst = GaussianTensors.zeros(int(n_out), prev.sh_degree, dev)
+    ws = _history_ws(dev)
+    check(lib().clsp_merge_updates(ctypes.byref(prev.as_params()), _u8(ind1, prev.n, "ind1"), _u8(ind2, prev.n, "ind2"),
+                                   ctypes.byref(o1.as_params()), ctypes.byref(o2.as_params()),
+                                   ctypes.byref(dst.as_params()), _ptr(ws), ws.numel(), _stream(stream)))
+    return dst

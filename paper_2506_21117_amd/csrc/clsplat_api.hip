@@ -569,6 +569,71 @@ clsp_status clsp_compact_rows(const clsp_params* src, const clsp_params* src_m, 
                     "compact_rows");
 }
 
+size_t clsp_history_workspace_bytes(void) { return clsp::history_workspace_bytes(); }
+
+namespace {
+clsp_status check_history_ws(void* ws, size_t ws_bytes) {
+  if (!ws || ws_bytes < clsp::history_workspace_bytes())
+    return fail(CLSP_ERR_INVALID_ARG, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
+                clsp::history_workspace_bytes());
+  return CLSP_OK;
+}
+clsp_status same_degree(const clsp_params* a, const clsp_params* b) {
+  if (a->sh_degree != b->sh_degree) return fail(CLSP_ERR_INVALID_ARG, "parameter sets of different sh degree");
+  return CLSP_OK;
+}
+}  // namespace
+
+clsp_status clsp_reorder_static_first(const clsp_params* src, const uint8_t* changed, const clsp_params* dst,
+                                      uint32_t* n_static, void* ws, size_t ws_bytes, clsp_stream stream) {
+  CHECK(check_params(src, "src"));
+  CHECK(check_params(dst, "dst"));
+  CHECK(same_degree(src, dst));
+  if (dst->n != src->n) return fail(CLSP_ERR_INVALID_ARG, "reorder_static_first: dst->n != src->n");
+  if (!n_static || (src->n > 0 && !changed)) return fail(CLSP_ERR_INVALID_ARG, "reorder_static_first pointer is NULL");
+  CHECK(check_history_ws(ws, ws_bytes));
+  return hip_status(clsp::launch_reorder_static_first(mut_params(src), changed, mut_params(dst), n_static, ws,
+                                                      reinterpret_cast<hipStream_t>(stream)),
+                    "reorder_static_first");
+}
+
+clsp_status clsp_recover_previous(const clsp_params* latest, const uint8_t* indicator,
+                                  const clsp_params* changed_before, const clsp_params* dst, void* ws,
+                                  size_t ws_bytes, clsp_stream stream) {
+  CHECK(check_params(latest, "latest"));
+  CHECK(check_params(changed_before, "changed_before"));
+  CHECK(check_params(dst, "dst"));
+  CHECK(same_degree(latest, dst));
+  CHECK(same_degree(changed_before, dst));
+  if (dst->n > 0 && !indicator) return fail(CLSP_ERR_INVALID_ARG, "recover_previous: indicator is NULL");
+  if (latest->n + changed_before->n < dst->n)
+    return fail(CLSP_ERR_INVALID_ARG, "recover_previous: %lld + %lld source rows cannot fill %lld",
+                (long long)latest->n, (long long)changed_before->n, (long long)dst->n);
+  CHECK(check_history_ws(ws, ws_bytes));
+  return hip_status(clsp::launch_recover_previous(mut_params(latest), indicator, mut_params(changed_before),
+                                                  mut_params(dst), ws, reinterpret_cast<hipStream_t>(stream)),
+                    "recover_previous");
+}
+
+clsp_status clsp_merge_updates(const clsp_params* prev, const uint8_t* ind1, const uint8_t* ind2,
+                               const clsp_params* o1, const clsp_params* o2, const clsp_params* dst, void* ws,
+                               size_t ws_bytes, clsp_stream stream) {
+  CHECK(check_params(prev, "prev"));
+  CHECK(check_params(o1, "o1"));
+  CHECK(check_params(o2, "o2"));
+  CHECK(check_params(dst, "dst"));
+  CHECK(same_degree(prev, dst));
+  CHECK(same_degree(o1, dst));
+  CHECK(same_degree(o2, dst));
+  if (prev->n > 0 && (!ind1 || !ind2)) return fail(CLSP_ERR_INVALID_ARG, "merge_updates: an indicator is NULL");
+  if (dst->n > prev->n + o1->n + o2->n)
+    return fail(CLSP_ERR_INVALID_ARG, "merge_updates: dst->n larger than the rows merged");
+  CHECK(check_history_ws(ws, ws_bytes));
+  return hip_status(clsp::launch_merge_updates(mut_params(prev), ind1, ind2, mut_params(o1), mut_params(o2),
+                                               mut_params(dst), ws, reinterpret_cast<hipStream_t>(stream)),
+                    "merge_updates");
+}
+
 clsp_status clsp_zero_grads(const clsp_params* grads, clsp_range active, clsp_stream stream) {
   CHECK(check_params(grads, "grads"));
   CHECK(check_range(active, grads->n));

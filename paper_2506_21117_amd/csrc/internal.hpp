@@ -58,6 +58,16 @@ struct MutParams {
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// Pointer to component c of a parameter set (means 0-2, log_scales 3-5, quats 6-9,
+// opacity 10, sh 11..); a row has 11 + 3 (sh_degree + 1)^2 components.
+__device__ __forceinline__ float* component(const MutParams& p, int c) {
+  if (c < 3) return p.means + (int64_t)c * p.n;
+  if (c < 6) return p.log_scales + (int64_t)(c - 3) * p.n;
+  if (c < 10) return p.quats + (int64_t)(c - 6) * p.n;
+  if (c == 10) return p.opac;
+  return p.sh + (int64_t)(c - 11) * p.n;
+}
+
 // ---------------------------------------------------------------- launchers
 // preprocess.hip
 // Projects entries [r0, r1) of view `view` (all n: r0 = 0, r1 = g.n).
@@ -136,6 +146,18 @@ hipError_t launch_dilate_masks(const uint8_t* masks, int views, int W, int H, in
 hipError_t launch_majority_vote(const float* means, int64_t nr, int64_t n, const DevCam* cams, int views,
                                 const uint8_t* masks, uint8_t* c_in, uint8_t* c_out, uint8_t* changed,
                                 uint32_t* n_changed, hipStream_t s);
+
+// history.hip
+size_t history_workspace_bytes();
+// dst = rows of src with changed = 0, then those with 1 (both in order); *n_static = zeros
+hipError_t launch_reorder_static_first(const MutParams& src, const uint8_t* changed, const MutParams& dst,
+                                       uint32_t* n_static, void* ws, hipStream_t s);
+// dst[i] = ind[i] ? older[rank among ones] : latest[rank among zeros], i < dst.n
+hipError_t launch_recover_previous(const MutParams& latest, const uint8_t* ind, const MutParams& older,
+                                   const MutParams& dst, void* ws, hipStream_t s);
+// dst = prev rows with ind1 = ind2 = 0, then o1, then o2
+hipError_t launch_merge_updates(const MutParams& prev, const uint8_t* ind1, const uint8_t* ind2, const MutParams& o1,
+                                const MutParams& o2, const MutParams& dst, void* ws, hipStream_t s);
 
 // adam.hip
 hipError_t launch_adam(const MutParams& p, const MutParams& g, const MutParams& m, const MutParams& v, int64_t a0,

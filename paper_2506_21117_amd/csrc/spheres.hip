@@ -150,16 +150,6 @@ __global__ void __launch_bounds__(NT) sphere_keep_kernel(const float* __restrict
   if (threadIdx.x == 0 && cnt) atomicAdd(kept, cnt);
 }
 
-// Pointer to component c of a parameter set (means 0-2, log_scales 3-5, quats 6-9,
-// opacity 10, sh 11..).
-__device__ __forceinline__ float* component(const MutParams& p, int c) {
-  if (c < 3) return p.means + (int64_t)c * p.n;
-  if (c < 6) return p.log_scales + (int64_t)(c - 3) * p.n;
-  if (c < 10) return p.quats + (int64_t)(c - 6) * p.n;
-  if (c == 10) return p.opac;
-  return p.sh + (int64_t)(c - 11) * p.n;
-}
-
 struct CompactSets {
   MutParams src[3], dst[3];
   int sets;        // 1: parameters only; 3: with both Adam moments

@@ -234,3 +234,23 @@ def test_lifting_calls_reject_invalid_arguments_on_the_host(L):
     assert L.clsp_majority_vote(fake, 10, 11, cam, 1, fake, fake, fake, fake, fake, None) == _ffi.CLSP_ERR_INVALID_ARG
     assert L.clsp_majority_vote(fake, 10, 10, cam, 0, fake, fake, fake, fake, fake, None) == _ffi.CLSP_ERR_INVALID_ARG
     assert L.clsp_majority_vote(fake, 10, 10, cam, 1, None, fake, fake, fake, fake, None) == _ffi.CLSP_ERR_INVALID_ARG
+
+
+@pytest.mark.skipif(_gpu_visible(), reason="passes the stand-in device address 0x1000 to entry points; run only "
+                                           "where no GPU could ever receive a launch on it")
+def test_history_calls_reject_invalid_arguments_on_the_host(L):
+    from paper_2506_21117_amd import _ffi
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    ws = L.clsp_history_workspace_bytes()
+    a = _ffi.Params(fake, fake, fake, fake, fake, 10, 0, 0)
+    b = _ffi.Params(fake, fake, fake, fake, fake, 9, 0, 0)
+    c = _ffi.Params(fake, fake, fake, fake, fake, 3, 0, 0)
+    d3 = _ffi.Params(fake, fake, fake, fake, fake, 10, 3, 0)
+    by = ctypes.byref
+    assert L.clsp_reorder_static_first(by(a), fake, by(b), fake, fake, ws, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_reorder_static_first(by(a), fake, by(d3), fake, fake, ws, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_reorder_static_first(by(a), fake, by(a), fake, fake, ws - 1, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_recover_previous(by(c), fake, by(c), by(a), fake, ws, None) == _ffi.CLSP_ERR_INVALID_ARG   # 3 + 3 < 10
+    assert L.clsp_recover_previous(by(b), None, by(c), by(a), fake, ws, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_merge_updates(by(c), fake, fake, by(c), by(c), by(a), fake, ws, None) == _ffi.CLSP_ERR_INVALID_ARG
+    assert L.clsp_merge_updates(by(a), fake, None, by(c), by(c), by(c), fake, ws, None) == _ffi.CLSP_ERR_INVALID_ARG
