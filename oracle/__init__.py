@@ -601,3 +601,78 @@ def merge_updates(prev, ind1, ind2, o1, o2):
     keep = ~(np.asarray(ind1, dtype=bool) | np.asarray(ind2, dtype=bool))
     return [np.concatenate([np.asarray(p)[..., keep], np.asarray(a), np.asarray(b)], axis=-1)
             for p, a, b in zip(prev, o1, o2)]
+
+
+# ------------------------------------------------------------------ L1 + D-SSIM loss
+# The paper trains with the default 3D Gaussian Splatting loss (Supp. "Implementation
+# Details"): (1 - lambda) L1 + lambda (1 - SSIM), lambda = 0.2, SSIM with an 11 x 11
+# Gaussian window of standard deviation 1.5, C1 = 0.01^2, C2 = 0.03^2, computed per
+# channel with zero padding at the image border and averaged over channels and pixels.
+SSIM_SIZE = 11
+SSIM_SIGMA = 1.5
+SSIM_C1 = 0.01 ** 2
+SSIM_C2 = 0.03 ** 2
+LAMBDA_DSSIM = 0.2
+
+
+def ssim_window():
+    """The 11 x 11 window: outer product of the normalised 1D Gaussian exp(-i^2 / (2
+    sigma^2)), i = -5..5."""
+    i = np.arange(SSIM_SIZE) - SSIM_SIZE // 2
+    g = np.exp(-(i * i) / (2.0 * SSIM_SIGMA ** 2))
+    g /= g.sum()
+    return np.outer(g, g)
+
+
+def _window_sum(a, w):
+    """sum over the window centred at each pixel of w(offset) a(pixel + offset), zero
+    outside the image; a [..., H, W]."""
+    r = w.shape[0] // 2
+    H, W = a.shape[-2:]
+    pad = np.zeros(a.shape[:-2] + (H + 2 * r, W + 2 * r))
+    pad[..., r:r + H, r:r + W] = a
+    out = np.zeros(a.shape)
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            out += w[dy + r, dx + r] * pad[..., r + dy:r + dy + H, r + dx:r + dx + W]
+    return out
+
+
+def ssim_map(x, y):
+    """Per-pixel SSIM [..., H, W] of images x, y [..., H, W] (float64)."""
+    x, y = _f64(x), _f64(y)
+    w = ssim_window()
+    mx, my = _window_sum(x, w), _window_sum(y, w)
+    exx, eyy, exy = _window_sum(x * x, w), _window_sum(y * y, w), _window_sum(x * y, w)
+    A = 2 * mx * my + SSIM_C1
+    B = 2 * (exy - mx * my) + SSIM_C2
+    C = mx * mx + my * my + SSIM_C1
+    D = (exx - mx * mx) + (eyy - my * my) + SSIM_C2
+    return A * B / (C * D)
+
+
+def l1_dssim_loss_grad(image, target, lam=LAMBDA_DSSIM):
+    """Loss (1 - lam) mean|x - y| + lam (1 - mean SSIM) over [3, H, W] images and its
+    gradient with respect to x.  SSIM at pixel p is a function of its window sums
+    mu_x, E[xx], E[xy] (and y's), so by the chain rule
+    d SSIM(p) / d x(q) = w(q - p) [d/dmu_x + 2 x(q) d/dE[xx] + y(q) d/dE[xy]] SSIM(p),
+    and the gradient at q is the window sum of those three partial maps, the zero padding
+    making them vanish outside the image."""
+    x, y = _f64(image), _f64(target)
+    n = x.size
+    w = ssim_window()
+    mx, my = _window_sum(x, w), _window_sum(y, w)
+    exx, eyy, exy = _window_sum(x * x, w), _window_sum(y * y, w), _window_sum(x * y, w)
+    A = 2 * mx * my + SSIM_C1
+    B = 2 * (exy - mx * my) + SSIM_C2
+    C = mx * mx + my * my + SSIM_C1
+    D = (exx - mx * mx) + (eyy - my * my) + SSIM_C2
+    s = A * B / (C * D)
+    # partials of s = A B / (C D) in (mu_x, E[xx], E[xy]) with A, B, C, D as above
+    d_mx = (2 * my * B - 2 * my * A) / (C * D) - s * (2 * mx / C - 2 * mx / D)
+    d_exx = -s / D
+    d_exy = 2 * A / (C * D)
+    g_ssim = _window_sum(d_mx, w) + 2 * x * _window_sum(d_exx, w) + y * _window_sum(d_exy, w)
+    loss = (1 - lam) * np.abs(x - y).sum() / n + lam * (1 - s.sum() / n)
+    grad = (1 - lam) * np.sign(x - y) / n - lam * g_ssim / n
+    return loss, grad
