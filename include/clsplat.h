@@ -322,6 +322,30 @@ clsp_status clsp_l1_loss_grad(const float *image, const float *target, const cls
                               clsp_stream stream);
 
 /* ---------------------------------------------------------------------------------
+ * The default 3D Gaussian Splatting loss, which the paper trains with (Supp.
+ * "Implementation Details"): L = (1 - lambda) L1 + lambda (1 - SSIM), SSIM per channel
+ * with an 11 x 11 Gaussian window of standard deviation CLSP_SSIM_SIGMA, constants
+ * CLSP_SSIM_C1, CLSP_SSIM_C2, zero padding at the image border, L1 and SSIM averaged
+ * over the 3 H W values of the whole image (lambda = CLSP_LAMBDA_DSSIM by default).
+ * Writes dL_dimage for the pixels of rendered tiles (others are not written) and adds
+ * the loss of those pixels to loss_sum (device float[1], may be NULL).  The gradient at
+ * a pixel reads the image within 10 pixels of it; pixels of tiles that were not
+ * rendered are read from frozen_image (device, like image; nullable), which local steps
+ * set to a render of the unchanged Gaussians alone: outside the render mask no changed
+ * Gaussian reaches, so that render is the current image there and the gradient on the
+ * masked tiles is the full-image gradient.  With frozen_image NULL every pixel is read
+ * from image (full steps render every tile).  Sums and SSIM partials are evaluated in
+ * double; dL_dimage is rounded to float once.
+ * Errors: as clsp_l1_loss_grad, plus lambda not in [0, 1]. */
+#define CLSP_SSIM_SIGMA 1.5
+#define CLSP_SSIM_C1 (0.01 * 0.01)
+#define CLSP_SSIM_C2 (0.03 * 0.03)
+#define CLSP_LAMBDA_DSSIM 0.2f
+clsp_status clsp_l1_dssim_loss_grad(const float *image, const float *target, const float *frozen_image,
+                                    const clsp_bins *bins, const clsp_camera *cams, int32_t n_views, float lambda,
+                                    float *dL_dimage, float *loss_sum, clsp_stream stream);
+
+/* ---------------------------------------------------------------------------------
  * Backward (Table tab:timings "Backward::Render" and "Backward::Preprocess"; Supp.
  * items 2-3).  Reverse compositing over the rendered tiles accumulates screen-space
  * gradients for the Gaussians in `active` only, then the chain rule to raw parameters

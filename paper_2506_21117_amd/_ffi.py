@@ -28,6 +28,7 @@ EXPORTED = (
     "clsp_render_backward_noalloc", "clsp_fit_spheres", "clsp_sphere_keep", "clsp_compact_rows_workspace_bytes",
     "clsp_compact_rows", "clsp_dilate_masks_workspace_bytes", "clsp_dilate_masks", "clsp_majority_vote",
     "clsp_history_workspace_bytes", "clsp_reorder_static_first", "clsp_recover_previous", "clsp_merge_updates",
+    "clsp_l1_dssim_loss_grad",
 )
 
 
@@ -162,6 +163,9 @@ def load(path: Path | None = None):
     L.clsp_merge_updates.restype = st
     L.clsp_merge_updates.argtypes = [POINTER(Params), c_void_p, c_void_p, POINTER(Params), POINTER(Params),
                                      POINTER(Params), c_void_p, c_size_t, c_void_p]
+    L.clsp_l1_dssim_loss_grad.restype = st
+    L.clsp_l1_dssim_loss_grad.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(Bins), POINTER(Camera), c_int32,
+                                          c_float, c_void_p, c_void_p, c_void_p]
     if path is None:
         _lib = L
     return L

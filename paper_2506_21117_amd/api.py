@@ -305,6 +305,24 @@ def l1_loss_grad(image, target, bins, cams, dL=None, loss_sum=None, stream=None)
     return dL
 
 
+LAMBDA_DSSIM = 0.2
+
+
+def l1_dssim_loss_grad(image, target, bins, cams, frozen=None, lam=LAMBDA_DSSIM, dL=None, loss_sum=None, stream=None):
+    """dL/dimage of (1 - lam) L1 + lam (1 - SSIM) on the rendered tiles; ``frozen`` (like
+    image) supplies the pixels of tiles that were not rendered (local steps)."""
+    if dL is None:
+        dL = torch.zeros_like(image)
+    for t in (target, frozen):
+        if t is not None and (tuple(t.shape) != tuple(image.shape) or t.dtype != torch.float32
+                              or not t.is_contiguous()):
+            raise ValueError("target and frozen must be contiguous float32 tensors shaped like image")
+    check(lib().clsp_l1_dssim_loss_grad(_ptr(image), _ptr(target), _ptr(frozen), ctypes.byref(bins.struct()),
+                                        camera_array(cams), len(cams), float(lam), _ptr(dL), _ptr(loss_sum),
+                                        _stream(stream)))
+    return dL
+
+
 def render_backward_workspace(n_active, views, device):
     """Zero-filled (render_backward_adam needs a zero workspace and leaves it zero)."""
     b = lib().clsp_render_backward_workspace_bytes(int(n_active), int(views))

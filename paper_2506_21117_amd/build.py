@@ -12,7 +12,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 OUT = PKG / "libclsplat.so"
 BUILD = ROOT / "_build"
-SOURCES = ["preprocess.hip", "binning.hip", "render.hip", "adam.hip", "spheres.hip", "lifting.hip", "history.hip", "clsplat_api.hip"]
+SOURCES = ["preprocess.hip", "binning.hip", "render.hip", "adam.hip", "spheres.hip", "lifting.hip", "history.hip", "ssim.hip", "clsplat_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -345,6 +345,20 @@ clsp_status clsp_l1_loss_grad(const float* image, const float* target, const cls
                     "l1_loss_grad");
 }
 
+clsp_status clsp_l1_dssim_loss_grad(const float* image, const float* target, const float* frozen_image,
+                                    const clsp_bins* bins, const clsp_camera* cams, int32_t n_views, float lambda,
+                                    float* dL_dimage, float* loss_sum, clsp_stream stream) {
+  CHECK(check_bins(bins));
+  CHECK(check_cams(cams, n_views));
+  if (!image || !target || !dL_dimage) return fail(CLSP_ERR_INVALID_ARG, "l1_dssim_loss_grad pointer is NULL");
+  if (!(lambda >= 0.0f && lambda <= 1.0f)) return fail(CLSP_ERR_INVALID_ARG, "lambda not in [0, 1]");
+  const int W = cams[0].width, H = cams[0].height;
+  return hip_status(clsp::launch_l1_dssim(image, target, frozen_image, *bins, n_views, W, H,
+                                          (W + CLSP_TILE - 1) / CLSP_TILE, (H + CLSP_TILE - 1) / CLSP_TILE, lambda,
+                                          dL_dimage, loss_sum, reinterpret_cast<hipStream_t>(stream)),
+                    "l1_dssim_loss_grad");
+}
+
 size_t clsp_render_backward_workspace_bytes(int64_t n_active, int32_t n_views) {
   if (n_active < 0 || n_views < 1) return 0;
   return (size_t)n_active * n_views * clsp::G2D_STRIDE * sizeof(float);

@@ -159,6 +159,11 @@ hipError_t launch_recover_previous(const MutParams& latest, const uint8_t* ind, 
 hipError_t launch_merge_updates(const MutParams& prev, const uint8_t* ind1, const uint8_t* ind2, const MutParams& o1,
                                 const MutParams& o2, const MutParams& dst, void* ws, hipStream_t s);
 
+// ssim.hip
+hipError_t launch_l1_dssim(const float* image, const float* target, const float* frozen, const clsp_bins& bins,
+                           int views, int W, int H, int TX, int TY, float lam, float* dL, float* loss_sum,
+                           hipStream_t s);
+
 // adam.hip
 hipError_t launch_adam(const MutParams& p, const MutParams& g, const MutParams& m, const MutParams& v, int64_t a0,
                        int64_t a1, const uint8_t* row_mask, const clsp_adam_hparams& hp, hipStream_t s);

@@ -21,7 +21,7 @@ from ._ffi import C_STICKY, check
 
 class SplatOptimizer:
     def __init__(self, params: api.GaussianTensors, cams, targets, active=None, local=True, bg=(0.0, 0.0, 0.0),
-                 capacity=None, lr=api.DEFAULT_LR, projection_cache_bytes=32 << 30):
+                 capacity=None, lr=api.DEFAULT_LR, projection_cache_bytes=32 << 30, loss="l1"):
         """params: device parameters (updated in place); cams: list of cameras of one
         size; targets: [V, 3, H, W] float32 device tensor; active: (a0, a1) change set
         (default: all rows); local: restrict rendering to the change set's tile mask.
@@ -30,7 +30,16 @@ class SplatOptimizer:
         view, when that fits in ``projection_cache_bytes``) and re-project only the
         change set's rows: the other rows are frozen, so their projection for a view is
         the same every time the view comes back.  Call ``invalidate_projections()`` after
-        changing rows outside the change set."""
+        changing rows outside the change set.
+
+        loss: "l1" (the benchmark's loss), or "l1_dssim", the default 3D Gaussian Splatting
+        loss the paper trains with, 0.8 L1 + 0.2 (1 - SSIM); its gradient on a masked tile
+        reads pixels around the tile, which local steps take from a render of the unchanged
+        Gaussians alone, made once per view (they never change)."""
+        if loss not in ("l1", "l1_dssim"):
+            raise ValueError("loss must be 'l1' or 'l1_dssim'")
+        self.loss = loss
+        self._frozen_images = {}
         self.params = params
         self.cams = list(cams)
         self.targets = targets
@@ -154,10 +163,33 @@ class SplatOptimizer:
         self._prepare_calls()
         return (a1 - a0) - k
 
+    def _frozen_image(self, view):
+        """Device pointer of the render of the unchanged rows [0, a0) from view ``view``
+        (made on first use, not part of a step)."""
+        if view not in self._frozen_images:
+            a0 = self.active[0]
+            dev = self.params.means.device
+            cam = [self.cams[view]]
+            g = api.GaussianTensors(*[getattr(self.params, k)[..., :a0].contiguous() for k in api.GaussianTensors.NAMES],
+                                    self.params.sh_degree)
+            proj = api.project_preprocess(g, cam)
+            cap = 1 << 20
+            while True:
+                bins = api.bin_and_sort(proj, cam, capacity=cap)
+                img, _, _ = api.render_forward(proj, bins, cam, self.bg)
+                c = bins.read_counters()
+                if not c["overflow"]:
+                    break
+                cap = int(c["pairs"] * 1.1) + 1024
+            self._frozen_images[view] = img
+        return ctypes.c_void_p(self._frozen_images[view].data_ptr())
+
     def invalidate_projections(self):
-        """The next step on each view projects every row again (needed after rows outside
-        the change set were modified)."""
+        """The next step on each view projects every row again, and renders the unchanged
+        rows again for the D-SSIM term (needed after rows outside the change set were
+        modified)."""
         self._projected = [False] * len(self.cams)
+        self._frozen_images = {}
 
     def overflowed(self) -> bool:
         """True if any step since the last check ran out of pair capacity (sticky
@@ -235,9 +267,17 @@ class SplatOptimizer:
         check(L.clsp_bin_and_sort(by(proj), cam, 1, self._range, use_mask, by(self._bins), st))
         mark("bin_and_sort", 1)
         mark("render_forward", 0)
-        # the forward also writes the L1 loss gradient of the pixels it renders
-        check(L.clsp_render_forward_l1(by(proj), by(self._bins), cam, 1, self._bg, P["targets"][view], P["image"],
-                                       P["T"], P["nc"], P["state"], self._sizes[2], P["dL"], P["loss"], st))
+        if self.loss == "l1":
+            # the forward also writes the L1 loss gradient of the pixels it renders
+            check(L.clsp_render_forward_l1(by(proj), by(self._bins), cam, 1, self._bg, P["targets"][view],
+                                           P["image"], P["T"], P["nc"], P["state"], self._sizes[2], P["dL"],
+                                           P["loss"], st))
+        else:
+            check(L.clsp_render_forward(by(proj), by(self._bins), cam, 1, self._bg, P["image"], P["T"], P["nc"],
+                                        P["state"], self._sizes[2], st))
+            frozen = self._frozen_image(view) if self.local else None
+            check(L.clsp_l1_dssim_loss_grad(P["image"], P["targets"][view], frozen, by(self._bins), cam, 1,
+                                            ctypes.c_float(api.LAMBDA_DSSIM), P["dL"], P["loss"], st))
         mark("render_forward", 1)
         self.step_count += 1
         self._hp.step = self.step_count

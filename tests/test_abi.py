@@ -254,3 +254,18 @@ def test_history_calls_reject_invalid_arguments_on_the_host(L):
     assert L.clsp_recover_previous(by(b), None, by(c), by(a), fake, ws, None) == _ffi.CLSP_ERR_INVALID_ARG
     assert L.clsp_merge_updates(by(c), fake, fake, by(c), by(c), by(a), fake, ws, None) == _ffi.CLSP_ERR_INVALID_ARG
     assert L.clsp_merge_updates(by(a), fake, None, by(c), by(c), by(c), fake, ws, None) == _ffi.CLSP_ERR_INVALID_ARG
+
+
+@pytest.mark.skipif(_gpu_visible(), reason="passes the stand-in device address 0x1000 to entry points; run only "
+                                           "where no GPU could ever receive a launch on it")
+def test_l1_dssim_rejects_invalid_arguments_on_the_host(L):
+    from paper_2506_21117_amd import _ffi
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    bins = _ffi.Bins(fake, fake, fake, fake, fake, fake, fake, fake, fake, 1 << 20, 100, 10, 1, 0)
+    cam = _cam()
+    f = lambda img, lam: L.clsp_l1_dssim_loss_grad(img, fake, None, ctypes.byref(bins), cam, 1, ctypes.c_float(lam),
+                                                   fake, None, None)
+    assert f(None, 0.2) == _ffi.CLSP_ERR_INVALID_ARG
+    assert f(fake, 1.5) == _ffi.CLSP_ERR_INVALID_ARG
+    assert f(fake, float("nan")) == _ffi.CLSP_ERR_INVALID_ARG
+    assert b"lambda" in L.clsp_last_error()
