@@ -31,6 +31,8 @@ def parse():
     ap.add_argument("--n", type=int, default=1_000_000, help="Gaussians (default: the 1M workload)")
     ap.add_argument("--no-full", action="store_true", help="skip the full-scene comparison")
     ap.add_argument("--only-full", action="store_true", help="time only the full-scene step (profiling)")
+    ap.add_argument("--only-visible", action="store_true",
+                    help="time only the local step with the change ball on the cube face z = +1 (profiling)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="time budget of the CPU oracle timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving latency leg")
@@ -153,6 +155,13 @@ def main():
         stats = {k: float(np.mean([st[k] for st in per_view])) for k in per_view[0]}
         return dt, call_ms, stats, opt
 
+    if args.only_visible:
+        del targets
+        wv = scenes.local_change(n=args.n, center=(0.0, 0.0, 1.0))
+        tv = render_targets(wv)
+        t_v, ms_v, st_v, _ = run(True, sc=wv.scene, targets=tv, a=(wv.active_begin, wv.scene.n))
+        log(f"visible: {args.steps / t_v:.1f} it/s, calls {ms_v}, {st_v}")
+        return 0
     if args.only_full:
         t_full, ms_full, st_full, _ = run(False)
         log(f"full: {args.steps / t_full:.1f} it/s, calls {ms_full}, {st_full}")

@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
   float Tr = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;   // colour of the flushed chunks
   float dr = 0.0f, dg = 0.0f, db = 0.0f;              // colour of the current chunk
   uint32_t last = 0;
-  bool done = !inside;
+  float live = inside ? 1.0f : 0.0f;   // 1 until the pixel stops compositing
   int chunk = 0;
   int chl = CH;  // the tile's current chunk length (uniform over the workgroup)
   if (PHASE == 2) {
@@ -202,13 +202,13 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
     dg = my_carry[5 * NT];
     db = my_carry[6 * NT];
     last = __float_as_uint(my_carry[7 * NT]);
-    done = my_carry[8 * NT] != 0.0f;
+    live = my_carry[8 * NT] != 0.0f ? 0.0f : 1.0f;
     // the first phase composited the whole first list (the tile was still alive)
     chl = chunk_len_after(len1);
     chunk = len1 / chl;
   }
   for (int kb = k_begin; kb < k_end; kb += NT) {
-    if (__syncthreads_count(done) == NT) break;
+    if (__syncthreads_count(live == 0.0f) == NT) break;
     const int k = kb + threadIdx.x;
     if (k < k_end) {
       const uint32_t e = list_entry(values, r1, r2, k);
@@ -221,38 +221,48 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
       const int next_b = ((kb + j) / chl + 1) * chl;
       const int jhi = min(cnt, next_b - kb);
       // Branch-free blending, FW_UNROLL records per iteration: their weights are
-      // computed first, then applied in order with selects; a lane that has stopped
-      // keeps its state (the same values as stopping with a branch).  The wave leaves
-      // the segment once all its lanes have stopped.
-      auto blend = [&](bool ok, float alpha, float4 b, float c, uint32_t k1) {
-        const float Tn = Tr * (1.0f - alpha);
-        const bool stop = ok && Tn < T_STOP;
-        const bool use = ok && !stop;
-        const float w = use ? alpha * Tr : 0.0f;  // colours are finite and >= 0: adding 0*c is exact
-        dr = fmaf(w, b.z, dr);
-        dg = fmaf(w, b.w, dg);
-        db = fmaf(w, c, db);
-        Tr = use ? Tn : Tr;
-        last = use ? k1 : last;
-        done = done || stop;
-      };
-      for (int jj = j; jj < jhi; jj += FW_UNROLL) {
-        if (__ballot(!done) == 0ull) break;
-        float al[FW_UNROLL], cq[FW_UNROLL];
+      // computed first, then applied in order.  The per-lane state is kept in floats so
+      // that no lane-mask logic is needed: `live` is 1 until the pixel stops, a skipped
+      // record gets weight 0 (then T * (1 - 0) = T exactly), and a record that would take
+      // T below T_STOP sets live to 0 and is not blended; this is the same arithmetic, and
+      // gives the same bits, as blending with branches.  A group that reaches past the
+      // segment's end (chunk boundaries of the second list, which starts anywhere, and the
+      // list's end) gives the records past it weight 0; whole groups need no check.  The
+      // wave leaves the segment once all its lanes have stopped.
+      auto group = [&](int jj, int lim) {
+        float ae[FW_UNROLL], cq[FW_UNROLL];
         float4 bq[FW_UNROLL];
-        bool okq[FW_UNROLL];
 #pragma unroll
         for (int u = 0; u < FW_UNROLL; ++u) {
-          const int ju = min(jj + u, jhi - 1);  // past the segment end: a masked-out copy of its last record
+          const int ju = jj + (u < lim ? u : lim - 1);   // uniform; lim = FW_UNROLL: jj + u
           const float4 aq = s_a[ju];
           bq[u] = s_b[ju];
           cq[u] = s_c[ju];
-          float dx, dy, G;
+          float dx, dy, G, al;
           bool cl;
-          okq[u] = splat_alpha(aq, bq[u], fx, fy, dx, dy, G, al[u], cl) && jj + u < jhi;
+          ae[u] = (splat_alpha(aq, bq[u], fx, fy, dx, dy, G, al, cl) && u < lim) ? al : 0.0f;
         }
 #pragma unroll
-        for (int u = 0; u < FW_UNROLL; ++u) blend(okq[u] && !done, al[u], bq[u], cq[u], (uint32_t)(kb + jj + u + 1));
+        for (int u = 0; u < FW_UNROLL; ++u) {
+          const float a2 = ae[u] * live;
+          const float Tn = Tr * (1.0f - a2);
+          const bool stop = Tn < T_STOP;        // only when a2 > 0: T >= T_STOP otherwise
+          live = stop ? 0.0f : live;
+          const float a3 = stop ? 0.0f : a2;
+          const float w = a3 * Tr;               // colours are finite and >= 0: adding 0*c is exact
+          dr = fmaf(w, bq[u].z, dr);
+          dg = fmaf(w, bq[u].w, dg);
+          db = fmaf(w, cq[u], db);
+          Tr = stop ? Tr : Tn;
+          last = a3 > 0.0f ? (uint32_t)(kb + jj + u + 1) : last;
+        }
+      };
+      for (int jj = j; jj < jhi; jj += FW_UNROLL) {
+        if (__ballot(live != 0.0f) == 0ull) break;
+        if (jj + FW_UNROLL <= jhi)
+          group(jj, FW_UNROLL);
+        else
+          group(jj, jhi - jj);
       }
       // a chunk boundary of the tile's list: record this pixel's state
       if (kb + jhi == next_b) {
@@ -279,7 +289,7 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
   }
   bool more = false;  // the second phase continues this tile
   if (PHASE == 1 && sliced) {
-    more = __syncthreads_count(done) < NT;
+    more = __syncthreads_count(live == 0.0f) < NT;
     if (more) {
       // save the state; the second list continues this tile
       my_carry[0 * NT] = Tr;
@@ -290,7 +300,7 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
       my_carry[5 * NT] = dg;
       my_carry[6 * NT] = db;
       my_carry[7 * NT] = __uint_as_float(last);
-      my_carry[8 * NT] = done ? 1.0f : 0.0f;
+      my_carry[8 * NT] = live == 0.0f ? 1.0f : 0.0f;
     }
     if (threadIdx.x == 0) {
       alive[slot] = more ? 1u : 0u;
