@@ -275,6 +275,37 @@ clsp_status clsp_bin_and_sort(const clsp_projected *proj, const clsp_camera *cam
                               int32_t use_mask, const clsp_bins *bins, clsp_stream stream);
 
 /* ---------------------------------------------------------------------------------
+ * Lists of local optimisation from a stored depth order of the unchanged Gaussians
+ * (Supp. "Local Optimization Kernel", item 1: the projection, and with it the depth
+ * order, of the Gaussians outside the change set is reused).  During local
+ * optimisation of the change set [a0, n) (the suffix after the unchanged rows, Supp.
+ * "3DGS Optimization in Changed Regions"), rows [0, a0) do not change, so for fixed
+ * cameras their entries' depth order does not either.
+ *
+ * clsp_frozen_order stores that order once: the entries v*n + i, i < a0, that are visible
+ * with a nonempty tile rectangle, in ascending (depth key, entry) order, with their
+ * rectangles.  order: device buffer of clsp_frozen_order_bytes(n, n_views, a0) bytes
+ * (16 bytes per entry plus a header; the call writes it, the caller owns it); ws:
+ * device scratch of at least clsp_bin_and_sort_workspace_bytes(n, n_views, width,
+ * height, 0) bytes (any bins' workspace for this n, views and size qualifies).
+ *
+ * clsp_bin_and_sort_frozen then builds exactly the lists clsp_bin_and_sort builds with
+ * use_mask = 1 and active = [a0, n): the mask comes from the changed rows, the unchanged
+ * entries with pairs are taken in the stored order, and only the changed entries are
+ * sorted and merged in.  `order` must come from clsp_frozen_order with the same a0,
+ * n_views and image size, on a projection whose rows [0, a0) equal `proj`'s (the call
+ * cannot check this: other contents give wrong lists).
+ * Errors: as clsp_bin_and_sort, plus a0 not in [0, n], an order buffer or workspace
+ * smaller than stated. */
+size_t clsp_frozen_order_bytes(int64_t n, int32_t n_views, int64_t a0);
+clsp_status clsp_frozen_order(const clsp_projected *proj, const clsp_camera *cams, int32_t n_views, int64_t n,
+                              int64_t a0, void *order, size_t order_bytes, void *ws, size_t ws_bytes,
+                              clsp_stream stream);
+clsp_status clsp_bin_and_sort_frozen(const clsp_projected *proj, const clsp_camera *cams, int32_t n_views, int64_t a0,
+                                     const void *order, size_t order_bytes, const clsp_bins *bins,
+                                     clsp_stream stream);
+
+/* ---------------------------------------------------------------------------------
  * Forward rendering of the rendered tiles (Sec. 3.3 step 2; Supp. item 2: threads of
  * unmasked tiles do no work).  bg: host float[3] background colour.  Writes image,
  * T_final and n_contrib (1 + position, within the tile's list, of the last Gaussian

@@ -21,7 +21,8 @@ BINS_COMPLETE, BINS_DEPTH_SLICED = 0, 1
 EXPORTED = (
     "clsp_version", "clsp_last_error", "clsp_project_preprocess", "clsp_project_preprocess_rows",
     "clsp_bin_and_sort_workspace_bytes",
-    "clsp_bin_and_sort", "clsp_render_state_bytes", "clsp_render_forward", "clsp_render_forward_l1",
+    "clsp_bin_and_sort", "clsp_frozen_order_bytes", "clsp_frozen_order", "clsp_bin_and_sort_frozen",
+    "clsp_render_state_bytes", "clsp_render_forward", "clsp_render_forward_l1",
     "clsp_l1_loss_grad",
     "clsp_render_backward_workspace_bytes",
     "clsp_render_backward", "clsp_masked_adam_step", "clsp_zero_grads", "clsp_render_backward_adam",
@@ -102,6 +103,14 @@ def load(path: Path | None = None):
     L.clsp_bin_and_sort.restype = st
     L.clsp_bin_and_sort.argtypes = [POINTER(Projected), POINTER(Camera), c_int32, Range, c_int32, POINTER(Bins),
                                     c_void_p]
+    L.clsp_frozen_order_bytes.restype = c_size_t
+    L.clsp_frozen_order_bytes.argtypes = [c_int64, c_int32, c_int64]
+    L.clsp_frozen_order.restype = st
+    L.clsp_frozen_order.argtypes = [POINTER(Projected), POINTER(Camera), c_int32, c_int64, c_int64, c_void_p, c_size_t,
+                                    c_void_p, c_size_t, c_void_p]
+    L.clsp_bin_and_sort_frozen.restype = st
+    L.clsp_bin_and_sort_frozen.argtypes = [POINTER(Projected), POINTER(Camera), c_int32, c_int64, c_void_p, c_size_t,
+                                           POINTER(Bins), c_void_p]
     L.clsp_render_state_bytes.restype = c_size_t
     L.clsp_render_state_bytes.argtypes = [c_int32, c_int32, c_int32]
     L.clsp_render_forward.restype = st

@@ -245,6 +245,54 @@ def bin_and_sort(proj: ProjectedBuffers, cams, active=None, use_mask=False, bins
     return bins
 
 
+@dataclass
+class FrozenOrder:
+    """Stored depth order of the unchanged rows [0, a0) (clsp_frozen_order): valid for
+    the projection rows, cameras and image size it was built from."""
+    buf: torch.Tensor   # device bytes
+    n: int
+    views: int
+    a0: int
+    width: int
+    height: int
+
+
+def frozen_order(proj: ProjectedBuffers, cams, a0, ws: torch.Tensor | None = None, stream=None) -> FrozenOrder:
+    """Depth order of the entries of rows [0, a0) of ``proj`` (made once per camera set
+    during local optimisation of the change set [a0, n)).  ``ws``: scratch of at least
+    ``clsp_bin_and_sort_workspace_bytes(n, views, w, h, 0)`` bytes (allocated when None)."""
+    n, V, W, H = proj.n, len(cams), cams[0].width, cams[0].height
+    L = lib()
+    nb = L.clsp_frozen_order_bytes(n, V, int(a0))
+    if nb == 0:
+        raise ValueError(f"a0 = {a0} not in [0, {n}]")
+    dev = proj.splat.device
+    buf = torch.empty(nb, dtype=torch.uint8, device=dev)
+    need = L.clsp_bin_and_sort_workspace_bytes(n, V, W, H, 0)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(1, need), dtype=torch.uint8, device=dev)
+    check(L.clsp_frozen_order(ctypes.byref(proj.struct()), camera_array(cams), V, n, int(a0), _ptr(buf), nb, _ptr(ws),
+                              ws.numel(), _stream(stream)))
+    return FrozenOrder(buf, n, V, int(a0), W, H)
+
+
+def bin_and_sort_frozen(proj: ProjectedBuffers, cams, order: FrozenOrder, bins: BinBuffers | None = None,
+                        capacity=None, mode=_ffi.BINS_DEPTH_SLICED, stream=None):
+    """``bin_and_sort(proj, cams, (order.a0, n), use_mask=True, ...)`` with the unchanged
+    rows' depth order taken from ``order`` (the same lists)."""
+    n, V = proj.n, len(cams)
+    if (order.n, order.views, order.width, order.height) != (n, V, cams[0].width, cams[0].height):
+        raise ValueError("frozen order built for another projection or camera set")
+    if bins is None:
+        cap = capacity if capacity is not None else max(1024, 64 * n * V)
+        bins = BinBuffers.alloc(n, V, cams[0].width, cams[0].height, cap, proj.splat.device, mode)
+    if bins.n != n or bins.views != V:
+        raise ValueError("bins sized for another projection")
+    check(lib().clsp_bin_and_sort_frozen(ctypes.byref(proj.struct()), camera_array(cams), V, order.a0, _ptr(order.buf),
+                                         order.buf.numel(), ctypes.byref(bins.struct()), _stream(stream)))
+    return bins
+
+
 def render_state(cams, device):
     """Device buffer for the forward's compositing state (needed by the backward)."""
     b = lib().clsp_render_state_bytes(len(cams), cams[0].width, cams[0].height)

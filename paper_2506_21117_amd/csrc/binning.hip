@@ -43,6 +43,8 @@ constexpr int C_PAIRS = 0, C_OVERFLOW = 1, C_TILES = 2, C_WRITTEN = 3, C_ENTRIES
               C_PAIRS1 = 7, C_ALIVE = 8;
 // scratch counter slots used while a slab is listed
 constexpr int C_SLAB_LO = 9, C_SLAB_N = 10, C_SLAB_PAIRS = 11, C_SLAB_BASE = 12;
+// scratch counter slots of lists built from a stored depth order of the unchanged rows
+constexpr int C_FSPLIT = 13, C_NACT = 14;
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
@@ -192,11 +194,12 @@ __device__ __forceinline__ uint32_t tab_rank(const uint32_t* tab, uint32_t vrow,
 // Pairs of each entry: the rectangle's area, or its set tiles in the mask (corner table).
 // Block b takes the span block_span(E, G, b, NT) of entries e = v*n + i, and also
 // writes how many of them have pairs to blk[b]: the first step of the compaction's
-// exclusive scan (scan_compact_kernel uses the same spans).
+// exclusive scan (scan_compact_kernel uses the same spans).  Rows i >= row_lim count
+// no pairs (row_lim = n: every row).
 __global__ void __launch_bounds__(NT) count_kernel(const uint2* __restrict__ rect, const uint32_t* __restrict__ flags,
                                                    const uint32_t* __restrict__ tab, uint32_t n, uint32_t E, int G,
-                                                   int TX, int TY, int use_mask, uint32_t* __restrict__ cnt,
-                                                   uint32_t* __restrict__ blk) {
+                                                   int TX, int TY, int use_mask, uint32_t row_lim,
+                                                   uint32_t* __restrict__ cnt, uint32_t* __restrict__ blk) {
   __shared__ uint32_t s4[4];
   uint32_t beg, end;
   block_span(E, G, blockIdx.x, NT, beg, end);
@@ -218,7 +221,8 @@ __global__ void __launch_bounds__(NT) count_kernel(const uint2* __restrict__ rec
       // a rectangle within the tile grid (preprocess writes no other), or none
       const uint32_t x0 = min(r[k].x & 0xffffu, (uint32_t)TX), x1 = min(r[k].x >> 16, (uint32_t)TX);
       const uint32_t y0 = min(r[k].y & 0xffffu, (uint32_t)TY), y1 = min(r[k].y >> 16, (uint32_t)TY);
-      const bool ok = (fl[k] & CLSP_FLAG_VISIBLE) && x1 > x0 && y1 > y0;
+      bool ok = (fl[k] & CLSP_FLAG_VISIBLE) && x1 > x0 && y1 > y0;
+      if (row_lim < n) ok = ok && e % n < row_lim;
       uint32_t c = 0;
       if (!use_mask) {
         c = (x1 - x0) * (y1 - y0);
@@ -291,6 +295,197 @@ __global__ void __launch_bounds__(NT) scan_compact_kernel(const uint32_t* __rest
       off += v[k];
     }
     base += tot;
+  }
+}
+
+// ------------------------------------------------------------------ 2-3 from a stored order
+// The unchanged rows [0, a0) of local optimisation keep their projection, so their
+// entries' depth order can be built once and reused (Supp. "Local Optimization Kernel",
+// item 1 reuses the projection for the per-tile depth ordering).  The stored order is
+// one buffer of 32-bit words: a header of ORD_HDR words ([0]: the number of entries
+// nF), then for cap = views * a0 slots the entry indices (ascending (depth key, entry)
+// order), their depth keys and their rectangles (uint2, 8-byte aligned).  It holds the
+// entries of the unchanged rows that are visible with a nonempty rectangle, the ones
+// that can have pairs under any mask.
+constexpr uint32_t ORD_HDR = 64;
+__host__ __device__ inline uint64_t ord_rect_word(uint64_t cap) { return (ORD_HDR + 2 * cap + 1) & ~1ull; }
+
+// Stored order of the build: its nF sorted entries and their rectangles.
+__global__ void __launch_bounds__(NT) order_store_kernel(const uint32_t* __restrict__ keys,
+                                                         const uint32_t* __restrict__ vals,
+                                                         const uint2* __restrict__ rect, uint32_t cap,
+                                                         uint32_t* __restrict__ ord) {
+  const uint32_t nF = min(ord[0], cap);
+  uint2* rects = reinterpret_cast<uint2*>(ord + ord_rect_word(cap));
+  for (uint32_t p = blockIdx.x * NT + threadIdx.x; p < nF; p += gridDim.x * NT) {
+    const uint32_t e = vals[p];
+    ord[ORD_HDR + p] = e;
+    ord[ORD_HDR + cap + p] = keys[p];
+    rects[p] = rect[e];
+  }
+}
+
+// Count pass over positions p in [0, cap + views * (n - a0)): position p < cap is slot p
+// of the stored order (no pairs when p >= nF), the others are the changed entries
+// v*n + i, i in [a0, n), view-major.  cnt[p] = masked tiles of the rectangle; blk[b] /
+// blkF[b] = positions of block b with pairs, all / those of the stored order (the
+// compaction then knows where the stored entries end).
+__global__ void __launch_bounds__(NT) count_frozen_kernel(const uint32_t* __restrict__ ord, uint32_t cap,
+                                                          const uint2* __restrict__ rect,
+                                                          const uint32_t* __restrict__ flags,
+                                                          const uint32_t* __restrict__ tab, uint32_t n, uint32_t a0,
+                                                          uint32_t NP, int G, int TX, int TY,
+                                                          uint32_t* __restrict__ cnt, uint32_t* __restrict__ blk,
+                                                          uint32_t* __restrict__ blkF) {
+  __shared__ uint32_t s4[4];
+  const uint32_t nF = min(ord[0], cap);
+  const uint32_t* fvals = ord + ORD_HDR;
+  const uint2* frect = reinterpret_cast<const uint2*>(ord + ord_rect_word(cap));
+  const uint32_t na = n - a0;
+  uint32_t beg, end;
+  block_span(NP, G, blockIdx.x, NT, beg, end);
+  uint32_t hasF = 0, hasA = 0;
+  constexpr int U = 4;
+  const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
+  for (uint32_t p0 = beg + threadIdx.x; p0 < end; p0 += U * NT) {
+    uint32_t fl[U], e[U];
+    uint2 r[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const uint32_t p = p0 + k * NT;
+      fl[k] = 0u;
+      e[k] = 0u;
+      r[k] = make_uint2(0u, 0u);
+      if (p < end) {
+        if (p < cap) {
+          if (p < nF) {
+            e[k] = fvals[p];
+            r[k] = frect[p];
+            fl[k] = e[k] < NP ? CLSP_FLAG_VISIBLE : 0u;  // (an order built for these sizes holds no other)
+            e[k] = e[k] < NP ? e[k] : 0u;
+          }
+        } else {
+          const uint32_t q = p - cap;
+          e[k] = (q / na) * n + a0 + q % na;
+          r[k] = rect[e[k]];
+          fl[k] = flags[e[k]];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const uint32_t p = p0 + k * NT;
+      const uint32_t x0 = min(r[k].x & 0xffffu, (uint32_t)TX), x1 = min(r[k].x >> 16, (uint32_t)TX);
+      const uint32_t y0 = min(r[k].y & 0xffffu, (uint32_t)TY), y1 = min(r[k].y >> 16, (uint32_t)TY);
+      const bool ok = (fl[k] & CLSP_FLAG_VISIBLE) && x1 > x0 && y1 > y0;
+      const uint32_t v = e[k] / n;
+      uint32_t c = tab_rect(tab, v * TYp, TXp, ok ? x0 : 0u, ok ? x1 : 0u, ok ? y0 : 0u, ok ? y1 : 0u);
+      c = ok ? c : 0u;
+      if (p < end) cnt[p] = c;
+      if (p < cap) hasF += c != 0u ? 1u : 0u;
+      else hasA += c != 0u ? 1u : 0u;
+    }
+  }
+  uint32_t totF, totA;
+  block_excl_scan(hasF, s4, totF);
+  block_excl_scan(hasA, s4, totA);
+  if (threadIdx.x == 0) {
+    blk[blockIdx.x] = totF + totA;
+    blkF[blockIdx.x] = totF;
+  }
+}
+
+// Compaction of the positions with pairs, in position order, as (depth key, entry): the
+// stored order's entries first (already in depth order), then the changed ones (entry
+// order).  Block 0 writes the total (counters[C_ENTRIES]), the stored entries among
+// them (counters[C_FSPLIT]) and the changed ones (counters[C_NACT]).
+__global__ void __launch_bounds__(NT) scan_compact_frozen_kernel(const uint32_t* __restrict__ cnt, uint32_t NP,
+                                                                 const uint32_t* __restrict__ blk,
+                                                                 const uint32_t* __restrict__ blkF, int G,
+                                                                 const uint32_t* __restrict__ ord, uint32_t cap,
+                                                                 const float* __restrict__ depth, uint32_t n,
+                                                                 uint32_t a0, uint32_t* __restrict__ keys,
+                                                                 uint32_t* __restrict__ vals,
+                                                                 uint32_t* __restrict__ counters) {
+  __shared__ uint32_t s4[4];
+  if (blockIdx.x == 0) {
+    const uint32_t all = block_sum_range(blk, 0, (uint32_t)G, s4);
+    const uint32_t fr = block_sum_range(blkF, 0, (uint32_t)G, s4);
+    if (threadIdx.x == 0) {
+      counters[C_ENTRIES] = all;
+      counters[C_FSPLIT] = fr;
+      counters[C_NACT] = all - fr;
+    }
+  }
+  const uint32_t na = n - a0;
+  uint32_t beg, end;
+  block_span(NP, G, blockIdx.x, NT, beg, end);
+  uint32_t base = block_sum_range(blk, 0, blockIdx.x, s4);
+  for (uint32_t c = beg; c < end; c += SCAN_CHUNK) {
+    uint32_t v[SCAN_ITEMS];
+    uint32_t sum = 0;
+    const uint32_t t0 = c + threadIdx.x * SCAN_ITEMS;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      v[k] = (t0 + k < end && cnt[t0 + k] != 0u) ? 1u : 0u;
+      sum += v[k];
+    }
+    uint32_t tot;
+    uint32_t off = base + block_excl_scan(sum, s4, tot);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      if (v[k]) {
+        const uint32_t p = t0 + k;
+        uint32_t e, key;
+        if (p < cap) {
+          e = ord[ORD_HDR + p];
+          key = ord[ORD_HDR + cap + p];
+        } else {
+          const uint32_t q = p - cap;
+          e = (q / na) * n + a0 + q % na;
+          key = __float_as_uint(depth[e]);
+        }
+        keys[off] = key;
+        vals[off] = e;
+      }
+      off += v[k];
+    }
+    base += tot;
+  }
+}
+
+// (key, entry) order; entries are distinct, so it is a strict total order.
+__device__ __forceinline__ bool key_entry_less(uint32_t ka, uint32_t ea, uint32_t kb, uint32_t eb) {
+  return ka < kb || (ka == kb && ea < eb);
+}
+
+// Merge of the two sorted runs A = [0, s) (stored entries) and B = [s, M) (changed
+// entries, sorted) of (keys, vals), s = counters[C_FSPLIT], M = counters[C_ENTRIES], into
+// out[0, M) (entries only).  Each thread writes MG_ITEMS consecutive outputs from output
+// position d: the number i of A entries among the first d outputs is the first mid
+// with A[mid] not before B[d - 1 - mid] (a binary search on the merge path), then it
+// merges sequentially.
+constexpr int MG_ITEMS = 8;
+__global__ void __launch_bounds__(NT) merge_runs_kernel(const uint32_t* __restrict__ keys,
+                                                        const uint32_t* __restrict__ vals,
+                                                        const uint32_t* __restrict__ counters,
+                                                        uint32_t* __restrict__ out) {
+  const uint32_t M = counters[C_ENTRIES], na = min(counters[C_FSPLIT], M), nb = M - na;
+  const uint32_t *ka = keys, *va = vals, *kb = keys + na, *vb = vals + na;
+  for (uint64_t d0 = ((uint64_t)blockIdx.x * NT + threadIdx.x) * MG_ITEMS; d0 < M;
+       d0 += (uint64_t)gridDim.x * NT * MG_ITEMS) {
+    const uint32_t d = (uint32_t)d0;
+    uint32_t lo = d > nb ? d - nb : 0u, hi = min(d, na);
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1, j = d - 1u - mid;
+      if (key_entry_less(ka[mid], va[mid], kb[j], vb[j])) lo = mid + 1u; else hi = mid;
+    }
+    uint32_t i = lo, j = d - lo;
+    const uint32_t end = min(d + (uint32_t)MG_ITEMS, M);
+    for (uint32_t o = d; o < end; ++o) {
+      const bool take_a = i < na && (j >= nb || key_entry_less(ka[i], va[i], kb[j], vb[j]));
+      out[o] = take_a ? va[i++] : vb[j++];
+    }
   }
 }
 
@@ -537,14 +732,17 @@ __global__ void __launch_bounds__(NT) gather_counts_kernel(const uint32_t* __res
   }
 }
 
-// ... or recounted against the tiles still alive (second slab).
+// ... or recounted from the rectangle against the corner table `tab` (second slab: the
+// tiles still alive; first slab of lists built from a stored depth order of the
+// unchanged entries, whose count pass ran in another order).
 __global__ void __launch_bounds__(NT) recount_kernel(const uint32_t* __restrict__ order, const uint2* __restrict__ rect,
                                                      const uint32_t* __restrict__ tab, uint32_t* counters, uint32_t n,
-                                                     int TX, int TY, int epb, uint32_t* __restrict__ out,
-                                                     uint2* __restrict__ rsort, uint32_t* __restrict__ blk) {
+                                                     int TX, int TY, int which, int sliced, int epb,
+                                                     uint32_t* __restrict__ out, uint2* __restrict__ rsort,
+                                                     uint32_t* __restrict__ blk) {
   __shared__ uint32_t s4[4];
   uint32_t lo, m;
-  slab_params(counters, 2, 1, lo, m);
+  slab_params(counters, which, sliced, lo, m);
   const uint32_t nq = (m + epb - 1) / epb, per_iter = NT / epb;
   const uint32_t g = threadIdx.x / epb, t = threadIdx.x % epb;
   for (uint32_t q0 = blockIdx.x * per_iter; q0 < nq; q0 += gridDim.x * per_iter) {
@@ -961,7 +1159,8 @@ void index_mask(const BinPlan& p, const uint32_t* mask, const WsPtrs& w, uint32_
 // counts, offsets, capacity check, emission (into `mask`'s tiles, whose index
 // w.wpre / `mlist` is built), tile sort, ranges.
 hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bins& bins, const WsPtrs& w, int which,
-                     int use_mask, const uint32_t* mask, const uint32_t* mlist, uint32_t* ranges, hipStream_t s) {
+                     int use_mask, const uint32_t* mask, const uint32_t* mlist, uint32_t* ranges, hipStream_t s,
+                     bool recount_first = false) {
   const int V = p.views;
   const int64_t n = p.n, E = p.entries;
   const int wpv = (p.T + 31) / 32;
@@ -977,12 +1176,13 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
                                : E;
   // counts and per-chunk pair counts, then the chunks' offsets (relative to the slab's
   // first pair) and the capacity check
-  if (which == 1)
+  const int sliced = bins.mode == CLSP_BINS_DEPTH_SLICED ? 1 : 0;
+  if (which == 1 && !recount_first)
     hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(slab_max)), dim3(NT), 0, s, order, w.cnt, rect, counters,
-                       bins.mode == CLSP_BINS_DEPTH_SLICED ? 1 : 0, epb, w.tmp, w.rsort, w.blk);
+                       sliced, epb, w.tmp, w.rsort, w.blk);
   else
     hipLaunchKernelGGL(recount_kernel, dim3(grid_for(slab_max)), dim3(NT), 0, s, order, rect, w.tab, counters,
-                       (uint32_t)n, p.TX, p.TY, epb, w.tmp, w.rsort, w.blk);
+                       (uint32_t)n, p.TX, p.TY, which, which == 1 ? sliced : 1, epb, w.tmp, w.rsort, w.blk);
   const int tpasses = passes_for(p.tile_bits);
   uint32_t* ek = (tpasses % 2 == 0) ? bins.keys : w.pairK;
   uint32_t* ev = (tpasses % 2 == 0) ? bins.values : w.pairV;
@@ -1068,16 +1268,17 @@ BinPlan make_bin_plan(int64_t n, int views, int W, int H, int64_t capacity) {
   return p;
 }
 
-hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int64_t a0, int64_t a1, int use_mask,
-                               const clsp_bins& bins, char* ws, hipStream_t s) {
+namespace {
+
+// Clears the outputs, builds the render mask (the rectangles of the visible entries of
+// rows [a0, a1), or every tile) and its index.
+hipError_t mask_and_index(const BinPlan& p, const clsp_projected& proj, int64_t a0, int64_t a1, int use_mask,
+                          const clsp_bins& bins, const WsPtrs& w, hipStream_t s) {
   const int V = p.views;
-  const int64_t n = p.n, E = p.entries, gt = (int64_t)V * p.T;
+  const int64_t n = p.n, gt = (int64_t)V * p.T;
   const int wpv = (p.T + 31) / 32;
-  const WsPtrs w = carve(p, ws);
   const uint2* rect = reinterpret_cast<const uint2*>(proj.rect);
   uint32_t* counters = bins.counters;
-  hipError_t err;
-
   // clear outputs (counters[C_STICKY] is left alone: it remembers any overflow)
   {
     ClearList c{};
@@ -1101,7 +1302,7 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
     for (int i = 0; i < c.k; ++i) total += c.n[i];
     hipLaunchKernelGGL(clear_kernel, dim3(grid_for(total, 2048)), dim3(NT), 0, s, c);
   }
-  // 1. mask, and its index: the sorted list of tiles to render (all tiles in full mode)
+  // the mask, and its index: the sorted list of tiles to render (all tiles in full mode)
   if (use_mask) {
     if (a1 > a0) {
       hipLaunchKernelGGL(mask_kernel, dim3(ceil_div(a1 - a0, NT), V), dim3(NT), wpv * 4, s, rect, proj.flags, n, a0,
@@ -1112,13 +1313,27 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
                        p.T, wpv);
   }
   index_mask(p, bins.tile_mask, w, bins.tile_list, counters + C_TILES, s);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int64_t a0, int64_t a1, int use_mask,
+                               const clsp_bins& bins, char* ws, hipStream_t s) {
+  const int64_t n = p.n, E = p.entries;
+  const WsPtrs w = carve(p, ws);
+  const uint2* rect = reinterpret_cast<const uint2*>(proj.rect);
+  uint32_t* counters = bins.counters;
+  hipError_t err;
+  // 1. mask and index
+  if ((err = mask_and_index(p, proj, a0, a1, use_mask, bins, w, s)) != hipSuccess) return err;
   if (E > 0) {
     // 2-3. counts (with the block sums of the has-pairs flags), then the compaction of
     // entries with pairs, keyed by depth
     {
       const int G = count_blocks(E);
       hipLaunchKernelGGL(count_kernel, dim3(G), dim3(NT), 0, s, rect, proj.flags, w.tab, (uint32_t)n, (uint32_t)E, G,
-                         p.TX, p.TY, use_mask, w.cnt, w.blk);
+                         p.TX, p.TY, use_mask, (uint32_t)n, w.cnt, w.blk);
       hipLaunchKernelGGL(scan_compact_kernel, dim3(G), dim3(NT), 0, s, w.cnt, (uint32_t)E, w.blk, G, proj.depth,
                          w.keyA, w.valA, counters + C_ENTRIES);
     }
@@ -1126,6 +1341,61 @@ hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int
     radix_sort(w.keyA, w.valA, w.keyB, w.valB, counters + C_ENTRIES, nullptr, E, 32, w.hist, w.dtot, s);
     // 5-7 for the first slab (the whole order for complete lists)
     if ((err = list_slab(p, proj, bins, w, 1, use_mask, bins.tile_mask, bins.tile_list, bins.ranges, s)) != hipSuccess)
+      return err;
+  }
+  return hipGetLastError();
+}
+
+size_t frozen_order_bytes(int64_t views, int64_t a0) {
+  const uint64_t cap = (uint64_t)views * (uint64_t)a0;
+  return (size_t)(ord_rect_word(cap) * 4 + cap * 8);
+}
+
+hipError_t launch_frozen_order(const BinPlan& p, const clsp_projected& proj, int64_t a0, uint32_t* ord, char* ws,
+                               hipStream_t s) {
+  const int64_t n = p.n, E = p.entries, cap = (int64_t)p.views * a0;
+  if (cap == 0) return launch_fill_u32(ord, 0u, 1, s);
+  const WsPtrs w = carve(p, ws);
+  const uint2* rect = reinterpret_cast<const uint2*>(proj.rect);
+  // the entries of rows [0, a0) with a visible nonempty rectangle, in entry order, then
+  // sorted by depth (stable: (depth key, entry) order), stored with their rectangles
+  const int G = count_blocks(E);
+  hipLaunchKernelGGL(count_kernel, dim3(G), dim3(NT), 0, s, rect, proj.flags, nullptr, (uint32_t)n, (uint32_t)E, G,
+                     p.TX, p.TY, 0, (uint32_t)a0, w.cnt, w.blk);
+  hipLaunchKernelGGL(scan_compact_kernel, dim3(G), dim3(NT), 0, s, w.cnt, (uint32_t)E, w.blk, G, proj.depth, w.keyA,
+                     w.valA, ord);
+  radix_sort(w.keyA, w.valA, w.keyB, w.valB, ord, nullptr, cap, 32, w.hist, w.dtot, s);
+  hipLaunchKernelGGL(order_store_kernel, dim3(grid_for(cap)), dim3(NT), 0, s, w.keyA, w.valA, rect, (uint32_t)cap,
+                     ord);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_and_sort_frozen(const BinPlan& p, const clsp_projected& proj, int64_t a0, const uint32_t* ord,
+                                      const clsp_bins& bins, char* ws, hipStream_t s) {
+  const int64_t n = p.n, E = p.entries, cap = (int64_t)p.views * a0, nact = (int64_t)p.views * (n - a0);
+  const WsPtrs w = carve(p, ws);
+  const uint2* rect = reinterpret_cast<const uint2*>(proj.rect);
+  uint32_t* counters = bins.counters;
+  hipError_t err;
+  // 1. the mask of the changed rows [a0, n), and its index
+  if ((err = mask_and_index(p, proj, a0, n, 1, bins, w, s)) != hipSuccess) return err;
+  if (E > 0) {
+    // 2-3. counts and compaction over the stored order, then the changed entries:
+    // (keyB, valB) = [stored entries with pairs, in depth order | changed ones]
+    const int G = count_blocks(E);
+    hipLaunchKernelGGL(count_frozen_kernel, dim3(G), dim3(NT), 0, s, ord, (uint32_t)cap, rect, proj.flags, w.tab,
+                       (uint32_t)n, (uint32_t)a0, (uint32_t)E, G, p.TX, p.TY, w.cnt, w.blk, w.tmp);
+    hipLaunchKernelGGL(scan_compact_frozen_kernel, dim3(G), dim3(NT), 0, s, w.cnt, (uint32_t)E, w.blk, w.tmp, G, ord,
+                       (uint32_t)cap, proj.depth, (uint32_t)n, (uint32_t)a0, w.keyB, w.valB, counters);
+    // 4. depth order: the changed entries sorted in place (4 passes return to (keyB,
+    // valB)), then both runs merged into valA
+    if (nact > 0 && radix_sort(w.keyB, w.valB, w.keyA, w.valA, counters + C_NACT, counters + C_FSPLIT, nact, 32,
+                               w.hist, w.dtot, s) != 0)
+      return hipErrorInvalidValue;
+    hipLaunchKernelGGL(merge_runs_kernel, dim3(grid_for((E + MG_ITEMS - 1) / MG_ITEMS, 4096)), dim3(NT), 0, s, w.keyB,
+                       w.valB, counters, w.valA);
+    // 5-7 for the first slab; its counts come from the rectangles again
+    if ((err = list_slab(p, proj, bins, w, 1, 1, bins.tile_mask, bins.tile_list, bins.ranges, s, true)) != hipSuccess)
       return err;
   }
   return hipGetLastError();

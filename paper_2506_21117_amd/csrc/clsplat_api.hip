@@ -288,6 +288,49 @@ clsp_status clsp_bin_and_sort(const clsp_projected* proj, const clsp_camera* cam
                     "bin_and_sort");
 }
 
+size_t clsp_frozen_order_bytes(int64_t n, int32_t n_views, int64_t a0) {
+  if (n < 0 || n_views < 1 || a0 < 0 || a0 > n || (int64_t)n_views * n > MAX_ENTRIES) return 0;
+  return clsp::frozen_order_bytes(n_views, a0);
+}
+
+clsp_status clsp_frozen_order(const clsp_projected* proj, const clsp_camera* cams, int32_t n_views, int64_t n,
+                              int64_t a0, void* order, size_t order_bytes, void* ws, size_t ws_bytes,
+                              clsp_stream stream) {
+  CHECK(check_projected(proj));
+  CHECK(check_cams(cams, n_views));
+  if (n < 0 || (int64_t)n_views * n > MAX_ENTRIES) return fail(CLSP_ERR_INVALID_ARG, "n < 0 or n_views * n >= 2^32");
+  if (a0 < 0 || a0 > n) return fail(CLSP_ERR_INVALID_ARG, "a0 = %lld not in [0, %lld]", (long long)a0, (long long)n);
+  if (!order || order_bytes < clsp::frozen_order_bytes(n_views, a0))
+    return fail(CLSP_ERR_INVALID_ARG, "order buffer of %zu bytes is smaller than the %zu needed", order_bytes,
+                clsp::frozen_order_bytes(n_views, a0));
+  const clsp::BinPlan plan = clsp::make_bin_plan(n, n_views, cams[0].width, cams[0].height, 0);
+  if (!ws || ws_bytes < plan.total)
+    return fail(CLSP_ERR_INVALID_ARG, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, plan.total);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return hip_status(clsp::launch_frozen_order(plan, *proj, a0, static_cast<uint32_t*>(order), static_cast<char*>(ws), s),
+                    "frozen_order");
+}
+
+clsp_status clsp_bin_and_sort_frozen(const clsp_projected* proj, const clsp_camera* cams, int32_t n_views, int64_t a0,
+                                     const void* order, size_t order_bytes, const clsp_bins* bins,
+                                     clsp_stream stream) {
+  CHECK(check_projected(proj));
+  CHECK(check_cams(cams, n_views));
+  CHECK(check_bins(bins));
+  const int64_t n = bins->n;
+  if ((int64_t)n_views * n > MAX_ENTRIES) return fail(CLSP_ERR_INVALID_ARG, "n_views * n >= 2^32");
+  if (a0 < 0 || a0 > n) return fail(CLSP_ERR_INVALID_ARG, "a0 = %lld not in [0, %lld]", (long long)a0, (long long)n);
+  if (!order || order_bytes < clsp::frozen_order_bytes(n_views, a0))
+    return fail(CLSP_ERR_INVALID_ARG, "order buffer of %zu bytes is smaller than the %zu needed", order_bytes,
+                clsp::frozen_order_bytes(n_views, a0));
+  const clsp::BinPlan plan = clsp::make_bin_plan(n, n_views, cams[0].width, cams[0].height, bins->capacity);
+  CHECK(check_bins_ws(bins, plan));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return hip_status(clsp::launch_bin_and_sort_frozen(plan, *proj, a0, static_cast<const uint32_t*>(order), *bins,
+                                                     static_cast<char*>(bins->ws), s),
+                    "bin_and_sort_frozen");
+}
+
 size_t clsp_render_state_bytes(int32_t n_views, int32_t width, int32_t height) {
   if (n_views < 1 || width < 1 || height < 1) return 0;
   return clsp::render_state_bytes(n_views, (width + CLSP_TILE - 1) / CLSP_TILE, (height + CLSP_TILE - 1) / CLSP_TILE);

@@ -107,6 +107,13 @@ struct BinPlan {
 BinPlan make_bin_plan(int64_t n, int views, int W, int H, int64_t capacity);
 hipError_t launch_bin_and_sort(const BinPlan& p, const clsp_projected& proj, int64_t a0, int64_t a1, int use_mask,
                                const clsp_bins& bins, char* ws, hipStream_t s);
+// Stored depth order of the unchanged rows [0, a0) (see binning.hip), and lists of the
+// changed rows [a0, n) built from it.
+size_t frozen_order_bytes(int64_t views, int64_t a0);
+hipError_t launch_frozen_order(const BinPlan& p, const clsp_projected& proj, int64_t a0, uint32_t* ord, char* ws,
+                               hipStream_t s);
+hipError_t launch_bin_and_sort_frozen(const BinPlan& p, const clsp_projected& proj, int64_t a0, const uint32_t* ord,
+                                      const clsp_bins& bins, char* ws, hipStream_t s);
 // Depth-sliced lists: list the second slab into the alive tiles (bins.alive_mask).
 hipError_t launch_list_second_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bins& bins, char* ws,
                                    hipStream_t s);

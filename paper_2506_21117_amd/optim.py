@@ -21,7 +21,7 @@ from ._ffi import C_STICKY, check
 
 class SplatOptimizer:
     def __init__(self, params: api.GaussianTensors, cams, targets, active=None, local=True, bg=(0.0, 0.0, 0.0),
-                 capacity=None, lr=api.DEFAULT_LR, projection_cache_bytes=32 << 30, loss="l1"):
+                 capacity=None, lr=api.DEFAULT_LR, projection_cache_bytes=32 << 30, loss="l1", frozen_order=True):
         """params: device parameters (updated in place); cams: list of cameras of one
         size; targets: [V, 3, H, W] float32 device tensor; active: (a0, a1) change set
         (default: all rows); local: restrict rendering to the change set's tile mask.
@@ -35,17 +35,24 @@ class SplatOptimizer:
         loss: "l1" (the benchmark's loss), or "l1_dssim", the default 3D Gaussian Splatting
         loss the paper trains with, 0.8 L1 + 0.2 (1 - SSIM); its gradient on a masked tile
         reads pixels around the tile, which local steps take from a render of the unchanged
-        Gaussians alone, made once per view (they never change)."""
+        Gaussians alone, made once per view (they never change).
+
+        frozen_order: local steps whose change set is the suffix [a0, n) keep each view's
+        depth order of the unchanged rows (16 B per entry, made on the view's first step)
+        and sort only the change set's entries into it (clsp_bin_and_sort_frozen; the
+        same lists as a full sort)."""
         if loss not in ("l1", "l1_dssim"):
             raise ValueError("loss must be 'l1' or 'l1_dssim'")
         self.loss = loss
         self._frozen_images = {}
+        self._frozen_orders = {}
         self.params = params
         self.cams = list(cams)
         self.targets = targets
         self.n = params.n
         self.local = bool(local)
         self.active = (0, self.n) if (active is None or not local) else (int(active[0]), int(active[1]))
+        self.frozen_order = bool(frozen_order) and self.local
         self.bg = tuple(float(x) for x in bg)
         self.lr = lr
         dev = params.means.device
@@ -159,6 +166,7 @@ class SplatOptimizer:
         if self.proj_views is not None:
             self.proj_views = [cut(pv) for pv in self.proj_views]
         self.bins.n = n_new
+        self._frozen_orders = {}
         self.bwd_ws = api.render_backward_workspace(k, 1, dev)
         self._prepare_calls()
         return (a1 - a0) - k
@@ -184,12 +192,27 @@ class SplatOptimizer:
             self._frozen_images[view] = img
         return ctypes.c_void_p(self._frozen_images[view].data_ptr())
 
+    def _frozen_order(self, view, proj, st):
+        """(pointer, bytes) of view ``view``'s stored depth order of the unchanged rows,
+        made from ``proj`` (the view's projection) on the step's stream on first use."""
+        if view not in self._frozen_orders:
+            L = api.lib()
+            a0 = self.active[0]
+            nb = L.clsp_frozen_order_bytes(self.n, 1, a0)
+            buf = torch.empty(max(1, nb), dtype=torch.uint8, device=self.params.means.device)
+            check(L.clsp_frozen_order(ctypes.byref(proj), self._cams[view], 1, self.n, a0, ctypes.c_void_p(buf.data_ptr()),
+                                      nb, self._ptrs["ws"], self._sizes[0], st))
+            self._frozen_orders[view] = (buf, ctypes.c_void_p(buf.data_ptr()), nb)
+        _, ptr, nb = self._frozen_orders[view]
+        return ptr, nb
+
     def invalidate_projections(self):
         """The next step on each view projects every row again, and renders the unchanged
-        rows again for the D-SSIM term (needed after rows outside the change set were
-        modified)."""
+        rows again for the D-SSIM term and sorts them again (needed after rows outside the
+        change set were modified)."""
         self._projected = [False] * len(self.cams)
         self._frozen_images = {}
+        self._frozen_orders = {}
 
     def overflowed(self) -> bool:
         """True if any step since the last check ran out of pair capacity (sticky
@@ -263,9 +286,15 @@ class SplatOptimizer:
                 self._projected[view] = True
         ev = events or {}
         mark = lambda name, i: ev[name][i].record(stream) if name in ev else None
-        mark("bin_and_sort", 0)
-        check(L.clsp_bin_and_sort(by(proj), cam, 1, self._range, use_mask, by(self._bins), st))
-        mark("bin_and_sort", 1)
+        if self.frozen_order and self.active[1] == self.n:
+            optr, onb = self._frozen_order(view, proj, st)
+            mark("bin_and_sort", 0)
+            check(L.clsp_bin_and_sort_frozen(by(proj), cam, 1, self.active[0], optr, onb, by(self._bins), st))
+            mark("bin_and_sort", 1)
+        else:
+            mark("bin_and_sort", 0)
+            check(L.clsp_bin_and_sort(by(proj), cam, 1, self._range, use_mask, by(self._bins), st))
+            mark("bin_and_sort", 1)
         mark("render_forward", 0)
         if self.loss == "l1":
             # the forward also writes the L1 loss gradient of the pixels it renders

@@ -269,3 +269,32 @@ def test_l1_dssim_rejects_invalid_arguments_on_the_host(L):
     assert f(fake, 1.5) == _ffi.CLSP_ERR_INVALID_ARG
     assert f(fake, float("nan")) == _ffi.CLSP_ERR_INVALID_ARG
     assert b"lambda" in L.clsp_last_error()
+
+
+@pytest.mark.skipif(_gpu_visible(), reason="passes the stand-in device address 0x1000 to entry points; run only "
+                                           "where no GPU could ever receive a launch on it")
+def test_frozen_order_calls_reject_invalid_arguments_on_the_host(L):
+    from paper_2506_21117_amd import _ffi
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    proj = _ffi.Projected(fake, fake, fake, fake)
+    cam = _cam()
+    nb = L.clsp_frozen_order_bytes(10, 1, 8)
+    assert nb >= 8 * 16 and L.clsp_frozen_order_bytes(10, 1, 11) == 0 and L.clsp_frozen_order_bytes(-1, 1, 0) == 0
+    ws = L.clsp_bin_and_sort_workspace_bytes(10, 1, 64, 48, 0)
+    by = ctypes.byref
+    f = lambda a0, obytes, wsb: L.clsp_frozen_order(by(proj), cam, 1, 10, a0, fake, obytes, fake, wsb, None)
+    assert f(11, 1 << 20, ws) == _ffi.CLSP_ERR_INVALID_ARG
+    assert b"a0" in L.clsp_last_error()
+    assert f(8, nb - 1, ws) == _ffi.CLSP_ERR_INVALID_ARG
+    assert b"order" in L.clsp_last_error()
+    assert f(8, nb, ws - 1) == _ffi.CLSP_ERR_INVALID_ARG
+    assert b"workspace" in L.clsp_last_error()
+    ws_need = L.clsp_bin_and_sort_workspace_bytes(10, 1, 64, 48, 100)
+    bins = _ffi.Bins(fake, fake, fake, fake, fake, fake, fake, fake, fake, ws_need, 100, 10, 1, 0)
+    g = lambda a0, obytes: L.clsp_bin_and_sort_frozen(by(proj), cam, 1, a0, fake, obytes, by(bins), None)
+    assert g(-1, 1 << 20) == _ffi.CLSP_ERR_INVALID_ARG
+    assert g(8, nb - 1) == _ffi.CLSP_ERR_INVALID_ARG
+    assert b"order" in L.clsp_last_error()
+    bins.ws_bytes = ws_need - 1
+    assert g(8, nb) == _ffi.CLSP_ERR_INVALID_ARG
+    assert b"workspace" in L.clsp_last_error()
