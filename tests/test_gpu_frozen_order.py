@@ -150,3 +150,20 @@ def test_optimizer_local_steps_with_and_without_frozen_order(dev):
         atol = 2 * 7 * lr_quats if k == "quats" else 1e-6
         np.testing.assert_allclose(a, b, rtol=1e-4, atol=atol, err_msg=k)
     assert not np.array_equal(to_np(opts[0].params.means)[:, a0:], sc.means[:, a0:])
+
+
+@pytest.mark.parametrize("a0", [0, 5000, 39_000])
+def test_frozen_order_change_set_sizes(dev, a0):
+    """Change sets of 80 000, 70 000 and 2 000 entries (several sort blocks, each with
+    several chunks, and one): the same lists as the full sort, both slabs."""
+    sc, cams, _ = _sliced_case("cloud")
+    g = api.GaussianTensors.from_scene(sc, dev)
+    proj = gpu_preprocess(g, cams)
+    fb, _ = _frozen_bins(proj, cams, a0, capacity=40_000_000)
+    pb = api.bin_and_sort(proj, cams, (a0, sc.n), True, capacity=40_000_000)
+    img_f, _, _ = api.render_forward(proj, fb, cams)
+    img_p, _, _ = api.render_forward(proj, pb, cams)
+    torch.cuda.synchronize()
+    c = _same_lists(fb, pb)
+    assert not c["overflow"] and c["entries"] > 0
+    np.testing.assert_array_equal(to_np(img_f), to_np(img_p))
