@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--summarize-trace", metavar="DB",
                     help="print per-step kernel averages and per-call sums from the results database of a "
                          "rocprofv3 --kernel-trace run of this script, and exit")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="print per-kernel averages of the counters in the output folders of rocprofv3 --pmc "
+                         "--output-format csv runs of the step")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="print per-call HBM bytes from the output folders of four rocprofv3 --pmc runs "
                          "(FETCH_SIZE and WRITE_SIZE of this script, then of --copy-calibration), and exit")
@@ -68,6 +71,9 @@ def main():
     args = parse()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.summary_steps, args.summary_note))
+        return 0
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters, k=args.summary_steps, notes=args.summary_note))
         return 0
     if args.summarize_traffic:
         print(summarize_traffic(*args.summarize_traffic, k=args.summary_steps, notes=args.summary_note))
@@ -615,6 +621,64 @@ def read_counter_csv(folder, counter):
             if r["Counter_Name"] == counter:
                 rows[int(r["Dispatch_Id"])] = (short_kernel_name(r["Kernel_Name"]), float(r["Counter_Value"]))
     return [rows[i] for i in sorted(rows)]
+
+
+def summarize_counters(folders, k=10, notes=()):
+    """Per-kernel averages (per dispatch, over the last ``k`` steps) of every counter in the
+    counter_collection.csv files under ``folders`` (one rocprofv3 --pmc run each), and the
+    ratios that read them: VALU instructions per wave, the share of wave-cycles a wave
+    waited for any instruction, and LDS bank-conflict cycles per LDS instruction."""
+    import collections
+    import csv
+
+    per_kernel = collections.defaultdict(lambda: collections.defaultdict(list))
+    order = []
+    for folder in folders:
+        files = sorted(Path(folder).rglob("*counter_collection.csv"))
+        if not files:
+            raise SystemExit(f"{folder}: no counter_collection.csv")
+        disp = collections.OrderedDict()
+        with open(files[0]) as fh:
+            for r in csv.DictReader(fh):
+                d = disp.setdefault(int(r["Dispatch_Id"]), (short_kernel_name(r["Kernel_Name"]), {}))
+                d[1][r["Counter_Name"]] = d[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        seq = [(name, vals) for _, (name, vals) in sorted(disp.items())]
+        steps = split_steps(seq, k)
+        if not steps:
+            raise SystemExit(f"{folder}: no complete step found")
+        for st, _ in steps:
+            for name, vals in st:
+                if name not in order:
+                    order.append(name)
+                for c, v in vals.items():
+                    per_kernel[name][c].append(v)
+    counters = sorted({c for kv in per_kernel.values() for c in kv})
+    mean = lambda x: sum(x) / len(x) if x else float("nan")
+    lines = [f"# {n}" for n in notes]
+    lines.append(f"# averages per dispatch over the last {k} steps; kernels in step order")
+    lines.append("kernel".ljust(34) + "".join(f"{c[:18]:>19s}" for c in counters))
+    for name in order:
+        kv = per_kernel[name]
+        lines.append(name[:34].ljust(34) + "".join(f"{mean(kv[c]):19.6g}" if c in kv else f"{'-':>19s}"
+                                                 for c in counters))
+    ratios = []
+    for name in order:
+        kv = {c: mean(v) for c, v in per_kernel[name].items()}
+        parts = []
+        if kv.get("SQ_WAVES") and "SQ_INSTS_VALU" in kv:
+            parts.append(f"VALU insts/wave {kv['SQ_INSTS_VALU'] / kv['SQ_WAVES']:.0f}")
+        if kv.get("SQ_WAVE_CYCLES") and "SQ_WAIT_INST_ANY" in kv:
+            parts.append(f"waiting {100 * kv['SQ_WAIT_INST_ANY'] / kv['SQ_WAVE_CYCLES']:.0f}% of wave-cycles")
+        if kv.get("SQ_WAVE_CYCLES") and "SQ_ACTIVE_INST_VALU" in kv:
+            parts.append(f"issuing VALU {100 * kv['SQ_ACTIVE_INST_VALU'] / kv['SQ_WAVE_CYCLES']:.0f}% of wave-cycles")
+        if kv.get("SQ_INSTS_LDS") and "SQ_LDS_BANK_CONFLICT" in kv:
+            parts.append(f"LDS bank-conflict cycles/LDS inst {kv['SQ_LDS_BANK_CONFLICT'] / kv['SQ_INSTS_LDS']:.3f}")
+        if parts:
+            ratios.append(f"#   {name}: " + "; ".join(parts))
+    if ratios:
+        lines.append("# ratios of the averages above")
+        lines += ratios
+    return "\n".join(lines)
 
 
 COPY_KIB = 262144.0  # the 256 MiB calibration copy, in KiB

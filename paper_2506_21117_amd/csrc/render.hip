@@ -190,7 +190,8 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
   float Tr = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;   // colour of the flushed chunks
   float dr = 0.0f, dg = 0.0f, db = 0.0f;              // colour of the current chunk
   uint32_t last = 0;
-  float live = inside ? 1.0f : 0.0f;   // 1 until the pixel stops compositing
+  // transmittance for blending: Tr while the pixel composites, 0 once it has stopped
+  float Tb = inside ? 1.0f : 0.0f;
   int chunk = 0;
   int chl = CH;  // the tile's current chunk length (uniform over the workgroup)
   if (PHASE == 2) {
@@ -202,13 +203,13 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
     dg = my_carry[5 * NT];
     db = my_carry[6 * NT];
     last = __float_as_uint(my_carry[7 * NT]);
-    live = my_carry[8 * NT] != 0.0f ? 0.0f : 1.0f;
+    Tb = my_carry[8 * NT] != 0.0f ? 0.0f : Tr;
     // the first phase composited the whole first list (the tile was still alive)
     chl = chunk_len_after(len1);
     chunk = len1 / chl;
   }
   for (int kb = k_begin; kb < k_end; kb += NT) {
-    if (__syncthreads_count(live == 0.0f) == NT) break;
+    if (__syncthreads_count(Tb == 0.0f) == NT) break;
     const int k = kb + threadIdx.x;
     if (k < k_end) {
       const uint32_t e = list_entry(values, r1, r2, k);
@@ -222,13 +223,15 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
       const int jhi = min(cnt, next_b - kb);
       // Branch-free blending, FW_UNROLL records per iteration: their weights are
       // computed first, then applied in order.  The per-lane state is kept in floats so
-      // that no lane-mask logic is needed: `live` is 1 until the pixel stops, a skipped
-      // record gets weight 0 (then T * (1 - 0) = T exactly), and a record that would take
-      // T below T_STOP sets live to 0 and is not blended; this is the same arithmetic, and
-      // gives the same bits, as blending with branches.  A group that reaches past the
-      // segment's end (chunk boundaries of the second list, which starts anywhere, and the
-      // list's end) gives the records past it weight 0; whole groups need no check.  The
-      // wave leaves the segment once all its lanes have stopped.
+      // that no lane-mask logic is needed: a skipped record has weight 0 (then
+      // Tb * (1 - 0) = Tb exactly), and a record that would take the transmittance below
+      // T_STOP is not blended and sets Tb to 0, which blends nothing more (0 * x = 0 and
+      // 0 < T_STOP), while Tr keeps the transmittance after the last blended record; this
+      // is the same arithmetic, and gives the same bits, as blending with branches.  A
+      // group that reaches past the segment's end (chunk boundaries of the second list,
+      // which starts anywhere, and the list's end) gives the records past it weight 0;
+      // whole groups need no check.  The wave leaves the segment once all its lanes have
+      // stopped.
       auto group = [&](int jj, int lim) {
         float ae[FW_UNROLL], cq[FW_UNROLL];
         float4 bq[FW_UNROLL];
@@ -242,23 +245,24 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
           bool cl;
           ae[u] = (splat_alpha(aq, bq[u], fx, fy, dx, dy, G, al, cl) && u < lim) ? al : 0.0f;
         }
+        uint32_t lastu = 0;   // 1 + the group's last blended record, 0 if none
 #pragma unroll
         for (int u = 0; u < FW_UNROLL; ++u) {
-          const float a2 = ae[u] * live;
-          const float Tn = Tr * (1.0f - a2);
-          const bool stop = Tn < T_STOP;        // only when a2 > 0: T >= T_STOP otherwise
-          live = stop ? 0.0f : live;
-          const float a3 = stop ? 0.0f : a2;
-          const float w = a3 * Tr;               // colours are finite and >= 0: adding 0*c is exact
+          const float Tn = Tb * (1.0f - ae[u]);
+          // (written as the condition to go on, which selects with the short encoding)
+          const bool go = Tn >= T_STOP;          // false only when ae > 0 or Tb = 0
+          const float w = go ? ae[u] * Tb : 0.0f;   // colours are finite and >= 0: adding 0*c is exact
           dr = fmaf(w, bq[u].z, dr);
           dg = fmaf(w, bq[u].w, dg);
           db = fmaf(w, cq[u], db);
-          Tr = stop ? Tr : Tn;
-          last = a3 > 0.0f ? (uint32_t)(kb + jj + u + 1) : last;
+          Tb = go ? Tn : 0.0f;
+          Tr = go ? Tn : Tr;
+          lastu = w > 0.0f ? (uint32_t)(u + 1) : lastu;
         }
+        last = lastu ? (uint32_t)(kb + jj) + lastu : last;
       };
       for (int jj = j; jj < jhi; jj += FW_UNROLL) {
-        if (__ballot(live != 0.0f) == 0ull) break;
+        if (__ballot(Tb != 0.0f) == 0ull) break;
         if (jj + FW_UNROLL <= jhi)
           group(jj, FW_UNROLL);
         else
@@ -289,7 +293,7 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
   }
   bool more = false;  // the second phase continues this tile
   if (PHASE == 1 && sliced) {
-    more = __syncthreads_count(live == 0.0f) < NT;
+    more = __syncthreads_count(Tb == 0.0f) < NT;
     if (more) {
       // save the state; the second list continues this tile
       my_carry[0 * NT] = Tr;
@@ -300,7 +304,7 @@ __global__ void __launch_bounds__(NT) render_forward_kernel(
       my_carry[5 * NT] = dg;
       my_carry[6 * NT] = db;
       my_carry[7 * NT] = __uint_as_float(last);
-      my_carry[8 * NT] = live == 0.0f ? 1.0f : 0.0f;
+      my_carry[8 * NT] = Tb == 0.0f ? 1.0f : 0.0f;
     }
     if (threadIdx.x == 0) {
       alive[slot] = more ? 1u : 0u;
