@@ -405,17 +405,72 @@ __device__ __forceinline__ float dpp_f(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
 }
 
-// Sum of v over the 64 lanes of the wave, valid in lane 63 (DPP row operations; every
-// lane of the wave must be active).
-__device__ __forceinline__ float wave_sum_lane63(float v) {
-  v += dpp_f<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f<0x141, 0xf>(v);  // row_half_mirror
-  v += dpp_f<0x140, 0xf>(v);  // row_mirror
-  v += dpp_f<0x142, 0xa>(v);  // row_bcast15 into rows 1 and 3
-  v += dpp_f<0x143, 0xc>(v);  // row_bcast31 into rows 2 and 3
-  return v;
+// Sums over the 64 lanes of a wave of each of N values per lane, scattered over the
+// lanes (a butterfly reduce-scatter): at each of six levels, lane distance 32, 16, ... 1,
+// a lane keeps one half of its values (the lower lane of a pair the first half) and
+// adds the partner's copy of that half, so a level of m values costs about m/2
+// exchanges and adds instead of the 6 m of separate reductions.  Afterwards the lane
+// with bfly_index >= 0 holds the sum of that value index in x[0].  Every lane of the
+// wave must be active.
+template <int D> __device__ __forceinline__ float lane_xor(float v);
+template <> __device__ __forceinline__ float lane_xor<16>(float v) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));  // lane ^ 16 within 32
 }
+template <> __device__ __forceinline__ float lane_xor<8>(float v) { return dpp_f<0x128, 0xf>(v); }  // row_ror:8
+template <> __device__ __forceinline__ float lane_xor<4>(float v) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x101F));  // lane ^ 4 within 32
+}
+template <> __device__ __forceinline__ float lane_xor<2>(float v) { return dpp_f<0x4e, 0xf>(v); }  // quad_perm [2,3,0,1]
+template <> __device__ __forceinline__ float lane_xor<1>(float v) { return dpp_f<0xb1, 0xf>(v); }  // quad_perm [1,0,3,2]
+
+// One level over the first M values (an odd count is padded with a zero).
+template <int M, int D>
+__device__ __forceinline__ void bfly_level(float* x, bool upper) {
+  constexpr int H = (M + 1) / 2;
+  if (M & 1) x[M] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const float send = upper ? x[i] : x[H + i];
+    const float keep = upper ? x[H + i] : x[i];
+    x[i] = keep + lane_xor<D>(send);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void bfly_reduce(float (&x)[N], uint32_t lane) {
+  static_assert(N % 2 == 0, "the first level takes pairs (i, N/2 + i)");
+  constexpr int H1 = N / 2;
+  // distance 32: one lane-half swap (v_permlane32_swap) moves both halves of a pair
+#pragma unroll
+  for (int i = 0; i < H1; ++i) {
+    const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[i]), __float_as_uint(x[H1 + i]), false, false);
+    x[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+  }
+  constexpr int M2 = H1, M3 = (M2 + 1) / 2, M4 = (M3 + 1) / 2, M5 = (M4 + 1) / 2, M6 = (M5 + 1) / 2;
+  bfly_level<M2, 16>(x, (lane & 16u) != 0);
+  bfly_level<M3, 8>(x, (lane & 8u) != 0);
+  bfly_level<M4, 4>(x, (lane & 4u) != 0);
+  bfly_level<M5, 2>(x, (lane & 2u) != 0);
+  bfly_level<M6, 1>(x, (lane & 1u) != 0);
+}
+
+// The value index whose sum bfly_reduce leaves in this lane, or -1 (a padding zero).
+template <int N>
+__device__ __forceinline__ int bfly_index(uint32_t lane) {
+  constexpr int M2 = N / 2, M3 = (M2 + 1) / 2, M4 = (M3 + 1) / 2, M5 = (M4 + 1) / 2, M6 = (M5 + 1) / 2;
+  const int m[6] = {N, M2, M3, M4, M5, M6};
+  const int h[6] = {N / 2, (M2 + 1) / 2, (M3 + 1) / 2, (M4 + 1) / 2, (M5 + 1) / 2, (M6 + 1) / 2};
+  int pos = 0;
+  bool ok = true;
+  for (int k = 5; k >= 0; --k) {
+    pos += (lane & (32u >> k)) ? h[k] : 0;
+    ok = ok && pos < m[k];
+  }
+  return ok ? pos : -1;
+}
+
+// Records whose gradient terms are reduced together (BW_GROUP * 9 values).
+constexpr int BW_GROUP = 4;
 
 // One workgroup per (rendered tile, chunk of its list): reverse traversal of the
 // chunk's entries from the chunk's stored end state.
@@ -497,6 +552,7 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
     const int64_t na = a1 - a0;
     const int64_t vbase = (int64_t)v * n;
     const uint32_t lane = threadIdx.x & 63;
+    const int bidx = bfly_index<BW_GROUP * 9>(lane);
 
     for (int end = k1; end > k0; end -= NT) {
       const int beg = max(k0, end - NT);
@@ -524,68 +580,72 @@ __global__ void __launch_bounds__(NT) render_backward_kernel(
         S2 = fmaf(w, c, S2);
         Tr = Tj;
       };
-      for (int j = cnt - 1; j >= 0; --j) {
-        const int k = beg + j;
-        if (!s_act[j]) {
-          if (j >= 1 && !s_act[j - 1]) {
-            // two frozen records: weights together, then undone in reverse order
-            const float4 a0 = s_a[j], b0 = s_b[j], a1 = s_a[j - 1], b1 = s_b[j - 1];
-            const float c0 = s_c[j], c1 = s_c[j - 1];
-            float dx0, dy0, G0, al0, dx1, dy1, G1, al1;
-            bool cl0, cl1;
-            const bool ok0 = splat_alpha(a0, b0, fx, fy, dx0, dy0, G0, al0, cl0) && k < (int)last;
-            const bool ok1 = splat_alpha(a1, b1, fx, fy, dx1, dy1, G1, al1, cl1) && k - 1 < (int)last;
-            unblend(ok0, al0, b0, c0);
-            unblend(ok1, al1, b1, c1);
-            --j;
-          } else {
-            const float4 a = s_a[j], b = s_b[j];
-            float dx, dy, G, alpha;
-            bool clamped;
-            const bool ok = splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped) && k < (int)last;
-            unblend(ok, alpha, b, s_c[j]);
-          }
-          continue;
-        }
-        // Every lane evaluates the record's weight; if some lane of the wave is touched,
-        // the gradient terms are computed branch-free, masked by 0/1 factors (exact: the
-        // unmasked terms are multiplied by 1, the masked ones add zeros), and reduced.
-        const float4 a = s_a[j], b = s_b[j];
-        const float cb = s_c[j];
-        float dx, dy, G, alpha;
-        bool clamped;
-        const bool contrib = splat_alpha(a, b, fx, fy, dx, dy, G, alpha, clamped) && k < (int)last;
-        if (__ballot(contrib)) {
-          const float om = 1.0f - alpha;
-          const float io = __builtin_amdgcn_rcpf(om);  // om in [0.01, 1]
-          const float Tj = Tr * io;
-          const float w = alpha * Tj;
-          const float dLda = g0 * (Tj * b.z - S0 * io) + g1 * (Tj * b.w - S1 * io) + g2 * (Tj * cb - S2 * io);
-          S0 = contrib ? fmaf(w, b.z, S0) : S0;
-          S1 = contrib ? fmaf(w, b.w, S1) : S1;
-          S2 = contrib ? fmaf(w, cb, S2) : S2;
-          Tr = contrib ? Tj : Tr;
-          const float cf = contrib ? 1.0f : 0.0f;
-          const float gf = (contrib && !clamped) ? 1.0f : 0.0f;  // the 0.99 clamp has zero derivative
-          const float gp = alpha * dLda * gf;                     // dL/dpower
-          // dL/du = gp (A dx + B dy), dL/dv = gp (B dx + C dy); in staged units A = A2 / K_AC,
-          // B = B2 / K_B = B2 / (2 K_AC), C = C2 / K_AC
-          const float gk = gp * (1.0f / K_AC);
-          float p[9];
-          p[0] = gk * (a.z * dx + 0.5f * a.w * dy);
-          p[1] = gk * (0.5f * a.w * dx + b.x * dy);
-          p[2] = -0.5f * gp * dx * dx;
-          p[3] = -gp * dx * dy;
-          p[4] = -0.5f * gp * dy * dy;
-          p[5] = G * dLda * gf;  // dL/dopacity
-          p[6] = w * g0 * cf;
-          p[7] = w * g1 * cf;
-          p[8] = w * g2 * cf;
+      // BW_GROUP records at a time: their weights first (independent), then in order the
+      // frozen ones un-blend and the active ones give their gradient terms (every lane
+      // evaluates the record's weight; if some lane of the wave is touched, the terms are
+      // computed branch-free, masked by 0/1 factors: exact, the unmasked terms are
+      // multiplied by 1, the masked ones add zeros); the group's terms are summed over the
+      // wave in one reduce-scatter.
+      for (int jb = cnt - 1; jb >= 0; jb -= BW_GROUP) {
+        float4 aq[BW_GROUP], bq[BW_GROUP];
+        float cq[BW_GROUP], dxq[BW_GROUP], dyq[BW_GROUP], Gq[BW_GROUP], alq[BW_GROUP];
+        bool okq[BW_GROUP], clq[BW_GROUP], actq[BW_GROUP];
 #pragma unroll
-          for (int c = 0; c < 9; ++c) {
-            const float sum = wave_sum_lane63(p[c]);
-            if (lane == 63 && sum != 0.0f) atomicAdd(&s_g[j][c], sum);
+        for (int q = 0; q < BW_GROUP; ++q) {
+          const int j = jb - q;
+          const int js = j >= 0 ? j : 0;
+          aq[q] = s_a[js];
+          bq[q] = s_b[js];
+          cq[q] = s_c[js];
+          actq[q] = j >= 0 && s_act[js] != 0u;
+          okq[q] = splat_alpha(aq[q], bq[q], fx, fy, dxq[q], dyq[q], Gq[q], alq[q], clq[q]) && j >= 0 &&
+                   beg + j < (int)last;
+        }
+        float P[BW_GROUP * 9];
+        bool any = false;  // some record of the group touched a lane of the wave (uniform)
+#pragma unroll
+        for (int q = 0; q < BW_GROUP; ++q) {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) P[q * 9 + c] = 0.0f;
+          if (!actq[q]) {  // (uniform: one record for the whole wave)
+            unblend(okq[q], alq[q], bq[q], cq[q]);
+            continue;
           }
+          const float4 a = aq[q], b = bq[q];
+          const float cb = cq[q], dx = dxq[q], dy = dyq[q], G = Gq[q], alpha = alq[q];
+          const bool contrib = okq[q], clamped = clq[q];
+          if (__ballot(contrib)) {
+            any = true;
+            const float om = 1.0f - alpha;
+            const float io = __builtin_amdgcn_rcpf(om);  // om in [0.01, 1]
+            const float Tj = Tr * io;
+            const float w = alpha * Tj;
+            const float dLda = g0 * (Tj * b.z - S0 * io) + g1 * (Tj * b.w - S1 * io) + g2 * (Tj * cb - S2 * io);
+            S0 = contrib ? fmaf(w, b.z, S0) : S0;
+            S1 = contrib ? fmaf(w, b.w, S1) : S1;
+            S2 = contrib ? fmaf(w, cb, S2) : S2;
+            Tr = contrib ? Tj : Tr;
+            const float cf = contrib ? 1.0f : 0.0f;
+            const float gf = (contrib && !clamped) ? 1.0f : 0.0f;  // the 0.99 clamp has zero derivative
+            const float gp = alpha * dLda * gf;                     // dL/dpower
+            // dL/du = gp (A dx + B dy), dL/dv = gp (B dx + C dy); in staged units A = A2 / K_AC,
+            // B = B2 / K_B = B2 / (2 K_AC), C = C2 / K_AC
+            const float gk = gp * (1.0f / K_AC);
+            P[q * 9 + 0] = gk * (a.z * dx + 0.5f * a.w * dy);
+            P[q * 9 + 1] = gk * (0.5f * a.w * dx + b.x * dy);
+            P[q * 9 + 2] = -0.5f * gp * dx * dx;
+            P[q * 9 + 3] = -gp * dx * dy;
+            P[q * 9 + 4] = -0.5f * gp * dy * dy;
+            P[q * 9 + 5] = G * dLda * gf;  // dL/dopacity
+            P[q * 9 + 6] = w * g0 * cf;
+            P[q * 9 + 7] = w * g1 * cf;
+            P[q * 9 + 8] = w * g2 * cf;
+          }
+        }
+        if (any) {
+          bfly_reduce(P, lane);
+          const int q = bidx / 9, c = bidx % 9;
+          if (bidx >= 0 && jb - q >= 0 && P[0] != 0.0f) atomicAdd(&s_g[jb - q][c], P[0]);
         }
       }
       __syncthreads();

@@ -124,8 +124,12 @@ def test_frozen_order_full_size_same_lists(dev, center):
 
 def test_optimizer_local_steps_with_and_without_frozen_order(dev):
     """Local steps over several views, two optimisers in lockstep: with the stored orders
-    every step's lists equal those of the full sort, bit for bit, so the parameters
-    differ only by the order of the backward's atomic gradient sums."""
+    every step's lists equal those of the full sort, bit for bit.  After the first step
+    the Adam moments (0.1 x the gradient) agree up to the order of the backward's float
+    additions (atomics and wave reductions): 1e-4 relative, with a floor of 1e-6 of the
+    largest moment for terms that cancel to rounding residue.  (Later
+    steps are not compared element by element: Adam turns the sign of such a residue into
+    a step of size lr.)"""
     from paper_2506_21117_amd.optim import SplatOptimizer
     w = scenes.local_change(n=40_000, n_views=3, width=320, height=180, fx=320.0, center=(0.0, 0.0, 1.0))
     sc, cams = w.scene, w.cameras
@@ -133,22 +137,28 @@ def test_optimizer_local_steps_with_and_without_frozen_order(dev):
     tg = torch.rand(3, 3, 180, 320, generator=torch.Generator(device=dev).manual_seed(5), device=dev)
     opts = [SplatOptimizer(api.GaussianTensors.from_scene(sc, dev), cams, tg, active=(a0, n), local=True,
                            frozen_order=f) for f in (True, False)]
+    compared = False
     for k in range(7):
         for o in opts:
             o.step(k % 3)
         torch.cuda.synchronize()
         c = _same_lists(opts[0].bins, opts[1].bins)
         assert c["pairs"] > 0
+        # the first step with gradients (before it nothing moved: zero gradients leave the
+        # moments and the parameters as they were)
+        m0 = {name: [to_np(getattr(o.m, name))[..., a0:].astype(np.float64) for o in opts]
+              for name in api.GaussianTensors.NAMES}
+        if not compared and sum(int(np.count_nonzero(x[0])) for x in m0.values()) > 1000:
+            # the change set is isotropic: its quaternion gradients are zero in exact
+            # arithmetic and rounding residue on both sides, so the floor is taken from the
+            # step's largest moment over all parameters
+            floor = 1e-6 * max(np.abs(x).max() for pair in m0.values() for x in pair)
+            for name, (a, b) in m0.items():
+                np.testing.assert_allclose(a, b, rtol=1e-4, atol=floor, err_msg=name)
+            compared = True
+    assert compared
     assert not any(o.overflowed() for o in opts)
     assert bool(opts[0]._frozen_orders) and not opts[1]._frozen_orders
-    # the quaternions of the isotropic change set get zero gradients in exact arithmetic:
-    # Adam turns their rounding residue (whose sign depends on the atomic order) into
-    # steps of up to lr, so they may differ by 2 lr per step
-    lr_quats = api.DEFAULT_LR[2]
-    for k in api.GaussianTensors.NAMES:
-        a, b = (to_np(getattr(o.params, k)).astype(np.float64) for o in opts)
-        atol = 2 * 7 * lr_quats if k == "quats" else 1e-6
-        np.testing.assert_allclose(a, b, rtol=1e-4, atol=atol, err_msg=k)
     assert not np.array_equal(to_np(opts[0].params.means)[:, a0:], sc.means[:, a0:])
 
 
