@@ -263,8 +263,8 @@ def main():
 # They describe the kernels whose sources hash to `source_sha256` and are reported only
 # while the sources still do (profiles/traffic_local_step_1M_1280x720.txt).
 MEASURED_TRAFFIC = {
-    "source_sha256": "e74fa3b85a338f40c824be184db430f78bcd060dc1b47a114c3f5bbac6c1eeae",
-    "bytes": {"bin_and_sort": 210.173e6, "render_forward": 17.277e6, "render_backward": 17.494e6},
+    "source_sha256": "171cb670aee557305448be97f9289e5be7b5ea5629b3e3f1f12e5c60690cb3be",
+    "bytes": {"bin_and_sort": 154.160e6, "render_forward": 18.245e6, "render_backward": 17.585e6},
 }
 
 
