@@ -966,6 +966,256 @@ __global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ o
   }
 }
 
+// ------------------------------------------------------------------ 5-7 by counting
+// Counting placement of a slab's pairs, when its count matrix fits (see list_slab): the
+// pairs are written straight into tile order, with no tile sort and no range scan.
+// The slab's entries are taken in chunks of CM_EPB (depth order).  A tile's "slot" is
+// its position in the slab's tile list (masked lists: the rank of the tile among the
+// view's set tiles, from the corner table; complete grids: the global tile).  For a
+// chunk, each slot's mask has bit j set when the chunk's entry j covers the slot, so
+// the chunk's entries of a tile, in depth order, are the mask's set bits in order.
+//   count : row q of the count matrix, cm[q * S + s] = popcount(mask of slot s, chunk q)
+//   scan  : each column's exclusive prefix over the chunks, and its total (the tile's
+//           pair count)
+//   emit  : the tiles' first positions (an exclusive scan of the totals), then pair k of
+//           slot s in chunk q goes to first(s) + cm[q][s] + k, its entry the mask's k-th
+//           set bit; block 0 also writes the tiles' ranges and runs the capacity check.
+constexpr int CM_EPB = 64;                     // one bit per entry of a chunk
+constexpr int64_t CM_MAX_WORDS = 8ll << 20;    // count matrix budget (32 MB)
+constexpr int CM_MAX_SLOTS = 3840;             // the emission keeps 16 B per slot in LDS
+
+// Slots [a, a + c) of row ty of the rectangle [x0, x1) (vb: the view's first table row,
+// masked, or its first global tile; vf: the view's first list position, masked).
+template <bool MASKED>
+__device__ __forceinline__ void cm_row_slots(const uint32_t* tb, uint32_t vb, uint32_t vf, uint32_t TXp, uint32_t TX,
+                                             uint32_t ty, uint32_t x0, uint32_t x1, uint32_t& a, uint32_t& c) {
+  if (MASKED) {
+    a = vf + tab_rank(tb, vb, TXp, ty, x0);
+    c = vf + tab_rank(tb, vb, TXp, ty, x1) - a;
+  } else {
+    a = vb + ty * TX + x0;
+    c = x1 - x0;
+  }
+}
+
+// Sets bit t of the mask of every slot entry t (t < cnt) of the chunk covers: the block's
+// threads take (entry, row) pairs, four rows of an entry at a time.
+template <bool MASKED>
+__device__ __forceinline__ void cm_build_masks(unsigned long long* s_mask, const uint2* s_r, const uint32_t* s_vb,
+                                               const uint32_t* s_vf, uint32_t cnt, const uint32_t* tb, uint32_t TXp,
+                                               uint32_t TX) {
+  const uint32_t t = threadIdx.x % CM_EPB, g = threadIdx.x / CM_EPB;
+  if (t >= cnt) return;
+  const uint2 r = s_r[t];
+  const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
+  for (uint32_t ty = y0 + g; ty < y1; ty += NT / CM_EPB) {
+    uint32_t a, c;
+    cm_row_slots<MASKED>(tb, s_vb[t], s_vf[t], TXp, TX, ty, x0, x1, a, c);
+    for (uint32_t i = 0; i < c; ++i) atomicOr(&s_mask[a + i], 1ull << t);
+  }
+}
+
+// The chunk's entries: index, rectangle and view bases (s_e, s_r, s_vb, s_vf).
+template <bool MASKED>
+__device__ __forceinline__ void cm_load_chunk(const uint32_t* __restrict__ order, const uint2* __restrict__ rect,
+                                              const uint32_t* __restrict__ vfirst, uint32_t j0, uint32_t cnt,
+                                              uint32_t n, uint32_t TYp, uint32_t T, uint32_t* s_e, uint2* s_r,
+                                              uint32_t* s_vb, uint32_t* s_vf, uint2* rsort) {
+  if (threadIdx.x < cnt) {
+    const uint32_t e = order[j0 + threadIdx.x];
+    const uint32_t v = e / n;
+    const uint2 r = rect[e];
+    s_e[threadIdx.x] = e;
+    s_r[threadIdx.x] = r;
+    s_vb[threadIdx.x] = MASKED ? v * TYp : v * T;
+    s_vf[threadIdx.x] = MASKED ? vfirst[v] : 0u;
+    if (rsort) rsort[j0 + threadIdx.x] = r;
+  }
+}
+
+template <bool MASKED>
+__global__ void __launch_bounds__(NT) cm_count_kernel(const uint32_t* __restrict__ order,
+                                                      const uint2* __restrict__ rect,
+                                                      const uint32_t* __restrict__ tab,
+                                                      const uint32_t* __restrict__ vfirst, uint32_t* counters,
+                                                      int which, int sliced, uint32_t n, int TX, int TY,
+                                                      uint32_t* __restrict__ cm) {
+  extern __shared__ unsigned long long s_mask[];  // [S]
+  __shared__ uint32_t s_e[CM_EPB], s_vb[CM_EPB], s_vf[CM_EPB];
+  __shared__ uint2 s_r[CM_EPB];
+  uint32_t lo, m;
+  slab_params(counters, which, sliced, lo, m);
+  const uint32_t S = counters[C_TILES];
+  const uint32_t nq = (m + CM_EPB - 1) / CM_EPB;
+  const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
+  order += lo;
+  for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+    const uint32_t j0 = q * CM_EPB, cnt = min((uint32_t)CM_EPB, m - j0);
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < S; s += NT) s_mask[s] = 0ull;
+    cm_load_chunk<MASKED>(order, rect, vfirst, j0, cnt, n, TYp, (uint32_t)(TX * TY), s_e, s_r, s_vb, s_vf, nullptr);
+    __syncthreads();
+    cm_build_masks<MASKED>(s_mask, s_r, s_vb, s_vf, cnt, tab, TXp, (uint32_t)TX);
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < S; s += NT) cm[(size_t)q * S + s] = (uint32_t)__popcll(s_mask[s]);
+  }
+}
+
+// Column scan of the count matrix (nq rows of S): each column's exclusive prefix over the
+// rows in place, and its total -> tot[s].  A block takes CS_COLS columns; its CS_SEGS
+// row groups each sum a contiguous segment of rows (CS_BATCH loads in flight), the
+// segments' bases come from a scan in LDS, then each group rewrites its segment.
+constexpr int CS_COLS = 64, CS_SEGS = 16, CS_NT = CS_COLS * CS_SEGS, CS_BATCH = 8;
+__global__ void __launch_bounds__(CS_NT) cm_scan_kernel(uint32_t* __restrict__ cm, const uint32_t* counters,
+                                                        uint32_t* __restrict__ tot) {
+  __shared__ uint32_t s_seg[CS_SEGS][CS_COLS];
+  const uint32_t m = counters[C_SLAB_N], S = counters[C_TILES];
+  const uint32_t nq = (m + CM_EPB - 1) / CM_EPB;
+  const uint32_t col = blockIdx.x * CS_COLS + (threadIdx.x % CS_COLS), seg = threadIdx.x / CS_COLS;
+  if (blockIdx.x * CS_COLS >= S) return;
+  const bool ok = col < S;
+  const uint32_t per = (nq + CS_SEGS - 1) / CS_SEGS;
+  const uint32_t r0 = min(seg * per, nq), r1 = min(r0 + per, nq);
+  uint32_t sum = 0;
+  for (uint32_t r = r0; r < r1; r += CS_BATCH) {
+    uint32_t x[CS_BATCH];
+#pragma unroll
+    for (int u = 0; u < CS_BATCH; ++u) x[u] = (ok && r + u < r1) ? cm[(size_t)(r + u) * S + col] : 0u;
+#pragma unroll
+    for (int u = 0; u < CS_BATCH; ++u) sum += x[u];
+  }
+  s_seg[seg][threadIdx.x % CS_COLS] = sum;
+  __syncthreads();
+  uint32_t run = 0;
+  for (uint32_t k = 0; k < seg; ++k) run += s_seg[k][threadIdx.x % CS_COLS];
+  if (ok && seg == CS_SEGS - 1) tot[col] = run + sum;
+  if (!ok) return;
+  for (uint32_t r = r0; r < r1; r += CS_BATCH) {
+    uint32_t x[CS_BATCH];
+#pragma unroll
+    for (int u = 0; u < CS_BATCH; ++u) x[u] = r + u < r1 ? cm[(size_t)(r + u) * S + col] : 0u;
+#pragma unroll
+    for (int u = 0; u < CS_BATCH; ++u)
+      if (r + u < r1) {
+        cm[(size_t)(r + u) * S + col] = run;
+        run += x[u];
+      }
+  }
+}
+
+// The k-th (0-based) set bit of m (m has more than k set bits).
+__device__ __forceinline__ uint32_t kth_set_bit(unsigned long long m, uint32_t k) {
+  uint32_t pos = 0;
+#pragma unroll
+  for (int w = 32; w > 0; w >>= 1) {
+    const uint32_t c = (uint32_t)__popcll(m & ((1ull << w) - 1ull));
+    if (k >= c) {
+      k -= c;
+      m >>= w;
+      pos += (uint32_t)w;
+    }
+  }
+  return pos;
+}
+
+// Emission by counting.  Dynamic LDS: the slots' masks (8 B each), then per slot its
+// first position plus this chunk's prefix (4 B) and the chunk's exclusive pair scan
+// (4 B, S + 1 words).
+template <bool MASKED>
+__global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict__ order,
+                                                     const uint2* __restrict__ rect,
+                                                     const uint32_t* __restrict__ tab,
+                                                     const uint32_t* __restrict__ vfirst,
+                                                     const uint32_t* __restrict__ list,
+                                                     const uint32_t* __restrict__ cm, const uint32_t* __restrict__ tot,
+                                                     uint32_t* __restrict__ counters, int which, uint32_t n, int TX,
+                                                     int TY, uint64_t capacity, uint32_t* __restrict__ pk,
+                                                     uint32_t* __restrict__ pv, uint2* __restrict__ ranges) {
+  extern __shared__ unsigned long long s_mask[];
+  __shared__ uint32_t s_e[CM_EPB], s_vb[CM_EPB], s_vf[CM_EPB];
+  __shared__ uint2 s_r[CM_EPB];
+  __shared__ uint32_t s4[4];
+  __shared__ uint32_t s_c[4];
+  if (threadIdx.x == 0) {
+    s_c[0] = counters[C_OVERFLOW];  // set when the first slab overflowed
+    s_c[1] = counters[C_SLAB_N];
+    s_c[2] = which == 1 ? 0u : counters[C_PAIRS1];
+    s_c[3] = counters[C_TILES];
+  }
+  __syncthreads();
+  if (s_c[0]) return;
+  const uint32_t m = s_c[1], S = s_c[3];
+  uint32_t* s_first = reinterpret_cast<uint32_t*>(s_mask + S);  // first position of the slot's run
+  uint32_t* s_scan = s_first + S;                                // [S + 1]
+  const uint32_t nq = (m + CM_EPB - 1) / CM_EPB;
+  const uint32_t base = s_c[2];
+  // the tiles' first positions: an exclusive scan of the column totals (runs of
+  // consecutive slots per thread), after the pairs of earlier slabs
+  uint32_t slab_pairs;
+  {
+    const uint32_t per = (S + NT - 1) / NT, s0 = min(threadIdx.x * per, S), s1 = min(s0 + per, S);
+    uint32_t sum = 0;
+    for (uint32_t s = s0; s < s1; ++s) sum += tot[s];
+    uint32_t run = block_excl_scan(sum, s4, slab_pairs);
+    for (uint32_t s = s0; s < s1; ++s) {
+      s_first[s] = base + run;
+      run += tot[s];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    counters[C_SLAB_PAIRS] = slab_pairs;
+    capacity_check(counters, capacity, which);
+  }
+  if ((uint64_t)base + slab_pairs > capacity) return;
+  __syncthreads();
+  if (blockIdx.x == 0 && which == 1) {
+    for (uint32_t s = threadIdx.x; s < S; s += NT) {
+      const uint32_t c = tot[s];
+      if (c) ranges[MASKED ? list[s] : s] = make_uint2(s_first[s], s_first[s] + c);
+    }
+  }
+  const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
+  order += counters[C_SLAB_LO];
+  for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+    const uint32_t j0 = q * CM_EPB, cnt = min((uint32_t)CM_EPB, m - j0);
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < S; s += NT) s_mask[s] = 0ull;
+    cm_load_chunk<MASKED>(order, rect, vfirst, j0, cnt, n, TYp, (uint32_t)(TX * TY), s_e, s_r, s_vb, s_vf, nullptr);
+    __syncthreads();
+    cm_build_masks<MASKED>(s_mask, s_r, s_vb, s_vf, cnt, tab, TXp, (uint32_t)TX);
+    __syncthreads();
+    // the chunk's pairs per slot, scanned: pair i of the chunk belongs to the slot s with
+    // s_scan[s] <= i < s_scan[s + 1]
+    uint32_t chunk_pairs;
+    {
+      const uint32_t per = (S + NT - 1) / NT, s0 = min(threadIdx.x * per, S), s1 = min(s0 + per, S);
+      uint32_t sum = 0;
+      for (uint32_t s = s0; s < s1; ++s) sum += (uint32_t)__popcll(s_mask[s]);
+      uint32_t run = block_excl_scan(sum, s4, chunk_pairs);
+      for (uint32_t s = s0; s < s1; ++s) {
+        s_scan[s] = run;
+        run += (uint32_t)__popcll(s_mask[s]);
+      }
+      if (threadIdx.x == 0) s_scan[S] = chunk_pairs;
+    }
+    __syncthreads();
+    const uint32_t* row = cm + (size_t)q * S;
+    for (uint32_t i = threadIdx.x; i < chunk_pairs; i += NT) {
+      uint32_t lo = 0, hi = S;  // the last slot with s_scan[s] <= i
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_scan[mid] <= i) lo = mid; else hi = mid;
+      }
+      const uint32_t s = lo, k = i - s_scan[s];
+      const uint32_t j = kth_set_bit(s_mask[s], k);
+      const uint32_t pos = s_first[s] + row[s] + k;
+      pk[pos] = MASKED ? list[s] : s;
+      pv[pos] = s_e[j];
+    }
+  }
+}
+
+
 // ------------------------------------------------------------------ 7. ranges, tile list
 // [start, end) of each tile's run among the slab's sorted pairs (absolute positions).
 __global__ void __launch_bounds__(NT) ranges_kernel(const uint32_t* __restrict__ keys,
@@ -1120,6 +1370,7 @@ int passes_for(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
 
 struct WsPtrs {
   uint32_t *cnt, *tmp, *keyA, *valA, *keyB, *valB, *blk, *hist, *dtot, *pairK, *pairV, *wpre, *tlist, *vfirst, *tab;
+  uint32_t *cm, *ctot;
   uint2* rsort;
 };
 
@@ -1141,6 +1392,8 @@ WsPtrs carve(const BinPlan& p, char* ws) {
   w.vfirst = reinterpret_cast<uint32_t*>(ws + p.off_vfirst);
   w.tab = reinterpret_cast<uint32_t*>(ws + p.off_tab);
   w.rsort = reinterpret_cast<uint2*>(ws + p.off_rsort);
+  w.cm = p.cm_words > 0 ? reinterpret_cast<uint32_t*>(ws + p.off_cm) : nullptr;
+  w.ctot = w.cm ? w.cm + p.cm_words : nullptr;
   return w;
 }
 
@@ -1177,6 +1430,31 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
   // counts and per-chunk pair counts, then the chunks' offsets (relative to the slab's
   // first pair) and the capacity check
   const int sliced = bins.mode == CLSP_BINS_DEPTH_SLICED ? 1 : 0;
+  // first slab by counting placement: count, column scan, emission straight into tile
+  // order (with the ranges); no tile sort, no range scan
+  const int64_t gt = (int64_t)V * p.T;
+  const int64_t nq_bound = (slab_max + CM_EPB - 1) / CM_EPB;
+  if (which == 1 && p.cm_words > 0 && nq_bound * gt <= p.cm_words) {
+    const int gq = (int)std::min<int64_t>(std::max<int64_t>(nq_bound, 1), 2048);
+    const size_t lds_count = (size_t)gt * 8, lds_emit = (size_t)gt * 16 + 4;
+    if (use_mask)
+      hipLaunchKernelGGL((cm_count_kernel<true>), dim3(gq), dim3(NT), lds_count, s, order, rect, w.tab, w.vfirst,
+                         counters, 1, sliced, (uint32_t)n, p.TX, p.TY, w.cm);
+    else
+      hipLaunchKernelGGL((cm_count_kernel<false>), dim3(gq), dim3(NT), lds_count, s, order, rect, w.tab, w.vfirst,
+                         counters, 1, sliced, (uint32_t)n, p.TX, p.TY, w.cm);
+    hipLaunchKernelGGL(cm_scan_kernel, dim3((unsigned)((gt + CS_COLS - 1) / CS_COLS)), dim3(CS_NT), 0, s, w.cm,
+                       counters, w.ctot);
+    if (use_mask)
+      hipLaunchKernelGGL((cm_emit_kernel<true>), dim3(gq), dim3(NT), lds_emit, s, order, rect, w.tab, w.vfirst, mlist,
+                         w.cm, w.ctot, counters, 1, (uint32_t)n, p.TX, p.TY, (uint64_t)p.capacity, bins.keys,
+                         bins.values, reinterpret_cast<uint2*>(ranges));
+    else
+      hipLaunchKernelGGL((cm_emit_kernel<false>), dim3(gq), dim3(NT), lds_emit, s, order, rect, w.tab, w.vfirst,
+                         mlist, w.cm, w.ctot, counters, 1, (uint32_t)n, p.TX, p.TY, (uint64_t)p.capacity, bins.keys,
+                         bins.values, reinterpret_cast<uint2*>(ranges));
+    return hipGetLastError();
+  }
   if (which == 1 && !recount_first)
     hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(slab_max)), dim3(NT), 0, s, order, w.cnt, rect, counters,
                        sliced, epb, w.tmp, w.rsort, w.blk);
@@ -1261,6 +1539,15 @@ BinPlan make_bin_plan(int64_t n, int views, int W, int H, int64_t capacity) {
   p.off_vfirst = take((size_t)views * 4);
   p.off_tab = take((size_t)views * (p.TY + 1) * (p.TX + 1) * 4);
   p.off_rsort = take(E * 8);
+  // the count matrix of the first slab's counting placement (and its column totals),
+  // when the slab's chunks times the tiles fit the budget (sized for depth-sliced
+  // lists; complete lists use it when their larger slab fits too)
+  {
+    const int64_t slab1 = std::min<int64_t>(E, std::max<int64_t>(E >> 4, 16384));
+    const int64_t words = (slab1 + CM_EPB - 1) / CM_EPB * gt;
+    p.cm_words = (gt <= CM_MAX_SLOTS && words <= CM_MAX_WORDS) ? words : 0;
+    p.off_cm = take(p.cm_words > 0 ? (size_t)(p.cm_words + gt) * 4 : 4);
+  }
   // per rendered tile slot: alive flag, and per pixel the carried compositing state
   p.off_alive = take(gt * 4);
   p.off_carry = take((size_t)gt * TILE_PIX * CARRY_FIELDS * 4);

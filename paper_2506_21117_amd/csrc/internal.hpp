@@ -100,7 +100,8 @@ struct BinPlan {
   int64_t entries;    // views * n
   // workspace carve-up (byte offsets)
   size_t off_cnt, off_flag, off_keyA, off_valA, off_keyB, off_valB, off_scanBlk, off_hist, off_digit,
-      off_pairK, off_pairV, off_tflag, off_vfirst, off_tab, off_rsort, off_alive, off_carry, total;
+      off_pairK, off_pairV, off_tflag, off_vfirst, off_tab, off_rsort, off_cm, off_alive, off_carry, total;
+  int64_t cm_words;   // count matrix of the first slab's counting placement (0: not used)
   int scan_blocks;
   int sort_blocks_gauss, sort_blocks_pairs;
 };
