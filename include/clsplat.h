@@ -166,6 +166,12 @@ typedef struct clsp_projected {
  *                           then a prefix of the complete one that reaches at least as
  *                           far as any pixel of the tile composites, so images and
  *                           gradients are the same as with complete lists.
+ *   CLSP_BINS_DEPTH_SLICED_LOCAL  the same lists as CLSP_BINS_DEPTH_SLICED, for steps in
+ *                           which few tiles need the second slab (local optimisation):
+ *                           the second slab's pairs are placed by counting per tile
+ *                           (work that grows with the tiles still compositing) instead
+ *                           of by a sort of its pairs (launches that cost the same when
+ *                           no tile needs it).
  *   values    uint32[capacity]: entry index v*n + i of each (tile, Gaussian) pair
  *   keys      uint32[capacity]: the global tile of each pair
  *             Pairs [0, counters[7]) hold the first lists sorted by (global tile, depth,
@@ -193,6 +199,7 @@ typedef struct clsp_projected {
  *   n:        Gaussians per view of the projection the lists are built from */
 #define CLSP_BINS_COMPLETE 0
 #define CLSP_BINS_DEPTH_SLICED 1
+#define CLSP_BINS_DEPTH_SLICED_LOCAL 2
 #define CLSP_COUNTERS 16
 typedef struct clsp_bins {
   uint32_t *values;

@@ -16,7 +16,7 @@ TILE = 16
 FLAG_VISIBLE, FLAG_CLAMP_X, FLAG_CLAMP_Y, FLAG_SHCLAMP_R = 1, 2, 4, 8
 C_PAIRS, C_OVERFLOW, C_TILES, C_WRITTEN, C_ENTRIES, C_STICKY, C_SLAB1, C_PAIRS1, C_ALIVE = 0, 1, 2, 3, 4, 5, 6, 7, 8
 N_COUNTERS = 16
-BINS_COMPLETE, BINS_DEPTH_SLICED = 0, 1
+BINS_COMPLETE, BINS_DEPTH_SLICED, BINS_DEPTH_SLICED_LOCAL = 0, 1, 2
 
 EXPORTED = (
     "clsp_version", "clsp_last_error", "clsp_project_preprocess", "clsp_project_preprocess_rows",

@@ -15,6 +15,10 @@
 //                order within a tile comes from step 4, so only ceil(log2(V*T)) key bits
 //                are sorted instead of tile + 32 depth bits;
 //   7. ranges  : [start, end) of each tile's run.
+// Masked slabs whose per-chunk tile counts fit a budget replace 5-7 by a counting
+// placement (see "5-7 by counting"): per chunk of 64 entries and per tile, which of
+// the chunk's entries cover the tile; the counts' prefix over the chunks gives every
+// pair its position in tile order directly.
 // Every kernel reads its element count from device memory, so nothing is read back.
 //
 // Depth-sliced lists: steps 5-7 first run for the nearest slab of the depth order
@@ -967,13 +971,13 @@ __global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ o
 }
 
 // ------------------------------------------------------------------ 5-7 by counting
-// Counting placement of a slab's pairs, when its count matrix fits (see list_slab): the
-// pairs are written straight into tile order, with no tile sort and no range scan.
-// The slab's entries are taken in chunks of CM_EPB (depth order).  A tile's "slot" is
-// its position in the slab's tile list (masked lists: the rank of the tile among the
-// view's set tiles, from the corner table; complete grids: the global tile).  For a
-// chunk, each slot's mask has bit j set when the chunk's entry j covers the slot, so
-// the chunk's entries of a tile, in depth order, are the mask's set bits in order.
+// Counting placement of a masked slab's pairs, when its count matrix fits (see
+// list_slab): the pairs are written straight into tile order, with no tile sort and no
+// range scan.  The slab's entries are taken in chunks of CM_EPB (depth order).  A tile's
+// "slot" is its position in the slab's tile list (the rank of the tile among the view's
+// set tiles, from the corner table).  For a chunk, each slot's mask has bit j set when
+// the chunk's entry j covers the slot, so the chunk's entries of a tile, in depth
+// order, are the mask's set bits in order.
 //   count : row q of the count matrix, cm[q * S + s] = popcount(mask of slot s, chunk q)
 //   scan  : each column's exclusive prefix over the chunks, and its total (the tile's
 //           pair count)
@@ -981,59 +985,48 @@ __global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ o
 //           slot s in chunk q goes to first(s) + cm[q][s] + k, its entry the mask's k-th
 //           set bit; block 0 also writes the tiles' ranges and runs the capacity check.
 constexpr int CM_EPB = 64;                     // one bit per entry of a chunk
-constexpr int64_t CM_MAX_WORDS = 8ll << 20;    // count matrix budget (32 MB)
+constexpr int64_t CM_MAX_WORDS = 64ll << 20;   // count matrix budget (256 MB)
 constexpr int CM_MAX_SLOTS = 3840;             // the emission keeps 16 B per slot in LDS
 
-// Slots [a, a + c) of row ty of the rectangle [x0, x1) (vb: the view's first table row,
-// masked, or its first global tile; vf: the view's first list position, masked).
-template <bool MASKED>
-__device__ __forceinline__ void cm_row_slots(const uint32_t* tb, uint32_t vb, uint32_t vf, uint32_t TXp, uint32_t TX,
-                                             uint32_t ty, uint32_t x0, uint32_t x1, uint32_t& a, uint32_t& c) {
-  if (MASKED) {
-    a = vf + tab_rank(tb, vb, TXp, ty, x0);
-    c = vf + tab_rank(tb, vb, TXp, ty, x1) - a;
-  } else {
-    a = vb + ty * TX + x0;
-    c = x1 - x0;
-  }
+// Slots [a, a + c) of row ty of the rectangle [x0, x1): list positions of the row's set
+// tiles (vb: the view's first table row; vf: the view's first list position).
+__device__ __forceinline__ void cm_row_slots(const uint32_t* tb, uint32_t vb, uint32_t vf, uint32_t TXp, uint32_t ty,
+                                             uint32_t x0, uint32_t x1, uint32_t& a, uint32_t& c) {
+  a = vf + tab_rank(tb, vb, TXp, ty, x0);
+  c = vf + tab_rank(tb, vb, TXp, ty, x1) - a;
 }
 
 // Sets bit t of the mask of every slot entry t (t < cnt) of the chunk covers: the block's
 // threads take (entry, row) pairs, four rows of an entry at a time.
-template <bool MASKED>
 __device__ __forceinline__ void cm_build_masks(unsigned long long* s_mask, const uint2* s_r, const uint32_t* s_vb,
-                                               const uint32_t* s_vf, uint32_t cnt, const uint32_t* tb, uint32_t TXp,
-                                               uint32_t TX) {
+                                               const uint32_t* s_vf, uint32_t cnt, const uint32_t* tb, uint32_t TXp) {
   const uint32_t t = threadIdx.x % CM_EPB, g = threadIdx.x / CM_EPB;
   if (t >= cnt) return;
   const uint2 r = s_r[t];
   const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
   for (uint32_t ty = y0 + g; ty < y1; ty += NT / CM_EPB) {
     uint32_t a, c;
-    cm_row_slots<MASKED>(tb, s_vb[t], s_vf[t], TXp, TX, ty, x0, x1, a, c);
+    cm_row_slots(tb, s_vb[t], s_vf[t], TXp, ty, x0, x1, a, c);
     for (uint32_t i = 0; i < c; ++i) atomicOr(&s_mask[a + i], 1ull << t);
   }
 }
 
 // The chunk's entries: index, rectangle and view bases (s_e, s_r, s_vb, s_vf).
-template <bool MASKED>
 __device__ __forceinline__ void cm_load_chunk(const uint32_t* __restrict__ order, const uint2* __restrict__ rect,
                                               const uint32_t* __restrict__ vfirst, uint32_t j0, uint32_t cnt,
-                                              uint32_t n, uint32_t TYp, uint32_t T, uint32_t* s_e, uint2* s_r,
-                                              uint32_t* s_vb, uint32_t* s_vf, uint2* rsort) {
+                                              uint32_t n, uint32_t TYp, uint32_t* s_e, uint2* s_r, uint32_t* s_vb,
+                                              uint32_t* s_vf) {
   if (threadIdx.x < cnt) {
     const uint32_t e = order[j0 + threadIdx.x];
     const uint32_t v = e / n;
     const uint2 r = rect[e];
     s_e[threadIdx.x] = e;
     s_r[threadIdx.x] = r;
-    s_vb[threadIdx.x] = MASKED ? v * TYp : v * T;
-    s_vf[threadIdx.x] = MASKED ? vfirst[v] : 0u;
-    if (rsort) rsort[j0 + threadIdx.x] = r;
+    s_vb[threadIdx.x] = v * TYp;
+    s_vf[threadIdx.x] = vfirst[v];
   }
 }
 
-template <bool MASKED>
 __global__ void __launch_bounds__(NT) cm_count_kernel(const uint32_t* __restrict__ order,
                                                       const uint2* __restrict__ rect,
                                                       const uint32_t* __restrict__ tab,
@@ -1045,7 +1038,7 @@ __global__ void __launch_bounds__(NT) cm_count_kernel(const uint32_t* __restrict
   __shared__ uint2 s_r[CM_EPB];
   uint32_t lo, m;
   slab_params(counters, which, sliced, lo, m);
-  const uint32_t S = counters[C_TILES];
+  const uint32_t S = counters[which == 1 ? C_TILES : C_ALIVE];
   const uint32_t nq = (m + CM_EPB - 1) / CM_EPB;
   const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
   order += lo;
@@ -1053,26 +1046,30 @@ __global__ void __launch_bounds__(NT) cm_count_kernel(const uint32_t* __restrict
     const uint32_t j0 = q * CM_EPB, cnt = min((uint32_t)CM_EPB, m - j0);
     __syncthreads();
     for (uint32_t s = threadIdx.x; s < S; s += NT) s_mask[s] = 0ull;
-    cm_load_chunk<MASKED>(order, rect, vfirst, j0, cnt, n, TYp, (uint32_t)(TX * TY), s_e, s_r, s_vb, s_vf, nullptr);
+    cm_load_chunk(order, rect, vfirst, j0, cnt, n, TYp, s_e, s_r, s_vb, s_vf);
     __syncthreads();
-    cm_build_masks<MASKED>(s_mask, s_r, s_vb, s_vf, cnt, tab, TXp, (uint32_t)TX);
+    cm_build_masks(s_mask, s_r, s_vb, s_vf, cnt, tab, TXp);
     __syncthreads();
     for (uint32_t s = threadIdx.x; s < S; s += NT) cm[(size_t)q * S + s] = (uint32_t)__popcll(s_mask[s]);
   }
 }
 
 // Column scan of the count matrix (nq rows of S): each column's exclusive prefix over the
-// rows in place, and its total -> tot[s].  A block takes CS_COLS columns; its CS_SEGS
-// row groups each sum a contiguous segment of rows (CS_BATCH loads in flight), the
-// segments' bases come from a scan in LDS, then each group rewrites its segment.
-constexpr int CS_COLS = 64, CS_SEGS = 16, CS_NT = CS_COLS * CS_SEGS, CS_BATCH = 8;
+// rows in place, and its total -> tot[s].  A block takes CS_COLS columns and splits the
+// rows into CS_SEGS contiguous segments, one thread per (segment, column) with the
+// columns fastest (coalesced row pieces): each thread sums its segment, the segment
+// sums are scanned per column in LDS (one wave pair per column), and each thread
+// rewrites its segment from its base.
+constexpr int CS_COLS = 8, CS_SEGS = 128, CS_NT = CS_COLS * CS_SEGS, CS_BATCH = 8;
 __global__ void __launch_bounds__(CS_NT) cm_scan_kernel(uint32_t* __restrict__ cm, const uint32_t* counters,
-                                                        uint32_t* __restrict__ tot) {
+                                                        int which, uint32_t* __restrict__ tot) {
   __shared__ uint32_t s_seg[CS_SEGS][CS_COLS];
-  const uint32_t m = counters[C_SLAB_N], S = counters[C_TILES];
-  const uint32_t nq = (m + CM_EPB - 1) / CM_EPB;
-  const uint32_t col = blockIdx.x * CS_COLS + (threadIdx.x % CS_COLS), seg = threadIdx.x / CS_COLS;
+  __shared__ uint32_t s_wave[CS_NT / 64];
+  const uint32_t m = counters[C_SLAB_N], S = counters[which == 1 ? C_TILES : C_ALIVE];
   if (blockIdx.x * CS_COLS >= S) return;
+  const uint32_t nq = (m + CM_EPB - 1) / CM_EPB;
+  const uint32_t c = threadIdx.x % CS_COLS, seg = threadIdx.x / CS_COLS;
+  const uint32_t col = blockIdx.x * CS_COLS + c;
   const bool ok = col < S;
   const uint32_t per = (nq + CS_SEGS - 1) / CS_SEGS;
   const uint32_t r0 = min(seg * per, nq), r1 = min(r0 + per, nq);
@@ -1084,12 +1081,25 @@ __global__ void __launch_bounds__(CS_NT) cm_scan_kernel(uint32_t* __restrict__ c
 #pragma unroll
     for (int u = 0; u < CS_BATCH; ++u) sum += x[u];
   }
-  s_seg[seg][threadIdx.x % CS_COLS] = sum;
+  s_seg[seg][c] = sum;
   __syncthreads();
-  uint32_t run = 0;
-  for (uint32_t k = 0; k < seg; ++k) run += s_seg[k][threadIdx.x % CS_COLS];
-  if (ok && seg == CS_SEGS - 1) tot[col] = run + sum;
+  {
+    // column-major pass: thread t scans segment t % CS_SEGS of column t / CS_SEGS
+    const uint32_t cc = threadIdx.x / CS_SEGS, sg = threadIdx.x % CS_SEGS;
+    const uint32_t v = s_seg[sg][cc];
+    const uint32_t inc = wave_incl_scan(v);
+    const uint32_t w = threadIdx.x >> 6;
+    if (lane_id() == 63) s_wave[w] = inc;
+    __syncthreads();
+    // the waves before this one within the column (CS_SEGS / 64 waves per column)
+    uint32_t carry = 0;
+    for (uint32_t k = cc * (CS_SEGS / 64); k < w; ++k) carry += s_wave[k];
+    s_seg[sg][cc] = carry + inc - v;  // exclusive base of the segment
+    if (sg == CS_SEGS - 1 && blockIdx.x * CS_COLS + cc < S) tot[blockIdx.x * CS_COLS + cc] = carry + inc;
+  }
+  __syncthreads();
   if (!ok) return;
+  uint32_t run = s_seg[seg][c];
   for (uint32_t r = r0; r < r1; r += CS_BATCH) {
     uint32_t x[CS_BATCH];
 #pragma unroll
@@ -1121,7 +1131,6 @@ __device__ __forceinline__ uint32_t kth_set_bit(unsigned long long m, uint32_t k
 // Emission by counting.  Dynamic LDS: the slots' masks (8 B each), then per slot its
 // first position plus this chunk's prefix (4 B) and the chunk's exclusive pair scan
 // (4 B, S + 1 words).
-template <bool MASKED>
 __global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict__ order,
                                                      const uint2* __restrict__ rect,
                                                      const uint32_t* __restrict__ tab,
@@ -1140,7 +1149,7 @@ __global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict_
     s_c[0] = counters[C_OVERFLOW];  // set when the first slab overflowed
     s_c[1] = counters[C_SLAB_N];
     s_c[2] = which == 1 ? 0u : counters[C_PAIRS1];
-    s_c[3] = counters[C_TILES];
+    s_c[3] = counters[which == 1 ? C_TILES : C_ALIVE];
   }
   __syncthreads();
   if (s_c[0]) return;
@@ -1171,7 +1180,7 @@ __global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict_
   if (blockIdx.x == 0 && which == 1) {
     for (uint32_t s = threadIdx.x; s < S; s += NT) {
       const uint32_t c = tot[s];
-      if (c) ranges[MASKED ? list[s] : s] = make_uint2(s_first[s], s_first[s] + c);
+      if (c) ranges[list[s]] = make_uint2(s_first[s], s_first[s] + c);
     }
   }
   const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
@@ -1180,9 +1189,9 @@ __global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict_
     const uint32_t j0 = q * CM_EPB, cnt = min((uint32_t)CM_EPB, m - j0);
     __syncthreads();
     for (uint32_t s = threadIdx.x; s < S; s += NT) s_mask[s] = 0ull;
-    cm_load_chunk<MASKED>(order, rect, vfirst, j0, cnt, n, TYp, (uint32_t)(TX * TY), s_e, s_r, s_vb, s_vf, nullptr);
+    cm_load_chunk(order, rect, vfirst, j0, cnt, n, TYp, s_e, s_r, s_vb, s_vf);
     __syncthreads();
-    cm_build_masks<MASKED>(s_mask, s_r, s_vb, s_vf, cnt, tab, TXp, (uint32_t)TX);
+    cm_build_masks(s_mask, s_r, s_vb, s_vf, cnt, tab, TXp);
     __syncthreads();
     // the chunk's pairs per slot, scanned: pair i of the chunk belongs to the slot s with
     // s_scan[s] <= i < s_scan[s + 1]
@@ -1209,7 +1218,7 @@ __global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict_
       const uint32_t s = lo, k = i - s_scan[s];
       const uint32_t j = kth_set_bit(s_mask[s], k);
       const uint32_t pos = s_first[s] + row[s] + k;
-      pk[pos] = MASKED ? list[s] : s;
+      pk[pos] = list[s];
       pv[pos] = s_e[j];
     }
   }
@@ -1424,35 +1433,29 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
   const int epb = which == 1 ? EMIT_EPB_NEAR : EMIT_EPB;
   // the most entries the slab can hold (the first slab of depth-sliced lists holds at
   // most max(E/16, 16384)); blocks loop beyond their grids
-  const int64_t slab_max = (which == 1 && bins.mode == CLSP_BINS_DEPTH_SLICED)
+  const int64_t slab_max = (which == 1 && bins.mode != CLSP_BINS_COMPLETE)
                                ? std::min<int64_t>(E, std::max<int64_t>(E >> 4, 16384))
                                : E;
   // counts and per-chunk pair counts, then the chunks' offsets (relative to the slab's
   // first pair) and the capacity check
-  const int sliced = bins.mode == CLSP_BINS_DEPTH_SLICED ? 1 : 0;
-  // first slab by counting placement: count, column scan, emission straight into tile
-  // order (with the ranges); no tile sort, no range scan
+  const int sliced = bins.mode != CLSP_BINS_COMPLETE ? 1 : 0;
+  // counting placement (the first slab, and the second of CLSP_BINS_DEPTH_SLICED_LOCAL
+  // lists) when the count matrix fits: count, column scan, emission straight into tile
+  // order (with the first slab's ranges); no tile sort, no range scan
   const int64_t gt = (int64_t)V * p.T;
   const int64_t nq_bound = (slab_max + CM_EPB - 1) / CM_EPB;
-  if (which == 1 && p.cm_words > 0 && nq_bound * gt <= p.cm_words) {
+  if (use_mask && p.cm_words > 0 && nq_bound * gt <= p.cm_words &&
+      (which == 1 || bins.mode == CLSP_BINS_DEPTH_SLICED_LOCAL)) {
     const int gq = (int)std::min<int64_t>(std::max<int64_t>(nq_bound, 1), 2048);
     const size_t lds_count = (size_t)gt * 8, lds_emit = (size_t)gt * 16 + 4;
-    if (use_mask)
-      hipLaunchKernelGGL((cm_count_kernel<true>), dim3(gq), dim3(NT), lds_count, s, order, rect, w.tab, w.vfirst,
-                         counters, 1, sliced, (uint32_t)n, p.TX, p.TY, w.cm);
-    else
-      hipLaunchKernelGGL((cm_count_kernel<false>), dim3(gq), dim3(NT), lds_count, s, order, rect, w.tab, w.vfirst,
-                         counters, 1, sliced, (uint32_t)n, p.TX, p.TY, w.cm);
+    const int slab_sliced = which == 1 ? sliced : 1;
+    hipLaunchKernelGGL(cm_count_kernel, dim3(gq), dim3(NT), lds_count, s, order, rect, w.tab, w.vfirst, counters,
+                       which, slab_sliced, (uint32_t)n, p.TX, p.TY, w.cm);
     hipLaunchKernelGGL(cm_scan_kernel, dim3((unsigned)((gt + CS_COLS - 1) / CS_COLS)), dim3(CS_NT), 0, s, w.cm,
-                       counters, w.ctot);
-    if (use_mask)
-      hipLaunchKernelGGL((cm_emit_kernel<true>), dim3(gq), dim3(NT), lds_emit, s, order, rect, w.tab, w.vfirst, mlist,
-                         w.cm, w.ctot, counters, 1, (uint32_t)n, p.TX, p.TY, (uint64_t)p.capacity, bins.keys,
-                         bins.values, reinterpret_cast<uint2*>(ranges));
-    else
-      hipLaunchKernelGGL((cm_emit_kernel<false>), dim3(gq), dim3(NT), lds_emit, s, order, rect, w.tab, w.vfirst,
-                         mlist, w.cm, w.ctot, counters, 1, (uint32_t)n, p.TX, p.TY, (uint64_t)p.capacity, bins.keys,
-                         bins.values, reinterpret_cast<uint2*>(ranges));
+                       counters, which, w.ctot);
+    hipLaunchKernelGGL(cm_emit_kernel, dim3(gq), dim3(NT), lds_emit, s, order, rect, w.tab, w.vfirst, mlist, w.cm,
+                       w.ctot, counters, which, (uint32_t)n, p.TX, p.TY, (uint64_t)p.capacity, bins.keys, bins.values,
+                       reinterpret_cast<uint2*>(ranges));
     return hipGetLastError();
   }
   if (which == 1 && !recount_first)
@@ -1539,13 +1542,13 @@ BinPlan make_bin_plan(int64_t n, int views, int W, int H, int64_t capacity) {
   p.off_vfirst = take((size_t)views * 4);
   p.off_tab = take((size_t)views * (p.TY + 1) * (p.TX + 1) * 4);
   p.off_rsort = take(E * 8);
-  // the count matrix of the first slab's counting placement (and its column totals),
-  // when the slab's chunks times the tiles fit the budget (sized for depth-sliced
-  // lists; complete lists use it when their larger slab fits too)
+  // the count matrix of the slabs' counting placement (and its column totals): sized
+  // for a slab of every entry when that fits the budget (then both slabs and complete
+  // lists use it), else for the depth-sliced first slab, else not at all
   {
     const int64_t slab1 = std::min<int64_t>(E, std::max<int64_t>(E >> 4, 16384));
-    const int64_t words = (slab1 + CM_EPB - 1) / CM_EPB * gt;
-    p.cm_words = (gt <= CM_MAX_SLOTS && words <= CM_MAX_WORDS) ? words : 0;
+    const int64_t w1 = (slab1 + CM_EPB - 1) / CM_EPB * gt, w2 = (E + CM_EPB - 1) / CM_EPB * gt;
+    p.cm_words = gt > CM_MAX_SLOTS ? 0 : (w2 <= CM_MAX_WORDS ? w2 : (w1 <= CM_MAX_WORDS ? w1 : 0));
     p.off_cm = take(p.cm_words > 0 ? (size_t)(p.cm_words + gt) * 4 : 4);
   }
   // per rendered tile slot: alive flag, and per pixel the carried compositing state

@@ -137,7 +137,7 @@ clsp_status check_bins(const clsp_bins* b) {
       !b->counters)
     return fail(CLSP_ERR_INVALID_ARG, "bins buffers missing");
   if (b->capacity < 0 || b->capacity > MAX_ENTRIES) return fail(CLSP_ERR_INVALID_ARG, "capacity not in 0..2^32-1");
-  if (b->mode != CLSP_BINS_COMPLETE && b->mode != CLSP_BINS_DEPTH_SLICED)
+  if (b->mode != CLSP_BINS_COMPLETE && b->mode != CLSP_BINS_DEPTH_SLICED && b->mode != CLSP_BINS_DEPTH_SLICED_LOCAL)
     return fail(CLSP_ERR_INVALID_ARG, "unknown bins mode %d", b->mode);
   if (b->n < 0) return fail(CLSP_ERR_INVALID_ARG, "bins n < 0");
   return CLSP_OK;

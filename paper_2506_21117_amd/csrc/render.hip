@@ -685,7 +685,7 @@ hipError_t launch_render_forward(const clsp_projected& proj, const clsp_bins& bi
   const L1Out l1{target, dL, loss_sum};
   const int T = TX * TY;
   const int blocks = views * T;
-  const int sliced = bins.mode == CLSP_BINS_DEPTH_SLICED;
+  const int sliced = bins.mode != CLSP_BINS_COMPLETE;
   const BinPlan plan = make_bin_plan(bins.n, views, W, H, bins.capacity);
   char* ws = static_cast<char*>(bins.ws);
   uint32_t* alive = bin_alive_flags(plan, ws);

@@ -100,7 +100,9 @@ class SplatOptimizer:
         del probe
         cap = int(need * headroom) + 1024
         if self.bins is None or self.bins.capacity < cap:
-            self.bins = api.BinBuffers.alloc(self.n, 1, W, H, cap, dev)
+            # local steps: few tiles need the second depth slab
+            mode = _ffi.BINS_DEPTH_SLICED_LOCAL if self.local else _ffi.BINS_DEPTH_SLICED
+            self.bins = api.BinBuffers.alloc(self.n, 1, W, H, cap, dev, mode)
         self.bins.counters.zero_()
         self._prepare_calls()
         return need

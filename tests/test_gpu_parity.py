@@ -314,7 +314,7 @@ def test_l1_loss_grad_exact(dev):
     assert abs(float(loss) - ref_loss) <= 1e-5 * ref_loss
 
 
-@pytest.mark.parametrize("mode", [COMPLETE, api._ffi.BINS_DEPTH_SLICED])
+@pytest.mark.parametrize("mode", [COMPLETE, api._ffi.BINS_DEPTH_SLICED, api._ffi.BINS_DEPTH_SLICED_LOCAL])
 @pytest.mark.parametrize("case,local", [("cloud", False), ("cloud", True), ("local", True)])
 def test_forward_with_l1_equals_forward_then_l1(dev, mode, case, local):
     """The forward's own L1 gradient (finished in the second phase for tiles that need
@@ -429,7 +429,7 @@ def _deep_scene():
     return sc, [cam]
 
 
-@pytest.mark.parametrize("mode", [COMPLETE, api._ffi.BINS_DEPTH_SLICED])
+@pytest.mark.parametrize("mode", [COMPLETE, api._ffi.BINS_DEPTH_SLICED, api._ffi.BINS_DEPTH_SLICED_LOCAL])
 def test_render_backward_deep_lists(dev, mode):
     """Lists far past CLSP_STATE_CHUNKS x CLSP_STATE_CHUNK entries: the forward merges the
     chunks of the compositing state and doubles their length, and the backward starts
@@ -734,16 +734,18 @@ def test_masked_adam_clears_gradients_when_asked(dev, with_mask):
 # ------------------------------------------------------------------ depth-sliced lists
 @pytest.mark.parametrize("case", ["tiny", "ring2", "local", "cloud"])
 @pytest.mark.parametrize("local", [False, True])
-def test_depth_sliced_lists_match_complete_lists(dev, case, local):
+@pytest.mark.parametrize("sliced_mode", [api._ffi.BINS_DEPTH_SLICED, api._ffi.BINS_DEPTH_SLICED_LOCAL])
+def test_depth_sliced_lists_match_complete_lists(dev, case, local, sliced_mode):
     """Every sliced list is a prefix of the complete list (the complete list itself for
     tiles that needed the second slab), and images, transmittance, contributor counts
-    are bit-identical; gradients agree up to float32 summation order."""
+    are bit-identical; gradients agree up to float32 summation order.  Both ways of
+    placing the second slab (sorted, or counted per tile)."""
     sc, cams, a = _sliced_case(case)
     act = a if local else None
     g = api.GaussianTensors.from_scene(sc, dev)
     proj = gpu_preprocess(g, cams)
     out = {}
-    for mode in (COMPLETE, api._ffi.BINS_DEPTH_SLICED):
+    for mode in (COMPLETE, sliced_mode):
         bins = api.bin_and_sort(proj, cams, act, local, capacity=8_000_000, mode=mode)
         state = api.render_state(cams, dev)
         img, T, nc = api.render_forward(proj, bins, cams, (0.1, 0.2, 0.3), state=state)
@@ -755,7 +757,7 @@ def test_depth_sliced_lists_match_complete_lists(dev, case, local):
         assert not c["overflow"]
         out[mode] = (bins, to_np(img), to_np(T), to_np(nc), grads, c)
     cb, ci, cT, cn, cg, cc = out[COMPLETE]
-    sb, si, sT, sn, sg, scn = out[api._ffi.BINS_DEPTH_SLICED]
+    sb, si, sT, sn, sg, scn = out[sliced_mode]
     np.testing.assert_array_equal(si, ci)
     np.testing.assert_array_equal(sT, cT)
     np.testing.assert_array_equal(sn, cn)
