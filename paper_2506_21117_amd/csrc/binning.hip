@@ -987,6 +987,19 @@ __global__ void __launch_bounds__(NT) emit_kernel(const uint32_t* __restrict__ o
 constexpr int CM_EPB = 64;                     // one bit per entry of a chunk
 constexpr int64_t CM_MAX_WORDS = 64ll << 20;   // count matrix budget (256 MB)
 constexpr int CM_MAX_SLOTS = 3840;             // the emission keeps 16 B per slot in LDS
+// With at most CM_SMALL_SLOTS slots (and a corner table of at most CM_TAB_WORDS) the
+// kernels also keep the corner table, and the emission the chunk's count-matrix row,
+// in LDS.
+constexpr int CM_SMALL_SLOTS = 1024;
+constexpr int CM_TAB_WORDS = 8192;
+__host__ __device__ inline size_t cm_count_lds(int64_t gt, int64_t tab_words) {
+  const size_t big = (size_t)gt * 8, small = (size_t)CM_SMALL_SLOTS * 8 + (size_t)tab_words * 4;
+  return tab_words <= CM_TAB_WORDS && small > big ? small : big;
+}
+__host__ __device__ inline size_t cm_emit_lds(int64_t gt, int64_t tab_words) {
+  const size_t big = (size_t)gt * 16 + 4, small = (size_t)CM_SMALL_SLOTS * 24 + 4 + (size_t)tab_words * 4;
+  return tab_words <= CM_TAB_WORDS && small > big ? small : big;
+}
 
 // Slots [a, a + c) of row ty of the rectangle [x0, x1): list positions of the row's set
 // tiles (vb: the view's first table row; vf: the view's first list position).
@@ -1027,30 +1040,58 @@ __device__ __forceinline__ void cm_load_chunk(const uint32_t* __restrict__ order
   }
 }
 
-__global__ void __launch_bounds__(NT) cm_count_kernel(const uint32_t* __restrict__ order,
-                                                      const uint2* __restrict__ rect,
-                                                      const uint32_t* __restrict__ tab,
-                                                      const uint32_t* __restrict__ vfirst, uint32_t* counters,
-                                                      int which, int sliced, uint32_t n, int TX, int TY,
-                                                      uint32_t* __restrict__ cm) {
-  extern __shared__ unsigned long long s_mask[];  // [S]
-  __shared__ uint32_t s_e[CM_EPB], s_vb[CM_EPB], s_vf[CM_EPB];
-  __shared__ uint2 s_r[CM_EPB];
-  uint32_t lo, m;
-  slab_params(counters, which, sliced, lo, m);
-  const uint32_t S = counters[which == 1 ? C_TILES : C_ALIVE];
+// (Copies the corner table into LDS.)
+__device__ __forceinline__ void cm_stage_table(uint32_t* s_tab, const uint32_t* __restrict__ tab, uint32_t words) {
+  for (uint32_t w0 = threadIdx.x; w0 < words; w0 += 4 * NT) {
+    uint32_t t[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) t[u] = w0 + u * NT < words ? tab[w0 + u * NT] : 0u;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (w0 + u * NT < words) s_tab[w0 + u * NT] = t[u];
+  }
+}
+
+template <bool STAGED>
+__device__ __forceinline__ void cm_count_chunks(unsigned long long* s_mask, const uint32_t* tb,
+                                                const uint32_t* __restrict__ order, const uint2* __restrict__ rect,
+                                                const uint32_t* __restrict__ vfirst, uint32_t m, uint32_t S,
+                                                uint32_t n, uint32_t TXp, uint32_t TYp, uint32_t* s_e, uint2* s_r,
+                                                uint32_t* s_vb, uint32_t* s_vf, uint32_t* __restrict__ cm) {
   const uint32_t nq = (m + CM_EPB - 1) / CM_EPB;
-  const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
-  order += lo;
   for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
     const uint32_t j0 = q * CM_EPB, cnt = min((uint32_t)CM_EPB, m - j0);
     __syncthreads();
     for (uint32_t s = threadIdx.x; s < S; s += NT) s_mask[s] = 0ull;
     cm_load_chunk(order, rect, vfirst, j0, cnt, n, TYp, s_e, s_r, s_vb, s_vf);
     __syncthreads();
-    cm_build_masks(s_mask, s_r, s_vb, s_vf, cnt, tab, TXp);
+    cm_build_masks(s_mask, s_r, s_vb, s_vf, cnt, tb, TXp);
     __syncthreads();
     for (uint32_t s = threadIdx.x; s < S; s += NT) cm[(size_t)q * S + s] = (uint32_t)__popcll(s_mask[s]);
+  }
+}
+
+__global__ void __launch_bounds__(NT) cm_count_kernel(const uint32_t* __restrict__ order,
+                                                      const uint2* __restrict__ rect,
+                                                      const uint32_t* __restrict__ tab,
+                                                      const uint32_t* __restrict__ vfirst, uint32_t* counters,
+                                                      int which, int sliced, uint32_t n, int TX, int TY,
+                                                      uint32_t tab_words, uint32_t* __restrict__ cm) {
+  extern __shared__ unsigned long long s_mask[];  // [S], then (small) the corner table
+  __shared__ uint32_t s_e[CM_EPB], s_vb[CM_EPB], s_vf[CM_EPB];
+  __shared__ uint2 s_r[CM_EPB];
+  uint32_t lo, m;
+  slab_params(counters, which, sliced, lo, m);
+  const uint32_t S = counters[which == 1 ? C_TILES : C_ALIVE];
+  const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
+  order += lo;
+  if (m == 0) return;
+  if (S <= CM_SMALL_SLOTS && tab_words <= CM_TAB_WORDS) {
+    uint32_t* s_tab = reinterpret_cast<uint32_t*>(s_mask + CM_SMALL_SLOTS);
+    cm_stage_table(s_tab, tab, tab_words);
+    cm_count_chunks<true>(s_mask, s_tab, order, rect, vfirst, m, S, n, TXp, TYp, s_e, s_r, s_vb, s_vf, cm);
+  } else {
+    cm_count_chunks<false>(s_mask, tab, order, rect, vfirst, m, S, n, TXp, TYp, s_e, s_r, s_vb, s_vf, cm);
   }
 }
 
@@ -1128,9 +1169,62 @@ __device__ __forceinline__ uint32_t kth_set_bit(unsigned long long m, uint32_t k
   return pos;
 }
 
-// Emission by counting.  Dynamic LDS: the slots' masks (8 B each), then per slot its
-// first position plus this chunk's prefix (4 B) and the chunk's exclusive pair scan
-// (4 B, S + 1 words).
+// Emission by counting.  Dynamic LDS: the slots' masks (8 B each), the slots' first
+// positions (4 B) and the chunk's exclusive pair scan (4 B, S + 1 words); with the
+// small layout (S <= CM_SMALL_SLOTS, arrays of CM_SMALL_SLOTS) also the chunk's
+// count-matrix row, the slots' tiles and the corner table.
+template <bool SMALL>
+__device__ __forceinline__ void cm_emit_chunks(unsigned long long* s_mask, uint32_t* s_first, uint32_t* s_scan,
+                                               uint32_t* s_row, const uint32_t* s_list, const uint32_t* tb,
+                                               const uint32_t* __restrict__ order, const uint2* __restrict__ rect,
+                                               const uint32_t* __restrict__ vfirst, const uint32_t* __restrict__ list,
+                                               const uint32_t* __restrict__ cm, uint32_t m, uint32_t S, uint32_t n,
+                                               uint32_t TXp, uint32_t TYp, uint32_t* s_e, uint2* s_r,
+                                               uint32_t* s_vb, uint32_t* s_vf, uint32_t* s4,
+                                               uint32_t* __restrict__ pk, uint32_t* __restrict__ pv) {
+  const uint32_t nq = (m + CM_EPB - 1) / CM_EPB;
+  for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+    const uint32_t j0 = q * CM_EPB, cnt = min((uint32_t)CM_EPB, m - j0);
+    const uint32_t* row = cm + (size_t)q * S;
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < S; s += NT) {
+      s_mask[s] = 0ull;
+      if (SMALL) s_row[s] = row[s];
+    }
+    cm_load_chunk(order, rect, vfirst, j0, cnt, n, TYp, s_e, s_r, s_vb, s_vf);
+    __syncthreads();
+    cm_build_masks(s_mask, s_r, s_vb, s_vf, cnt, tb, TXp);
+    __syncthreads();
+    // the chunk's pairs per slot, scanned: pair i of the chunk belongs to the slot s with
+    // s_scan[s] <= i < s_scan[s + 1]
+    uint32_t chunk_pairs;
+    {
+      const uint32_t per = (S + NT - 1) / NT, s0 = min(threadIdx.x * per, S), s1 = min(s0 + per, S);
+      uint32_t sum = 0;
+      for (uint32_t s = s0; s < s1; ++s) sum += (uint32_t)__popcll(s_mask[s]);
+      uint32_t run = block_excl_scan(sum, s4, chunk_pairs);
+      for (uint32_t s = s0; s < s1; ++s) {
+        s_scan[s] = run;
+        run += (uint32_t)__popcll(s_mask[s]);
+      }
+      if (threadIdx.x == 0) s_scan[S] = chunk_pairs;
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < chunk_pairs; i += NT) {
+      uint32_t lo = 0, hi = S;  // the last slot with s_scan[s] <= i
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_scan[mid] <= i) lo = mid; else hi = mid;
+      }
+      const uint32_t s = lo, k = i - s_scan[s];
+      const uint32_t j = kth_set_bit(s_mask[s], k);
+      const uint32_t pos = s_first[s] + (SMALL ? s_row[s] : row[s]) + k;
+      pk[pos] = SMALL ? s_list[s] : list[s];
+      pv[pos] = s_e[j];
+    }
+  }
+}
+
 __global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict__ order,
                                                      const uint2* __restrict__ rect,
                                                      const uint32_t* __restrict__ tab,
@@ -1138,8 +1232,9 @@ __global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict_
                                                      const uint32_t* __restrict__ list,
                                                      const uint32_t* __restrict__ cm, const uint32_t* __restrict__ tot,
                                                      uint32_t* __restrict__ counters, int which, uint32_t n, int TX,
-                                                     int TY, uint64_t capacity, uint32_t* __restrict__ pk,
-                                                     uint32_t* __restrict__ pv, uint2* __restrict__ ranges) {
+                                                     int TY, uint32_t tab_words, uint64_t capacity,
+                                                     uint32_t* __restrict__ pk, uint32_t* __restrict__ pv,
+                                                     uint2* __restrict__ ranges) {
   extern __shared__ unsigned long long s_mask[];
   __shared__ uint32_t s_e[CM_EPB], s_vb[CM_EPB], s_vf[CM_EPB];
   __shared__ uint2 s_r[CM_EPB];
@@ -1154,9 +1249,13 @@ __global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict_
   __syncthreads();
   if (s_c[0]) return;
   const uint32_t m = s_c[1], S = s_c[3];
-  uint32_t* s_first = reinterpret_cast<uint32_t*>(s_mask + S);  // first position of the slot's run
-  uint32_t* s_scan = s_first + S;                                // [S + 1]
-  const uint32_t nq = (m + CM_EPB - 1) / CM_EPB;
+  const bool small = S <= CM_SMALL_SLOTS && tab_words <= CM_TAB_WORDS;
+  const uint32_t SA = small ? (uint32_t)CM_SMALL_SLOTS : S;       // array length of the layout
+  uint32_t* s_first = reinterpret_cast<uint32_t*>(s_mask + SA);  // first position of the slot's run
+  uint32_t* s_scan = s_first + SA;                               // [S + 1]
+  uint32_t* s_row = s_scan + SA + 1;                             // small: the chunk's count-matrix row
+  uint32_t* s_list = s_row + SA;                                 // small: the slots' tiles
+  uint32_t* s_tab = s_list + SA;                                 // small: the corner table
   const uint32_t base = s_c[2];
   // the tiles' first positions: an exclusive scan of the column totals (runs of
   // consecutive slots per thread), after the pairs of earlier slabs
@@ -1185,45 +1284,17 @@ __global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict_
   }
   const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
   order += counters[C_SLAB_LO];
-  for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
-    const uint32_t j0 = q * CM_EPB, cnt = min((uint32_t)CM_EPB, m - j0);
-    __syncthreads();
-    for (uint32_t s = threadIdx.x; s < S; s += NT) s_mask[s] = 0ull;
-    cm_load_chunk(order, rect, vfirst, j0, cnt, n, TYp, s_e, s_r, s_vb, s_vf);
-    __syncthreads();
-    cm_build_masks(s_mask, s_r, s_vb, s_vf, cnt, tab, TXp);
-    __syncthreads();
-    // the chunk's pairs per slot, scanned: pair i of the chunk belongs to the slot s with
-    // s_scan[s] <= i < s_scan[s + 1]
-    uint32_t chunk_pairs;
-    {
-      const uint32_t per = (S + NT - 1) / NT, s0 = min(threadIdx.x * per, S), s1 = min(s0 + per, S);
-      uint32_t sum = 0;
-      for (uint32_t s = s0; s < s1; ++s) sum += (uint32_t)__popcll(s_mask[s]);
-      uint32_t run = block_excl_scan(sum, s4, chunk_pairs);
-      for (uint32_t s = s0; s < s1; ++s) {
-        s_scan[s] = run;
-        run += (uint32_t)__popcll(s_mask[s]);
-      }
-      if (threadIdx.x == 0) s_scan[S] = chunk_pairs;
-    }
-    __syncthreads();
-    const uint32_t* row = cm + (size_t)q * S;
-    for (uint32_t i = threadIdx.x; i < chunk_pairs; i += NT) {
-      uint32_t lo = 0, hi = S;  // the last slot with s_scan[s] <= i
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_scan[mid] <= i) lo = mid; else hi = mid;
-      }
-      const uint32_t s = lo, k = i - s_scan[s];
-      const uint32_t j = kth_set_bit(s_mask[s], k);
-      const uint32_t pos = s_first[s] + row[s] + k;
-      pk[pos] = list[s];
-      pv[pos] = s_e[j];
-    }
+  if ((uint64_t)blockIdx.x * CM_EPB >= m) return;
+  if (small) {
+    cm_stage_table(s_tab, tab, tab_words);
+    for (uint32_t s2 = threadIdx.x; s2 < S; s2 += NT) s_list[s2] = list[s2];
+    cm_emit_chunks<true>(s_mask, s_first, s_scan, s_row, s_list, s_tab, order, rect, vfirst, list, cm, m, S, n, TXp,
+                         TYp, s_e, s_r, s_vb, s_vf, s4, pk, pv);
+  } else {
+    cm_emit_chunks<false>(s_mask, s_first, s_scan, s_row, nullptr, tab, order, rect, vfirst, list, cm, m, S, n, TXp,
+                          TYp, s_e, s_r, s_vb, s_vf, s4, pk, pv);
   }
 }
-
 
 // ------------------------------------------------------------------ 7. ranges, tile list
 // [start, end) of each tile's run among the slab's sorted pairs (absolute positions).
@@ -1247,6 +1318,7 @@ __global__ void __launch_bounds__(NT) ranges_kernel(const uint32_t* __restrict__
 constexpr int MI_NT = 1024;
 constexpr int MI_ITEMS = 4;
 constexpr int MI_TAB_WORDS = 12288;  // corner tables up to 48 KB are built in LDS
+constexpr int MI_MASK_WORDS = 2048;  // masks up to 8 KB are kept in LDS
 
 __global__ void __launch_bounds__(MI_NT) mask_index_kernel(const uint32_t* __restrict__ mask, int views, int wpv,
                                                            int TX, int TY, uint32_t* __restrict__ wpre,
@@ -1259,7 +1331,9 @@ __global__ void __launch_bounds__(MI_NT) mask_index_kernel(const uint32_t* __res
   const int T = TX * TY;
   __shared__ uint32_t s_w[MI_NT / 64];
   __shared__ uint32_t s_carry;
+  __shared__ uint32_t s_words[MI_MASK_WORDS];  // the mask, when it fits, for the corner table
   const uint32_t nw = (uint32_t)views * (uint32_t)wpv;
+  const bool lds_mask = nw <= MI_MASK_WORDS;
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
   for (uint32_t base = 0; base < nw; base += MI_NT * MI_ITEMS) {
@@ -1285,6 +1359,7 @@ __global__ void __launch_bounds__(MI_NT) mask_index_kernel(const uint32_t* __res
     for (int k = 0; k < MI_ITEMS; ++k) {
       const uint32_t idx = base + threadIdx.x * MI_ITEMS + k;
       if (idx < nw) {
+        if (lds_mask) s_words[idx] = wd[k];
         wpre[idx] = run;
         const uint32_t v = idx / (uint32_t)wpv, t0 = (idx % (uint32_t)wpv) * 32u;
         for (uint32_t bits = wd[k]; bits; bits &= bits - 1u) list[run++] = v * (uint32_t)T + t0 + (__ffs(bits) - 1u);
@@ -1305,17 +1380,29 @@ __global__ void __launch_bounds__(MI_NT) mask_index_kernel(const uint32_t* __res
   const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
   const uint32_t words = (uint32_t)views * TYp * TXp;
   uint32_t* tb = lds_tab ? s_tab : tab;
+  const uint32_t* mk = lds_mask ? s_words : mask;
   for (uint32_t i = threadIdx.x; i < words; i += MI_NT) {
     const uint32_t x = i % TXp, row = i / TXp, v = row / TYp, ty = row % TYp;
-    tb[i] = ty == 0 ? 0u : count_bits(mask + (size_t)v * wpv, (ty - 1) * TX, (ty - 1) * TX + x);
+    tb[i] = ty == 0 ? 0u : count_bits(mk + (size_t)v * wpv, (ty - 1) * TX, (ty - 1) * TX + x);
   }
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < (uint32_t)views * TXp; i += MI_NT) {
-    uint32_t* col = tb + (size_t)(i / TXp) * TYp * TXp + i % TXp;
-    uint32_t acc = 0;
-    for (uint32_t ty = 1; ty < TYp; ++ty) {
-      acc += col[(size_t)ty * TXp];
-      col[(size_t)ty * TXp] = acc;
+  if (TYp <= 64) {
+    // running sums down each column: one wave per column, a lane per row
+    const uint32_t lane = lane_id();
+    for (uint32_t i = threadIdx.x >> 6; i < (uint32_t)views * TXp; i += MI_NT / 64) {
+      uint32_t* col = tb + (size_t)(i / TXp) * TYp * TXp + i % TXp;
+      const uint32_t x = lane < TYp ? col[(size_t)lane * TXp] : 0u;
+      const uint32_t inc = wave_incl_scan(x);
+      if (lane < TYp) col[(size_t)lane * TXp] = inc;
+    }
+  } else {
+    for (uint32_t i = threadIdx.x; i < (uint32_t)views * TXp; i += MI_NT) {
+      uint32_t* col = tb + (size_t)(i / TXp) * TYp * TXp + i % TXp;
+      uint32_t acc = 0;
+      for (uint32_t ty = 1; ty < TYp; ++ty) {
+        acc += col[(size_t)ty * TXp];
+        col[(size_t)ty * TXp] = acc;
+      }
     }
   }
   if (lds_tab) {
@@ -1447,15 +1534,16 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
   if (use_mask && p.cm_words > 0 && nq_bound * gt <= p.cm_words &&
       (which == 1 || bins.mode == CLSP_BINS_DEPTH_SLICED_LOCAL)) {
     const int gq = (int)std::min<int64_t>(std::max<int64_t>(nq_bound, 1), 2048);
-    const size_t lds_count = (size_t)gt * 8, lds_emit = (size_t)gt * 16 + 4;
+    const uint32_t tab_words = (uint32_t)(V * (p.TY + 1) * (p.TX + 1));
+    const size_t lds_count = cm_count_lds(gt, tab_words), lds_emit = cm_emit_lds(gt, tab_words);
     const int slab_sliced = which == 1 ? sliced : 1;
     hipLaunchKernelGGL(cm_count_kernel, dim3(gq), dim3(NT), lds_count, s, order, rect, w.tab, w.vfirst, counters,
-                       which, slab_sliced, (uint32_t)n, p.TX, p.TY, w.cm);
+                       which, slab_sliced, (uint32_t)n, p.TX, p.TY, tab_words, w.cm);
     hipLaunchKernelGGL(cm_scan_kernel, dim3((unsigned)((gt + CS_COLS - 1) / CS_COLS)), dim3(CS_NT), 0, s, w.cm,
                        counters, which, w.ctot);
     hipLaunchKernelGGL(cm_emit_kernel, dim3(gq), dim3(NT), lds_emit, s, order, rect, w.tab, w.vfirst, mlist, w.cm,
-                       w.ctot, counters, which, (uint32_t)n, p.TX, p.TY, (uint64_t)p.capacity, bins.keys, bins.values,
-                       reinterpret_cast<uint2*>(ranges));
+                       w.ctot, counters, which, (uint32_t)n, p.TX, p.TY, tab_words, (uint64_t)p.capacity, bins.keys,
+                       bins.values, reinterpret_cast<uint2*>(ranges));
     return hipGetLastError();
   }
   if (which == 1 && !recount_first)
