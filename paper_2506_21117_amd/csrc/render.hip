@@ -17,7 +17,6 @@ namespace {
 
 constexpr int NT = TILE_PIX;
 constexpr int C_OVERFLOW = 1, C_TILES = 2, C_ALIVE = 8, C_SLAB_PAIRS = 11, C_SLAB_BASE = 12;
-constexpr int FW_UNROLL = 8;  // records whose weights the forward computes together
 
 // Opacity of a record at a pixel centre, evaluated with explicitly rounded operations
 // so the forward and the backward take the same decisions bit for bit.
@@ -146,7 +145,13 @@ struct L1Out {
 // alive tiles with their second lists from that state.  Chunk boundaries (every CH
 // list positions) and all arithmetic are the same as in one pass over the whole list,
 // so the outputs are identical bit for bit.
-template <int PHASE>
+// Records whose weights the forward computes together: 8, or 16 for the lists of the
+// optimiser's local steps, where few tiles are rendered and each wave's own
+// instruction-level parallelism sets the pace (the larger group costs registers, and so
+// occupancy, which full renders need).
+constexpr int FW_GROUP = 8, FW_GROUP_LOCAL = 16;
+
+template <int PHASE, int FW_UNROLL>
 __global__ void __launch_bounds__(NT) render_forward_kernel(
     const float* __restrict__ splat, const uint32_t* __restrict__ values, const uint32_t* __restrict__ pair_keys,
     const uint2* __restrict__ ranges, uint2* __restrict__ ranges2, const uint32_t* __restrict__ tile_list,
@@ -691,17 +696,24 @@ hipError_t launch_render_forward(const clsp_projected& proj, const clsp_bins& bi
   uint32_t* alive = bin_alive_flags(plan, ws);
   float* carry = bin_carry(plan, ws);
   const int wpv = (T + 31) / 32;
-  hipLaunchKernelGGL(render_forward_kernel<1>, dim3(blocks), dim3(NT), 0, s, proj.splat, bins.values, bins.keys,
-                     reinterpret_cast<const uint2*>(bins.ranges), reinterpret_cast<uint2*>(bins.ranges2),
-                     bins.tile_list, bins.counters, T, TX, W, H, bg[0], bg[1], bg[2], image, T_final, n_contrib, state,
-                     (int64_t)blocks, sliced, alive, bins.alive_mask, wpv, carry, l1);
+  auto phase = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(NT), 0, s, proj.splat, bins.values, bins.keys,
+                       reinterpret_cast<const uint2*>(bins.ranges), reinterpret_cast<uint2*>(bins.ranges2),
+                       bins.tile_list, bins.counters, T, TX, W, H, bg[0], bg[1], bg[2], image, T_final, n_contrib,
+                       state, (int64_t)blocks, sliced, alive, bins.alive_mask, wpv, carry, l1);
+  };
+  const bool local = bins.mode == CLSP_BINS_DEPTH_SLICED_LOCAL;
+  if (local)
+    phase(render_forward_kernel<1, FW_GROUP_LOCAL>);
+  else
+    phase(render_forward_kernel<1, FW_GROUP>);
   if (!sliced) return hipGetLastError();
   hipError_t err = launch_list_second_slab(plan, proj, bins, ws, s);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(render_forward_kernel<2>, dim3(blocks), dim3(NT), 0, s, proj.splat, bins.values, bins.keys,
-                     reinterpret_cast<const uint2*>(bins.ranges), reinterpret_cast<uint2*>(bins.ranges2),
-                     bins.tile_list, bins.counters, T, TX, W, H, bg[0], bg[1], bg[2], image, T_final, n_contrib, state,
-                     (int64_t)blocks, sliced, alive, bins.alive_mask, wpv, carry, l1);
+  if (local)
+    phase(render_forward_kernel<2, FW_GROUP_LOCAL>);
+  else
+    phase(render_forward_kernel<2, FW_GROUP>);
   return hipGetLastError();
 }
 
