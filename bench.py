@@ -263,8 +263,8 @@ def main():
 # They describe the kernels whose sources hash to `source_sha256` and are reported only
 # while the sources still do (profiles/traffic_local_step_1M_1280x720.txt).
 MEASURED_TRAFFIC = {
-    "source_sha256": "171cb670aee557305448be97f9289e5be7b5ea5629b3e3f1f12e5c60690cb3be",
-    "bytes": {"bin_and_sort": 154.160e6, "render_forward": 18.245e6, "render_backward": 17.585e6},
+    "source_sha256": "6b1057319bb3fd8b4d0386a9190ee6ae9f485febbe0f83341a3747bb353edc06",
+    "bytes": {"bin_and_sort": 85.921e6, "render_forward": 18.103e6, "render_backward": 17.590e6},
 }
 
 
@@ -530,7 +530,7 @@ def cpu_single_thread(sc, cams, a, scene_gt, order, log):
 # A step of this script's timed loop starts at preprocess_kernel and ends with the Adam
 # update: adam_kernel (full steps), or preprocess_backward_adam_kernel, which holds it
 # (local steps).  Within it the C-ABI calls are: bin_and_sort = the kernels after
-# preprocess_kernel up to the first render_forward_kernel<1>; render_forward = that one
+# preprocess_kernel up to the first phase-1 forward kernel; render_forward = that one
 # up to the last render_forward_kernel (the second depth slab's listing runs between the
 # two phases; local steps compute the L1 gradient inside the forward); render_backward =
 # the kernels after l1_loss_grad_kernel (or after the forward) up to the preprocess
@@ -558,7 +558,7 @@ def split_steps(seq, k):
         st = st[:ends[0] + 1]
         names = names[:len(st)]
         try:
-            i_f1 = names.index("render_forward_kernel<1>")
+            i_f1 = next(i for i, nm in enumerate(names) if nm.startswith("render_forward_kernel<1"))
             i_f2 = max(i for i, nm in enumerate(names) if nm.startswith("render_forward_kernel"))
             i_l1 = names.index("l1_loss_grad_kernel") if "l1_loss_grad_kernel" in names else i_f2
             i_pb = max(i for i, nm in enumerate(names) if nm.startswith("preprocess_backward"))
