@@ -992,6 +992,7 @@ constexpr int CM_MAX_SLOTS = 3840;             // the emission keeps 16 B per sl
 // in LDS.
 constexpr int CM_SMALL_SLOTS = 1024;
 constexpr int CM_TAB_WORDS = 8192;
+constexpr int CM_PAIR_ROUND = 2048;  // a chunk's pairs placed at once by the small-layout emission (16-bit words in LDS)
 __host__ __device__ inline size_t cm_count_lds(int64_t gt, int64_t tab_words) {
   const size_t big = (size_t)gt * 8, small = (size_t)CM_SMALL_SLOTS * 8 + (size_t)tab_words * 4;
   return tab_words <= CM_TAB_WORDS && small > big ? small : big;
@@ -1180,7 +1181,7 @@ __device__ __forceinline__ void cm_emit_chunks(unsigned long long* s_mask, uint3
                                                const uint32_t* __restrict__ vfirst, const uint32_t* __restrict__ list,
                                                const uint32_t* __restrict__ cm, uint32_t m, uint32_t S, uint32_t n,
                                                uint32_t TXp, uint32_t TYp, uint32_t* s_e, uint2* s_r,
-                                               uint32_t* s_vb, uint32_t* s_vf, uint32_t* s4,
+                                               uint32_t* s_vb, uint32_t* s_vf, uint32_t* s4, uint16_t* s_pair,
                                                uint32_t* __restrict__ pk, uint32_t* __restrict__ pv) {
   const uint32_t nq = (m + CM_EPB - 1) / CM_EPB;
   for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
@@ -1209,18 +1210,49 @@ __device__ __forceinline__ void cm_emit_chunks(unsigned long long* s_mask, uint3
       }
       if (threadIdx.x == 0) s_scan[S] = chunk_pairs;
     }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < chunk_pairs; i += NT) {
-      uint32_t lo = 0, hi = S;  // the last slot with s_scan[s] <= i
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_scan[mid] <= i) lo = mid; else hi = mid;
+    if (SMALL) {
+      // pair i of the chunk, in rounds of CM_PAIR_ROUND: first each slot's thread writes
+      // (slot, entry) of the slot's pairs in the round (its mask's set bits in order)
+      // into s_pair, then every thread stores pairs i, i + NT, ... (consecutive pairs
+      // of a slot go to consecutive positions)
+      for (uint32_t r0 = 0; r0 < chunk_pairs; r0 += CM_PAIR_ROUND) {
+        const uint32_t r1 = min(chunk_pairs, r0 + (uint32_t)CM_PAIR_ROUND);
+        __syncthreads();
+        for (uint32_t s = threadIdx.x; s < S; s += NT) {
+          const uint32_t i0 = max(s_scan[s], r0), i1 = min(s_scan[s + 1], r1);
+          if (i0 >= i1) continue;
+          unsigned long long msk = s_mask[s];
+          // drop the slot's pairs before the round
+          const uint32_t skip = i0 - s_scan[s];
+          if (skip) msk &= ~0ull << kth_set_bit(msk, skip);
+          for (uint32_t i = i0; i < i1; ++i) {
+            const uint32_t j = (uint32_t)__ffsll(msk) - 1u;
+            msk &= msk - 1ull;
+            s_pair[i - r0] = (uint16_t)((s << 6) | j);
+          }
+        }
+        __syncthreads();
+        for (uint32_t i = r0 + threadIdx.x; i < r1; i += NT) {
+          const uint32_t wd = s_pair[i - r0], s = wd >> 6, j = wd & 63u;
+          const uint32_t pos = s_first[s] + s_row[s] + (i - s_scan[s]);
+          pk[pos] = s_list[s];
+          pv[pos] = s_e[j];
+        }
       }
-      const uint32_t s = lo, k = i - s_scan[s];
-      const uint32_t j = kth_set_bit(s_mask[s], k);
-      const uint32_t pos = s_first[s] + (SMALL ? s_row[s] : row[s]) + k;
-      pk[pos] = SMALL ? s_list[s] : list[s];
-      pv[pos] = s_e[j];
+    } else {
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < chunk_pairs; i += NT) {
+        uint32_t lo = 0, hi = S;  // the last slot with s_scan[s] <= i
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (s_scan[mid] <= i) lo = mid; else hi = mid;
+        }
+        const uint32_t s = lo, k = i - s_scan[s];
+        const uint32_t j = kth_set_bit(s_mask[s], k);
+        const uint32_t pos = s_first[s] + row[s] + k;
+        pk[pos] = list[s];
+        pv[pos] = s_e[j];
+      }
     }
   }
 }
@@ -1240,6 +1272,7 @@ __global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict_
   __shared__ uint2 s_r[CM_EPB];
   __shared__ uint32_t s4[4];
   __shared__ uint32_t s_c[4];
+  __shared__ uint16_t s_pair[CM_PAIR_ROUND];
   if (threadIdx.x == 0) {
     s_c[0] = counters[C_OVERFLOW];  // set when the first slab overflowed
     s_c[1] = counters[C_SLAB_N];
@@ -1289,10 +1322,10 @@ __global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict_
     cm_stage_table(s_tab, tab, tab_words);
     for (uint32_t s2 = threadIdx.x; s2 < S; s2 += NT) s_list[s2] = list[s2];
     cm_emit_chunks<true>(s_mask, s_first, s_scan, s_row, s_list, s_tab, order, rect, vfirst, list, cm, m, S, n, TXp,
-                         TYp, s_e, s_r, s_vb, s_vf, s4, pk, pv);
+                         TYp, s_e, s_r, s_vb, s_vf, s4, s_pair, pk, pv);
   } else {
     cm_emit_chunks<false>(s_mask, s_first, s_scan, s_row, nullptr, tab, order, rect, vfirst, list, cm, m, S, n, TXp,
-                          TYp, s_e, s_r, s_vb, s_vf, s4, pk, pv);
+                          TYp, s_e, s_r, s_vb, s_vf, s4, s_pair, pk, pv);
   }
 }
 
