@@ -1058,7 +1058,8 @@ __device__ __forceinline__ void cm_count_chunks(unsigned long long* s_mask, cons
                                                 const uint32_t* __restrict__ order, const uint2* __restrict__ rect,
                                                 const uint32_t* __restrict__ vfirst, uint32_t m, uint32_t S,
                                                 uint32_t n, uint32_t TXp, uint32_t TYp, uint32_t* s_e, uint2* s_r,
-                                                uint32_t* s_vb, uint32_t* s_vf, uint32_t* __restrict__ cm) {
+                                                uint32_t* s_vb, uint32_t* s_vf, uint32_t* __restrict__ cm,
+                                                unsigned long long* __restrict__ cmask) {
   const uint32_t nq = (m + CM_EPB - 1) / CM_EPB;
   for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
     const uint32_t j0 = q * CM_EPB, cnt = min((uint32_t)CM_EPB, m - j0);
@@ -1068,7 +1069,11 @@ __device__ __forceinline__ void cm_count_chunks(unsigned long long* s_mask, cons
     __syncthreads();
     cm_build_masks(s_mask, s_r, s_vb, s_vf, cnt, tb, TXp);
     __syncthreads();
-    for (uint32_t s = threadIdx.x; s < S; s += NT) cm[(size_t)q * S + s] = (uint32_t)__popcll(s_mask[s]);
+    for (uint32_t s = threadIdx.x; s < S; s += NT) {
+      const unsigned long long msk = s_mask[s];
+      cm[(size_t)q * S + s] = (uint32_t)__popcll(msk);
+      if (cmask) cmask[(size_t)q * S + s] = msk;
+    }
   }
 }
 
@@ -1077,7 +1082,8 @@ __global__ void __launch_bounds__(NT) cm_count_kernel(const uint32_t* __restrict
                                                       const uint32_t* __restrict__ tab,
                                                       const uint32_t* __restrict__ vfirst, uint32_t* counters,
                                                       int which, int sliced, uint32_t n, int TX, int TY,
-                                                      uint32_t tab_words, uint32_t* __restrict__ cm) {
+                                                      uint32_t tab_words, uint32_t* __restrict__ cm,
+                                                      unsigned long long* __restrict__ cmask) {
   extern __shared__ unsigned long long s_mask[];  // [S], then (small) the corner table
   __shared__ uint32_t s_e[CM_EPB], s_vb[CM_EPB], s_vf[CM_EPB];
   __shared__ uint2 s_r[CM_EPB];
@@ -1090,9 +1096,9 @@ __global__ void __launch_bounds__(NT) cm_count_kernel(const uint32_t* __restrict
   if (S <= CM_SMALL_SLOTS && tab_words <= CM_TAB_WORDS) {
     uint32_t* s_tab = reinterpret_cast<uint32_t*>(s_mask + CM_SMALL_SLOTS);
     cm_stage_table(s_tab, tab, tab_words);
-    cm_count_chunks<true>(s_mask, s_tab, order, rect, vfirst, m, S, n, TXp, TYp, s_e, s_r, s_vb, s_vf, cm);
+    cm_count_chunks<true>(s_mask, s_tab, order, rect, vfirst, m, S, n, TXp, TYp, s_e, s_r, s_vb, s_vf, cm, cmask);
   } else {
-    cm_count_chunks<false>(s_mask, tab, order, rect, vfirst, m, S, n, TXp, TYp, s_e, s_r, s_vb, s_vf, cm);
+    cm_count_chunks<false>(s_mask, tab, order, rect, vfirst, m, S, n, TXp, TYp, s_e, s_r, s_vb, s_vf, cm, cmask);
   }
 }
 
@@ -1182,20 +1188,27 @@ __device__ __forceinline__ void cm_emit_chunks(unsigned long long* s_mask, uint3
                                                const uint32_t* __restrict__ cm, uint32_t m, uint32_t S, uint32_t n,
                                                uint32_t TXp, uint32_t TYp, uint32_t* s_e, uint2* s_r,
                                                uint32_t* s_vb, uint32_t* s_vf, uint32_t* s4, uint16_t* s_pair,
-                                               uint32_t* __restrict__ pk, uint32_t* __restrict__ pv) {
+                                               uint32_t* __restrict__ pk, uint32_t* __restrict__ pv,
+                                               const unsigned long long* __restrict__ cmask) {
   const uint32_t nq = (m + CM_EPB - 1) / CM_EPB;
   for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
     const uint32_t j0 = q * CM_EPB, cnt = min((uint32_t)CM_EPB, m - j0);
     const uint32_t* row = cm + (size_t)q * S;
     __syncthreads();
+    // the chunk's tile masks: kept by the count pass, or built again from the rectangles
     for (uint32_t s = threadIdx.x; s < S; s += NT) {
-      s_mask[s] = 0ull;
+      s_mask[s] = cmask ? cmask[(size_t)q * S + s] : 0ull;
       if (SMALL) s_row[s] = row[s];
     }
-    cm_load_chunk(order, rect, vfirst, j0, cnt, n, TYp, s_e, s_r, s_vb, s_vf);
-    __syncthreads();
-    cm_build_masks(s_mask, s_r, s_vb, s_vf, cnt, tb, TXp);
-    __syncthreads();
+    if (cmask) {
+      if (threadIdx.x < cnt) s_e[threadIdx.x] = order[j0 + threadIdx.x];
+      __syncthreads();
+    } else {
+      cm_load_chunk(order, rect, vfirst, j0, cnt, n, TYp, s_e, s_r, s_vb, s_vf);
+      __syncthreads();
+      cm_build_masks(s_mask, s_r, s_vb, s_vf, cnt, tb, TXp);
+      __syncthreads();
+    }
     // the chunk's pairs per slot, scanned: pair i of the chunk belongs to the slot s with
     // s_scan[s] <= i < s_scan[s + 1]
     uint32_t chunk_pairs;
@@ -1266,7 +1279,8 @@ __global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict_
                                                      uint32_t* __restrict__ counters, int which, uint32_t n, int TX,
                                                      int TY, uint32_t tab_words, uint64_t capacity,
                                                      uint32_t* __restrict__ pk, uint32_t* __restrict__ pv,
-                                                     uint2* __restrict__ ranges) {
+                                                     uint2* __restrict__ ranges,
+                                                     const unsigned long long* __restrict__ cmask) {
   extern __shared__ unsigned long long s_mask[];
   __shared__ uint32_t s_e[CM_EPB], s_vb[CM_EPB], s_vf[CM_EPB];
   __shared__ uint2 s_r[CM_EPB];
@@ -1319,13 +1333,13 @@ __global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict_
   order += counters[C_SLAB_LO];
   if ((uint64_t)blockIdx.x * CM_EPB >= m) return;
   if (small) {
-    cm_stage_table(s_tab, tab, tab_words);
+    if (!cmask) cm_stage_table(s_tab, tab, tab_words);
     for (uint32_t s2 = threadIdx.x; s2 < S; s2 += NT) s_list[s2] = list[s2];
     cm_emit_chunks<true>(s_mask, s_first, s_scan, s_row, s_list, s_tab, order, rect, vfirst, list, cm, m, S, n, TXp,
-                         TYp, s_e, s_r, s_vb, s_vf, s4, s_pair, pk, pv);
+                         TYp, s_e, s_r, s_vb, s_vf, s4, s_pair, pk, pv, cmask);
   } else {
     cm_emit_chunks<false>(s_mask, s_first, s_scan, s_row, nullptr, tab, order, rect, vfirst, list, cm, m, S, n, TXp,
-                          TYp, s_e, s_r, s_vb, s_vf, s4, s_pair, pk, pv);
+                          TYp, s_e, s_r, s_vb, s_vf, s4, s_pair, pk, pv, cmask);
   }
 }
 
@@ -1500,6 +1514,7 @@ int passes_for(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
 struct WsPtrs {
   uint32_t *cnt, *tmp, *keyA, *valA, *keyB, *valB, *blk, *hist, *dtot, *pairK, *pairV, *wpre, *tlist, *vfirst, *tab;
   uint32_t *cm, *ctot;
+  unsigned long long* cmask;
   uint2* rsort;
 };
 
@@ -1523,6 +1538,7 @@ WsPtrs carve(const BinPlan& p, char* ws) {
   w.rsort = reinterpret_cast<uint2*>(ws + p.off_rsort);
   w.cm = p.cm_words > 0 ? reinterpret_cast<uint32_t*>(ws + p.off_cm) : nullptr;
   w.ctot = w.cm ? w.cm + p.cm_words : nullptr;
+  w.cmask = p.cmask_words > 0 ? reinterpret_cast<unsigned long long*>(ws + p.off_cmask) : nullptr;
   return w;
 }
 
@@ -1570,13 +1586,15 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
     const uint32_t tab_words = (uint32_t)(V * (p.TY + 1) * (p.TX + 1));
     const size_t lds_count = cm_count_lds(gt, tab_words), lds_emit = cm_emit_lds(gt, tab_words);
     const int slab_sliced = which == 1 ? sliced : 1;
+    // the first slab's tile masks pass from the count to the emission when they fit
+    unsigned long long* cmask = which == 1 && w.cmask && nq_bound * gt <= p.cmask_words ? w.cmask : nullptr;
     hipLaunchKernelGGL(cm_count_kernel, dim3(gq), dim3(NT), lds_count, s, order, rect, w.tab, w.vfirst, counters,
-                       which, slab_sliced, (uint32_t)n, p.TX, p.TY, tab_words, w.cm);
+                       which, slab_sliced, (uint32_t)n, p.TX, p.TY, tab_words, w.cm, cmask);
     hipLaunchKernelGGL(cm_scan_kernel, dim3((unsigned)((gt + CS_COLS - 1) / CS_COLS)), dim3(CS_NT), 0, s, w.cm,
                        counters, which, w.ctot);
     hipLaunchKernelGGL(cm_emit_kernel, dim3(gq), dim3(NT), lds_emit, s, order, rect, w.tab, w.vfirst, mlist, w.cm,
                        w.ctot, counters, which, (uint32_t)n, p.TX, p.TY, tab_words, (uint64_t)p.capacity, bins.keys,
-                       bins.values, reinterpret_cast<uint2*>(ranges));
+                       bins.values, reinterpret_cast<uint2*>(ranges), cmask);
     return hipGetLastError();
   }
   if (which == 1 && !recount_first)
@@ -1671,6 +1689,9 @@ BinPlan make_bin_plan(int64_t n, int views, int W, int H, int64_t capacity) {
     const int64_t w1 = (slab1 + CM_EPB - 1) / CM_EPB * gt, w2 = (E + CM_EPB - 1) / CM_EPB * gt;
     p.cm_words = gt > CM_MAX_SLOTS ? 0 : (w2 <= CM_MAX_WORDS ? w2 : (w1 <= CM_MAX_WORDS ? w1 : 0));
     p.off_cm = take(p.cm_words > 0 ? (size_t)(p.cm_words + gt) * 4 : 4);
+    // the count pass's tile masks of the depth-sliced first slab, kept for its emission
+    p.cmask_words = p.cm_words > 0 && w1 <= CM_MAX_WORDS ? w1 : 0;
+    p.off_cmask = take(p.cmask_words > 0 ? (size_t)p.cmask_words * 8 : 8);
   }
   // per rendered tile slot: alive flag, and per pixel the carried compositing state
   p.off_alive = take(gt * 4);

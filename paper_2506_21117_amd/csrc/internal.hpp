@@ -102,6 +102,8 @@ struct BinPlan {
   size_t off_cnt, off_flag, off_keyA, off_valA, off_keyB, off_valB, off_scanBlk, off_hist, off_digit,
       off_pairK, off_pairV, off_tflag, off_vfirst, off_tab, off_rsort, off_cm, off_alive, off_carry, total;
   int64_t cm_words;   // count matrix of the first slab's counting placement (0: not used)
+  size_t off_cmask;
+  int64_t cmask_words;  // the depth-sliced first slab's tile masks per (chunk, slot), 64-bit (0: not kept)
   int scan_blocks;
   int sort_blocks_gauss, sort_blocks_pairs;
 };
