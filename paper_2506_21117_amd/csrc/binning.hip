@@ -992,6 +992,7 @@ constexpr int CM_MAX_SLOTS = 3840;             // the emission keeps 16 B per sl
 // in LDS.
 constexpr int CM_SMALL_SLOTS = 1024;
 constexpr int CM_TAB_WORDS = 8192;
+constexpr int64_t CM_MASK_WORDS = 8ll << 20;  // kept tile masks (64-bit words): 64 MB
 constexpr int CM_PAIR_ROUND = 2048;  // a chunk's pairs placed at once by the small-layout emission (16-bit words in LDS)
 __host__ __device__ inline size_t cm_count_lds(int64_t gt, int64_t tab_words) {
   const size_t big = (size_t)gt * 8, small = (size_t)CM_SMALL_SLOTS * 8 + (size_t)tab_words * 4;
@@ -1083,13 +1084,14 @@ __global__ void __launch_bounds__(NT) cm_count_kernel(const uint32_t* __restrict
                                                       const uint32_t* __restrict__ vfirst, uint32_t* counters,
                                                       int which, int sliced, uint32_t n, int TX, int TY,
                                                       uint32_t tab_words, uint32_t* __restrict__ cm,
-                                                      unsigned long long* __restrict__ cmask) {
+                                                      unsigned long long* __restrict__ cmask, uint64_t cmask_words) {
   extern __shared__ unsigned long long s_mask[];  // [S], then (small) the corner table
   __shared__ uint32_t s_e[CM_EPB], s_vb[CM_EPB], s_vf[CM_EPB];
   __shared__ uint2 s_r[CM_EPB];
   uint32_t lo, m;
   slab_params(counters, which, sliced, lo, m);
   const uint32_t S = counters[which == 1 ? C_TILES : C_ALIVE];
+  if ((uint64_t)((m + CM_EPB - 1) / CM_EPB) * S > cmask_words) cmask = nullptr;
   const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
   order += lo;
   if (m == 0) return;
@@ -1280,7 +1282,8 @@ __global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict_
                                                      int TY, uint32_t tab_words, uint64_t capacity,
                                                      uint32_t* __restrict__ pk, uint32_t* __restrict__ pv,
                                                      uint2* __restrict__ ranges,
-                                                     const unsigned long long* __restrict__ cmask) {
+                                                     const unsigned long long* __restrict__ cmask,
+                                                     uint64_t cmask_words) {
   extern __shared__ unsigned long long s_mask[];
   __shared__ uint32_t s_e[CM_EPB], s_vb[CM_EPB], s_vf[CM_EPB];
   __shared__ uint2 s_r[CM_EPB];
@@ -1296,6 +1299,8 @@ __global__ void __launch_bounds__(NT) cm_emit_kernel(const uint32_t* __restrict_
   __syncthreads();
   if (s_c[0]) return;
   const uint32_t m = s_c[1], S = s_c[3];
+  // (the count pass kept the masks under the same condition)
+  if ((uint64_t)((m + CM_EPB - 1) / CM_EPB) * S > cmask_words) cmask = nullptr;
   const bool small = S <= CM_SMALL_SLOTS && tab_words <= CM_TAB_WORDS;
   const uint32_t SA = small ? (uint32_t)CM_SMALL_SLOTS : S;       // array length of the layout
   uint32_t* s_first = reinterpret_cast<uint32_t*>(s_mask + SA);  // first position of the slot's run
@@ -1586,15 +1591,16 @@ hipError_t list_slab(const BinPlan& p, const clsp_projected& proj, const clsp_bi
     const uint32_t tab_words = (uint32_t)(V * (p.TY + 1) * (p.TX + 1));
     const size_t lds_count = cm_count_lds(gt, tab_words), lds_emit = cm_emit_lds(gt, tab_words);
     const int slab_sliced = which == 1 ? sliced : 1;
-    // the first slab's tile masks pass from the count to the emission when they fit
-    unsigned long long* cmask = which == 1 && w.cmask && nq_bound * gt <= p.cmask_words ? w.cmask : nullptr;
+    // the tile masks pass from the count to the emission when the slab's fit
+    unsigned long long* cmask = w.cmask;
+    const uint64_t cmw = (uint64_t)p.cmask_words;
     hipLaunchKernelGGL(cm_count_kernel, dim3(gq), dim3(NT), lds_count, s, order, rect, w.tab, w.vfirst, counters,
-                       which, slab_sliced, (uint32_t)n, p.TX, p.TY, tab_words, w.cm, cmask);
+                       which, slab_sliced, (uint32_t)n, p.TX, p.TY, tab_words, w.cm, cmask, cmw);
     hipLaunchKernelGGL(cm_scan_kernel, dim3((unsigned)((gt + CS_COLS - 1) / CS_COLS)), dim3(CS_NT), 0, s, w.cm,
                        counters, which, w.ctot);
     hipLaunchKernelGGL(cm_emit_kernel, dim3(gq), dim3(NT), lds_emit, s, order, rect, w.tab, w.vfirst, mlist, w.cm,
                        w.ctot, counters, which, (uint32_t)n, p.TX, p.TY, tab_words, (uint64_t)p.capacity, bins.keys,
-                       bins.values, reinterpret_cast<uint2*>(ranges), cmask);
+                       bins.values, reinterpret_cast<uint2*>(ranges), cmask, cmw);
     return hipGetLastError();
   }
   if (which == 1 && !recount_first)
@@ -1689,8 +1695,9 @@ BinPlan make_bin_plan(int64_t n, int views, int W, int H, int64_t capacity) {
     const int64_t w1 = (slab1 + CM_EPB - 1) / CM_EPB * gt, w2 = (E + CM_EPB - 1) / CM_EPB * gt;
     p.cm_words = gt > CM_MAX_SLOTS ? 0 : (w2 <= CM_MAX_WORDS ? w2 : (w1 <= CM_MAX_WORDS ? w1 : 0));
     p.off_cm = take(p.cm_words > 0 ? (size_t)(p.cm_words + gt) * 4 : 4);
-    // the count pass's tile masks of the depth-sliced first slab, kept for its emission
-    p.cmask_words = p.cm_words > 0 && w1 <= CM_MAX_WORDS ? w1 : 0;
+    // the count pass's tile masks, kept for the emission when a slab's chunks x slots
+    // fit (decided on the device by both kernels alike)
+    p.cmask_words = p.cm_words > 0 ? std::min<int64_t>(p.cm_words, CM_MASK_WORDS) : 0;
     p.off_cmask = take(p.cmask_words > 0 ? (size_t)p.cmask_words * 8 : 8);
   }
   // per rendered tile slot: alive flag, and per pixel the carried compositing state
