@@ -1413,6 +1413,7 @@ __global__ void __launch_bounds__(MI_NT) mask_index_kernel(const uint32_t* __res
       if (idx < nw) {
         if (lds_mask) s_words[idx] = wd[k];
         wpre[idx] = run;
+        if (idx % (uint32_t)wpv == 0u) vfirst[idx / (uint32_t)wpv] = run;  // a view's first word
         const uint32_t v = idx / (uint32_t)wpv, t0 = (idx % (uint32_t)wpv) * 32u;
         for (uint32_t bits = wd[k]; bits; bits &= bits - 1u) list[run++] = v * (uint32_t)T + t0 + (__ffs(bits) - 1u);
       }
@@ -1426,7 +1427,6 @@ __global__ void __launch_bounds__(MI_NT) mask_index_kernel(const uint32_t* __res
     if (count_out) *count_out = s_carry;
   }
   __syncthreads();
-  for (int v = threadIdx.x; v < views; v += MI_NT) vfirst[v] = wpre[(uint32_t)v * wpv];
   // corner table, built in LDS when it fits (lds_tab): first each row's prefix counts
   // (all rows in parallel), then running sums down each column
   const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
