@@ -1427,27 +1427,29 @@ __global__ void __launch_bounds__(MI_NT) mask_index_kernel(const uint32_t* __res
     if (count_out) *count_out = s_carry;
   }
   __syncthreads();
-  // corner table, built in LDS when it fits (lds_tab): first each row's prefix counts
-  // (all rows in parallel), then running sums down each column
+  // corner table, built in LDS when it fits (lds_tab): each row's prefix counts summed
+  // down each column
   const uint32_t TXp = (uint32_t)TX + 1, TYp = (uint32_t)TY + 1;
   const uint32_t words = (uint32_t)views * TYp * TXp;
   uint32_t* tb = lds_tab ? s_tab : tab;
   const uint32_t* mk = lds_mask ? s_words : mask;
-  for (uint32_t i = threadIdx.x; i < words; i += MI_NT) {
-    const uint32_t x = i % TXp, row = i / TXp, v = row / TYp, ty = row % TYp;
-    tb[i] = ty == 0 ? 0u : count_bits(mk + (size_t)v * wpv, (ty - 1) * TX, (ty - 1) * TX + x);
-  }
-  __syncthreads();
   if (TYp <= 64) {
-    // running sums down each column: one wave per column, a lane per row
+    // one wave per column x, a lane per table row: each lane counts the set bits of its
+    // row left of x, and a wave scan sums them down the column
     const uint32_t lane = lane_id();
     for (uint32_t i = threadIdx.x >> 6; i < (uint32_t)views * TXp; i += MI_NT / 64) {
-      uint32_t* col = tb + (size_t)(i / TXp) * TYp * TXp + i % TXp;
-      const uint32_t x = lane < TYp ? col[(size_t)lane * TXp] : 0u;
-      const uint32_t inc = wave_incl_scan(x);
-      if (lane < TYp) col[(size_t)lane * TXp] = inc;
+      const uint32_t v = i / TXp, x = i % TXp;
+      const uint32_t c = lane >= 1 && lane < TYp ? count_bits(mk + (size_t)v * wpv, (lane - 1) * TX, (lane - 1) * TX + x)
+                                                 : 0u;
+      const uint32_t inc = wave_incl_scan(c);
+      if (lane < TYp) tb[((size_t)v * TYp + lane) * TXp + x] = inc;
     }
   } else {
+    for (uint32_t i = threadIdx.x; i < words; i += MI_NT) {
+      const uint32_t x = i % TXp, row = i / TXp, v = row / TYp, ty = row % TYp;
+      tb[i] = ty == 0 ? 0u : count_bits(mk + (size_t)v * wpv, (ty - 1) * TX, (ty - 1) * TX + x);
+    }
+    __syncthreads();
     for (uint32_t i = threadIdx.x; i < (uint32_t)views * TXp; i += MI_NT) {
       uint32_t* col = tb + (size_t)(i / TXp) * TYp * TXp + i % TXp;
       uint32_t acc = 0;
