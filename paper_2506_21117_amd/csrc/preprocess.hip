@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(256) preprocess_kernel(RawParams g, DevCam cam
 // log_scales[3], quats[4], opacity, sh[3K] (sh coefficient k of channel ch is
 // 11 + 3k + ch); components without a gradient (invisible, clamped channel, no
 // screen-space gradient) are not handed over.
-template <class Put>
+template <int KD = -1, class Put>
 __device__ __forceinline__ void backward_row(const RawParams& g, const DevCam& cam, int view, int64_t i, int64_t a0,
                                              int64_t a1, const uint32_t* __restrict__ flags,
                                              const float* __restrict__ grad2d, Put put) {
@@ -275,7 +275,9 @@ __device__ __forceinline__ void backward_row(const RawParams& g, const DevCam& c
   Geo q;
   load_geo(g, row, cam, q);
   const int64_t nr = g.n_rows;
-  const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+  // (KD: the SH degree when the caller fixes it at compile time, so that every component
+  // index handed to put is a constant)
+  const int K = KD >= 0 ? (KD + 1) * (KD + 1) : (g.sh_degree + 1) * (g.sh_degree + 1);
 
   float dmu[3] = {0.f, 0.f, 0.f};
 
@@ -407,64 +409,61 @@ __global__ void __launch_bounds__(128) preprocess_backward_kernel(RawParams g, D
 
 // The same for a single view, followed by one Adam step of the row with those
 // gradients (the rest zero), exactly as zeroed gradients + the kernel above + the Adam
-// kernel would do it.
-__global__ void __launch_bounds__(128) preprocess_backward_adam_kernel(RawParams g, DevCam cam, int64_t a0,
-                                                                       int64_t a1, const uint32_t* __restrict__ flags,
-                                                                       const float* __restrict__ grad2d, FusedAdam A) {
-  const int64_t i = a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// kernel would do it.  D: the SH degree.  The row's gradients are collected first (every
+// component index a constant), then every component gets the same Adam update, sixteen
+// at a time with their moments and parameters all read before any is written (the
+// arrays may alias as far as the compiler knows); the first sixteen are read before the
+// gradients are computed, together with the step's skip flag and count.
+template <int D>
+__device__ __forceinline__ void backward_adam_row(const RawParams& g, const DevCam& cam, int64_t a0, int64_t a1,
+                                                  const uint32_t* __restrict__ flags,
+                                                  const float* __restrict__ grad2d, const FusedAdam& A, int64_t i) {
+  constexpr int C = 11 + 3 * (D + 1) * (D + 1), G = 16, G0 = C < G ? C : G;
+  float m0[G0], v0[G0], p0[G0];
+#pragma unroll
+  for (int c = 0; c < G0; ++c) {
+    m0[c] = *param_comp(A.M, c, i);
+    v0[c] = *param_comp(A.V, c, i);
+    p0[c] = *param_comp(A.P, c, i);
+  }
   // a step whose lists ran out of pair capacity updates nothing (the raster backward
   // wrote no gradient either, so the workspace is still zero)
-  if (i >= a1 || (A.skip && *A.skip)) return;
+  if (A.skip && *A.skip) return;
   float bc1 = A.bc1, bc2 = A.bc2;
   if (A.step_dev) {
     const float t = (float)max(*A.step_dev, 1);
     bc1 = 1.0f - powf(A.b1, t);
     bc2 = 1.0f - powf(A.b2, t);
   }
-  auto step = [&](int c, float gg) {
+  float gr[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) gr[c] = 0.0f;
+  // the gradient as the separate calls see it: 0 + v
+  backward_row<D>(g, cam, 0, i, a0, a1, flags, grad2d, [&](int c, float v) { gr[c] = 0.0f + v; });
+  auto update = [&](int c, float m, float v, float p, float gg) {
     const int grp = c < 3 ? 0 : c < 6 ? 1 : c < 10 ? 2 : c == 10 ? 3 : c < 14 ? 4 : 5;
-    float* m = param_comp(A.M, c, i);
-    float* v = param_comp(A.V, c, i);
-    float* p = param_comp(A.P, c, i);
-    const float mm = A.b1 * (*m) + (1.0f - A.b1) * gg;
-    const float vv = A.b2 * (*v) + (1.0f - A.b2) * gg * gg;
-    *m = mm;
-    *v = vv;
-    *p -= A.lr[grp] * (mm / bc1) / (sqrtf(vv / bc2) + A.eps);
+    const float mm = A.b1 * m + (1.0f - A.b1) * gg;
+    const float vv = A.b2 * v + (1.0f - A.b2) * gg * gg;
+    *param_comp(A.M, c, i) = mm;
+    *param_comp(A.V, c, i) = vv;
+    *param_comp(A.P, c, i) = p - A.lr[grp] * (mm / bc1) / (sqrtf(vv / bc2) + A.eps);
   };
-  uint64_t got = 0;  // components updated with their gradient
-  backward_row(g, cam, 0, i, a0, a1, flags, grad2d, [&](int c, float v) {
-    step(c, 0.0f + v);  // the gradient as the separate calls see it: 0 + v
-    got |= 1ull << c;
-  });
-  // the components without a gradient, sixteen at a time: their moments and parameters
-  // are all read before any is written (the arrays may alias as far as the compiler
-  // knows, so a write in between would order every later read after it)
-  const int C = 11 + 3 * (A.P.sh_degree + 1) * (A.P.sh_degree + 1);
-  for (int c0 = 0; c0 < C; c0 += 16) {
-    float mv[16], vv[16], pv[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int c = c0 + u;
-      if (c < C && !((got >> c) & 1ull)) {
-        mv[u] = *param_comp(A.M, c, i);
-        vv[u] = *param_comp(A.V, c, i);
-        pv[u] = *param_comp(A.P, c, i);
+  for (int c = 0; c < G0; ++c) update(c, m0[c], v0[c], p0[c], gr[c]);
+#pragma unroll
+  for (int c0 = G; c0 < C; c0 += G) {
+    float mv[G], vv[G], pv[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      if (c0 + u < C) {
+        mv[u] = *param_comp(A.M, c0 + u, i);
+        vv[u] = *param_comp(A.V, c0 + u, i);
+        pv[u] = *param_comp(A.P, c0 + u, i);
       }
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int c = c0 + u;
-      if (c < C && !((got >> c) & 1ull)) {
-        const int grp = c < 3 ? 0 : c < 6 ? 1 : c < 10 ? 2 : c == 10 ? 3 : c < 14 ? 4 : 5;
-        const float gg = 0.0f;
-        const float mm = A.b1 * mv[u] + (1.0f - A.b1) * gg;
-        const float v2 = A.b2 * vv[u] + (1.0f - A.b2) * gg * gg;
-        *param_comp(A.M, c, i) = mm;
-        *param_comp(A.V, c, i) = v2;
-        *param_comp(A.P, c, i) = pv[u] - A.lr[grp] * (mm / bc1) / (sqrtf(v2 / bc2) + A.eps);
-      }
-    }
+    for (int u = 0; u < G; ++u)
+      if (c0 + u < C) update(c0 + u, mv[u], vv[u], pv[u], gr[c0 + u]);
   }
   // leave the row's screen-space gradient zero for the next call, which then needs no
   // clearing launch (rows never reached here were never written)
@@ -473,6 +472,19 @@ __global__ void __launch_bounds__(128) preprocess_backward_adam_kernel(RawParams
   gp[0] = z;
   gp[1] = z;
   gp[2] = z;
+}
+
+__global__ void __launch_bounds__(128) preprocess_backward_adam_kernel(RawParams g, DevCam cam, int64_t a0,
+                                                                       int64_t a1, const uint32_t* __restrict__ flags,
+                                                                       const float* __restrict__ grad2d, FusedAdam A) {
+  const int64_t i = a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a1) return;
+  switch (A.P.sh_degree) {
+    case 0: backward_adam_row<0>(g, cam, a0, a1, flags, grad2d, A, i); break;
+    case 1: backward_adam_row<1>(g, cam, a0, a1, flags, grad2d, A, i); break;
+    case 2: backward_adam_row<2>(g, cam, a0, a1, flags, grad2d, A, i); break;
+    default: backward_adam_row<3>(g, cam, a0, a1, flags, grad2d, A, i); break;
+  }
 }
 
 }  // namespace
