@@ -263,8 +263,8 @@ def main():
 # They describe the kernels whose sources hash to `source_sha256` and are reported only
 # while the sources still do (profiles/traffic_local_step_1M_1280x720.txt).
 MEASURED_TRAFFIC = {
-    "source_sha256": "39cfb8570784fa34a9a107b3a6bff7d65f4c0aa29ed45533234bb2b27d827618",
-    "bytes": {"bin_and_sort": 84.570e6, "render_forward": 18.102e6, "render_backward": 17.590e6},
+    "source_sha256": "d36dc28e2258052340991f3f96ed608cdeb8cc838d6f7d257352a46a26c7da2e",
+    "bytes": {"bin_and_sort": 84.568e6, "render_forward": 18.099e6, "render_backward": 17.452e6},
 }
 
 
