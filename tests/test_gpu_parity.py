@@ -213,6 +213,32 @@ def test_bin_and_sort_many_tile_bits(dev):
         _check_bins(bins, proj, cams, (3000, 4000), use_mask)
 
 
+@pytest.mark.parametrize("mode", [COMPLETE, api._ffi.BINS_DEPTH_SLICED, api._ffi.BINS_DEPTH_SLICED_LOCAL])
+def test_counting_placement_with_more_than_1024_masked_tiles(dev, mode):
+    """One 1280x720 view whose render mask covers more than 1 024 of its 3 600 tiles: the
+    counting placement's layout for that many tile slots (masks and scans without the
+    LDS copies of the corner table), against the reference bit for bit, and complete
+    and depth-sliced lists giving the same image."""
+    w = scenes.full_scene(n=4000, n_views=1, res=960, fx=1320.0)
+    cams = [scenes.Camera(c.R, c.t, 1280, 1280, 640, 360, 1280, 720) for c in w.cameras]
+    g = api.GaussianTensors.from_scene(w.scene, dev)
+    proj = gpu_preprocess(g, cams)
+    active = (1000, 4000)
+    bins = api.bin_and_sort(proj, cams, active, True, capacity=2_000_000, mode=mode)
+    img, T, nc = api.render_forward(proj, bins, cams)
+    torch.cuda.synchronize()
+    c = bins.read_counters()
+    assert c["tiles"] > 1024, c["tiles"]
+    if mode == COMPLETE:
+        _check_bins(bins, proj, cams, active, True)
+    else:
+        ref = api.bin_and_sort(proj, cams, active, True, capacity=2_000_000, mode=COMPLETE)
+        img_c, T_c, nc_c = api.render_forward(proj, ref, cams)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(to_np(img), to_np(img_c))
+        np.testing.assert_array_equal(to_np(nc), to_np(nc_c))
+
+
 def test_capacity_overflow_is_reported_and_recoverable(dev):
     sc, cams = workload("tiny")
     g = api.GaussianTensors.from_scene(sc, dev)
