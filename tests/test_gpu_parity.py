@@ -239,6 +239,30 @@ def test_counting_placement_with_more_than_1024_masked_tiles(dev, mode):
         np.testing.assert_array_equal(to_np(nc), to_np(nc_c))
 
 
+def test_counting_placement_without_kept_masks(dev):
+    """A slab whose chunks x tile slots exceed the kept-mask budget (over 150 000 entries
+    of one view, all in the first slab of complete lists, over more than 3 000 tiles:
+    2 344 x 3 600 > 8 Mi words) makes the emission build its tile masks again: its image
+    and contributor counts equal those of depth-sliced lists, whose first slab keeps its
+    masks."""
+    w = scenes.full_scene(n=350_000, n_views=1, res=960, fx=1320.0)
+    cams = [scenes.Camera(c.R, c.t, 1280, 1280, 640, 360, 1280, 720) for c in w.cameras]
+    g = api.GaussianTensors.from_scene(w.scene, dev)
+    proj = gpu_preprocess(g, cams)
+    out = []
+    for mode in (COMPLETE, api._ffi.BINS_DEPTH_SLICED):
+        bins = api.bin_and_sort(proj, cams, (0, 350_000), True, capacity=60_000_000, mode=mode)
+        img, T, nc = api.render_forward(proj, bins, cams)
+        torch.cuda.synchronize()
+        c = bins.read_counters()
+        assert not c["overflow"] and c["tiles"] > 3000
+        out.append((to_np(img), to_np(nc), c))
+    c0 = out[0][2]
+    assert ((c0["entries"] + 63) // 64) * c0["tiles"] > 8 << 20, c0
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
 def test_capacity_overflow_is_reported_and_recoverable(dev):
     sc, cams = workload("tiny")
     g = api.GaussianTensors.from_scene(sc, dev)
