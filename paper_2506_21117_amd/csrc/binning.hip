@@ -38,6 +38,7 @@ constexpr int RS_ITEMS = 4;                 // keys per thread per chunk
 constexpr int RS_CHUNK = NT * RS_ITEMS;     // 1024 keys staged in LDS per chunk
 constexpr int RS_WAVE_SPAN = 64 * RS_ITEMS; // consecutive keys one wave ranks per chunk
 constexpr int MAX_SORT_BLOCKS = 2048;
+constexpr int RS_RAW_BLOCKS = 64;  // sorts of at most this many blocks skip the digit-scan launch
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_CHUNK = NT * SCAN_ITEMS;
 constexpr int MAX_SCAN_BLOCKS = 1024;
@@ -507,7 +508,7 @@ __device__ __forceinline__ int rs_blocks(uint32_t n, int G) {
 // Digit histogram of each block's span: hist[d * Ge + b], Ge = rs_blocks(n, G).
 __global__ void __launch_bounds__(NT) rs_upsweep_kernel(const uint32_t* __restrict__ keys, const uint32_t* n_ptr,
                                                         const uint32_t* off_ptr, int shift, int bits,
-                                                        uint32_t* __restrict__ hist, int G) {
+                                                        uint32_t* __restrict__ hist, int G, int raw) {
   __shared__ uint32_t h[4][256];
   const uint32_t n = *n_ptr;
   const int Ge = rs_blocks(n, G);
@@ -534,7 +535,10 @@ __global__ void __launch_bounds__(NT) rs_upsweep_kernel(const uint32_t* __restri
     for (int u = 0; u < RS_ITEMS; ++u) k[u] = e0 + u * NT < end ? keys[e0 + u * NT] : 0u;
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < radix; d += NT) hist[(int64_t)d * Ge + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+  // digit-major for the scan kernel; block-major (raw) for a downsweep that reads every
+  // block's counts itself
+  for (int d = threadIdx.x; d < radix; d += NT)
+    hist[raw ? (int64_t)blockIdx.x * radix + d : (int64_t)d * Ge + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
 // Block d: exclusive scan over blocks of digit d's counts; digit total -> tot[d].
@@ -564,6 +568,7 @@ __global__ void __launch_bounds__(NT) rs_scan_kernel(uint32_t* __restrict__ hist
 // Stable scatter of each block's span.  Each wave ranks RS_WAVE_SPAN consecutive keys with
 // ballot-based digit matching; the block then stages the chunk in LDS ordered by digit
 // and writes every digit's run contiguously.
+template <bool RAW>
 __global__ void __launch_bounds__(NT) rs_downsweep_kernel(const uint32_t* __restrict__ kin,
                                                           const uint32_t* __restrict__ vin,
                                                           uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -608,11 +613,29 @@ __global__ void __launch_bounds__(NT) rs_downsweep_kernel(const uint32_t* __rest
       val[it] = e < end ? vin[e] : 0u;
     }
     if (c == beg) {
-      // the global base of each digit for this block, while the first loads are in flight
-      const uint32_t t = tid < radix ? tot[tid] : 0u;
+      // the global base of each digit for this block, while the first loads are in flight:
+      // from the digit totals and the scanned block counts, or (raw: a sort of at most
+      // RS_RAW_BLOCKS blocks, no scan launch) from the upsweep's counts of every block
+      uint32_t t = 0, before = 0;
+      if (tid < radix) {
+        if (RAW) {
+          // (block-major counts: coalesced, all in flight together)
+          uint32_t x[RS_RAW_BLOCKS];
+#pragma unroll
+          for (int b = 0; b < RS_RAW_BLOCKS; ++b) x[b] = b < G ? hist[(int64_t)b * radix + tid] : 0u;
+#pragma unroll
+          for (int b = 0; b < RS_RAW_BLOCKS; ++b) {
+            t += x[b];
+            before += b < (int)blockIdx.x ? x[b] : 0u;
+          }
+        } else {
+          t = tot[tid];
+          before = hist[(int64_t)tid * G + blockIdx.x];
+        }
+      }
       uint32_t all;
       const uint32_t ex = block_excl_scan(t, s4, all);
-      if (tid < radix) s_base[tid] = ex + hist[(int64_t)tid * G + blockIdx.x];
+      if (tid < radix) s_base[tid] = ex + before;
     }
     for (int d = tid; d < 4 * 256; d += NT) (&s_wcnt[0][0])[d] = 0;
     __syncthreads();
@@ -1506,10 +1529,16 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uin
     uint32_t* vi = cur ? v1 : v0;
     uint32_t* ko = cur ? k0 : k1;
     uint32_t* vo = cur ? v0 : v1;
-    hipLaunchKernelGGL(rs_upsweep_kernel, dim3(G), dim3(NT), 0, s, ki, n_ptr, off_ptr, shift, bits, hist, G);
-    hipLaunchKernelGGL(rs_scan_kernel, dim3(1 << bits), dim3(NT), 0, s, hist, n_ptr, G, tot);
-    hipLaunchKernelGGL(rs_downsweep_kernel, dim3(G), dim3(NT), 0, s, ki, vi, ko, vo, n_ptr, off_ptr, shift, bits, hist,
-                       tot, G);
+    // few blocks: the downsweep sums the block counts itself (one launch fewer per pass)
+    const int raw = G <= RS_RAW_BLOCKS ? 1 : 0;
+    hipLaunchKernelGGL(rs_upsweep_kernel, dim3(G), dim3(NT), 0, s, ki, n_ptr, off_ptr, shift, bits, hist, G, raw);
+    if (!raw) hipLaunchKernelGGL(rs_scan_kernel, dim3(1 << bits), dim3(NT), 0, s, hist, n_ptr, G, tot);
+    if (raw)
+      hipLaunchKernelGGL(rs_downsweep_kernel<true>, dim3(G), dim3(NT), 0, s, ki, vi, ko, vo, n_ptr, off_ptr, shift, bits,
+                         hist, tot, G);
+    else
+      hipLaunchKernelGGL(rs_downsweep_kernel<false>, dim3(G), dim3(NT), 0, s, ki, vi, ko, vo, n_ptr, off_ptr, shift, bits,
+                         hist, tot, G);
     shift += bits;
     cur ^= 1;
   }
