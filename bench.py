@@ -263,8 +263,8 @@ def main():
 # They describe the kernels whose sources hash to `source_sha256` and are reported only
 # while the sources still do (profiles/traffic_local_step_1M_1280x720.txt).
 MEASURED_TRAFFIC = {
-    "source_sha256": "d36dc28e2258052340991f3f96ed608cdeb8cc838d6f7d257352a46a26c7da2e",
-    "bytes": {"bin_and_sort": 84.568e6, "render_forward": 18.099e6, "render_backward": 17.452e6},
+    "source_sha256": "3008baab7da9acbd15d0f483f73876ed3ebf9597763c4bbd0521af40a08b3a58",
+    "bytes": {"bin_and_sort": 83.640e6, "render_forward": 18.101e6, "render_backward": 17.452e6},
 }
 
 
